@@ -1,0 +1,396 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks an oracle function against something other than itself: a
+closed form, a library routine (LAPACK through numpy/scipy), the SVD form of
+ridge regression the paper states in Sec. 6.2, polynomial reproduction and
+interpolation properties of the least-squares fit of Algorithm 1, or an
+invariant of the whole pipeline.  The cases are chosen so that a dropped term,
+a wrong sign or index, or a transposed operand fails at least one of them.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+import workloads
+
+EPS = np.finfo(np.float64).eps
+
+
+def spd(d, seed, cond=100.0):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    ev = np.logspace(0, -np.log10(cond), d)
+    return (Q * ev) @ Q.T
+
+
+# ------------------------------------------------------------------ folds / Gram
+
+@pytest.mark.parametrize("n,k", [(10, 5), (11, 5), (2048, 5), (7, 3), (2, 2)])
+def test_fold_bounds_match_array_split(n, k):
+    sizes = [len(a) for a in np.array_split(np.arange(n), k)]
+    b = oracle.fold_bounds(n, k)
+    assert list(np.diff(b)) == sizes
+    assert b[0] == 0 and b[-1] == n
+
+
+@pytest.mark.parametrize("normalize", [True, False])
+def test_fold_gram_bruteforce(normalize):
+    rng = np.random.default_rng(1)
+    n, d, c, k = 53, 7, 3, 5
+    X = rng.standard_normal((n, d))
+    Y = rng.standard_normal((n, c))
+    b = oracle.fold_bounds(n, k)
+    Gsum = np.zeros((d, d))
+    for f in range(k):
+        H, B, ntr = oracle.fold_gram(X, Y, k, f, normalize)
+        mask = np.ones(n, bool)
+        mask[b[f]:b[f + 1]] = False
+        Xt, Yt = X[mask], Y[mask]
+        s = 1.0 / ntr if normalize else 1.0
+        assert ntr == mask.sum()
+        np.testing.assert_allclose(H, Xt.T @ Xt * s, rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose(B, Xt.T @ Yt * s, rtol=1e-13, atol=1e-14)
+        assert np.array_equal(H, H.T)
+        Xv = X[b[f]:b[f + 1]]
+        Gsum += Xv.T @ Xv
+    # the validation blocks tile the rows: their Grams add up to the full one
+    np.testing.assert_allclose(Gsum, X.T @ X, rtol=1e-12)
+
+
+# ------------------------------------------------------------------ Cholesky
+
+def test_cholesky_1x1():
+    L, info = oracle.cholesky(np.array([[3.0]]), 1.5)
+    assert info == 0
+    assert L[0, 0] == np.sqrt(4.5)
+
+
+@pytest.mark.parametrize("a,b,c,lam", [(4.0, 2.0, 3.0, 1.0), (2.0, -1.5, 5.0, 0.25),
+                                       (1e-3, 1e-4, 2e-3, 1e-6)])
+def test_cholesky_2x2_closed_form(a, b, c, lam):
+    A = np.array([[a, b], [b, c]])
+    L, info = oracle.cholesky(A, lam)
+    assert info == 0
+    l11 = np.sqrt(a + lam)
+    l21 = b / l11
+    l22 = np.sqrt(c + lam - b * b / (a + lam))
+    np.testing.assert_allclose(L, [[l11, 0.0], [l21, l22]], rtol=4 * EPS)
+
+
+def test_cholesky_diagonal_closed_form():
+    h = np.array([0.5, 2.0, 1e-3, 7.0, 0.0])
+    L, info = oracle.cholesky(np.diag(h), 0.3)
+    assert info == 0
+    np.testing.assert_allclose(L, np.diag(np.sqrt(h + 0.3)), rtol=2 * EPS)
+
+
+@pytest.mark.parametrize("d,seed,lam", [(1, 0, 0.1), (9, 1, 1e-3), (37, 2, 0.0),
+                                        (64, 3, 1e-5), (130, 4, 2.0)])
+def test_cholesky_matches_lapack(d, seed, lam):
+    A = spd(d, seed, cond=1e3)
+    L, info = oracle.cholesky(A, lam)
+    assert info == 0
+    Lref = np.linalg.cholesky(A + lam * np.eye(d))
+    np.testing.assert_allclose(L, Lref, rtol=0, atol=1e-12 * np.abs(Lref).max())
+    assert np.all(np.triu(L, 1) == 0.0)
+    assert np.all(np.diag(L) > 0)
+
+
+@pytest.mark.parametrize("d", [5, 40, 200])
+def test_cholesky_backward_error(d):
+    A = spd(d, 10 + d, cond=1e6)
+    lam = 1e-7
+    L, info = oracle.cholesky(A, lam)
+    assert info == 0
+    Al = A + lam * np.eye(d)
+    resid = np.linalg.norm(L @ L.T - Al, 2)
+    assert resid <= 4 * d * EPS * np.linalg.norm(Al, 2)
+
+
+def test_cholesky_reads_lower_triangle_only():
+    A = spd(6, 5)
+    junk = A.copy()
+    junk[np.triu_indices(6, 1)] = 1e6
+    L1, _ = oracle.cholesky(A, 0.1)
+    L2, _ = oracle.cholesky(junk, 0.1)
+    assert np.array_equal(L1, L2)
+
+
+def test_cholesky_not_positive_definite_reports_first_column():
+    # leading minors of order 1, 2 are positive, order 3 is not
+    A = np.diag([1.0, 2.0, -1.0, 4.0])
+    assert oracle.cholesky(A, 0.5)[1] == 3
+    assert oracle.cholesky(A, 1.5)[1] == 0
+    B = np.array([[1.0, 2.0], [2.0, 1.0]])  # indefinite: 1 - 4 < 0
+    assert oracle.cholesky(B, 0.0)[1] == 2
+    assert oracle.cholesky(np.array([[np.nan]]), 0.0)[1] == 1
+
+
+def test_pack_roundtrip():
+    rng = np.random.default_rng(3)
+    L = np.tril(rng.standard_normal((9, 9)))
+    t = oracle.pack_lower(L)
+    assert t.shape == (45,)
+    assert t[3 * 4 // 2 + 2] == L[3, 2]
+    assert np.array_equal(oracle.unpack_lower(t, 9), L)
+
+
+# ------------------------------------------------------------------ fit / evaluate
+
+def _quadratic_targets(lam, D, seed, deg=2):
+    """Target rows whose every entry is a polynomial of degree deg in lambda."""
+    rng = np.random.default_rng(seed)
+    coef = rng.standard_normal((deg + 1, D))
+    V = np.vander(lam, deg + 1, increasing=True)
+    return V @ coef, coef
+
+
+@pytest.mark.parametrize("g,r", [(3, 2), (4, 2), (6, 2), (5, 3), (4, 1), (3, 0)])
+def test_fit_reproduces_polynomials(g, r):
+    lam_s = np.array([0.05, 0.3, 0.9, 1.7, 2.2, 3.1])[:g]
+    T, coef = _quadratic_targets(lam_s, 11, seed=g, deg=r)
+    lam_ref = 2.5
+    Theta = oracle.fit(T, lam_s, r, lam_ref)
+    for lam in [0.0, 0.07, 1.0, 2.9, 4.0]:
+        want = np.vander([lam], r + 1, increasing=True)[0] @ coef
+        np.testing.assert_allclose(oracle.evaluate(Theta, lam, lam_ref), want,
+                                   rtol=1e-11, atol=1e-11)
+    # coefficients are in tau = lambda / lam_ref
+    np.testing.assert_allclose(Theta, coef * (lam_ref ** np.arange(r + 1))[:, None],
+                               rtol=1e-10, atol=1e-11)
+
+
+@pytest.mark.parametrize("g", [2, 3, 4, 6])
+def test_fit_interpolates_samples_when_degree_is_g_minus_1(g):
+    rng = np.random.default_rng(20 + g)
+    lam_s = np.sort(rng.uniform(0.01, 1.0, g))
+    T = rng.standard_normal((g, 17))
+    Theta = oracle.fit(T, lam_s, g - 1, lam_s.max())
+    # Algorithm 1 solves the normal equations, whose rounding error grows
+    # with cond(V)^2
+    cond = np.linalg.cond(np.vander(lam_s / lam_s.max(), g, increasing=True))
+    tol = 10 * cond ** 2 * EPS * np.abs(T).max()
+    for s in range(g):
+        np.testing.assert_allclose(oracle.evaluate(Theta, lam_s[s], lam_s.max()),
+                                   T[s], rtol=0, atol=tol)
+
+
+def test_fit_is_the_least_squares_solution():
+    rng = np.random.default_rng(7)
+    g, r, D = 6, 2, 23
+    lam_s = np.logspace(-3, 0, g)
+    T = rng.standard_normal((g, D))
+    lam_ref = lam_s.max()
+    Theta = oracle.fit(T, lam_s, r, lam_ref)
+    V = np.vander(lam_s / lam_ref, r + 1, increasing=True)
+    # normal-equation residual V^T (T - V Theta) = 0
+    np.testing.assert_allclose(V.T @ (T - V @ Theta), 0.0, atol=1e-12)
+    # LAPACK least squares (QR/SVD based) gives the same polynomial
+    ref, *_ = np.linalg.lstsq(V, T, rcond=None)
+    np.testing.assert_allclose(Theta, ref, rtol=1e-10, atol=1e-12)
+
+
+def test_fit_does_not_depend_on_basis_scale():
+    rng = np.random.default_rng(8)
+    lam_s = np.array([1e-3, 1e-2, 0.1, 1.0])
+    T = rng.standard_normal((4, 13))
+    a = oracle.fit(T, lam_s, 2, 1.0)
+    b = oracle.fit(T, lam_s, 2, 0.37)
+    for lam in [5e-4, 0.05, 0.6]:
+        np.testing.assert_allclose(oracle.evaluate(a, lam, 1.0),
+                                   oracle.evaluate(b, lam, 0.37), rtol=1e-11,
+                                   atol=1e-12)
+
+
+def test_fit_rejects_bad_arguments():
+    T = np.ones((3, 4))
+    with pytest.raises(ValueError):
+        oracle.fit(T, [0.1, 0.2, 0.3], 3, 1.0)  # r >= g
+    with pytest.raises(ValueError):
+        oracle.fit(T, [0.1, 0.1, 0.3], 2, 1.0)  # repeated sample
+    with pytest.raises(ValueError):
+        oracle.fit(T, [0.1, 0.2, 0.3], 1, 0.0)  # lam_ref <= 0
+
+
+def test_interpolated_factor_tracks_exact_factor():
+    """Sec. 3.3 / Fig. 2: second-order polynomials through a few exact factors
+    trace the factor entries closely between the samples."""
+    A = spd(8, 30, cond=50.0)
+    lam_s = np.array([0.1, 0.2, 0.35, 0.5, 0.7])
+    T = np.stack([oracle.pack_lower(oracle.cholesky(A, l)[0]) for l in lam_s])
+    Theta = oracle.fit(T, lam_s, 2, 0.7)
+    spread = np.linalg.norm(T[-1] - T[0])
+    for lam in [0.15, 0.3, 0.6]:
+        exact = oracle.pack_lower(oracle.cholesky(A, lam)[0])
+        approx = oracle.evaluate(Theta, lam, 0.7)
+        err = np.linalg.norm(approx - exact)
+        assert err <= 1e-2 * np.linalg.norm(exact)
+        assert err <= 0.05 * spread
+
+
+# ------------------------------------------------------------------ solves / hold-out
+
+def test_solve_diagonal_closed_form():
+    Ld = np.diag([2.0, 0.5, 3.0])
+    B = np.array([[1.0, 2.0], [3.0, -1.0], [0.5, 0.25]])
+    W, fl = oracle.solve(Ld, B)
+    assert fl == 0
+    np.testing.assert_allclose(W, B / np.diag(Ld)[:, None] ** 2, rtol=2 * EPS)
+
+
+@pytest.mark.parametrize("d,c", [(1, 1), (12, 3), (70, 10)])
+def test_solve_matches_lapack_triangular(d, c):
+    rng = np.random.default_rng(d)
+    L = np.linalg.cholesky(spd(d, d + 100, cond=1e3))
+    B = rng.standard_normal((d, c))
+    W, fl = oracle.solve(L, B)
+    assert fl == 0
+    U = scipy.linalg.solve_triangular(L, B, lower=True)
+    Wref = scipy.linalg.solve_triangular(L.T, U, lower=False)
+    np.testing.assert_allclose(W, Wref, rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(L @ (L.T @ W), B, atol=1e-10)
+
+
+def test_solve_flags():
+    L = np.array([[1.0, 0.0], [0.5, -2.0]])
+    _, fl = oracle.solve(L, np.ones(2))
+    assert fl & 2
+    L0 = np.array([[1.0, 0.0], [0.5, 0.0]])
+    _, fl = oracle.solve(L0, np.ones(2))
+    assert fl == 3  # zero pivot: not positive and a non-finite solution
+
+
+def test_holdout_definition_and_gram_identity():
+    rng = np.random.default_rng(4)
+    nv, d, c = 31, 6, 3
+    Xv = rng.standard_normal((nv, d))
+    Yv = np.sign(rng.standard_normal((nv, c)))
+    W = rng.standard_normal((d, c))
+    R = Yv - Xv @ W
+    sse = oracle.holdout_sse(Xv, Yv, W)
+    np.testing.assert_allclose(sse, np.sum(R * R), rtol=1e-13)
+    # sum R^2 = |Y|^2 - 2 <W, X^T Y> + tr(W^T X^T X W)
+    ident = np.sum(Yv * Yv) - 2 * np.sum(W * (Xv.T @ Yv)) + np.sum(W * (Xv.T @ Xv @ W))
+    np.testing.assert_allclose(sse, ident, rtol=1e-12)
+    sst = oracle.holdout_sst(Yv)
+    np.testing.assert_allclose(sst, np.sum((Yv - Yv.mean(0)) ** 2), rtol=1e-13)
+
+
+# ------------------------------------------------------------------ pipelines
+
+def _ridge_svd(Xt, Yt, lam, ntr):
+    """Sec. 6.2 closed form theta = V diag(sig/(sig^2+lam)) U^T y, applied to
+    the normalised training data X_tr/sqrt(n_tr), Y_tr/sqrt(n_tr)."""
+    Xs = Xt / np.sqrt(ntr)
+    Ys = Yt / np.sqrt(ntr)
+    U, sig, Vt = np.linalg.svd(Xs, full_matrices=False)
+    return Vt.T @ ((sig / (sig ** 2 + lam))[:, None] * (U.T @ Ys))
+
+
+@pytest.mark.parametrize("n,d,c,k", [(60, 5, 2, 3), (203, 17, 4, 5), (41, 40, 1, 2)])
+def test_exact_cv_matches_svd_ridge_form(n, d, c, k):
+    p = workloads.gaussian_problem(n, d, c, seed=n, k=k, q=7)
+    out = oracle.cv_exact(p.X, p.Y, k, p.lam_grid, want_W=True)
+    b = oracle.fold_bounds(n, k)
+    assert np.all(out["info"] == 0) and np.all(out["flags"] == 0)
+    for f in range(k):
+        mask = np.ones(n, bool)
+        mask[b[f]:b[f + 1]] = False
+        Xt, Yt = p.X[mask], p.Y[mask]
+        Xv, Yv = p.X[~mask], p.Y[~mask]
+        for t, lam in enumerate(p.lam_grid):
+            th = _ridge_svd(Xt, Yt, lam, mask.sum())
+            scale = np.abs(th).max()
+            np.testing.assert_allclose(out["W"][f, t], th, rtol=0,
+                                       atol=1e-9 * scale)
+            mse = np.sum((Yv - Xv @ th) ** 2) / (Yv.size)
+            np.testing.assert_allclose(out["mse"][f, t], mse, rtol=1e-9)
+
+
+def test_interp_equals_exact_when_samples_are_the_grid():
+    """With g = q, the samples equal to the grid and r = g - 1 the fit
+    interpolates every exact factor, so piCholesky CV is exact CV."""
+    p = workloads.gaussian_problem(300, 24, 3, seed=5, q=4, lam_range=(1e-2, 1.0))
+    ex = oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid, want_W=True)
+    pi = oracle.cv_interp(p.X, p.Y, p.k, p.lam_grid, p.lam_grid, 3, want_W=True)
+    np.testing.assert_allclose(pi["mse"], ex["mse"], rtol=1e-9)
+    np.testing.assert_allclose(pi["W"], ex["W"], rtol=0, atol=1e-8 * np.abs(ex["W"]).max())
+
+
+def test_interp_cv_reproduces_sample_points():
+    """At grid values that coincide with samples, r = g - 1 reproduces the
+    exact hold-out errors even when the rest of the grid is interpolated."""
+    p = workloads.gaussian_problem(400, 30, 2, seed=9, g=4, q=10, lam_range=(1e-3, 1.0))
+    lam_s = p.lam_grid[[0, 3, 6, 9]]
+    ex = oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid)
+    pi = oracle.cv_interp(p.X, p.Y, p.k, lam_s, p.lam_grid, 3)
+    np.testing.assert_allclose(pi["mse"][:, [0, 3, 6, 9]], ex["mse"][:, [0, 3, 6, 9]],
+                               rtol=1e-9)
+
+
+def test_fold_interp_matches_cv_interp():
+    p = workloads.gaussian_problem(250, 20, 3, seed=2, g=4, q=9)
+    full = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r, want_W=True)
+    b = oracle.fold_bounds(p.n, p.k)
+    for f in [0, 4]:
+        H, B, _ = oracle.fold_gram(p.X, p.Y, p.k, f)
+        one = oracle.fold_interp(H, B, p.X[b[f]:b[f + 1]], p.Y[b[f]:b[f + 1]],
+                                 p.lam_s, p.lam_grid, p.r, want_W=True)
+        np.testing.assert_array_equal(one["mse"], full["mse"][f])
+        np.testing.assert_array_equal(one["W"], full["W"][f])
+
+
+def test_not_pd_sample_sets_info_and_nan():
+    rng = np.random.default_rng(0)
+    n, d = 40, 6
+    X = rng.standard_normal((n, d))
+    Y = rng.standard_normal((n, 1))
+    # a negative sample lambda larger than the smallest eigenvalue of H_f
+    lam_s = np.array([-50.0, 0.1, 0.2])
+    out = oracle.cv_interp(X, Y, 2, lam_s, np.array([0.15]), 2, lam_ref=0.2)
+    assert np.all(out["info"][:, 0] > 0)
+    assert np.all(np.isnan(out["mse"]))
+    assert np.all(out["flags"] & 1)
+
+
+def test_selection_helpers():
+    curve = np.array([3.0, 1.0, 1.0, np.nan, 2.0])
+    assert oracle.select(curve) == 1  # ties go to the smallest lambda
+    g = oracle.gaps(np.array([1.0, 0.5, 2.0]), np.array([1.0, 0.6, 0.4]),
+                    np.array([0.1, 1.0, 10.0]))
+    assert g["t_pi"] == 1 and g["t_ex"] == 2
+    np.testing.assert_allclose(g["regret"], 0.2)
+    np.testing.assert_allclose(g["sel_err_log10"], 1.0)
+    np.testing.assert_allclose(g["curve_gap"], 4.0)
+
+
+def test_config1_matches_known_behaviour():
+    """Config 1 (Gaussian, n=2000, d=256): piCholesky selects the same grid
+    value as exact CV and its curve stays within 1% of it."""
+    p = workloads.config(1)
+    ex = oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid)
+    pi = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r)
+    g = oracle.gaps(oracle.cv_curve(pi["mse"]), oracle.cv_curve(ex["mse"]), p.lam_grid)
+    assert g["t_pi"] == g["t_ex"]
+    assert g["curve_gap"] < 1e-2
+    # at the sample values (grid indices 0, 10, 20, 30) the fit of degree 2
+    # through 4 samples is not an interpolant, but stays close
+    np.testing.assert_allclose(p.lam_s, p.lam_grid[[0, 10, 20, 30]], rtol=1e-12)
+
+
+def test_cholesky_derivative_matches_frechet_form():
+    """Thm. 4.1: the derivative of the factor along Delta = I is the
+    lower-triangular Gamma with Gamma L^T + L Gamma^T = I, i.e.
+    Gamma = L Phi(L^-1 L^-T) where Phi keeps the strict lower triangle and half
+    the diagonal.  Central differences of the oracle's factor must agree."""
+    A = spd(7, 40, cond=20.0)
+    lam, h = 0.3, 1e-5
+    L, _ = oracle.cholesky(A, lam)
+    fd = (oracle.cholesky(A, lam + h)[0] - oracle.cholesky(A, lam - h)[0]) / (2 * h)
+    Li = np.linalg.inv(L)
+    S = Li @ Li.T
+    Phi = np.tril(S, -1) + 0.5 * np.diag(np.diag(S))
+    Gamma = L @ Phi
+    np.testing.assert_allclose(Gamma @ L.T + L @ Gamma.T, np.eye(7), atol=1e-12)
+    np.testing.assert_allclose(fd, Gamma, rtol=0, atol=1e-8)
