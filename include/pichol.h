@@ -1,0 +1,304 @@
+/*
+ * pichol.h -- C-ABI of the MI355X (gfx950) piCholesky cross-validation
+ * library.
+ *
+ * Method: Kuang, Gittens, Hamid, "Cholesky Factor Interpolation for
+ * Efficient Approximate Cross-Validation" (arXiv 1404.0466).  Ridge
+ * regression theta = (H + lambda I)^{-1} g with H = X^T X, g = X^T y
+ * (Sec. 3.1, regularised normal equations), solved through a Cholesky factor
+ * and two triangular solves (Sec. 3.2).  piCholesky (Algorithm 1, Sec. 3.3)
+ * factors H + lambda_s I exactly at g sample values, fits a polynomial of
+ * degree r in lambda to every entry of the factor by least squares, and
+ * evaluates the polynomials at the dense grid instead of factoring there.
+ *
+ * General conventions
+ * -------------------
+ *  - Every pointer documented "device" is HIP device memory owned by the
+ *    caller; "host" pointers are read before the call returns.  The library
+ *    allocates no memory: scratch space comes from the caller's workspace.
+ *  - Work is enqueued on the caller's stream; calls return after enqueueing.
+ *    Inputs must stay valid until the stream reaches the end of the work.
+ *  - Argument errors are returned synchronously before anything is
+ *    enqueued.  Data errors are reported asynchronously in device arrays:
+ *      info[u]  = 0, or j+1 when the pivot of column j (0-based) of a shifted
+ *                 matrix was not positive (LAPACK convention); the outputs
+ *                 that depend on that factor are then NaN;
+ *      flags[u] bit0 = a solution or hold-out error is not finite,
+ *               bit1 = a diagonal entry of the (interpolated) factor is <= 0.
+ *  - Results are bitwise reproducible from run to run (no floating-point
+ *    atomics; every reduction has a fixed order).
+ *  - All arithmetic is IEEE FP64.
+ *
+ * Folds: k contiguous folds; fold f holds rows [start_f, start_{f+1}) with
+ * sizes as numpy.array_split (the first n mod k folds get one extra row).
+ * The training set of fold f is every other row.
+ *
+ * Tile-packed triangle ("packed" below)
+ * -------------------------------------
+ * A d x d lower triangle is stored as the lower triangle of 128 x 128 tiles:
+ * nt = ceil(d/128) tile rows, tile (I,J) with J <= I at element offset
+ * (I(I+1)/2 + J) * 16384, each tile column-major (entry (i,j) of the tile at
+ * j*128 + i).  pichol_packed_elems(d) = nt(nt+1)/2 * 16384.  Rows and
+ * columns at index >= d are padding: 1 on the diagonal, 0 elsewhere.  In a
+ * factor, the strict upper part of every diagonal tile is 0; in a symmetric
+ * input only entries with i >= j are read.
+ * "dp" below is the padded order nt*128.
+ *
+ * Right-hand-side slab
+ * --------------------
+ * Solutions for q lambda values of one fold share a row-major dp x ldz
+ * matrix, ldz = pichol_slab_cols(q, c) = q*c rounded up to a multiple of
+ * 128; column t*c + j holds right-hand side j for lambda index t.
+ */
+#ifndef PICHOL_H
+#define PICHOL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PICHOL_OK = 0,
+  PICHOL_ERR_ARG = -1,       /* invalid argument or shape                  */
+  PICHOL_ERR_WORKSPACE = -2, /* workspace missing or smaller than required */
+  PICHOL_ERR_HIP = -3,       /* a HIP runtime call failed                  */
+  PICHOL_ERR_NOT_PD = -4,    /* returned by pichol_check only              */
+  PICHOL_ERR_DATA = -5       /* returned by pichol_check only: flags set   */
+} pichol_status;
+
+typedef enum {
+  PICHOL_METHOD_INTERP = 1, /* piCholesky: Algorithm 1 + evaluation         */
+  PICHOL_METHOD_EXACT = 2   /* one exact factorization per grid value       */
+} pichol_method;
+
+/* Problem description shared by the pipeline calls.
+ *   n, d, c   rows of X, features, right-hand sides (label columns);
+ *             n >= k, d >= 1, 1 <= c
+ *   k         folds, 2 <= k <= n
+ *   g, r, q   sample lambdas, polynomial degree (0 <= r < g <= 32,
+ *             r <= 7), dense grid size (q >= 1)
+ *   normalize 1: H_f = X_tr^T X_tr / n_tr and B_f = X_tr^T Y_tr / n_tr;
+ *             0: no division (the paper's X^T X, X^T y)
+ *   ldx, ldy  row-major leading dimensions of X (n x d) and Y (n x c),
+ *             ldx >= d, ldy >= c                                            */
+typedef struct {
+  int64_t n, d, c;
+  int32_t k, g, r, q;
+  int32_t normalize;
+  int64_t ldx, ldy;
+} pichol_problem;
+
+/* ---------------------------------------------------------------- layout */
+
+/* Elements of one tile-packed triangle of order d (0 when d < 1). */
+int64_t pichol_packed_elems(int64_t d);
+/* Padded order nt*128 of a tile-packed triangle of order d. */
+int64_t pichol_padded_order(int64_t d);
+/* Column count of a right-hand-side slab holding q*c columns. */
+int64_t pichol_slab_cols(int64_t q, int64_t c);
+
+/* Dense -> packed.  A: nmat row-major d x d matrices (device, leading
+ * dimension lda >= d, consecutive matrices lda*d apart); only entries with
+ * i >= j are read.  P: nmat packed triangles (device), padding written as
+ * above; the strict upper part of diagonal tiles is written as 0. */
+pichol_status pichol_pack(int64_t d, int32_t nmat, const double *A,
+                          int64_t lda, double *P, hipStream_t stream);
+
+/* Packed -> dense lower triangle.  A receives nmat row-major d x d
+ * matrices (device, leading dimension lda >= d) with zeros above the
+ * diagonal. */
+pichol_status pichol_unpack(int64_t d, int32_t nmat, const double *P,
+                            double *A, int64_t lda, hipStream_t stream);
+
+/* -------------------------------------------------------------- step calls */
+
+/* Fold Gram matrices (Sec. 3.1: H = X^T X, g = X^T y).
+ * In:  X n x d, Y n x c (device, row-major, leading dims in p).
+ * Out (device):
+ *   G   k x dp x dp: G[b] = X_b^T X_b over the rows of fold b, both
+ *       triangles, stored as nt x nt column-major 128 x 128 tiles (tile
+ *       (I,J) at (I*nt + J)*16384), padding 0;
+ *   C   k x dp x c row-major: C[b] = X_b^T Y_b, padding rows 0;
+ *   yy  k: yy[b] = sum of Y_b^2;
+ *   H   k packed: H_f = sum_{b != f} G[b] (/ n_tr when normalize);
+ *   B   k x dp x c row-major: B_f = sum_{b != f} C[b] (/ n_tr).
+ * Sums over blocks run in increasing block order. */
+pichol_status pichol_gram(const pichol_problem *p, const double *X,
+                          const double *Y, double *G, double *C, double *yy,
+                          double *H, double *B, hipStream_t stream);
+
+/* Scratch bytes needed by pichol_potrf_shifted_batched for nmat*nshift
+ * factorizations. */
+size_t pichol_potrf_workspace(int32_t nmat, int32_t nshift);
+
+/* Batched exact Cholesky of shifted matrices (Sec. 3.2; Algorithm 1 step 1).
+ * In:  H nmat packed symmetric matrices of order d (device);
+ *      lam nshift shifts (host).
+ * Out: L nmat*nshift packed factors (device), factor (m,s) at
+ *      (m*nshift + s) * pichol_packed_elems(d): L L^T = H_m + lam_s I on the
+ *      first d rows/columns, lower triangular with positive diagonal;
+ *      info nmat*nshift (device, int32), see the conventions above.
+ * Blocked right-looking algorithm on 128-wide panels; the trailing updates
+ * run on FP64 MFMA.  ws: pichol_potrf_workspace(nmat, nshift) bytes. */
+pichol_status pichol_potrf_shifted_batched(int64_t d, int32_t nmat,
+                                           const double *H, int32_t nshift,
+                                           const double *lam, double *L,
+                                           int32_t *info, void *ws,
+                                           size_t ws_bytes,
+                                           hipStream_t stream);
+
+/* Least-squares polynomial fit of every factor entry (Algorithm 1 steps
+ * 2-6).  The basis is the monomials 1, tau, ..., tau^r of
+ * tau = lambda / lam_ref (the same polynomial space as monomials in lambda;
+ * lam_ref > 0, normally the largest sample).  Theta = V^+ T with
+ * V[s][j] = tau_s^j, the pseudo-inverse V^+ computed on the host in FP64 by
+ * Householder QR.
+ * In:  L nmat*g packed factors (device), factor (m,s) at (m*g + s)*S;
+ *      lam_s g distinct sample values (host).
+ * Out: theta nmat*(r+1) packed coefficient planes (device), plane (m,j) at
+ *      (m*(r+1) + j)*S;
+ *      theta_t (optional, may be NULL) the same planes with every tile
+ *      stored row-major instead of column-major (used by the backward
+ *      solve of pichol_solve_interp). */
+pichol_status pichol_fit(int64_t d, int32_t nmat, int32_t g, int32_t r,
+                         const double *lam_s, double lam_ref, const double *L,
+                         double *theta, double *theta_t, hipStream_t stream);
+
+/* Scratch bytes for pichol_eval and pichol_solve_interp with nlam values. */
+size_t pichol_lambda_workspace(int32_t nlam);
+
+/* Evaluate the fitted factor at nlam values (Sec. 3.3):
+ * Lhat(m,t) = sum_j (lam_t/lam_ref)^j theta(m,j).
+ * Out: Lhat nmat*nlam packed (device), (m,t) at (m*nlam + t)*S.
+ * ws: pichol_lambda_workspace(nlam) bytes. */
+pichol_status pichol_eval(int64_t d, int32_t nmat, int32_t r,
+                          const double *theta, int32_t nlam,
+                          const double *lam, double lam_ref, double *Lhat,
+                          void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Interpolated solves for all q grid values of nmat folds (Sec. 3.2 applied
+ * to the evaluated factor of Sec. 3.3), without materialising the factors:
+ * forward substitution Lhat_t U = B then back substitution Lhat_t^T W = U,
+ * blocked over 128-row tiles, the off-diagonal updates of all q values done
+ * as one FP64 MFMA product with the r+1 coefficient planes.
+ * In:  theta, theta_t from pichol_fit (device); B nmat x dp x c row-major
+ *      (device, padding rows 0); lam q values (host).
+ * Out: Z nmat slabs of dp x pichol_slab_cols(q,c) (device): W for every
+ *      (fold, lambda); flags nmat*q (device, int32), zeroed then set.
+ * ws: pichol_lambda_workspace(q) bytes. */
+pichol_status pichol_solve_interp(int64_t d, int32_t nmat, int32_t c,
+                                  int32_t r, const double *theta,
+                                  const double *theta_t, const double *B,
+                                  int32_t q, const double *lam,
+                                  double lam_ref, double *Z, int32_t *flags,
+                                  void *ws, size_t ws_bytes,
+                                  hipStream_t stream);
+
+/* Exact solves with given factors (Sec. 3.2): for fold m and index t,
+ * L(m,t) W = B_m by forward then back substitution.
+ * In:  L nmat*nper packed factors (device), (m,t) at (m*nper + t)*S;
+ *      B nmat x dp x c row-major (device).
+ * Out: Z nmat slabs dp x pichol_slab_cols(nper,c) (device);
+ *      flags nmat*nper (device), zeroed then set. */
+pichol_status pichol_solve_factors(int64_t d, int32_t nmat, int32_t nper,
+                                   int32_t c, const double *L,
+                                   const double *B, double *Z,
+                                   int32_t *flags, hipStream_t stream);
+
+/* Scratch bytes for pichol_holdout. */
+size_t pichol_holdout_workspace(int64_t d, int32_t nmat, int32_t q,
+                                int32_t c);
+
+/* Hold-out error of every (fold, lambda): with R = Y_v - X_v W,
+ * sse = |R|_F^2 computed as |Y_v|^2 - 2<W, X_v^T Y_v> + <W, X_v^T X_v W>,
+ * err = sse / (nv * c).
+ * In:  Z nmat slabs (device, as produced by the solve calls);
+ *      G, C, yy of the validation blocks (device, as from pichol_gram);
+ *      nv nmat validation row counts (host).
+ * Out: err nmat*q (device, FP64); flags nmat*q (device): bit0 is OR-ed in
+ *      when err is not finite.
+ * ws: pichol_holdout_workspace(d, nmat, q, c) bytes. */
+pichol_status pichol_holdout(int64_t d, int32_t nmat, int32_t c, int32_t q,
+                             const double *Z, const double *G,
+                             const double *C, const double *yy,
+                             const int64_t *nv, double *err, int32_t *flags,
+                             void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Copy slabs to the k x q x d x c weight layout: W[m][t][i][j] =
+ * Z[m][i][t*c + j]. */
+pichol_status pichol_slab_to_weights(int64_t d, int32_t nmat, int32_t q,
+                                     int32_t c, const double *Z, double *W,
+                                     hipStream_t stream);
+
+/* --------------------------------------------------------------- pipelines */
+
+/* Workspace bytes for the pipeline calls below with the given method(s)
+ * (a bitwise OR of pichol_method values: one workspace sized for both
+ * serves both). */
+pichol_status pichol_workspace_size(const pichol_problem *p, int32_t methods,
+                                    size_t *bytes);
+
+/* Stage 1: the fold Gram matrices of X, Y into the workspace. */
+pichol_status pichol_cv_gram(const pichol_problem *p, const double *X,
+                             const double *Y, void *ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+/* Stage 2 (piCholesky): from the Grams in ws, the g sample factorizations
+ * per fold, the fit, the solves at the q grid values and the hold-out
+ * errors.
+ *   lam_s (host, g distinct values), lam_grid (host, q), lam_ref > 0
+ *   err  k*q (device) hold-out mean squared error
+ *   W    k*q*d*c (device) weights, or NULL
+ *   info k*g (device) status of the sample factorizations
+ *   flags k*q (device) */
+pichol_status pichol_cv_interp(const pichol_problem *p, const double *lam_s,
+                               const double *lam_grid, double lam_ref,
+                               void *ws, size_t ws_bytes, double *err,
+                               double *W, int32_t *info, int32_t *flags,
+                               hipStream_t stream);
+
+/* Stage 2 (exact baseline): one exact factorization per (fold, grid
+ * value), the solves and the hold-out errors.  info is k*q. */
+pichol_status pichol_cv_exact(const pichol_problem *p, const double *lam_grid,
+                              void *ws, size_t ws_bytes, double *err,
+                              double *W, int32_t *info, int32_t *flags,
+                              hipStream_t stream);
+
+/* pichol_cv_gram followed by pichol_cv_interp. */
+pichol_status pichol_cv(const pichol_problem *p, const double *X,
+                        const double *Y, const double *lam_s,
+                        const double *lam_grid, double lam_ref, void *ws,
+                        size_t ws_bytes, double *err, double *W,
+                        int32_t *info, int32_t *flags, hipStream_t stream);
+
+/* pichol_cv_gram followed by pichol_cv_exact. */
+pichol_status pichol_exact_cv(const pichol_problem *p, const double *X,
+                              const double *Y, const double *lam_grid,
+                              void *ws, size_t ws_bytes, double *err,
+                              double *W, int32_t *info, int32_t *flags,
+                              hipStream_t stream);
+
+/* ------------------------------------------------------------------ misc */
+
+/* Synchronise the stream and inspect info/flags (device arrays, either may
+ * be NULL): PICHOL_ERR_NOT_PD when some info is non-zero, PICHOL_ERR_DATA
+ * when some flag is set, PICHOL_ERR_HIP on a runtime failure. */
+pichol_status pichol_check(const int32_t *info, int64_t n_info,
+                           const int32_t *flags, int64_t n_flags,
+                           hipStream_t stream);
+
+/* Static description of a status code. */
+const char *pichol_status_string(pichol_status s);
+
+/* Text of the last HIP error the library saw on this thread ("" if none). */
+const char *pichol_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PICHOL_H */

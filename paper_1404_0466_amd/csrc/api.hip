@@ -1,0 +1,524 @@
+// C-ABI of the piCholesky library (declared in include/pichol.h): argument
+// validation, workspace layout, host-side FP64 set-up (the pseudo-inverse of
+// the observation matrix, lambda scaling) and the order of kernel launches.
+#include <math.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "pichol.h"
+
+namespace pichol {
+
+static thread_local std::string g_last_error;
+
+hipError_t record_hip_error_code(hipError_t e) {
+  if (e != hipSuccess) g_last_error = hipGetErrorString(e);
+  return e;
+}
+
+static pichol_status hip_status(hipError_t e) {
+  if (e == hipSuccess) return PICHOL_OK;
+  record_hip_error_code(e);
+  return PICHOL_ERR_HIP;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Householder QR of V (g x m, m <= g) and P = V^+ = R^{-1} Q^T (m x g).
+// Returns false when V is rank deficient.
+static bool pseudo_inverse(int g, int m, const double* V, double* P) {
+  std::vector<double> A(V, V + (size_t)g * m);  // row-major g x m
+  std::vector<double> Qt((size_t)g * g, 0.0);   // accumulates H_m..H_1
+  for (int i = 0; i < g; ++i) Qt[(size_t)i * g + i] = 1.0;
+  std::vector<double> v(g);
+  for (int j = 0; j < m; ++j) {
+    double norm = 0.0;
+    for (int i = j; i < g; ++i) norm += A[(size_t)i * m + j] * A[(size_t)i * m + j];
+    norm = sqrt(norm);
+    if (!(norm > 0.0)) return false;
+    const double alpha = A[(size_t)j * m + j] > 0 ? -norm : norm;
+    for (int i = 0; i < g; ++i) v[i] = 0.0;
+    for (int i = j; i < g; ++i) v[i] = A[(size_t)i * m + j];
+    v[j] -= alpha;
+    double vv = 0.0;
+    for (int i = j; i < g; ++i) vv += v[i] * v[i];
+    if (!(vv > 0.0)) continue;
+    // apply I - 2 v v^T / (v^T v) to the columns of A and of Qt
+    for (int c = j; c < m; ++c) {
+      double s = 0.0;
+      for (int i = j; i < g; ++i) s += v[i] * A[(size_t)i * m + c];
+      s = 2.0 * s / vv;
+      for (int i = j; i < g; ++i) A[(size_t)i * m + c] -= s * v[i];
+    }
+    for (int c = 0; c < g; ++c) {
+      double s = 0.0;
+      for (int i = j; i < g; ++i) s += v[i] * Qt[(size_t)i * g + c];
+      s = 2.0 * s / vv;
+      for (int i = j; i < g; ++i) Qt[(size_t)i * g + c] -= s * v[i];
+    }
+  }
+  // R = A[0:m, 0:m] (upper), P = R^{-1} Qt[0:m, :]
+  for (int c = 0; c < g; ++c) {
+    for (int i = m - 1; i >= 0; --i) {
+      double s = Qt[(size_t)i * g + c];
+      for (int k = i + 1; k < m; ++k) s -= A[(size_t)i * m + k] * P[(size_t)k * g + c];
+      const double rii = A[(size_t)i * m + i];
+      if (!(fabs(rii) > 0.0)) return false;
+      P[(size_t)i * g + c] = s / rii;
+    }
+  }
+  return true;
+}
+
+static bool fold_split(int64_t n, int k, int normalize, FoldSplit* fs) {
+  if (k < 2 || k > 64 || n < k) return false;
+  memset(fs, 0, sizeof(*fs));
+  fs->k = k;
+  const int64_t base = n / k, extra = n % k;
+  fs->start[0] = 0;
+  for (int f = 0; f < k; ++f) {
+    fs->start[f + 1] = fs->start[f] + base + (f < extra ? 1 : 0);
+    const int64_t ntr = n - (fs->start[f + 1] - fs->start[f]);
+    fs->scale[f] = normalize ? 1.0 / (double)ntr : 1.0;
+  }
+  return true;
+}
+
+static bool problem_ok(const pichol_problem* p) {
+  return p && p->n >= 1 && p->d >= 1 && p->c >= 1 && p->k >= 2 && p->k <= 64 &&
+         p->n >= p->k && p->ldx >= p->d && p->ldy >= p->c && p->q >= 1 &&
+         p->g >= 1 && p->g <= 32 && p->r >= 0 && p->r <= 7 && p->r < p->g;
+}
+
+static bool samples_ok(const double* lam, int g) {
+  for (int s = 0; s < g; ++s) {
+    if (!isfinite(lam[s])) return false;
+    for (int t = 0; t < s; ++t)
+      if (lam[t] == lam[s]) return false;
+  }
+  return true;
+}
+
+static bool fit_coef(int g, int r, const double* lam_s, double lam_ref,
+                     FitCoef* fc) {
+  const int m = r + 1;
+  memset(fc, 0, sizeof(*fc));
+  fc->g = g;
+  fc->m = m;
+  std::vector<double> V((size_t)g * m), P((size_t)m * g);
+  for (int s = 0; s < g; ++s) {
+    const double tau = lam_s[s] / lam_ref;
+    double pw = 1.0;
+    for (int j = 0; j < m; ++j) {
+      V[(size_t)s * m + j] = pw;
+      pw *= tau;
+    }
+  }
+  if (!pseudo_inverse(g, m, V.data(), P.data())) return false;
+  for (int j = 0; j < m; ++j)
+    for (int s = 0; s < g; ++s) fc->P[j][s] = P[(size_t)j * g + s];
+  return true;
+}
+
+// Workspace layout of the pipeline calls.
+struct Layout {
+  int64_t d, nt, dp, S, ldz;
+  size_t G, C, yy, H, B, region;  // byte offsets
+  // interpolated region
+  size_t i_lam, i_tau, i_L, i_linv, i_th, i_tht, i_Z, i_part, i_end;
+  // exact region
+  size_t e_lam, e_L, e_linv, e_Z, e_part, e_end;
+};
+
+static Layout layout_of(const pichol_problem* p) {
+  Layout L;
+  L.d = p->d;
+  L.nt = ntiles_of(p->d);
+  L.dp = L.nt * NB;
+  L.S = packed_elems_of(p->d);
+  L.ldz = ((int64_t)p->q * p->c + NB - 1) / NB * NB;
+  const size_t k = (size_t)p->k, dbl = sizeof(double);
+  size_t o = 0;
+  L.G = o; o += align256(k * L.dp * L.dp * dbl);
+  L.C = o; o += align256(k * L.dp * p->c * dbl);
+  L.yy = o; o += align256(k * dbl);
+  L.H = o; o += align256(k * L.S * dbl);
+  L.B = o; o += align256(k * L.dp * p->c * dbl);
+  L.region = o;
+  const size_t g = (size_t)p->g, q = (size_t)p->q, M = (size_t)p->r + 1;
+  size_t a = o;
+  L.i_lam = a; a += align256(g * dbl);
+  L.i_tau = a; a += align256(q * dbl);
+  L.i_L = a; a += align256(k * g * L.S * dbl);
+  L.i_linv = a; a += align256(k * g * NB2 * dbl);
+  L.i_th = a; a += align256(k * M * L.S * dbl);
+  L.i_tht = a; a += align256(k * M * L.S * dbl);
+  L.i_Z = a; a += align256(k * L.dp * L.ldz * dbl);
+  L.i_part = a; a += align256(k * L.nt * L.ldz * dbl);
+  L.i_end = a;
+  a = o;
+  L.e_lam = a; a += align256(q * dbl);
+  L.e_L = a; a += align256(k * q * L.S * dbl);
+  L.e_linv = a; a += align256(k * q * NB2 * dbl);
+  L.e_Z = a; a += align256(k * L.dp * L.ldz * dbl);
+  L.e_part = a; a += align256(k * L.nt * L.ldz * dbl);
+  L.e_end = a;
+  return L;
+}
+
+template <typename T>
+static T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+static void holdout_norm(const pichol_problem* p, HoldoutNorm* hn) {
+  FoldSplit fs;
+  fold_split(p->n, p->k, p->normalize, &fs);
+  memset(hn, 0, sizeof(*hn));
+  hn->nmat = p->k;
+  for (int f = 0; f < p->k; ++f)
+    hn->count[f] = (double)(fs.start[f + 1] - fs.start[f]) * (double)p->c;
+}
+
+}  // namespace pichol
+
+using namespace pichol;
+
+extern "C" {
+
+int64_t pichol_packed_elems(int64_t d) { return packed_elems_of(d); }
+int64_t pichol_padded_order(int64_t d) { return d < 1 ? 0 : ntiles_of(d) * NB; }
+int64_t pichol_slab_cols(int64_t q, int64_t c) {
+  return (q < 1 || c < 1) ? 0 : (q * c + NB - 1) / NB * NB;
+}
+
+const char* pichol_status_string(pichol_status s) {
+  switch (s) {
+    case PICHOL_OK: return "ok";
+    case PICHOL_ERR_ARG: return "invalid argument";
+    case PICHOL_ERR_WORKSPACE: return "workspace missing or too small";
+    case PICHOL_ERR_HIP: return "HIP runtime error";
+    case PICHOL_ERR_NOT_PD: return "a shifted matrix is not positive definite";
+    case PICHOL_ERR_DATA: return "non-finite result or non-positive interpolated pivot";
+  }
+  return "unknown status";
+}
+
+const char* pichol_last_error(void) { return g_last_error.c_str(); }
+
+pichol_status pichol_pack(int64_t d, int32_t nmat, const double* A, int64_t lda,
+                          double* P, hipStream_t stream) {
+  if (d < 1 || nmat < 1 || !A || !P || lda < d) return PICHOL_ERR_ARG;
+  return hip_status(launch_pack(d, nmat, A, lda, P, stream));
+}
+
+pichol_status pichol_unpack(int64_t d, int32_t nmat, const double* P, double* A,
+                            int64_t lda, hipStream_t stream) {
+  if (d < 1 || nmat < 1 || !A || !P || lda < d) return PICHOL_ERR_ARG;
+  return hip_status(launch_unpack(d, nmat, P, A, lda, stream));
+}
+
+pichol_status pichol_gram(const pichol_problem* p, const double* X,
+                          const double* Y, double* G, double* C, double* yy,
+                          double* H, double* B, hipStream_t stream) {
+  if (!p || p->n < 1 || p->d < 1 || p->c < 1 || p->ldx < p->d || p->ldy < p->c)
+    return PICHOL_ERR_ARG;
+  if (!X || !Y || !G || !C || !yy || !H || !B) return PICHOL_ERR_ARG;
+  FoldSplit fs;
+  if (!fold_split(p->n, p->k, p->normalize, &fs)) return PICHOL_ERR_ARG;
+  return hip_status(launch_gram(X, p->ldx, Y, p->ldy, p->d, p->c, fs, G, C, yy,
+                                H, B, stream));
+}
+
+size_t pichol_potrf_workspace(int32_t nmat, int32_t nshift) {
+  if (nmat < 1 || nshift < 1) return 0;
+  return align256((size_t)nshift * sizeof(double)) +
+         align256((size_t)nmat * nshift * NB2 * sizeof(double));
+}
+
+pichol_status pichol_potrf_shifted_batched(int64_t d, int32_t nmat,
+                                           const double* H, int32_t nshift,
+                                           const double* lam, double* L,
+                                           int32_t* info, void* ws,
+                                           size_t ws_bytes,
+                                           hipStream_t stream) {
+  if (d < 1 || nmat < 1 || nshift < 1 || !H || !lam || !L || !info)
+    return PICHOL_ERR_ARG;
+  for (int s = 0; s < nshift; ++s)
+    if (!isfinite(lam[s])) return PICHOL_ERR_ARG;
+  if (!ws || ws_bytes < pichol_potrf_workspace(nmat, nshift))
+    return PICHOL_ERR_WORKSPACE;
+  double* lam_dev = at<double>(ws, 0);
+  double* linv = at<double>(ws, align256((size_t)nshift * sizeof(double)));
+  hipError_t e = launch_store_doubles(lam, nshift, lam_dev, stream);
+  if (e != hipSuccess) return hip_status(e);
+  e = launch_shift_copy(d, nmat, H, nshift, lam_dev, L, info, stream);
+  if (e != hipSuccess) return hip_status(e);
+  return hip_status(launch_potrf_blocked(d, nmat * nshift, L, info, linv, stream));
+}
+
+pichol_status pichol_fit(int64_t d, int32_t nmat, int32_t g, int32_t r,
+                         const double* lam_s, double lam_ref, const double* L,
+                         double* theta, double* theta_t, hipStream_t stream) {
+  if (d < 1 || nmat < 1 || g < 1 || g > 32 || r < 0 || r > 7 || r >= g ||
+      !lam_s || !L || !theta || !(lam_ref > 0.0) || !isfinite(lam_ref))
+    return PICHOL_ERR_ARG;
+  if (!samples_ok(lam_s, g)) return PICHOL_ERR_ARG;
+  FitCoef fc;
+  if (!fit_coef(g, r, lam_s, lam_ref, &fc)) return PICHOL_ERR_ARG;
+  return hip_status(launch_fit(d, nmat, fc, L, theta, theta_t, stream));
+}
+
+size_t pichol_lambda_workspace(int32_t nlam) {
+  return nlam < 1 ? 0 : align256((size_t)nlam * sizeof(double));
+}
+
+static hipError_t upload_tau(const double* lam, int nlam, double lam_ref,
+                             double* dst, hipStream_t stream) {
+  std::vector<double> tau(nlam);
+  for (int t = 0; t < nlam; ++t) tau[t] = lam[t] / lam_ref;
+  return launch_store_doubles(tau.data(), nlam, dst, stream);
+}
+
+pichol_status pichol_eval(int64_t d, int32_t nmat, int32_t r,
+                          const double* theta, int32_t nlam, const double* lam,
+                          double lam_ref, double* Lhat, void* ws,
+                          size_t ws_bytes, hipStream_t stream) {
+  if (d < 1 || nmat < 1 || r < 0 || r > 7 || nlam < 1 || !theta || !lam ||
+      !Lhat || !(lam_ref > 0.0) || !isfinite(lam_ref))
+    return PICHOL_ERR_ARG;
+  if (!ws || ws_bytes < pichol_lambda_workspace(nlam)) return PICHOL_ERR_WORKSPACE;
+  double* tau = at<double>(ws, 0);
+  hipError_t e = upload_tau(lam, nlam, lam_ref, tau, stream);
+  if (e != hipSuccess) return hip_status(e);
+  return hip_status(launch_eval(d, nmat, r + 1, theta, nlam, tau, Lhat, stream));
+}
+
+pichol_status pichol_solve_interp(int64_t d, int32_t nmat, int32_t c, int32_t r,
+                                  const double* theta, const double* theta_t,
+                                  const double* B, int32_t q, const double* lam,
+                                  double lam_ref, double* Z, int32_t* flags,
+                                  void* ws, size_t ws_bytes,
+                                  hipStream_t stream) {
+  if (d < 1 || nmat < 1 || c < 1 || r < 0 || r > 7 || q < 1 || !theta ||
+      !theta_t || !B || !lam || !Z || !flags || !(lam_ref > 0.0) ||
+      !isfinite(lam_ref))
+    return PICHOL_ERR_ARG;
+  if (!ws || ws_bytes < pichol_lambda_workspace(q)) return PICHOL_ERR_WORKSPACE;
+  const int64_t ldz = pichol_slab_cols(q, c);
+  double* tau = at<double>(ws, 0);
+  hipError_t e = upload_tau(lam, q, lam_ref, tau, stream);
+  if (e == hipSuccess) e = launch_slab_init(d, nmat, q, c, ldz, B, Z, flags, stream);
+  if (e == hipSuccess)
+    e = launch_solve_interp(d, nmat, c, r + 1, theta, theta_t, q, tau, ldz, Z,
+                            flags, stream);
+  return hip_status(e);
+}
+
+pichol_status pichol_solve_factors(int64_t d, int32_t nmat, int32_t nper,
+                                   int32_t c, const double* L, const double* B,
+                                   double* Z, int32_t* flags,
+                                   hipStream_t stream) {
+  if (d < 1 || nmat < 1 || nper < 1 || c < 1 || !L || !B || !Z || !flags)
+    return PICHOL_ERR_ARG;
+  const int64_t ldz = pichol_slab_cols(nper, c);
+  hipError_t e = launch_slab_init(d, nmat, nper, c, ldz, B, Z, flags, stream);
+  if (e == hipSuccess)
+    e = launch_solve_factors(d, nmat, nper, c, L, ldz, Z, flags, stream);
+  return hip_status(e);
+}
+
+size_t pichol_holdout_workspace(int64_t d, int32_t nmat, int32_t q, int32_t c) {
+  if (d < 1 || nmat < 1 || q < 1 || c < 1) return 0;
+  return align256((size_t)nmat * ntiles_of(d) * pichol_slab_cols(q, c) *
+                  sizeof(double));
+}
+
+pichol_status pichol_holdout(int64_t d, int32_t nmat, int32_t c, int32_t q,
+                             const double* Z, const double* G, const double* C,
+                             const double* yy, const int64_t* nv, double* err,
+                             int32_t* flags, void* ws, size_t ws_bytes,
+                             hipStream_t stream) {
+  if (d < 1 || nmat < 1 || nmat > 64 || c < 1 || q < 1 || !Z || !G || !C ||
+      !yy || !nv || !err || !flags)
+    return PICHOL_ERR_ARG;
+  if (!ws || ws_bytes < pichol_holdout_workspace(d, nmat, q, c))
+    return PICHOL_ERR_WORKSPACE;
+  HoldoutNorm hn;
+  memset(&hn, 0, sizeof(hn));
+  hn.nmat = nmat;
+  for (int m = 0; m < nmat; ++m) {
+    if (nv[m] < 1) return PICHOL_ERR_ARG;
+    hn.count[m] = (double)nv[m] * (double)c;
+  }
+  return hip_status(launch_holdout(d, nmat, c, q, pichol_slab_cols(q, c), Z, G,
+                                   C, yy, hn, static_cast<double*>(ws), err,
+                                   flags, stream));
+}
+
+pichol_status pichol_slab_to_weights(int64_t d, int32_t nmat, int32_t q,
+                                     int32_t c, const double* Z, double* W,
+                                     hipStream_t stream) {
+  if (d < 1 || nmat < 1 || q < 1 || c < 1 || !Z || !W) return PICHOL_ERR_ARG;
+  return hip_status(launch_slab_to_weights(d, nmat, q, c, pichol_slab_cols(q, c),
+                                           Z, W, stream));
+}
+
+pichol_status pichol_workspace_size(const pichol_problem* p, int32_t methods,
+                                    size_t* bytes) {
+  if (!bytes || !problem_ok(p) ||
+      (methods & ~(PICHOL_METHOD_INTERP | PICHOL_METHOD_EXACT)) || !methods)
+    return PICHOL_ERR_ARG;
+  const Layout L = layout_of(p);
+  size_t end = L.region;
+  if (methods & PICHOL_METHOD_INTERP) end = end > L.i_end ? end : L.i_end;
+  if (methods & PICHOL_METHOD_EXACT) end = end > L.e_end ? end : L.e_end;
+  *bytes = end;
+  return PICHOL_OK;
+}
+
+pichol_status pichol_cv_gram(const pichol_problem* p, const double* X,
+                             const double* Y, void* ws, size_t ws_bytes,
+                             hipStream_t stream) {
+  if (!problem_ok(p) || !X || !Y) return PICHOL_ERR_ARG;
+  const Layout L = layout_of(p);
+  if (!ws || ws_bytes < L.region) return PICHOL_ERR_WORKSPACE;
+  return pichol_gram(p, X, Y, at<double>(ws, L.G), at<double>(ws, L.C),
+                     at<double>(ws, L.yy), at<double>(ws, L.H),
+                     at<double>(ws, L.B), stream);
+}
+
+pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
+                               const double* lam_grid, double lam_ref, void* ws,
+                               size_t ws_bytes, double* err, double* W,
+                               int32_t* info, int32_t* flags,
+                               hipStream_t stream) {
+  if (!problem_ok(p) || !lam_s || !lam_grid || !err || !info || !flags ||
+      !(lam_ref > 0.0) || !isfinite(lam_ref))
+    return PICHOL_ERR_ARG;
+  if (!samples_ok(lam_s, p->g)) return PICHOL_ERR_ARG;
+  for (int t = 0; t < p->q; ++t)
+    if (!isfinite(lam_grid[t])) return PICHOL_ERR_ARG;
+  const Layout L = layout_of(p);
+  if (!ws || ws_bytes < L.i_end) return PICHOL_ERR_WORKSPACE;
+  FitCoef fc;
+  if (!fit_coef(p->g, p->r, lam_s, lam_ref, &fc)) return PICHOL_ERR_ARG;
+  HoldoutNorm hn;
+  holdout_norm(p, &hn);
+  const int k = p->k, g = p->g, q = p->q, c = (int)p->c, M = p->r + 1;
+  double* lam_dev = at<double>(ws, L.i_lam);
+  double* tau = at<double>(ws, L.i_tau);
+  double* Lf = at<double>(ws, L.i_L);
+  double* th = at<double>(ws, L.i_th);
+  double* tht = at<double>(ws, L.i_tht);
+  double* Z = at<double>(ws, L.i_Z);
+  hipError_t e = launch_store_doubles(lam_s, g, lam_dev, stream);
+  if (e == hipSuccess) e = upload_tau(lam_grid, q, lam_ref, tau, stream);
+  if (e == hipSuccess)
+    e = launch_shift_copy(p->d, k, at<double>(ws, L.H), g, lam_dev, Lf, info,
+                          stream);
+  if (e == hipSuccess)
+    e = launch_potrf_blocked(p->d, k * g, Lf, info, at<double>(ws, L.i_linv),
+                             stream);
+  if (e == hipSuccess) e = launch_fit(p->d, k, fc, Lf, th, tht, stream);
+  if (e == hipSuccess)
+    e = launch_slab_init(p->d, k, q, c, L.ldz, at<double>(ws, L.B), Z, flags,
+                         stream);
+  if (e == hipSuccess)
+    e = launch_solve_interp(p->d, k, c, M, th, tht, q, tau, L.ldz, Z, flags,
+                            stream);
+  if (e == hipSuccess)
+    e = launch_holdout(p->d, k, c, q, L.ldz, Z, at<double>(ws, L.G),
+                       at<double>(ws, L.C), at<double>(ws, L.yy), hn,
+                       at<double>(ws, L.i_part), err, flags, stream);
+  if (e == hipSuccess && W)
+    e = launch_slab_to_weights(p->d, k, q, c, L.ldz, Z, W, stream);
+  return hip_status(e);
+}
+
+pichol_status pichol_cv_exact(const pichol_problem* p, const double* lam_grid,
+                              void* ws, size_t ws_bytes, double* err, double* W,
+                              int32_t* info, int32_t* flags,
+                              hipStream_t stream) {
+  if (!problem_ok(p) || !lam_grid || !err || !info || !flags)
+    return PICHOL_ERR_ARG;
+  for (int t = 0; t < p->q; ++t)
+    if (!isfinite(lam_grid[t])) return PICHOL_ERR_ARG;
+  const Layout L = layout_of(p);
+  if (!ws || ws_bytes < L.e_end) return PICHOL_ERR_WORKSPACE;
+  HoldoutNorm hn;
+  holdout_norm(p, &hn);
+  const int k = p->k, q = p->q, c = (int)p->c;
+  double* lam_dev = at<double>(ws, L.e_lam);
+  double* Lf = at<double>(ws, L.e_L);
+  double* Z = at<double>(ws, L.e_Z);
+  hipError_t e = launch_store_doubles(lam_grid, q, lam_dev, stream);
+  if (e == hipSuccess)
+    e = launch_shift_copy(p->d, k, at<double>(ws, L.H), q, lam_dev, Lf, info,
+                          stream);
+  if (e == hipSuccess)
+    e = launch_potrf_blocked(p->d, k * q, Lf, info, at<double>(ws, L.e_linv),
+                             stream);
+  if (e == hipSuccess)
+    e = launch_slab_init(p->d, k, q, c, L.ldz, at<double>(ws, L.B), Z, flags,
+                         stream);
+  if (e == hipSuccess)
+    e = launch_solve_factors(p->d, k, q, c, Lf, L.ldz, Z, flags, stream);
+  if (e == hipSuccess)
+    e = launch_holdout(p->d, k, c, q, L.ldz, Z, at<double>(ws, L.G),
+                       at<double>(ws, L.C), at<double>(ws, L.yy), hn,
+                       at<double>(ws, L.e_part), err, flags, stream);
+  if (e == hipSuccess && W)
+    e = launch_slab_to_weights(p->d, k, q, c, L.ldz, Z, W, stream);
+  return hip_status(e);
+}
+
+pichol_status pichol_cv(const pichol_problem* p, const double* X,
+                        const double* Y, const double* lam_s,
+                        const double* lam_grid, double lam_ref, void* ws,
+                        size_t ws_bytes, double* err, double* W, int32_t* info,
+                        int32_t* flags, hipStream_t stream) {
+  pichol_status st = pichol_cv_gram(p, X, Y, ws, ws_bytes, stream);
+  if (st != PICHOL_OK) return st;
+  return pichol_cv_interp(p, lam_s, lam_grid, lam_ref, ws, ws_bytes, err, W,
+                          info, flags, stream);
+}
+
+pichol_status pichol_exact_cv(const pichol_problem* p, const double* X,
+                              const double* Y, const double* lam_grid, void* ws,
+                              size_t ws_bytes, double* err, double* W,
+                              int32_t* info, int32_t* flags,
+                              hipStream_t stream) {
+  pichol_status st = pichol_cv_gram(p, X, Y, ws, ws_bytes, stream);
+  if (st != PICHOL_OK) return st;
+  return pichol_cv_exact(p, lam_grid, ws, ws_bytes, err, W, info, flags, stream);
+}
+
+pichol_status pichol_check(const int32_t* info, int64_t n_info,
+                           const int32_t* flags, int64_t n_flags,
+                           hipStream_t stream) {
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_status(e);
+  std::vector<int32_t> h;
+  if (info && n_info > 0) {
+    h.resize(n_info);
+    e = hipMemcpy(h.data(), info, sizeof(int32_t) * n_info, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_status(e);
+    for (int32_t v : h)
+      if (v != 0) return PICHOL_ERR_NOT_PD;
+  }
+  if (flags && n_flags > 0) {
+    h.resize(n_flags);
+    e = hipMemcpy(h.data(), flags, sizeof(int32_t) * n_flags, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_status(e);
+    for (int64_t i = 0; i < n_flags; ++i)
+      if (h[i] != 0) return PICHOL_ERR_DATA;
+  }
+  return PICHOL_OK;
+}
+
+}  // extern "C"

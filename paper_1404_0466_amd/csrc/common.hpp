@@ -1,0 +1,118 @@
+// Internal definitions shared by the gfx950 kernels of the piCholesky
+// library: tile geometry of the packed layout, the FP64 MFMA micro-kernel,
+// and launch helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pichol {
+
+constexpr int NB = 128;          // tile edge
+constexpr int NB2 = NB * NB;     // elements per tile
+constexpr int LDS_LD = NB + 1;   // padded leading dimension of LDS tiles
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+__host__ __device__ inline int64_t tri(int64_t I) { return I * (I + 1) / 2; }
+
+// Element offset of tile (I,J), J <= I, inside one packed triangle.
+__host__ __device__ inline int64_t tile_off(int64_t I, int64_t J) {
+  return (tri(I) + J) * (int64_t)NB2;
+}
+
+__host__ __device__ inline int64_t ntiles_of(int64_t d) {
+  return (d + NB - 1) / NB;
+}
+
+__host__ __device__ inline int64_t packed_elems_of(int64_t d) {
+  return d < 1 ? 0 : tri(ntiles_of(d)) * (int64_t)NB2;
+}
+
+// Row index r of linear index t in a triangle enumerated row by row
+// (t = r(r+1)/2 + col, 0 <= col <= r).
+__device__ inline int tri_row(int t) {
+  int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  while (tri(r + 1) <= t) ++r;
+  while (tri(r) > t) --r;
+  return r;
+}
+
+__device__ inline v4d ld4(const double* p) { return *(const v4d*)p; }
+__device__ inline void st4(double* p, v4d v) { *(v4d*)p = v; }
+
+// ---------------------------------------------------------------------------
+// FP64 MFMA micro-kernel for one 64 x 64 block per wavefront.
+//
+// v_mfma_f64_16x16x4f64 computes D(16x16) += A(16x4) B(4x16); lane l
+// supplies A[l%16][l/16] and B[l/16][l%16] and holds D[4(l/16)+v][l%16] in
+// element v of its accumulator.
+//
+// The wave's block is the product D'(i,j) = sum_k A'(i,k) B'(k,j) for
+// i, j in [0,64).  Operands are read from memory where the non-k index is
+// contiguous: A'(i,k) at a[k*lda + i], B'(k,j) at b[k*ldb + j].  To read each
+// operand with one 32-byte load per lane and k-step, MFMA block bi takes the
+// rows i = 4*(l%16) + bi, and block bj the columns j = 4*(l%16) + bj: lane l
+// loads the four consecutive values a[k*lda + 4*(l%16) .. +3] and uses one
+// in each block.  Accumulator acc[bi][bj] element v of lane l then holds
+//     D'(i = 16*(l/16) + 4*v + bi,  j = 4*(l%16) + bj)
+// so the four bj accumulators of a lane are four consecutive j: the
+// epilogue writes them with one 32-byte store.
+// ---------------------------------------------------------------------------
+struct Acc64 {
+  v4d c[4][4];
+  __device__ inline void zero() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) c[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  __device__ inline void mma(const v4d& a, const v4d& b) {
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj)
+        c[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj],
+                                                          c[bi][bj], 0, 0, 0);
+  }
+  // Values of row i = 16*(l/16) + 4*v + bi at columns 4*(l%16) .. +3.
+  __device__ inline v4d row(int v, int bi) const {
+    return v4d{c[bi][0][v], c[bi][1][v], c[bi][2][v], c[bi][3][v]};
+  }
+};
+
+// acc += sum over k in [0,K) of A'(i,k) B'(k,j); K a multiple of 4.
+// a, b point at A'(0,0) and B'(0,0) of the wave's block.
+__device__ inline void mma_panel(Acc64& acc, const double* a, int64_t lda,
+                                 const double* b, int64_t ldb, int K) {
+  const int l = threadIdx.x & 63;
+  const double* pa = a + (int64_t)(l >> 4) * lda + 4 * (l & 15);
+  const double* pb = b + (int64_t)(l >> 4) * ldb + 4 * (l & 15);
+  const int64_t sa = 4 * lda, sb = 4 * ldb;
+  v4d av = ld4(pa), bv = ld4(pb);
+  for (int k0 = 4; k0 < K; k0 += 4) {
+    pa += sa;
+    pb += sb;
+    v4d an = ld4(pa), bn = ld4(pb);
+    acc.mma(av, bv);
+    av = an;
+    bv = bn;
+  }
+  acc.mma(av, bv);
+}
+
+// Lane coordinates inside a 64 x 64 wave block.
+struct LaneXY {
+  int lq;  // l / 16
+  int lr;  // l % 16
+  __device__ inline LaneXY() {
+    int l = threadIdx.x & 63;
+    lq = l >> 4;
+    lr = l & 15;
+  }
+  __device__ inline int row(int v, int bi) const { return 16 * lq + 4 * v + bi; }
+  __device__ inline int col0() const { return 4 * lr; }
+};
+
+}  // namespace pichol

@@ -1,0 +1,119 @@
+// Least-squares fit of every factor entry (Algorithm 1 steps 2-6) and
+// evaluation of the fitted factor (Sec. 3.3).
+//
+// Algorithm 1 stacks the g sample factors as the rows of T and solves the
+// normal equations for Theta.  Here the packed factors already are the
+// rows of T (the tile-packed triangle is the vectorisation), and Theta is
+// formed as P T with P = V^+ computed once on the host.  The inner dimension
+// is g, so both kernels stream memory: one read of every sample entry, one
+// write of every coefficient.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pichol {
+
+// Theta(m, p) tile (I,J) = sum_s P[p][s] L(m, s) tile (I,J); also written
+// with the tile stored row-major into theta_t (when non-null).
+template <int M>
+__global__ void __launch_bounds__(256) k_fit(int64_t S, FitCoef fc,
+                                             const double* L, double* theta,
+                                             double* theta_t) {
+  __shared__ double lds[16 * LDS_LD];
+  const int64_t m = blockIdx.y;
+  const int I = tri_row(blockIdx.x), J = blockIdx.x - (int)tri(I);
+  const int64_t toff = tile_off(I, J);
+  const int g = fc.g;
+  const int tid = threadIdx.x;
+  for (int cb = 0; cb < NB / 16; ++cb) {
+    double th[8][M];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = cb * 16 * NB + tid + 256 * u;
+#pragma unroll
+      for (int p = 0; p < M; ++p) th[u][p] = 0.0;
+      for (int s = 0; s < g; ++s) {
+        const double t = L[(m * g + s) * S + toff + e];
+#pragma unroll
+        for (int p = 0; p < M; ++p) th[u][p] += fc.P[p][s] * t;
+      }
+#pragma unroll
+      for (int p = 0; p < M; ++p) theta[(m * M + p) * S + toff + e] = th[u][p];
+    }
+    if (theta_t == nullptr) continue;
+#pragma unroll
+    for (int p = 0; p < M; ++p) {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = tid + 256 * u;  // within the 16-column chunk
+        lds[(e >> 7) * LDS_LD + (e & (NB - 1))] = th[u][p];
+      }
+      __syncthreads();
+      double* dst = theta_t + (m * M + p) * S + toff + cb * 16;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = tid + 256 * u;
+        const int a = e >> 4, bl = e & 15;
+        dst[a * NB + bl] = lds[bl * LDS_LD + a];
+      }
+    }
+  }
+}
+
+// Lhat(m, t) = sum_p tau_t^p Theta(m, p), four entries per thread.
+__global__ void __launch_bounds__(256) k_eval(int64_t S, int M,
+                                              const double* theta,
+                                              int nlam, const double* tau,
+                                              double* Lhat) {
+  const int64_t m = blockIdx.z;
+  const int t = blockIdx.y;
+  const double tv = tau[t];
+  for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e < S;
+       e += (int64_t)gridDim.x * blockDim.x * 4) {
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    double pw = 1.0;
+    for (int p = 0; p < M; ++p) {
+      acc += pw * ld4(theta + (m * M + p) * S + e);
+      pw *= tv;
+    }
+    st4(Lhat + (m * nlam + t) * S + e, acc);
+  }
+}
+
+hipError_t launch_fit(int64_t d, int nmat, const FitCoef& fc, const double* L,
+                      double* theta, double* theta_t, hipStream_t s) {
+  const int64_t nt = ntiles_of(d), S = packed_elems_of(d);
+  dim3 grid((unsigned)tri(nt), (unsigned)nmat);
+  switch (fc.m) {
+#define PICHOL_FIT_CASE(MM)                                                   \
+  case MM:                                                                    \
+    hipLaunchKernelGGL(k_fit<MM>, grid, dim3(256), 0, s, S, fc, L, theta,     \
+                       theta_t);                                              \
+    break;
+    PICHOL_FIT_CASE(1)
+    PICHOL_FIT_CASE(2)
+    PICHOL_FIT_CASE(3)
+    PICHOL_FIT_CASE(4)
+    PICHOL_FIT_CASE(5)
+    PICHOL_FIT_CASE(6)
+    PICHOL_FIT_CASE(7)
+    PICHOL_FIT_CASE(8)
+#undef PICHOL_FIT_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(int64_t d, int nmat, int m, const double* theta,
+                       int nlam, const double* tau_dev, double* Lhat,
+                       hipStream_t s) {
+  const int64_t S = packed_elems_of(d);
+  unsigned bx = (unsigned)((S / 4 + 255) / 256);
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(k_eval, dim3(bx, (unsigned)nlam, (unsigned)nmat),
+                     dim3(256), 0, s, S, m, theta, nlam, tau_dev, Lhat);
+  return hipGetLastError();
+}
+
+}  // namespace pichol

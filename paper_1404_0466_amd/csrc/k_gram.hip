@@ -1,0 +1,196 @@
+// Fold Gram matrices (Sec. 3.1: H = X^T X, g = X^T y) for k-fold
+// cross-validation.  Each fold's validation block b contributes
+// G_b = X_b^T X_b and C_b = X_b^T Y_b; the training Gram of fold f is the sum
+// of the other blocks, so no cancellation occurs.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pichol {
+
+__device__ inline v4d ld4_masked(const double* rowp, int64_t col, int64_t d,
+                                 bool row_ok) {
+  v4d v = {0.0, 0.0, 0.0, 0.0};
+  if (row_ok) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (col + e < d) v[e] = rowp[col + e];
+  }
+  return v;
+}
+
+// G_b tile (I,J), J <= I, over the rows of block b; FP64 MFMA.  The wave
+// computes D'(n,m) = sum_r X[r][J*128+n] X[r][I*128+m] for its 64 x 64 part,
+// i.e. G(I*128+m, J*128+n), which is element n*128+m of the column-major tile
+// (I,J); the mirror tile (J,I) receives the transpose.
+__global__ void __launch_bounds__(256) k_gram_tiles(const double* X,
+                                                    int64_t ldx, int64_t d,
+                                                    int64_t nt, FoldSplit fs,
+                                                    double* G, int vec_ok) {
+  const int b = blockIdx.y;
+  const int I = tri_row(blockIdx.x), J = blockIdx.x - (int)tri(I);
+  const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
+  const int64_t r0 = fs.start[b], r1 = fs.start[b + 1];
+  const int64_t K = r1 - r0;
+  const int64_t ncol = (int64_t)J * NB + wi * 64;  // A' columns of X
+  const int64_t mcol = (int64_t)I * NB + wj * 64;  // B' columns of X
+  const LaneXY lx;
+
+  Acc64 acc;
+  acc.zero();
+  const bool fast = vec_ok && ncol + 64 <= d && mcol + 64 <= d;
+  int64_t kdone = 0;
+  if (fast && K >= 4) {
+    const int64_t K4 = K & ~(int64_t)3;
+    // mma_panel takes an int K; split very long blocks into chunks
+    for (int64_t k0 = 0; k0 < K4; k0 += (1 << 28)) {
+      int kk = (int)((K4 - k0) < (1 << 28) ? (K4 - k0) : (1 << 28));
+      mma_panel(acc, X + (r0 + k0) * ldx + ncol, ldx,
+                X + (r0 + k0) * ldx + mcol, ldx, kk);
+    }
+    kdone = K4;
+  }
+  // remaining rows (all rows on the masked path), four at a time
+  for (int64_t k0 = kdone; k0 < K; k0 += 4) {
+    const int64_t r = r0 + k0 + lx.lq;
+    const bool ok = r < r1;
+    const double* rowp = X + (ok ? r : r0) * ldx;
+    v4d av = ld4_masked(rowp, ncol + lx.col0(), d, ok);
+    v4d bv = ld4_masked(rowp, mcol + lx.col0(), d, ok);
+    acc.mma(av, bv);
+  }
+
+  double* gb = G + (int64_t)b * nt * nt * NB2;
+  double* gt = gb + ((int64_t)I * nt + J) * NB2;
+  double* gm = gb + ((int64_t)J * nt + I) * NB2;
+  const int m0 = wj * 64 + lx.col0();
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+      const int n = wi * 64 + lx.row(v, bi);
+      const v4d val = acc.row(v, bi);
+      st4(gt + n * NB + m0, val);
+      if (I != J) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) gm[(m0 + e) * NB + n] = val[e];
+      }
+    }
+}
+
+// C_b = X_b^T Y_b (dp x c, row-major, padding rows 0); one thread per row i
+// of C_b, sums over the block's rows in increasing order.
+__global__ void __launch_bounds__(256) k_gram_rhs(const double* X, int64_t ldx,
+                                                  const double* Y, int64_t ldy,
+                                                  int64_t d, int64_t c,
+                                                  int64_t dp, FoldSplit fs,
+                                                  double* C) {
+  const int b = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= dp) return;
+  const int64_t r0 = fs.start[b], r1 = fs.start[b + 1];
+  double* crow = C + ((int64_t)b * dp + i) * c;
+  for (int64_t c0 = 0; c0 < c; c0 += 8) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t cn = (c - c0) < 8 ? (c - c0) : 8;
+    if (i < d) {
+      for (int64_t r = r0; r < r1; ++r) {
+        const double x = X[r * ldx + i];
+        const double* y = Y + r * ldy + c0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (j < cn) acc[j] += x * y[j];
+      }
+    }
+    for (int j = 0; j < cn; ++j) crow[c0 + j] = acc[j];
+  }
+}
+
+// yy[b] = sum of squares of Y over block b; fixed-order tree reduction.
+__global__ void __launch_bounds__(256) k_gram_yy(const double* Y, int64_t ldy,
+                                                 int64_t c, FoldSplit fs,
+                                                 double* yy) {
+  __shared__ double red[256];
+  const int b = blockIdx.x;
+  const int64_t r0 = fs.start[b], r1 = fs.start[b + 1];
+  const int64_t n = (r1 - r0) * c;
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const double y = Y[(r0 + e / c) * ldy + e % c];
+    acc += y * y;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) yy[b] = red[0];
+}
+
+// H_f (packed) = scale_f * sum_{b != f} G_b over the lower tiles, identity
+// padding.
+__global__ void __launch_bounds__(256) k_gram_combine_h(int64_t d, int64_t nt,
+                                                        FoldSplit fs,
+                                                        const double* G,
+                                                        double* H, int64_t S) {
+  const int f = blockIdx.y;
+  const int I = tri_row(blockIdx.x), J = blockIdx.x - (int)tri(I);
+  const double sc = fs.scale[f];
+  double* h = H + (int64_t)f * S + tile_off(I, J);
+  const int64_t gstride = nt * nt * NB2;
+  const double* g0 = G + ((int64_t)I * nt + J) * NB2;
+  for (int e = threadIdx.x; e < NB2; e += blockDim.x) {
+    const int64_t i = (int64_t)I * NB + (e & (NB - 1));
+    const int64_t j = (int64_t)J * NB + (e >> 7);
+    double v;
+    if (i >= d || j >= d) {
+      v = (i == j) ? 1.0 : 0.0;
+    } else {
+      double acc = 0.0;
+      for (int b = 0; b < fs.k; ++b)
+        if (b != f) acc += g0[b * gstride + e];
+      v = acc * sc;
+    }
+    h[e] = v;
+  }
+}
+
+// B_f = scale_f * sum_{b != f} C_b.
+__global__ void __launch_bounds__(256) k_gram_combine_b(int64_t n_el,
+                                                        FoldSplit fs,
+                                                        const double* C,
+                                                        double* B) {
+  const int f = blockIdx.y;
+  const double sc = fs.scale[f];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_el;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int b = 0; b < fs.k; ++b)
+      if (b != f) acc += C[b * n_el + e];
+    B[f * n_el + e] = acc * sc;
+  }
+}
+
+hipError_t launch_gram(const double* X, int64_t ldx, const double* Y,
+                       int64_t ldy, int64_t d, int64_t c,
+                       const FoldSplit& fs, double* G, double* C, double* yy,
+                       double* H, double* B, hipStream_t s) {
+  const int64_t nt = ntiles_of(d), dp = nt * NB, S = packed_elems_of(d);
+  const int vec_ok = ((ldx & 3) == 0) && ((((uintptr_t)X) & 31) == 0);
+  hipLaunchKernelGGL(k_gram_tiles, dim3((unsigned)tri(nt), (unsigned)fs.k),
+                     dim3(256), 0, s, X, ldx, d, nt, fs, G, vec_ok);
+  hipLaunchKernelGGL(k_gram_rhs, dim3((unsigned)((dp + 255) / 256), (unsigned)fs.k),
+                     dim3(256), 0, s, X, ldx, Y, ldy, d, c, dp, fs, C);
+  hipLaunchKernelGGL(k_gram_yy, dim3((unsigned)fs.k), dim3(256), 0, s, Y, ldy,
+                     c, fs, yy);
+  hipLaunchKernelGGL(k_gram_combine_h, dim3((unsigned)tri(nt), (unsigned)fs.k),
+                     dim3(256), 0, s, d, nt, fs, G, H, S);
+  const int64_t nb = dp * c;
+  unsigned bx = (unsigned)((nb + 255) / 256);
+  if (bx > 2048) bx = 2048;
+  hipLaunchKernelGGL(k_gram_combine_b, dim3(bx, (unsigned)fs.k), dim3(256), 0,
+                     s, nb, fs, C, B);
+  return hipGetLastError();
+}
+
+}  // namespace pichol

@@ -1,0 +1,111 @@
+// Hold-out error of every (fold, lambda).  With R = Y_v - X_v W the sum of
+// squares is expanded as
+//     |R|^2 = |Y_v|^2 - 2 <W, X_v^T Y_v> + <W, (X_v^T X_v) W>,
+// using the validation block's Gram matrices from the Gram step, so the
+// q*c solutions of a fold cost one FP64 MFMA product with the d x d block
+// Gram instead of one with the n_v x d block of X.
+// Reductions run in a fixed order (no floating-point atomics).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pichol {
+
+// Partial sums over the rows of tile row I of
+//     W(r, col) * ((G W)(r, col) - 2 C(r, col mod c))
+// for the 128 slab columns of block cb; written to
+// partial[m][I][col].
+__global__ void __launch_bounds__(256) k_holdout_partial(
+    int64_t d, int q, int c, int64_t ldz, const double* Z, const double* G,
+    const double* C, double* partial) {
+  __shared__ double red[64 * 2];
+  const int cb = blockIdx.x;
+  const int I = blockIdx.y;
+  const int64_t m = blockIdx.z;
+  const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
+  const int64_t nt = ntiles_of(d), dp = nt * NB;
+  const LaneXY lx;
+  const double* gm = G + m * dp * dp + (int64_t)I * nt * NB2 + wi * 64;
+  const double* zm = Z + m * dp * ldz + (int64_t)cb * NB + wj * 64;
+  Acc64 acc;
+  acc.zero();
+  for (int J = 0; J < nt; ++J)
+    mma_panel(acc, gm + (int64_t)J * NB2, NB, zm + (int64_t)J * NB * ldz, ldz,
+              NB);
+
+  const int64_t col = (int64_t)cb * NB + wj * 64 + lx.col0();
+  const int64_t qc = (int64_t)q * c;
+  int cmod[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) cmod[e] = (int)((col + e) % c);
+  v4d part = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+      const int64_t r = (int64_t)I * NB + wi * 64 + lx.row(v, bi);
+      const v4d wv = ld4(Z + (m * dp + r) * ldz + col);
+      const v4d gw = acc.row(v, bi);
+      const double* cr = C + (m * dp + r) * c;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        part[e] += wv[e] * (gw[e] - 2.0 * cr[cmod[e]]);
+    }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    double x = part[e];
+    x += __shfl_xor(x, 16);
+    x += __shfl_xor(x, 32);
+    part[e] = x;
+  }
+  // combine the two waves that share these columns
+  if (wi == 1 && lx.lq == 0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) red[wj * 64 + lx.col0() + e] = part[e];
+  }
+  __syncthreads();
+  if (wi == 0 && lx.lq == 0) {
+    double* out = partial + (m * nt + I) * ldz + col;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const double v = (col + e) < qc ? part[e] + red[wj * 64 + lx.col0() + e] : 0.0;
+      out[e] = v;
+    }
+  }
+}
+
+// err[m][t] = (yy[m] + sum_I sum_j partial[m][I][t*c + j]) / (n_v * c).
+__global__ void __launch_bounds__(64) k_holdout_final(int64_t nt, int q, int c,
+                                                      int64_t ldz,
+                                                      const double* partial,
+                                                      const double* yy,
+                                                      HoldoutNorm hn,
+                                                      double* err, int* flags) {
+  const int64_t m = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= q) return;
+  double sse = yy[m];
+  for (int64_t I = 0; I < nt; ++I) {
+    const double* p = partial + (m * nt + I) * ldz + (int64_t)t * c;
+    for (int j = 0; j < c; ++j) sse += p[j];
+  }
+  const double e = sse / hn.count[m];
+  err[m * q + t] = e;
+  if (!isfinite(e)) flags[m * q + t] |= 1;
+}
+
+hipError_t launch_holdout(int64_t d, int nmat, int c, int q, int64_t ldz,
+                          const double* Z, const double* G, const double* C,
+                          const double* yy, const HoldoutNorm& hn,
+                          double* partial, double* err, int* flags,
+                          hipStream_t s) {
+  const int64_t nt = ntiles_of(d);
+  hipLaunchKernelGGL(k_holdout_partial,
+                     dim3((unsigned)(ldz / NB), (unsigned)nt, (unsigned)nmat),
+                     dim3(256), 0, s, d, q, c, ldz, Z, G, C, partial);
+  hipLaunchKernelGGL(k_holdout_final,
+                     dim3((unsigned)((q + 63) / 64), (unsigned)nmat), dim3(64),
+                     0, s, nt, q, c, ldz, partial, yy, hn, err, flags);
+  return hipGetLastError();
+}
+
+}  // namespace pichol

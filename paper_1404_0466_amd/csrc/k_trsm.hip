@@ -1,0 +1,321 @@
+// Forward and back substitution (Sec. 3.2) for many right-hand sides and
+// many factors at once, blocked over 128-row tiles.
+//
+// The right-hand sides of one fold live in a row-major slab Z (dp x ldz);
+// columns t*c .. t*c+c-1 belong to lambda index t.  Forward substitution
+// walks the tile rows i = 0..nt-1: solve the diagonal block of every
+// lambda (k_diag_solve), then subtract the contribution of the solved rows
+// from every later tile row (update kernels).  Back substitution walks the
+// tile rows in reverse with the transposed blocks.
+//
+// Interpolated factors (Sec. 3.3) are never materialised.  Their diagonal
+// blocks are evaluated in LDS, and the off-diagonal update of all lambdas is
+// one FP64 MFMA product: Lhat_t(I,i) U_t = sum_p Theta_p(I,i) (tau_t^p U_t),
+// so each coefficient tile is read once per step for all q values.
+// Exact factors (the per-lambda baseline) use one factor per lambda.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pichol {
+
+__device__ inline double bcast_lane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Z[m][i][col] = B[m][i][col % c] for col < q*c, 0 beyond; flags cleared.
+__global__ void __launch_bounds__(256) k_slab_init(int64_t dp, int q, int c,
+                                                   int64_t ldz,
+                                                   const double* B, double* Z,
+                                                   int* flags) {
+  const int64_t m = blockIdx.y;
+  const int64_t n = dp * ldz;
+  const int64_t qc = (int64_t)q * c;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / ldz, col = e % ldz;
+    Z[m * n + e] = col < qc ? B[(m * dp + i) * c + col % c] : 0.0;
+  }
+  if (blockIdx.x == 0)
+    for (int t = threadIdx.x; t < q; t += blockDim.x) flags[m * q + t] = 0;
+}
+
+// Where the factors come from.
+struct FactorSrc {
+  const double* base;
+  int64_t S;      // packed elements per triangle
+  int M;          // interpolated: coefficient planes per fold
+  int exact;      // 1: factor (m,t) at base + (m*nper + t)*S
+  int nper;       // lambda values per fold
+  const double* tau;  // interpolated: tau_t = lambda_t / lambda_ref
+};
+
+// Solve the diagonal block of tile row i for lambda t = blockIdx.x of fold
+// m = blockIdx.y, in place in the slab: forward L x = z, or back L^T x = z.
+template <bool FWD>
+__global__ void __launch_bounds__(256) k_diag_solve(int64_t d, int i,
+                                                    FactorSrc src, int c,
+                                                    int64_t ldz, double* Z,
+                                                    int* flags) {
+  __shared__ double a[NB * LDS_LD];
+  const int t = blockIdx.x;
+  const int64_t m = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int64_t dp = ntiles_of(d) * NB;
+  const int64_t toff = tile_off(i, i);
+  if (src.exact) {
+    const double* p = src.base + (m * src.nper + t) * src.S + toff;
+    for (int e = tid; e < NB2; e += blockDim.x)
+      a[(e >> 7) * LDS_LD + (e & (NB - 1))] = p[e];
+  } else {
+    const double tv = src.tau[t];
+    const double* p = src.base + m * src.M * src.S + toff;
+    for (int e = tid; e < NB2; e += blockDim.x) {
+      double acc = 0.0, pw = 1.0;
+      for (int q = 0; q < src.M; ++q) {
+        acc += pw * p[q * src.S + e];
+        pw *= tv;
+      }
+      a[(e >> 7) * LDS_LD + (e & (NB - 1))] = acc;
+    }
+  }
+  __syncthreads();
+  if (FWD && tid < NB && (int64_t)i * NB + tid < d &&
+      !(a[tid * LDS_LD + tid] > 0.0))
+    atomicOr(flags + m * src.nper + t, 2);
+
+  const int lane = tid & 63, w = tid >> 6;
+  const int r0 = lane, r1 = lane + 64;
+  double* zbase = Z + (m * dp + (int64_t)i * NB) * ldz + (int64_t)t * c;
+  for (int cg = 0; cg < c; cg += 16) {
+    double z[4][2];
+    int ncol = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int cc = cg + w + 4 * u;
+      if (cc < c && cc < cg + 16) {
+        z[u][0] = zbase[(int64_t)r0 * ldz + cc];
+        z[u][1] = zbase[(int64_t)r1 * ldz + cc];
+        ncol = u + 1;
+      } else {
+        z[u][0] = z[u][1] = 0.0;
+      }
+    }
+    if (FWD) {
+      for (int j = 0; j < NB; ++j) {
+        const double piv = a[j * LDS_LD + j];
+        const double l0 = a[j * LDS_LD + r0], l1 = a[j * LDS_LD + r1];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (u >= ncol) break;
+          const double xj = bcast_lane(j < 64 ? z[u][0] : z[u][1], j & 63) / piv;
+          if (r0 == j) z[u][0] = xj; else if (r0 > j) z[u][0] -= l0 * xj;
+          if (r1 == j) z[u][1] = xj; else if (r1 > j) z[u][1] -= l1 * xj;
+        }
+      }
+    } else {
+      for (int j = NB - 1; j >= 0; --j) {
+        const double piv = a[j * LDS_LD + j];
+        // L(j, r) is row j, column r of the tile
+        const double l0 = a[r0 * LDS_LD + j], l1 = a[r1 * LDS_LD + j];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (u >= ncol) break;
+          const double xj = bcast_lane(j < 64 ? z[u][0] : z[u][1], j & 63) / piv;
+          if (r0 == j) z[u][0] = xj; else if (r0 < j) z[u][0] -= l0 * xj;
+          if (r1 == j) z[u][1] = xj; else if (r1 < j) z[u][1] -= l1 * xj;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int cc = cg + w + 4 * u;
+      if (u < ncol) {
+        zbase[(int64_t)r0 * ldz + cc] = z[u][0];
+        zbase[(int64_t)r1 * ldz + cc] = z[u][1];
+      }
+    }
+  }
+}
+
+// acc += sum_k A'(i,k) (scale .* B'(k,j)); scale holds the factor of the
+// lane's four columns.
+__device__ inline void mma_panel_scaled(Acc64& acc, const double* a,
+                                        int64_t lda, const double* b,
+                                        int64_t ldb, int K, v4d scale) {
+  const int l = threadIdx.x & 63;
+  const double* pa = a + (int64_t)(l >> 4) * lda + 4 * (l & 15);
+  const double* pb = b + (int64_t)(l >> 4) * ldb + 4 * (l & 15);
+  const int64_t sa = 4 * lda, sb = 4 * ldb;
+  v4d av = ld4(pa), bv = ld4(pb);
+  for (int k0 = 4; k0 < K; k0 += 4) {
+    pa += sa;
+    pb += sb;
+    v4d an = ld4(pa), bn = ld4(pb);
+    acc.mma(av, bv * scale);
+    av = an;
+    bv = bn;
+  }
+  acc.mma(av, bv * scale);
+}
+
+// Off-diagonal update for interpolated factors.  Forward step i: rows of
+// tile I > i lose sum_p Theta_p(I,i) (tau^p .* U_i); backward step i: rows
+// of tile I < i lose sum_p Theta_p(i,I)^T (tau^p .* W_i), read from the
+// row-major copy of the planes.
+template <bool FWD>
+__global__ void __launch_bounds__(256) k_update_interp(
+    int64_t d, int i, const double* theta, const double* theta_t, int64_t S,
+    int M, int q, int c, const double* tau, int64_t ldz, double* Z) {
+  const int cb = blockIdx.x;
+  const int I = FWD ? i + 1 + (int)blockIdx.y : (int)blockIdx.y;
+  const int64_t m = blockIdx.z;
+  const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
+  const int64_t dp = ntiles_of(d) * NB;
+  const LaneXY lx;
+  const int64_t col = (int64_t)cb * NB + wj * 64 + lx.col0();
+  const int64_t qc = (int64_t)q * c;
+  v4d tau4;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    tau4[e] = (col + e) < qc ? tau[(col + e) / c] : 0.0;
+
+  const double* planes = FWD ? theta + m * M * S + tile_off(I, i)
+                             : theta_t + m * M * S + tile_off(i, I);
+  const double* bsrc = Z + (m * dp + (int64_t)i * NB) * ldz + cb * NB + wj * 64;
+  Acc64 acc;
+  acc.zero();
+  v4d scale = {1.0, 1.0, 1.0, 1.0};
+  for (int p = 0; p < M; ++p) {
+    mma_panel_scaled(acc, planes + p * S + wi * 64, NB, bsrc, ldz, NB, scale);
+    scale *= tau4;
+  }
+  double* zt = Z + (m * dp + (int64_t)I * NB) * ldz + col;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+      const int r = wi * 64 + lx.row(v, bi);
+      double* p = zt + (int64_t)r * ldz;
+      st4(p, ld4(p) - acc.row(v, bi));
+    }
+}
+
+// Off-diagonal update for exact factors, one factor per lambda t:
+// forward rows of tile I > i lose L_t(I,i) U_i, backward rows of tile I < i
+// lose L_t(i,I)^T W_i.  The tile is staged in LDS with a padded leading
+// dimension so that both orientations read without bank conflicts.
+template <bool FWD>
+__global__ void __launch_bounds__(256) k_update_factors(int64_t d, int i,
+                                                        const double* L,
+                                                        int64_t S, int nper,
+                                                        int c, int64_t ldz,
+                                                        double* Z) {
+  __shared__ double lt[NB * LDS_LD];
+  __shared__ double zs[NB * 16];
+  const int I = FWD ? i + 1 + (int)blockIdx.x : (int)blockIdx.x;
+  const int t = blockIdx.y;
+  const int64_t m = blockIdx.z;
+  const int tid = threadIdx.x;
+  const int64_t dp = ntiles_of(d) * NB;
+  const double* tile = L + (m * nper + t) * S + (FWD ? tile_off(I, i) : tile_off(i, I));
+  for (int e = tid; e < NB2; e += blockDim.x)
+    lt[(e >> 7) * LDS_LD + (e & (NB - 1))] = tile[e];
+  const double* zsrc = Z + (m * dp + (int64_t)i * NB) * ldz + (int64_t)t * c;
+  double* zdst = Z + (m * dp + (int64_t)I * NB) * ldz + (int64_t)t * c;
+  const int row = tid & (NB - 1), half = tid >> 7;
+  for (int cg = 0; cg < c; cg += 16) {
+    const int cn = (c - cg) < 16 ? (c - cg) : 16;
+    __syncthreads();
+    for (int e = tid; e < NB * 16; e += blockDim.x) {
+      const int k = e >> 4, cc = e & 15;
+      zs[e] = cc < cn ? zsrc[(int64_t)k * ldz + cg + cc] : 0.0;
+    }
+    __syncthreads();
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < NB; ++k) {
+      const double lv = FWD ? lt[k * LDS_LD + row] : lt[row * LDS_LD + k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += lv * zs[k * 16 + half + 2 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int cc = half + 2 * u;
+      if (cc < cn) zdst[(int64_t)row * ldz + cg + cc] -= acc[u];
+    }
+  }
+}
+
+static hipError_t slab_init(int64_t d, int nmat, int q, int c, int64_t ldz,
+                            const double* B, double* Z, int* flags,
+                            hipStream_t s) {
+  const int64_t dp = ntiles_of(d) * NB;
+  unsigned bx = (unsigned)((dp * ldz + 255) / 256);
+  if (bx > 4096) bx = 4096;
+  hipLaunchKernelGGL(k_slab_init, dim3(bx, (unsigned)nmat), dim3(256), 0, s,
+                     dp, q, c, ldz, B, Z, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_slab_init(int64_t d, int nmat, int q, int c, int64_t ldz,
+                            const double* B, double* Z, int* flags,
+                            hipStream_t s) {
+  return slab_init(d, nmat, q, c, ldz, B, Z, flags, s);
+}
+
+hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
+                               const double* theta, const double* theta_t,
+                               int q, const double* tau_dev, int64_t ldz,
+                               double* Z, int* flags, hipStream_t s) {
+  const int nt = (int)ntiles_of(d);
+  const int64_t S = packed_elems_of(d);
+  const unsigned ncb = (unsigned)(ldz / NB);
+  FactorSrc src{theta, S, M, 0, q, tau_dev};
+  for (int i = 0; i < nt; ++i) {
+    hipLaunchKernelGGL(k_diag_solve<true>, dim3((unsigned)q, (unsigned)nmat),
+                       dim3(256), 0, s, d, i, src, c, ldz, Z, flags);
+    if (i + 1 < nt)
+      hipLaunchKernelGGL(k_update_interp<true>,
+                         dim3(ncb, (unsigned)(nt - i - 1), (unsigned)nmat),
+                         dim3(256), 0, s, d, i, theta, theta_t, S, M, q, c,
+                         tau_dev, ldz, Z);
+  }
+  for (int i = nt - 1; i >= 0; --i) {
+    hipLaunchKernelGGL(k_diag_solve<false>, dim3((unsigned)q, (unsigned)nmat),
+                       dim3(256), 0, s, d, i, src, c, ldz, Z, flags);
+    if (i > 0)
+      hipLaunchKernelGGL(k_update_interp<false>,
+                         dim3(ncb, (unsigned)i, (unsigned)nmat), dim3(256), 0,
+                         s, d, i, theta, theta_t, S, M, q, c, tau_dev, ldz, Z);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_factors(int64_t d, int nmat, int nper, int c,
+                                const double* L, int64_t ldz, double* Z,
+                                int* flags, hipStream_t s) {
+  const int nt = (int)ntiles_of(d);
+  const int64_t S = packed_elems_of(d);
+  FactorSrc src{L, S, 1, 1, nper, nullptr};
+  for (int i = 0; i < nt; ++i) {
+    hipLaunchKernelGGL(k_diag_solve<true>, dim3((unsigned)nper, (unsigned)nmat),
+                       dim3(256), 0, s, d, i, src, c, ldz, Z, flags);
+    if (i + 1 < nt)
+      hipLaunchKernelGGL(k_update_factors<true>,
+                         dim3((unsigned)(nt - i - 1), (unsigned)nper, (unsigned)nmat),
+                         dim3(256), 0, s, d, i, L, S, nper, c, ldz, Z);
+  }
+  for (int i = nt - 1; i >= 0; --i) {
+    hipLaunchKernelGGL(k_diag_solve<false>, dim3((unsigned)nper, (unsigned)nmat),
+                       dim3(256), 0, s, d, i, src, c, ldz, Z, flags);
+    if (i > 0)
+      hipLaunchKernelGGL(k_update_factors<false>,
+                         dim3((unsigned)i, (unsigned)nper, (unsigned)nmat),
+                         dim3(256), 0, s, d, i, L, S, nper, c, ldz, Z);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pichol

@@ -1,0 +1,80 @@
+// Host-side launchers of the gfx950 kernels.  Each launcher enqueues its
+// kernels on `stream` and returns the HIP launch status; shapes are
+// validated by the C-ABI layer before any launcher runs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pichol {
+
+hipError_t record_hip_error_code(hipError_t e);
+inline int record_hip_error(hipError_t e) {
+  record_hip_error_code(e);
+  return -3;  // PICHOL_ERR_HIP
+}
+
+// ---- layout (k_layout.hip)
+hipError_t launch_store_doubles(const double* host, int n, double* dev,
+                                hipStream_t s);
+hipError_t launch_pack(int64_t d, int nmat, const double* A, int64_t lda,
+                       double* P, hipStream_t s);
+hipError_t launch_unpack(int64_t d, int nmat, const double* P, double* A,
+                         int64_t lda, hipStream_t s);
+hipError_t launch_slab_to_weights(int64_t d, int nmat, int q, int c,
+                                  int64_t ldz, const double* Z, double* W,
+                                  hipStream_t s);
+
+// ---- Gram (k_gram.hip)
+struct FoldSplit {
+  int k;
+  int64_t start[65];  // start[f] .. start[f+1] rows of fold f (k <= 64)
+  double scale[64];   // 1/n_tr or 1
+};
+hipError_t launch_gram(const double* X, int64_t ldx, const double* Y,
+                       int64_t ldy, int64_t d, int64_t c,
+                       const FoldSplit& fs, double* G, double* C, double* yy,
+                       double* H, double* B, hipStream_t s);
+
+// ---- POTRF (k_potrf.hip)
+hipError_t launch_shift_copy(int64_t d, int nmat, const double* H, int nshift,
+                             const double* lam_dev, double* L, int* info,
+                             hipStream_t s);
+hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
+                                double* linv_ws, hipStream_t s);
+
+// ---- fit / evaluate (k_fit.hip)
+struct FitCoef {
+  int g, m;          // samples, planes (r+1)
+  double P[8][32];   // pseudo-inverse of V: m x g
+};
+hipError_t launch_fit(int64_t d, int nmat, const FitCoef& fc, const double* L,
+                      double* theta, double* theta_t, hipStream_t s);
+hipError_t launch_eval(int64_t d, int nmat, int m, const double* theta,
+                       int nlam, const double* tau_dev, double* Lhat,
+                       hipStream_t s);
+
+// ---- triangular solves (k_trsm.hip)
+hipError_t launch_slab_init(int64_t d, int nmat, int q, int c, int64_t ldz,
+                            const double* B, double* Z, int* flags,
+                            hipStream_t s);
+hipError_t launch_solve_interp(int64_t d, int nmat, int c, int m,
+                               const double* theta, const double* theta_t,
+                               int q, const double* tau_dev, int64_t ldz,
+                               double* Z, int* flags, hipStream_t s);
+hipError_t launch_solve_factors(int64_t d, int nmat, int nper, int c,
+                                const double* L, int64_t ldz, double* Z,
+                                int* flags, hipStream_t s);
+
+// ---- hold-out (k_holdout.hip)
+struct HoldoutNorm {
+  int nmat;
+  double count[64];  // n_v * c per fold
+};
+hipError_t launch_holdout(int64_t d, int nmat, int c, int q, int64_t ldz,
+                          const double* Z, const double* G, const double* C,
+                          const double* yy, const HoldoutNorm& hn,
+                          double* partial, double* err, int* flags,
+                          hipStream_t s);
+
+}  // namespace pichol

@@ -1,0 +1,103 @@
+"""Helpers for the GPU tests: run library entry points through the C-ABI
+binding with torch-allocated device buffers, and convert the tile-packed
+layout to dense arrays on the host for comparison with the oracle."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from paper_1404_0466_amd import binding as B
+
+NB = B.NB
+DEV = "cuda:0"
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(DEV, dtype=dtype)
+
+
+def empty(n, dtype=torch.float64):
+    return torch.empty(int(n), dtype=dtype, device=DEV)
+
+
+def ws(nbytes):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=DEV)
+
+
+def unpack(P, d, nmat):
+    """Packed device triangles -> (nmat, d, d) host lower triangles."""
+    A = empty(nmat * d * d)
+    B.pichol_unpack(d, nmat, P, A, d)
+    torch.cuda.synchronize()
+    return A.cpu().numpy().reshape(nmat, d, d)
+
+
+def pack(A, d):
+    """(nmat, d, d) host symmetric/lower matrices -> packed device."""
+    A = np.ascontiguousarray(A, dtype=np.float64).reshape(-1, d, d)
+    nmat = A.shape[0]
+    P = empty(nmat * B.pichol_packed_elems(d))
+    B.pichol_pack(d, nmat, dev(A.reshape(-1)), d, P)
+    return P
+
+
+def slab_to_w(Z, d, nmat, q, c):
+    W = empty(nmat * q * d * c)
+    B.pichol_slab_to_weights(d, nmat, q, c, Z, W)
+    torch.cuda.synchronize()
+    return W.cpu().numpy().reshape(nmat, q, d, c)
+
+
+def fold_sizes(n, k):
+    return np.array([len(a) for a in np.array_split(np.arange(n), k)], dtype=np.int64)
+
+
+def gram(X, Y, k, normalize=True):
+    n, d = X.shape
+    c = Y.shape[1]
+    p = B.make_problem(n, d, c, k, normalize=normalize)
+    dp = B.pichol_padded_order(d)
+    S = B.pichol_packed_elems(d)
+    out = {
+        "G": empty(k * dp * dp), "C": empty(k * dp * c), "yy": empty(k),
+        "H": empty(k * S), "B": empty(k * dp * c),
+    }
+    B.pichol_gram(p, dev(X), dev(Y), out["G"], out["C"], out["yy"], out["H"],
+                  out["B"])
+    return out
+
+
+def cv(prob, method, X=None, Y=None, lam_s=None, lam_grid=None, r=None,
+       want_W=True, normalize=True, k=None):
+    """Run the pipeline (gram + interp or exact) on the GPU."""
+    X = prob.X if X is None else X
+    Y = prob.Y if Y is None else Y
+    lam_s = prob.lam_s if lam_s is None else np.asarray(lam_s)
+    lam_grid = prob.lam_grid if lam_grid is None else np.asarray(lam_grid)
+    r = prob.r if r is None else r
+    k = prob.k if k is None else k
+    n, d = X.shape
+    c = Y.shape[1]
+    g, q = len(lam_s), len(lam_grid)
+    p = B.make_problem(n, d, c, k, g, r, q, normalize)
+    m = B.PICHOL_METHOD_INTERP if method == "interp" else B.PICHOL_METHOD_EXACT
+    nbytes = B.pichol_workspace_size(p, m)
+    w = ws(nbytes)
+    err = empty(k * q)
+    W = empty(k * q * d * c) if want_W else None
+    flags = empty(k * q, torch.int32)
+    Xd, Yd = dev(X), dev(Y)
+    if method == "interp":
+        info = empty(k * g, torch.int32)
+        B.pichol_cv(p, Xd, Yd, lam_s, lam_grid, float(np.max(lam_s)), w, nbytes,
+                    err, W, info, flags)
+    else:
+        info = empty(k * q, torch.int32)
+        B.pichol_exact_cv(p, Xd, Yd, lam_grid, w, nbytes, err, W, info, flags)
+    torch.cuda.synchronize()
+    return {
+        "mse": err.cpu().numpy().reshape(k, q),
+        "W": W.cpu().numpy().reshape(k, q, d, c) if want_W else None,
+        "info": info.cpu().numpy().reshape(k, -1),
+        "flags": flags.cpu().numpy().reshape(k, q),
+    }

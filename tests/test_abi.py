@@ -1,0 +1,85 @@
+"""The C-ABI library loads on a machine without a GPU and exports every
+function include/pichol.h declares; host-only entry points (sizes, layout
+arithmetic, argument validation) behave as documented.  No compute call is
+made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1404_0466_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pichol.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(pichol_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("libpichol.so is not built (python -m paper_1404_0466_amd.build)")
+    return B.load()
+
+
+def test_header_declares_the_expected_calls():
+    names = declared_functions()
+    for must in ["pichol_cv", "pichol_exact_cv", "pichol_potrf_shifted_batched",
+                 "pichol_fit", "pichol_eval", "pichol_solve_interp",
+                 "pichol_solve_factors", "pichol_holdout", "pichol_gram"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    raw = ctypes.CDLL(B.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(raw, name), name
+
+
+def test_binding_covers_the_header():
+    assert sorted(B.EXPORTED) == declared_functions()
+
+
+def test_layout_arithmetic(lib):
+    assert B.pichol_packed_elems(0) == 0
+    assert B.pichol_packed_elems(1) == 128 * 128
+    assert B.pichol_packed_elems(128) == 128 * 128
+    assert B.pichol_packed_elems(129) == 3 * 128 * 128
+    assert B.pichol_packed_elems(4096) == 32 * 33 // 2 * 128 * 128
+    assert B.pichol_padded_order(300) == 384
+    assert B.pichol_slab_cols(64, 10) == 640
+    assert B.pichol_slab_cols(31, 10) == 384
+    assert B.pichol_slab_cols(1, 1) == 128
+
+
+def test_workspace_size_and_argument_checks(lib):
+    p = B.make_problem(60000, 4096, 10, 5, g=6, r=2, q=64)
+    wi = B.pichol_workspace_size(p, B.PICHOL_METHOD_INTERP)
+    we = B.pichol_workspace_size(p, B.PICHOL_METHOD_EXACT)
+    both = B.pichol_workspace_size(p, B.PICHOL_METHOD_INTERP | B.PICHOL_METHOD_EXACT)
+    assert both == max(wi, we)
+    S = B.pichol_packed_elems(4096)
+    assert wi > 5 * 6 * S * 8 and we > 5 * 64 * S * 8
+    for bad in [dict(r=6, g=6), dict(k=1), dict(k=65), dict(g=33), dict(r=8, g=9),
+                dict(q=0)]:
+        kw = dict(g=6, r=2, q=64, k=5)
+        kw.update(bad)
+        k = kw.pop("k")
+        p = B.make_problem(60000, 4096, 10, k, **kw)
+        with pytest.raises(B.PicholError) as e:
+            B.pichol_workspace_size(p, B.PICHOL_METHOD_INTERP)
+        assert e.value.status == B.PICHOL_ERR_ARG
+    p = B.make_problem(100, 10, 2, 5, g=3, r=2, q=4, ldx=9)  # ldx < d
+    with pytest.raises(B.PicholError):
+        B.pichol_workspace_size(p, B.PICHOL_METHOD_EXACT)
+
+
+def test_status_strings(lib):
+    for s in [0, -1, -2, -3, -4, -5]:
+        assert lib.pichol_status_string(s)

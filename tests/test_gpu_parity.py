@@ -1,0 +1,358 @@
+"""Parity of the HIP path with the CPU oracle, element by element, on
+seeded inputs.  Every call goes through the C-ABI (``binding``).
+
+Tolerances.  Both sides compute in IEEE FP64 but accumulate in different
+orders (blocked MFMA sums on the GPU, left-to-right loops in the oracle).
+For a Cholesky factor of a matrix with condition number kappa the entrywise
+difference of two backward-stable FP64 factorizations is bounded by a
+modest multiple of kappa * d * eps * |L|; the inputs below have kappa <= 1e4
+and d <= 400, which puts the bound near 1e-9 |L| in the worst case and
+observed differences far below.  The pipeline's hold-out errors are held to
+the 1e-10 relative bar the method's FP64 path is specified at.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def gu(gpu):
+    import gpu_util
+    return gpu_util
+
+
+def spd(d, seed, cond=1e3):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    ev = np.logspace(0, -np.log10(cond), d)
+    return (Q * ev) @ Q.T
+
+
+def close(a, b, rel, name=""):
+    scale = max(np.max(np.abs(b)), 1e-300)
+    diff = np.max(np.abs(a - b)) if a.size else 0.0
+    assert np.all(np.isfinite(a)) == np.all(np.isfinite(b)), name
+    assert diff <= rel * scale, f"{name}: max diff {diff:.3e} > {rel:.1e} * {scale:.3e}"
+
+
+# ------------------------------------------------------------------ layout
+
+@pytest.mark.parametrize("d", [1, 7, 127, 128, 129, 300])
+def test_pack_unpack_roundtrip(gu, d):
+    rng = np.random.default_rng(d)
+    A = rng.standard_normal((2, d, d))
+    P = gu.pack(A, d)
+    L = gu.unpack(P, d, 2)
+    np.testing.assert_array_equal(L, np.tril(A))
+
+
+# ------------------------------------------------------------------ Gram
+
+@pytest.mark.parametrize("n,d,c,k", [(53, 7, 3, 5), (1003, 300, 4, 5), (640, 128, 10, 4),
+                                     (97, 129, 1, 3)])
+def test_gram_matches_oracle(gu, n, d, c, k):
+    rng = np.random.default_rng(n + d)
+    X = rng.standard_normal((n, d))
+    Y = np.sign(rng.standard_normal((n, c)))
+    out = gu.gram(X, Y, k)
+    torch.cuda.synchronize()
+    H = gu.unpack(out["H"], d, k)
+    dp = gu.B.pichol_padded_order(d)
+    Bf = out["B"].cpu().numpy().reshape(k, dp, c)
+    sizes = gu.fold_sizes(n, k)
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    G = out["G"].cpu().numpy().reshape(k, dp // 128, dp // 128, 128, 128)
+    C = out["C"].cpu().numpy().reshape(k, dp, c)
+    yy = out["yy"].cpu().numpy()
+    for f in range(k):
+        Ho, Bo, _ = oracle.fold_gram(X, Y, k, f)
+        close(H[f], np.tril(Ho), 1e-13, "H")
+        close(Bf[f, :d], Bo, 1e-13, "B")
+        assert np.all(Bf[f, d:] == 0.0)
+        # validation-block Grams: X_b^T X_b as full tiles, column-major
+        Xb, Yb = X[starts[f]:starts[f + 1]], Y[starts[f]:starts[f + 1]]
+        Gd = G[f].transpose(0, 3, 1, 2).reshape(dp, dp)  # tile (I,J) elem (r,c) at [c][r]
+        close(Gd[:d, :d], Xb.T @ Xb, 1e-13, "G")
+        assert np.all(Gd[d:, :] == 0.0) and np.all(Gd[:, d:] == 0.0)
+        close(C[f, :d], Xb.T @ Yb, 1e-13, "C")
+        np.testing.assert_allclose(yy[f], np.sum(Yb * Yb), rtol=1e-13)
+
+
+# ------------------------------------------------------------------ factorization
+
+@pytest.mark.parametrize("d", [1, 5, 127, 128, 129, 257, 384])
+def test_potrf_matches_oracle(gu, d):
+    nmat, lam = 2, np.array([1e-3, 0.05, 1.0])
+    H = np.stack([spd(d, 10 * d + m, cond=1e3) for m in range(nmat)])
+    Hp = gu.pack(H, d)
+    S = gu.B.pichol_packed_elems(d)
+    L = gu.empty(nmat * len(lam) * S)
+    info = gu.empty(nmat * len(lam), torch.int32)
+    nb = gu.B.pichol_potrf_workspace(nmat, len(lam))
+    w = gu.ws(nb)
+    gu.B.pichol_potrf_shifted_batched(d, nmat, Hp, len(lam), lam, L, info, w, nb)
+    Lg = gu.unpack(L, d, nmat * len(lam))
+    assert np.all(info.cpu().numpy() == 0)
+    for m in range(nmat):
+        for s, l in enumerate(lam):
+            Lo, io = oracle.cholesky(H[m], l)
+            assert io == 0
+            close(Lg[m * len(lam) + s], Lo, 1e-11, f"L d={d} m={m} s={s}")
+
+
+def test_potrf_padding_and_upper_zero(gu):
+    d = 200
+    H = spd(d, 3)
+    S = gu.B.pichol_packed_elems(d)
+    L = gu.empty(S)
+    info = gu.empty(1, torch.int32)
+    nb = gu.B.pichol_potrf_workspace(1, 1)
+    gu.B.pichol_potrf_shifted_batched(d, 1, gu.pack(H[None], d), 1, [0.1], L, info,
+                                      gu.ws(nb), nb)
+    torch.cuda.synchronize()
+    P = L.cpu().numpy().reshape(-1, 128, 128)  # tiles (0,0), (1,0), (1,1)
+    t11 = P[2].T  # column-major storage -> [row][col]
+    assert np.all(np.triu(P[0].T, 1) == 0.0) and np.all(np.triu(t11, 1) == 0.0)
+    pad = d - 128
+    np.testing.assert_array_equal(t11[pad:, pad:], np.eye(128 - pad))
+    assert np.all(t11[pad:, :pad] == 0.0)
+    assert np.all(P[1].T[pad:, :] == 0.0)
+
+
+@pytest.mark.parametrize("col", [0, 130, 199])
+def test_potrf_reports_first_failing_pivot(gu, col):
+    d = 200
+    h = np.linspace(1.0, 2.0, d)
+    h[col] = -1.0
+    H = np.diag(h)
+    H[col, 0 if col else 1] = H[0 if col else 1, col] = 0.01
+    S = gu.B.pichol_packed_elems(d)
+    L = gu.empty(2 * S)
+    info = gu.empty(2, torch.int32)
+    nb = gu.B.pichol_potrf_workspace(1, 2)
+    lam = [0.5, 2.0]
+    gu.B.pichol_potrf_shifted_batched(d, 1, gu.pack(H[None], d), 2, lam, L, info,
+                                      gu.ws(nb), nb)
+    got = info.cpu().numpy()
+    want = [oracle.cholesky(H, l)[1] for l in lam]
+    assert want[0] == col + 1 and want[1] == 0
+    np.testing.assert_array_equal(got, want)
+    assert gu.B.pichol_check(info, 2, None, 0) == gu.B.PICHOL_ERR_NOT_PD
+
+
+# ------------------------------------------------------------------ fit / evaluate
+
+@pytest.mark.parametrize("d,g,r", [(129, 4, 2), (300, 6, 2), (64, 3, 2), (150, 5, 4)])
+def test_fit_and_eval_match_oracle(gu, d, g, r):
+    H = spd(d, d + g, cond=1e2)
+    lam_s = np.logspace(-3, 0, g)
+    lam_ref = lam_s.max()
+    S = gu.B.pichol_packed_elems(d)
+    L = gu.empty(g * S)
+    info = gu.empty(g, torch.int32)
+    nb = gu.B.pichol_potrf_workspace(1, g)
+    gu.B.pichol_potrf_shifted_batched(d, 1, gu.pack(H[None], d), g, lam_s, L, info,
+                                      gu.ws(nb), nb)
+    th = gu.empty((r + 1) * S)
+    tht = gu.empty((r + 1) * S)
+    gu.B.pichol_fit(d, 1, g, r, lam_s, lam_ref, L, th, tht)
+    lam_t = np.array([2e-3, 0.02, 0.3, 0.9])
+    Lh = gu.empty(len(lam_t) * S)
+    nb = gu.B.pichol_lambda_workspace(len(lam_t))
+    gu.B.pichol_eval(d, 1, r, th, len(lam_t), lam_t, lam_ref, Lh, gu.ws(nb), nb)
+    Thg = gu.unpack(th, d, r + 1)
+    Lhg = gu.unpack(Lh, d, len(lam_t))
+    # oracle: its own factors, Algorithm 1, evaluation
+    T = np.stack([oracle.pack_lower(oracle.cholesky(H, l)[0]) for l in lam_s])
+    Tho = oracle.fit(T, lam_s, r, lam_ref)
+    cond = np.linalg.cond(np.vander(lam_s / lam_ref, r + 1, increasing=True))
+    for j in range(r + 1):
+        close(Thg[j], oracle.unpack_lower(Tho[j], d), 1e-11 * cond ** 2, f"theta{j}")
+    for t, lam in enumerate(lam_t):
+        Lo = oracle.unpack_lower(oracle.evaluate(Tho, lam, lam_ref), d)
+        close(Lhg[t], Lo, 1e-11 * cond ** 2, f"Lhat t={t}")
+    # the row-major copy holds the same planes with every tile transposed
+    a = th.cpu().numpy().reshape(-1, 128, 128)
+    b = tht.cpu().numpy().reshape(-1, 128, 128)
+    np.testing.assert_array_equal(a, b.transpose(0, 2, 1))
+
+
+# ------------------------------------------------------------------ solves
+
+def _factors(gu, H, lam, d):
+    nm = len(lam)
+    S = gu.B.pichol_packed_elems(d)
+    L = gu.empty(nm * S)
+    info = gu.empty(nm, torch.int32)
+    nb = gu.B.pichol_potrf_workspace(1, nm)
+    gu.B.pichol_potrf_shifted_batched(d, 1, gu.pack(H[None], d), nm, lam, L, info,
+                                      gu.ws(nb), nb)
+    return L
+
+
+@pytest.mark.parametrize("d,c,q", [(1, 1, 2), (100, 3, 5), (128, 10, 13), (300, 10, 31),
+                                   (257, 17, 3)])
+def test_solve_factors_matches_oracle(gu, d, c, q):
+    rng = np.random.default_rng(d + c)
+    H = spd(d, d, cond=1e3)
+    lam = np.logspace(-3, 0, q)
+    L = _factors(gu, H, lam, d)
+    dp = gu.B.pichol_padded_order(d)
+    Bh = np.zeros((dp, c))
+    Bh[:d] = rng.standard_normal((d, c))
+    ldz = gu.B.pichol_slab_cols(q, c)
+    Z = gu.empty(dp * ldz)
+    flags = gu.empty(q, torch.int32)
+    gu.B.pichol_solve_factors(d, 1, q, c, L, gu.dev(Bh), Z, flags)
+    Wg = gu.slab_to_w(Z, d, 1, q, c)[0]
+    assert np.all(flags.cpu().numpy() == 0)
+    Zh = Z.cpu().numpy().reshape(dp, ldz)
+    assert np.all(Zh[d:] == 0.0) and np.all(Zh[:, q * c:] == 0.0)
+    for t in range(q):
+        Lo, _ = oracle.cholesky(H, lam[t])
+        Wo, fo = oracle.solve(Lo, Bh[:d])
+        assert fo == 0
+        close(Wg[t], Wo, 1e-10, f"W t={t}")
+
+
+@pytest.mark.parametrize("d,c,g,r,q", [(1, 2, 3, 2, 4), (129, 3, 4, 2, 7), (300, 10, 6, 2, 31),
+                                       (256, 10, 4, 2, 64), (140, 5, 5, 4, 9)])
+def test_solve_interp_matches_oracle(gu, d, c, g, r, q):
+    rng = np.random.default_rng(d * q)
+    H = spd(d, d + 1, cond=1e2)
+    lam_s = np.logspace(-3, 0, g)
+    lam_ref = lam_s.max()
+    lam = np.logspace(-3, 0, q)
+    L = _factors(gu, H, lam_s, d)
+    S = gu.B.pichol_packed_elems(d)
+    th = gu.empty((r + 1) * S)
+    tht = gu.empty((r + 1) * S)
+    gu.B.pichol_fit(d, 1, g, r, lam_s, lam_ref, L, th, tht)
+    dp = gu.B.pichol_padded_order(d)
+    Bh = np.zeros((dp, c))
+    Bh[:d] = rng.standard_normal((d, c))
+    ldz = gu.B.pichol_slab_cols(q, c)
+    Z = gu.empty(dp * ldz)
+    flags = gu.empty(q, torch.int32)
+    nb = gu.B.pichol_lambda_workspace(q)
+    gu.B.pichol_solve_interp(d, 1, c, r, th, tht, gu.dev(Bh), q, lam, lam_ref, Z,
+                             flags, gu.ws(nb), nb)
+    Wg = gu.slab_to_w(Z, d, 1, q, c)[0]
+    T = np.stack([oracle.pack_lower(oracle.cholesky(H, l)[0]) for l in lam_s])
+    Tho = oracle.fit(T, lam_s, r, lam_ref)
+    fl = flags.cpu().numpy()
+    for t in range(q):
+        Lo = oracle.unpack_lower(oracle.evaluate(Tho, lam[t], lam_ref), d)
+        Wo, fo = oracle.solve(Lo, Bh[:d])
+        assert fl[t] == fo
+        close(Wg[t], Wo, 1e-9, f"W t={t}")
+
+
+# ------------------------------------------------------------------ pipelines
+
+def _check_cv(got, want, rel_err=1e-10, rel_w=1e-9):
+    np.testing.assert_array_equal(got["info"], want["info"])
+    np.testing.assert_array_equal(got["flags"], want["flags"])
+    np.testing.assert_allclose(got["mse"], want["mse"], rtol=rel_err, atol=0)
+    if want.get("W") is not None:
+        close(got["W"], want["W"], rel_w, "W")
+
+
+def test_cv_interp_config1(gu):
+    p = workloads.config(1)
+    got = gu.cv(p, "interp")
+    want = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r, want_W=True)
+    _check_cv(got, want)
+
+
+def test_cv_exact_config1(gu):
+    p = workloads.config(1)
+    got = gu.cv(p, "exact")
+    want = oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid, want_W=True)
+    _check_cv(got, want)
+
+
+@pytest.mark.parametrize("method", ["interp", "exact"])
+def test_cv_ragged(gu, method):
+    """Ragged everywhere: n not divisible by k, d not a multiple of the tile,
+    q*c not a multiple of 128, c > 16 on the exact path."""
+    p = workloads.gaussian_problem(1003, 300, 3, seed=11, g=5, q=13)
+    if method == "interp":
+        got = gu.cv(p, "interp")
+        want = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r, want_W=True)
+    else:
+        p = workloads.gaussian_problem(700, 150, 18, seed=12, q=5)
+        got = gu.cv(p, "exact")
+        want = oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid, want_W=True)
+    _check_cv(got, want)
+
+
+def test_cv_rff_midsize(gu):
+    """Random-Fourier-feature workload (the structure of the benchmark's
+    data) at a size the oracle finishes in seconds: three tile rows."""
+    p = workloads.rff_problem(3000, 384, 10, seed=3, q=64)
+    got = gu.cv(p, "interp", want_W=False)
+    want = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r)
+    _check_cv(got, want)
+    gote = gu.cv(p, "exact", want_W=False)
+    wante = oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid)
+    _check_cv(gote, wante)
+
+
+def test_cv_interp_is_exact_when_samples_are_the_grid(gu):
+    p = workloads.gaussian_problem(600, 40, 3, seed=5, q=4, lam_range=(1e-2, 1.0))
+    gi = gu.cv(p, "interp", lam_s=p.lam_grid, r=3)
+    ge = gu.cv(p, "exact")
+    np.testing.assert_allclose(gi["mse"], ge["mse"], rtol=1e-9)
+
+
+def test_cv_flags_nonpositive_interpolated_pivot(gu):
+    """Far outside the samples a high-degree fit can drive a diagonal entry
+    of the interpolated factor negative: both sides flag the same (fold,
+    lambda) units."""
+    p = workloads.gaussian_problem(400, 30, 2, seed=4, g=4, q=6, lam_range=(1e-2, 1.0))
+    lam_s = np.array([0.5, 0.6, 0.7, 0.8]) * p.scale
+    lam_grid = np.array([1e-3, 0.1, 0.55, 0.75, 5.0, 50.0]) * p.scale
+    got = gu.cv(p, "interp", lam_s=lam_s, lam_grid=lam_grid, r=3)
+    want = oracle.cv_interp(p.X, p.Y, p.k, lam_s, lam_grid, 3, want_W=True)
+    assert np.any(want["flags"] & 2)
+    np.testing.assert_array_equal(got["flags"] & 2, want["flags"] & 2)
+    ok = want["flags"] == 0
+    np.testing.assert_allclose(got["mse"][ok], want["mse"][ok], rtol=1e-8)
+
+
+def test_cv_is_deterministic(gu):
+    p = workloads.gaussian_problem(900, 200, 10, seed=8, g=4, q=16)
+    a = gu.cv(p, "interp")
+    b = gu.cv(p, "interp")
+    np.testing.assert_array_equal(a["mse"], b["mse"])
+    np.testing.assert_array_equal(a["W"], b["W"])
+
+
+def test_argument_errors(gu):
+    B = gu.B
+    p = B.make_problem(100, 10, 2, 5, g=3, r=3, q=4)  # r >= g
+    with pytest.raises(B.PicholError) as e:
+        B.pichol_workspace_size(p, B.PICHOL_METHOD_INTERP)
+    assert e.value.status == B.PICHOL_ERR_ARG
+    p = B.make_problem(100, 10, 2, 5, g=3, r=2, q=4)
+    nbytes = B.pichol_workspace_size(p, B.PICHOL_METHOD_INTERP)
+    w = gu.ws(16)
+    err = gu.empty(20)
+    info = gu.empty(15, torch.int32)
+    flags = gu.empty(20, torch.int32)
+    with pytest.raises(B.PicholError) as e:
+        B.pichol_cv_interp(p, [0.1, 0.2, 0.3], [0.1] * 4, 0.3, w, 16, err, None, info, flags)
+    assert e.value.status == B.PICHOL_ERR_WORKSPACE
+    w = gu.ws(nbytes)
+    with pytest.raises(B.PicholError) as e:  # repeated sample value
+        B.pichol_cv_interp(p, [0.1, 0.1, 0.3], [0.1] * 4, 0.3, w, nbytes, err, None, info,
+                           flags)
+    assert e.value.status == B.PICHOL_ERR_ARG
