@@ -1,0 +1,258 @@
+#!/usr/bin/env python3
+"""Benchmark: interpolated (piCholesky) vs exact per-lambda Cholesky k-fold
+cross-validation on one MI355X, FP64.
+
+One step is one pass of the whole path over the benchmark workload (random
+Fourier features, n=60000, d=4096, c=10, k=5, g=6, r=2, q=64, lambda range
+[1e-6, 1] * trace(X^T X / n)/d):
+    fold Gram matrices -> piCholesky CV (g sample factorizations per fold,
+    fit, fused evaluation + solves at q values, hold-out errors)
+    -> exact CV (q factorizations per fold, solves, hold-out errors).
+The headline value is interpolated lambda-solves per second, k*q / (time of
+the piCholesky stage), with the Gram matrices resident (they are shared by
+both methods and timed separately).  A lambda-solve is one (fold, lambda)
+pair: its c-column ridge solution and its hold-out error.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("interpolated λ-solves/sec vs exact per-λ Cholesky CV "
+          "(d=4096,k=5,q=64); err gap")
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+PEAK_HBM_GBS = 8000.0
+NB = 128
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def update_flops(d: int, nfac: int) -> list[float]:
+    """Algorithmic flops of each trailing-update launch of a blocked
+    factorization of nfac matrices of order d: the rank-128 update of the
+    m x m trailing lower triangle costs 128 * m * (m + 1) flops."""
+    nt = (d + NB - 1) // NB
+    out = []
+    for kk in range(nt - 1):
+        m = max(0, d - (kk + 1) * NB)
+        out.append(float(nfac) * NB * m * (m + 1))
+    return out
+
+
+def gaps(cp, ce, lam):
+    tp = int(np.argmin(np.where(np.isfinite(cp), cp, np.inf)))
+    te = int(np.argmin(np.where(np.isfinite(ce), ce, np.inf)))
+    return {
+        "curve_gap_max_rel": float(np.max(np.abs(cp - ce) / np.abs(ce))),
+        "min_err_interp": float(cp.min()), "min_err_exact": float(ce.min()),
+        "min_gap_rel": float((cp.min() - ce.min()) / ce.min()),
+        "regret": float(ce[tp] - ce.min()),
+        "sel_lambda_interp": float(lam[tp]), "sel_lambda_exact": float(lam[te]),
+        "sel_err_log10": float(abs(np.log10(lam[tp] / lam[te]))),
+    }
+
+
+def cpu_baseline(prob, gpu_err_fold0):
+    """The oracle on a bounded sample: fold 0 of the workload from its Gram
+    matrices (formed with numpy outside the timed region), i.e. the g sample
+    factorizations, the fit, and q evaluations + solves + hold-out errors."""
+    import oracle
+    nv = len(np.array_split(np.arange(prob.n), prob.k)[0])
+    Xv, Yv = prob.X[:nv], prob.Y[:nv]
+    Xt, Yt = prob.X[nv:], prob.Y[nv:]
+    log("cpu baseline: forming fold-0 Gram matrices with numpy (untimed)")
+    H = Xt.T @ Xt / Xt.shape[0]
+    Bm = Xt.T @ Yt / Xt.shape[0]
+    oracle.build()
+    log(f"cpu baseline: oracle fold 0 on {oracle.num_threads()} threads")
+    t0 = time.perf_counter()
+    out = oracle.fold_interp(H, Bm, Xv, Yv, prob.lam_s, prob.lam_grid, prob.r)
+    dt = time.perf_counter() - t0
+    rel = np.abs(np.asarray(gpu_err_fold0) - out["mse"]) / np.abs(out["mse"])
+    log(f"cpu baseline: {dt:.1f} s, max rel diff vs GPU fold-0 errors {rel.max():.2e}")
+    return {
+        "value": prob.q / dt, "unit": "λ-solves/s",
+        "cores": oracle.num_threads(), "kind": "oracle",
+        "sample": (f"fold 0 of {prob.k} at n={prob.n}, d={prob.d}, c={prob.c}: "
+                   f"g={prob.g} sample factorizations, fit, q={prob.q} "
+                   "evaluations + solves + hold-out errors, from numpy-formed "
+                   "Gram matrices"),
+        "seconds": dt,
+        "fold0_err_max_rel_diff_vs_gpu": float(rel.max()),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=3,
+                    help="workload: 1 (d=256), 2 (d=2048), 3 (d=4096, default)")
+    ap.add_argument("--no-exact", action="store_true",
+                    help="skip the exact baseline stage")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip the per-kernel event pass (no roofline)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    from paper_1404_0466_amd import binding as B
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    B.load()
+    dev = torch.device("cuda:0")
+
+    log(f"generating workload {args.config}")
+    t0 = time.perf_counter()
+    prob = workloads.config(args.config)
+    log(f"workload {prob.name}: n={prob.n} d={prob.d} c={prob.c} k={prob.k} "
+        f"g={prob.g} r={prob.r} q={prob.q} ({time.perf_counter() - t0:.1f} s)")
+    n, d, c, k, g, r, q = prob.n, prob.d, prob.c, prob.k, prob.g, prob.r, prob.q
+
+    X = torch.from_numpy(prob.X).to(dev)
+    Y = torch.from_numpy(prob.Y).to(dev)
+    p = B.make_problem(n, d, c, k, g, r, q, True)
+    methods = B.PICHOL_METHOD_INTERP | (0 if args.no_exact else B.PICHOL_METHOD_EXACT)
+    nbytes = B.pichol_workspace_size(p, methods)
+    log(f"workspace {nbytes / 2**30:.2f} GiB")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    err_i = torch.empty(k * q, dtype=torch.float64, device=dev)
+    err_e = torch.empty(k * q, dtype=torch.float64, device=dev)
+    info_i = torch.empty(k * g, dtype=torch.int32, device=dev)
+    info_e = torch.empty(k * q, dtype=torch.int32, device=dev)
+    flags_i = torch.empty(k * q, dtype=torch.int32, device=dev)
+    flags_e = torch.empty(k * q, dtype=torch.int32, device=dev)
+    lam_s, lam_grid, lam_ref = prob.lam_s, prob.lam_grid, prob.lam_ref
+    stream = torch.cuda.current_stream()
+
+    def step(ev):
+        ev[0].record(stream)
+        B.pichol_cv_gram(p, X, Y, ws, nbytes)
+        ev[1].record(stream)
+        B.pichol_cv_interp(p, lam_s, lam_grid, lam_ref, ws, nbytes, err_i, None,
+                           info_i, flags_i)
+        ev[2].record(stream)
+        if not args.no_exact:
+            B.pichol_cv_exact(p, lam_grid, ws, nbytes, err_e, None, info_e, flags_e)
+        ev[3].record(stream)
+
+    def new_events():
+        return [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    log(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        step(new_events())
+    torch.cuda.synchronize()
+
+    log(f"timing {args.steps} steps")
+    evs = [new_events() for _ in range(args.steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for i in range(args.steps):
+        step(evs[i])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    t_gram = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    t_int = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    t_ex = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    ms_per_step = total_ms / args.steps
+    value = k * q / (t_int * 1e-3)
+    log(f"step {ms_per_step:.2f} ms: gram {t_gram:.2f} ms, interp {t_int:.2f} ms, "
+        f"exact {t_ex:.2f} ms -> {value:.1f} interpolated lambda-solves/s")
+
+    ei = err_i.cpu().numpy().reshape(k, q)
+    ok_i = bool((info_i.cpu().numpy() == 0).all() and (flags_i.cpu().numpy() == 0).all())
+    result_extra = {
+        "interp_ms": t_int, "gram_ms": t_gram,
+        "value_with_gram": k * q / ((t_int + t_gram) * 1e-3),
+        "interp_ok": ok_i,
+    }
+    if not args.no_exact:
+        ee = err_e.cpu().numpy().reshape(k, q)
+        ok_e = bool((info_e.cpu().numpy() == 0).all() and (flags_e.cpu().numpy() == 0).all())
+        result_extra.update({
+            "exact_ms": t_ex, "exact_value": k * q / (t_ex * 1e-3),
+            "speedup_vs_exact": t_ex / t_int, "exact_ok": ok_e,
+            "err_gap": gaps(ei.mean(0), ee.mean(0), lam_grid),
+        })
+
+    roofline = None
+    kernels = None
+    if not args.no_profile:
+        log("per-kernel event pass")
+        B.pichol_profile_start(4000 * max(1, args.steps))
+        for i in range(args.steps):
+            step(new_events())
+        torch.cuda.synchronize()
+        B.pichol_profile_stop()
+        summ = B.pichol_profile_summary()
+        B.pichol_profile_reset()
+        kernels = {name: {"launches": nl, "avg_ms": tot / nl, "total_ms_per_step": tot / args.steps}
+                   for name, (nl, tot) in sorted(summ.items(), key=lambda kv: -kv[1][1])}
+        upd = summ.get("k_potrf_update")
+        if upd:
+            flops = update_flops(d, k * g)
+            if not args.no_exact:
+                flops += update_flops(d, k * q)
+            per_step_launches = len(flops)
+            nl, tot = upd
+            assert nl == per_step_launches * args.steps, (nl, per_step_launches)
+            avg_flops = sum(flops) / per_step_launches
+            avg_ms = tot / nl
+            achieved = avg_flops / (avg_ms * 1e-3) / 1e12
+            roofline = {
+                "kernel": "k_potrf_update", "bound": "mfma",
+                "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "flops_per_launch": avg_flops, "avg_launch_ms": avg_ms,
+            }
+            log(f"k_potrf_update: {achieved:.2f} TFLOP/s "
+                f"({100 * achieved / PEAK_FP64_TFLOPS:.1f}% of FP64 peak)")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(prob, ei[0])
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "λ-solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": prob.name, "n": n, "d": d, "c": c, "k": k, "g": g,
+                   "r": r, "q": q, "lam_range": list(prob.meta.get("lam_range", [])),
+                   "kind": prob.meta.get("kind")},
+        **result_extra,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -298,6 +298,30 @@ const char *pichol_status_string(pichol_status s);
 /* Text of the last HIP error the library saw on this thread ("" if none). */
 const char *pichol_last_error(void);
 
+/* ------------------------------------------------------------- profiling */
+
+/* Per-kernel timing with HIP events, for benchmarks and tuning.  While
+ * enabled, every kernel launch the library makes is bracketed by two HIP
+ * events recorded on the launch stream; the first `capacity` launches are
+ * recorded, later ones are not.  pichol_profile_start creates the 2*capacity
+ * events (it allocates; the compute calls never do) and clears earlier
+ * records.  Recording is process-wide: enable it only while one host thread
+ * issues library calls. */
+pichol_status pichol_profile_start(int32_t capacity);
+
+/* Stop recording; the records stay readable. */
+pichol_status pichol_profile_stop(void);
+
+/* Wait for the recorded events and aggregate them by kernel name.  Fills
+ * up to `max` entries of names / launches / total_ms (any may be NULL;
+ * names stay valid until the next profiling call) and returns the number
+ * of distinct kernels, or -1 on a HIP error. */
+int32_t pichol_profile_summary(int32_t max, const char **names,
+                               int64_t *launches, double *total_ms);
+
+/* Destroy the events and records. */
+pichol_status pichol_profile_reset(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -87,6 +87,12 @@ _SIGNATURES = {
     "pichol_exact_cv": (_i32, [_pprob, _vp, _vp, _vp, _vp, _sz, _vp, _vp, _vp,
                                _vp, _vp]),
     "pichol_check": (_i32, [_vp, _i64, _vp, _i64, _vp]),
+    "pichol_profile_start": (_i32, [_i32]),
+    "pichol_profile_stop": (_i32, []),
+    "pichol_profile_summary": (_i32, [_i32, ctypes.POINTER(ctypes.c_char_p),
+                                      ctypes.POINTER(_i64),
+                                      ctypes.POINTER(_dbl)]),
+    "pichol_profile_reset": (_i32, []),
     "pichol_status_string": (ctypes.c_char_p, [_i32]),
     "pichol_last_error": (ctypes.c_char_p, []),
 }
@@ -321,3 +327,31 @@ def pichol_check(info, n_info, flags, n_flags, stream=None) -> int:
     return int(load().pichol_check(_dev(info, _i32t()), n_info,
                                    _dev(flags, _i32t()), n_flags,
                                    _stream(stream)))
+
+
+# ------------------------------------------------------------------ profiling
+
+def pichol_profile_start(capacity: int):
+    _check("pichol_profile_start", load().pichol_profile_start(capacity))
+
+
+def pichol_profile_stop():
+    _check("pichol_profile_stop", load().pichol_profile_stop())
+
+
+def pichol_profile_summary(max_kernels: int = 256) -> dict:
+    """{kernel name: (launches, total milliseconds)} of the recorded
+    launches."""
+    names = (ctypes.c_char_p * max_kernels)()
+    launches = (_i64 * max_kernels)()
+    total = (_dbl * max_kernels)()
+    n = load().pichol_profile_summary(max_kernels, names, launches, total)
+    if n < 0:
+        raise PicholError("pichol_profile_summary", PICHOL_ERR_HIP,
+                          load().pichol_last_error().decode())
+    return {names[i].decode(): (int(launches[i]), float(total[i]))
+            for i in range(min(n, max_kernels))}
+
+
+def pichol_profile_reset():
+    _check("pichol_profile_reset", load().pichol_profile_reset())

@@ -4,6 +4,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -27,6 +29,39 @@ static pichol_status hip_status(hipError_t e) {
 }
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------- profiling
+struct ProfState {
+  std::mutex mu;
+  bool on = false;
+  int cap = 0, used = 0;
+  std::vector<hipEvent_t> ev;       // 2 per slot
+  std::vector<const char*> name;    // per slot
+  std::vector<std::string> names_out;
+};
+static ProfState g_prof;
+
+ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), stream(s), slot(-1) {
+  if (!g_prof.on) return;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  if (!g_prof.on || g_prof.used >= g_prof.cap) return;
+  slot = g_prof.used++;
+  g_prof.name[slot] = n;
+  (void)hipEventRecord(g_prof.ev[2 * slot], s);
+}
+
+ProfScope::~ProfScope() {
+  if (slot < 0) return;
+  (void)hipEventRecord(g_prof.ev[2 * slot + 1], stream);
+}
+
+static void prof_destroy() {
+  for (hipEvent_t e : g_prof.ev) (void)hipEventDestroy(e);
+  g_prof.ev.clear();
+  g_prof.name.clear();
+  g_prof.cap = g_prof.used = 0;
+  g_prof.on = false;
+}
 
 // Householder QR of V (g x m, m <= g) and P = V^+ = R^{-1} Q^T (m x g).
 // Returns false when V is rank deficient.
@@ -209,6 +244,68 @@ const char* pichol_status_string(pichol_status s) {
 }
 
 const char* pichol_last_error(void) { return g_last_error.c_str(); }
+
+pichol_status pichol_profile_start(int32_t capacity) {
+  if (capacity < 1) return PICHOL_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  prof_destroy();
+  g_prof.ev.resize(2 * (size_t)capacity, nullptr);
+  for (auto& e : g_prof.ev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      e = nullptr;
+      prof_destroy();
+      return hip_status(r);
+    }
+  }
+  g_prof.name.assign(capacity, nullptr);
+  g_prof.cap = capacity;
+  g_prof.used = 0;
+  g_prof.on = true;
+  return PICHOL_OK;
+}
+
+pichol_status pichol_profile_stop(void) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = false;
+  return PICHOL_OK;
+}
+
+int32_t pichol_profile_summary(int32_t max, const char** names,
+                               int64_t* launches, double* total_ms) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  std::map<std::string, std::pair<int64_t, double>> agg;
+  for (int sl = 0; sl < g_prof.used; ++sl) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(g_prof.ev[2 * sl + 1]) != hipSuccess) return -1;
+    if (hipEventElapsedTime(&ms, g_prof.ev[2 * sl], g_prof.ev[2 * sl + 1]) != hipSuccess)
+      return -1;
+    auto& a = agg[g_prof.name[sl]];
+    a.first += 1;
+    a.second += ms;
+  }
+  g_prof.names_out.clear();
+  int32_t i = 0;
+  for (auto& kv : agg) {
+    if (i < max) {
+      g_prof.names_out.push_back(kv.first);
+      if (launches) launches[i] = kv.second.first;
+      if (total_ms) total_ms[i] = kv.second.second;
+    }
+    ++i;
+  }
+  if (names)
+    for (int32_t j = 0; j < (int32_t)g_prof.names_out.size(); ++j)
+      names[j] = g_prof.names_out[j].c_str();
+  return i;
+}
+
+pichol_status pichol_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  prof_destroy();
+  g_prof.names_out.clear();
+  return PICHOL_OK;
+}
 
 pichol_status pichol_pack(int64_t d, int32_t nmat, const double* A, int64_t lda,
                           double* P, hipStream_t stream) {

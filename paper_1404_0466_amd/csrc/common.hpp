@@ -46,8 +46,8 @@ __device__ inline void st4(double* p, v4d v) { *(v4d*)p = v; }
 // FP64 MFMA micro-kernel for one 64 x 64 block per wavefront.
 //
 // v_mfma_f64_16x16x4f64 computes D(16x16) += A(16x4) B(4x16); lane l
-// supplies A[l%16][l/16] and B[l/16][l%16] and holds D[4(l/16)+v][l%16] in
-// element v of its accumulator.
+// supplies A[l%16][l/16] and B[l/16][l%16] and holds D[4v + l/16][l%16] in
+// element v of its accumulator (checked on gfx950).
 //
 // The wave's block is the product D'(i,j) = sum_k A'(i,k) B'(k,j) for
 // i, j in [0,64).  Operands are read from memory where the non-k index is
@@ -56,7 +56,7 @@ __device__ inline void st4(double* p, v4d v) { *(v4d*)p = v; }
 // rows i = 4*(l%16) + bi, and block bj the columns j = 4*(l%16) + bj: lane l
 // loads the four consecutive values a[k*lda + 4*(l%16) .. +3] and uses one
 // in each block.  Accumulator acc[bi][bj] element v of lane l then holds
-//     D'(i = 16*(l/16) + 4*v + bi,  j = 4*(l%16) + bj)
+//     D'(i = 16*v + 4*(l/16) + bi,  j = 4*(l%16) + bj)
 // so the four bj accumulators of a lane are four consecutive j: the
 // epilogue writes them with one 32-byte store.
 // ---------------------------------------------------------------------------
@@ -76,7 +76,7 @@ struct Acc64 {
         c[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj],
                                                           c[bi][bj], 0, 0, 0);
   }
-  // Values of row i = 16*(l/16) + 4*v + bi at columns 4*(l%16) .. +3.
+  // Values of row i = 16*v + 4*(l/16) + bi at columns 4*(l%16) .. +3.
   __device__ inline v4d row(int v, int bi) const {
     return v4d{c[bi][0][v], c[bi][1][v], c[bi][2][v], c[bi][3][v]};
   }
@@ -111,7 +111,7 @@ struct LaneXY {
     lq = l >> 4;
     lr = l & 15;
   }
-  __device__ inline int row(int v, int bi) const { return 16 * lq + 4 * v + bi; }
+  __device__ inline int row(int v, int bi) const { return 16 * v + 4 * lq + bi; }
   __device__ inline int col0() const { return 4 * lr; }
 };
 

@@ -87,7 +87,7 @@ hipError_t launch_fit(int64_t d, int nmat, const FitCoef& fc, const double* L,
   switch (fc.m) {
 #define PICHOL_FIT_CASE(MM)                                                   \
   case MM:                                                                    \
-    hipLaunchKernelGGL(k_fit<MM>, grid, dim3(256), 0, s, S, fc, L, theta,     \
+    PICHOL_LAUNCH(k_fit<MM>, grid, dim3(256), 0, s, S, fc, L, theta,     \
                        theta_t);                                              \
     break;
     PICHOL_FIT_CASE(1)
@@ -111,7 +111,7 @@ hipError_t launch_eval(int64_t d, int nmat, int m, const double* theta,
   const int64_t S = packed_elems_of(d);
   unsigned bx = (unsigned)((S / 4 + 255) / 256);
   if (bx > 1024) bx = 1024;
-  hipLaunchKernelGGL(k_eval, dim3(bx, (unsigned)nlam, (unsigned)nmat),
+  PICHOL_LAUNCH(k_eval, dim3(bx, (unsigned)nlam, (unsigned)nmat),
                      dim3(256), 0, s, S, m, theta, nlam, tau_dev, Lhat);
   return hipGetLastError();
 }

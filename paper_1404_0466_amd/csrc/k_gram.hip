@@ -177,18 +177,18 @@ hipError_t launch_gram(const double* X, int64_t ldx, const double* Y,
                        double* H, double* B, hipStream_t s) {
   const int64_t nt = ntiles_of(d), dp = nt * NB, S = packed_elems_of(d);
   const int vec_ok = ((ldx & 3) == 0) && ((((uintptr_t)X) & 31) == 0);
-  hipLaunchKernelGGL(k_gram_tiles, dim3((unsigned)tri(nt), (unsigned)fs.k),
+  PICHOL_LAUNCH(k_gram_tiles, dim3((unsigned)tri(nt), (unsigned)fs.k),
                      dim3(256), 0, s, X, ldx, d, nt, fs, G, vec_ok);
-  hipLaunchKernelGGL(k_gram_rhs, dim3((unsigned)((dp + 255) / 256), (unsigned)fs.k),
+  PICHOL_LAUNCH(k_gram_rhs, dim3((unsigned)((dp + 255) / 256), (unsigned)fs.k),
                      dim3(256), 0, s, X, ldx, Y, ldy, d, c, dp, fs, C);
-  hipLaunchKernelGGL(k_gram_yy, dim3((unsigned)fs.k), dim3(256), 0, s, Y, ldy,
+  PICHOL_LAUNCH(k_gram_yy, dim3((unsigned)fs.k), dim3(256), 0, s, Y, ldy,
                      c, fs, yy);
-  hipLaunchKernelGGL(k_gram_combine_h, dim3((unsigned)tri(nt), (unsigned)fs.k),
+  PICHOL_LAUNCH(k_gram_combine_h, dim3((unsigned)tri(nt), (unsigned)fs.k),
                      dim3(256), 0, s, d, nt, fs, G, H, S);
   const int64_t nb = dp * c;
   unsigned bx = (unsigned)((nb + 255) / 256);
   if (bx > 2048) bx = 2048;
-  hipLaunchKernelGGL(k_gram_combine_b, dim3(bx, (unsigned)fs.k), dim3(256), 0,
+  PICHOL_LAUNCH(k_gram_combine_b, dim3(bx, (unsigned)fs.k), dim3(256), 0,
                      s, nb, fs, C, B);
   return hipGetLastError();
 }

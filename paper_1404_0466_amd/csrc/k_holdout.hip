@@ -99,10 +99,10 @@ hipError_t launch_holdout(int64_t d, int nmat, int c, int q, int64_t ldz,
                           double* partial, double* err, int* flags,
                           hipStream_t s) {
   const int64_t nt = ntiles_of(d);
-  hipLaunchKernelGGL(k_holdout_partial,
+  PICHOL_LAUNCH(k_holdout_partial,
                      dim3((unsigned)(ldz / NB), (unsigned)nt, (unsigned)nmat),
                      dim3(256), 0, s, d, q, c, ldz, Z, G, C, partial);
-  hipLaunchKernelGGL(k_holdout_final,
+  PICHOL_LAUNCH(k_holdout_final,
                      dim3((unsigned)((q + 63) / 64), (unsigned)nmat), dim3(64),
                      0, s, nt, q, c, ldz, partial, yy, hn, err, flags);
   return hipGetLastError();

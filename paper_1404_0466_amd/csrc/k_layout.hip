@@ -81,7 +81,7 @@ hipError_t launch_store_doubles(const double* host, int n, double* dev,
     DoubleChunk ch;
     ch.n = (n - o) < 256 ? (n - o) : 256;
     for (int i = 0; i < ch.n; ++i) ch.v[i] = host[o + i];
-    hipLaunchKernelGGL(k_store_doubles, dim3(1), dim3(256), 0, s, ch, dev + o);
+    PICHOL_LAUNCH(k_store_doubles, dim3(1), dim3(256), 0, s, ch, dev + o);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -92,7 +92,7 @@ hipError_t launch_pack(int64_t d, int nmat, const double* A, int64_t lda,
                        double* P, hipStream_t s) {
   const int64_t nt = ntiles_of(d);
   dim3 grid((unsigned)tri(nt), (unsigned)nmat);
-  hipLaunchKernelGGL(k_pack, grid, dim3(256), 0, s, d, A, lda, P,
+  PICHOL_LAUNCH(k_pack, grid, dim3(256), 0, s, d, A, lda, P,
                      packed_elems_of(d));
   return hipGetLastError();
 }
@@ -100,7 +100,7 @@ hipError_t launch_pack(int64_t d, int nmat, const double* A, int64_t lda,
 hipError_t launch_unpack(int64_t d, int nmat, const double* P, double* A,
                          int64_t lda, hipStream_t s) {
   dim3 grid((unsigned)d, (unsigned)nmat);
-  hipLaunchKernelGGL(k_unpack, grid, dim3(256), 0, s, d, P,
+  PICHOL_LAUNCH(k_unpack, grid, dim3(256), 0, s, d, P,
                      packed_elems_of(d), A, lda);
   return hipGetLastError();
 }
@@ -112,7 +112,7 @@ hipError_t launch_slab_to_weights(int64_t d, int nmat, int q, int c,
   unsigned bx = (unsigned)((n + 255) / 256);
   if (bx > 4096) bx = 4096;
   dim3 grid(bx, (unsigned)q, (unsigned)nmat);
-  hipLaunchKernelGGL(k_slab_to_weights, grid, dim3(256), 0, s, d, q, c, ldz,
+  PICHOL_LAUNCH(k_slab_to_weights, grid, dim3(256), 0, s, d, q, c, ldz,
                      ntiles_of(d) * NB, Z, W);
   return hipGetLastError();
 }

@@ -177,7 +177,7 @@ hipError_t launch_shift_copy(int64_t d, int nmat, const double* H, int nshift,
                              const double* lam_dev, double* L, int* info,
                              hipStream_t s) {
   const int64_t nt = ntiles_of(d);
-  hipLaunchKernelGGL(k_shift_copy,
+  PICHOL_LAUNCH(k_shift_copy,
                      dim3((unsigned)tri(nt), (unsigned)(nmat * nshift)),
                      dim3(256), 0, s, d, packed_elems_of(d), H, nshift,
                      lam_dev, L, info);
@@ -189,13 +189,13 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
   for (int kk = 0; kk < nt; ++kk) {
-    hipLaunchKernelGGL(k_potrf_diag, dim3((unsigned)nfac), dim3(256), 0, s, d,
+    PICHOL_LAUNCH(k_potrf_diag, dim3((unsigned)nfac), dim3(256), 0, s, d,
                        S, kk, L, info, linv_ws);
     const int rest = nt - kk - 1;
     if (rest > 0) {
-      hipLaunchKernelGGL(k_potrf_panel, dim3((unsigned)rest, (unsigned)nfac),
+      PICHOL_LAUNCH(k_potrf_panel, dim3((unsigned)rest, (unsigned)nfac),
                          dim3(256), 0, s, S, kk, L, linv_ws);
-      hipLaunchKernelGGL(k_potrf_update,
+      PICHOL_LAUNCH(k_potrf_update,
                          dim3((unsigned)tri(rest), (unsigned)nfac), dim3(256),
                          0, s, S, kk, kk, kk + 1, L);
     }

@@ -254,7 +254,7 @@ static hipError_t slab_init(int64_t d, int nmat, int q, int c, int64_t ldz,
   const int64_t dp = ntiles_of(d) * NB;
   unsigned bx = (unsigned)((dp * ldz + 255) / 256);
   if (bx > 4096) bx = 4096;
-  hipLaunchKernelGGL(k_slab_init, dim3(bx, (unsigned)nmat), dim3(256), 0, s,
+  PICHOL_LAUNCH(k_slab_init, dim3(bx, (unsigned)nmat), dim3(256), 0, s,
                      dp, q, c, ldz, B, Z, flags);
   return hipGetLastError();
 }
@@ -274,19 +274,19 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
   const unsigned ncb = (unsigned)(ldz / NB);
   FactorSrc src{theta, S, M, 0, q, tau_dev};
   for (int i = 0; i < nt; ++i) {
-    hipLaunchKernelGGL(k_diag_solve<true>, dim3((unsigned)q, (unsigned)nmat),
+    PICHOL_LAUNCH(k_diag_solve<true>, dim3((unsigned)q, (unsigned)nmat),
                        dim3(256), 0, s, d, i, src, c, ldz, Z, flags);
     if (i + 1 < nt)
-      hipLaunchKernelGGL(k_update_interp<true>,
+      PICHOL_LAUNCH(k_update_interp<true>,
                          dim3(ncb, (unsigned)(nt - i - 1), (unsigned)nmat),
                          dim3(256), 0, s, d, i, theta, theta_t, S, M, q, c,
                          tau_dev, ldz, Z);
   }
   for (int i = nt - 1; i >= 0; --i) {
-    hipLaunchKernelGGL(k_diag_solve<false>, dim3((unsigned)q, (unsigned)nmat),
+    PICHOL_LAUNCH(k_diag_solve<false>, dim3((unsigned)q, (unsigned)nmat),
                        dim3(256), 0, s, d, i, src, c, ldz, Z, flags);
     if (i > 0)
-      hipLaunchKernelGGL(k_update_interp<false>,
+      PICHOL_LAUNCH(k_update_interp<false>,
                          dim3(ncb, (unsigned)i, (unsigned)nmat), dim3(256), 0,
                          s, d, i, theta, theta_t, S, M, q, c, tau_dev, ldz, Z);
   }
@@ -300,18 +300,18 @@ hipError_t launch_solve_factors(int64_t d, int nmat, int nper, int c,
   const int64_t S = packed_elems_of(d);
   FactorSrc src{L, S, 1, 1, nper, nullptr};
   for (int i = 0; i < nt; ++i) {
-    hipLaunchKernelGGL(k_diag_solve<true>, dim3((unsigned)nper, (unsigned)nmat),
+    PICHOL_LAUNCH(k_diag_solve<true>, dim3((unsigned)nper, (unsigned)nmat),
                        dim3(256), 0, s, d, i, src, c, ldz, Z, flags);
     if (i + 1 < nt)
-      hipLaunchKernelGGL(k_update_factors<true>,
+      PICHOL_LAUNCH(k_update_factors<true>,
                          dim3((unsigned)(nt - i - 1), (unsigned)nper, (unsigned)nmat),
                          dim3(256), 0, s, d, i, L, S, nper, c, ldz, Z);
   }
   for (int i = nt - 1; i >= 0; --i) {
-    hipLaunchKernelGGL(k_diag_solve<false>, dim3((unsigned)nper, (unsigned)nmat),
+    PICHOL_LAUNCH(k_diag_solve<false>, dim3((unsigned)nper, (unsigned)nmat),
                        dim3(256), 0, s, d, i, src, c, ldz, Z, flags);
     if (i > 0)
-      hipLaunchKernelGGL(k_update_factors<false>,
+      PICHOL_LAUNCH(k_update_factors<false>,
                          dim3((unsigned)i, (unsigned)nper, (unsigned)nmat),
                          dim3(256), 0, s, d, i, L, S, nper, c, ldz, Z);
   }

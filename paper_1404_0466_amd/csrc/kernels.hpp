@@ -8,6 +8,23 @@
 
 namespace pichol {
 
+// Opt-in per-kernel timing (pichol_profile_* in the C-ABI): while enabled,
+// every launch made through PICHOL_LAUNCH is bracketed by a pair of HIP
+// events recorded on the launch stream.  Disabled, it costs one flag test.
+struct ProfScope {
+  const char* name;
+  hipStream_t stream;
+  int slot;
+  ProfScope(const char* n, hipStream_t s);
+  ~ProfScope();
+};
+
+#define PICHOL_LAUNCH(K, GRID, BLOCK, SHMEM, STREAM, ...)                 \
+  do {                                                                    \
+    ::pichol::ProfScope prof_scope_(#K, STREAM);                          \
+    hipLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);       \
+  } while (0)
+
 hipError_t record_hip_error_code(hipError_t e);
 inline int record_hip_error(hipError_t e) {
   record_hip_error_code(e);
