@@ -107,6 +107,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-kernel event pass (no roofline)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="finish with one plain device copy of this many MiB "
+                         "(reference dispatch for hardware byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -233,6 +236,16 @@ def main():
             }
             log(f"k_potrf_update: {achieved:.2f} TFLOP/s "
                 f"({100 * achieved / PEAK_FP64_TFLOPS:.1f}% of FP64 peak)")
+
+    if args.calibrate_copy_mib > 0:
+        nel = args.calibrate_copy_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibrate_copy_mib} MiB read + written")
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:
