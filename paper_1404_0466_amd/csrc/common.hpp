@@ -76,6 +76,11 @@ struct Acc64 {
         c[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj],
                                                           c[bi][bj], 0, 0, 0);
   }
+  // Set row i = 16*v + 4*(l/16) + bi at columns 4*(l%16) .. +3.
+  __device__ inline void set_row(int v, int bi, const v4d& x) {
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) c[bi][bj][v] = x[bj];
+  }
   // Values of row i = 16*v + 4*(l/16) + bi at columns 4*(l%16) .. +3.
   __device__ inline v4d row(int v, int bi) const {
     return v4d{c[bi][0][v], c[bi][1][v], c[bi][2][v], c[bi][3][v]};
@@ -100,6 +105,35 @@ __device__ inline void mma_panel(Acc64& acc, const double* a, int64_t lda,
     bv = bn;
   }
   acc.mma(av, bv);
+}
+
+// acc -= sum over k in [0,K) of A'(i,k) B'(k,j) (the A operand negated).
+__device__ inline void mma_panel_sub(Acc64& acc, const double* a, int64_t lda,
+                                     const double* b, int64_t ldb, int K) {
+  const int l = threadIdx.x & 63;
+  const double* pa = a + (int64_t)(l >> 4) * lda + 4 * (l & 15);
+  const double* pb = b + (int64_t)(l >> 4) * ldb + 4 * (l & 15);
+  const int64_t sa = 4 * lda, sb = 4 * ldb;
+  v4d av = ld4(pa), bv = ld4(pb);
+  for (int k0 = 4; k0 < K; k0 += 4) {
+    pa += sa;
+    pb += sb;
+    v4d an = ld4(pa), bn = ld4(pb);
+    acc.mma(-av, bv);
+    av = an;
+    bv = bn;
+  }
+  acc.mma(-av, bv);
+}
+
+// Workgroups are dispatched to the eight XCDs round-robin by linear id, and
+// each XCD has its own L2.  This maps the hardware id to a logical id such
+// that every XCD receives one contiguous range of logical ids, so work items
+// that share operands (tiles of one matrix) meet in the same L2.
+__device__ inline int xcd_remap(int id, int n) {
+  const int q = n >> 3, rem = n & 7;
+  const int xcd = id & 7, slot = id >> 3;
+  return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
 }
 
 // Lane coordinates inside a 64 x 64 wave block.

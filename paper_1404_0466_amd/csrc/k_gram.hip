@@ -77,31 +77,43 @@ __global__ void __launch_bounds__(256) k_gram_tiles(const double* X,
     }
 }
 
-// C_b = X_b^T Y_b (dp x c, row-major, padding rows 0); one thread per row i
-// of C_b, sums over the block's rows in increasing order.
+// C_b = X_b^T Y_b (dp x c, row-major, padding rows 0).  A workgroup takes
+// 64 rows i of C_b; its four wavefronts sum over interleaved quarters of the
+// block's rows (row r0 + 4u + w), then the quarters are added in a fixed
+// order.
 __global__ void __launch_bounds__(256) k_gram_rhs(const double* X, int64_t ldx,
                                                   const double* Y, int64_t ldy,
                                                   int64_t d, int64_t c,
                                                   int64_t dp, FoldSplit fs,
                                                   double* C) {
+  __shared__ double part[4][64][17];
   const int b = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= dp) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   const int64_t r0 = fs.start[b], r1 = fs.start[b + 1];
   double* crow = C + ((int64_t)b * dp + i) * c;
-  for (int64_t c0 = 0; c0 < c; c0 += 8) {
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const int64_t cn = (c - c0) < 8 ? (c - c0) : 8;
+  for (int64_t c0 = 0; c0 < c; c0 += 16) {
+    const int cn = (int)((c - c0) < 16 ? (c - c0) : 16);
+    double acc[16] = {};
     if (i < d) {
-      for (int64_t r = r0; r < r1; ++r) {
+#pragma unroll 4
+      for (int64_t r = r0 + w; r < r1; r += 4) {
         const double x = X[r * ldx + i];
         const double* y = Y + r * ldy + c0;
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
+        for (int j = 0; j < 16; ++j)
           if (j < cn) acc[j] += x * y[j];
       }
     }
-    for (int j = 0; j < cn; ++j) crow[c0 + j] = acc[j];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) part[w][lane][j] = acc[j];
+    __syncthreads();
+    if (w == 0 && i < dp) {
+      for (int j = 0; j < cn; ++j)
+        crow[c0 + j] = ((part[0][lane][j] + part[1][lane][j]) + part[2][lane][j]) +
+                       part[3][lane][j];
+    }
+    __syncthreads();
   }
 }
 
@@ -179,7 +191,7 @@ hipError_t launch_gram(const double* X, int64_t ldx, const double* Y,
   const int vec_ok = ((ldx & 3) == 0) && ((((uintptr_t)X) & 31) == 0);
   PICHOL_LAUNCH(k_gram_tiles, dim3((unsigned)tri(nt), (unsigned)fs.k),
                      dim3(256), 0, s, X, ldx, d, nt, fs, G, vec_ok);
-  PICHOL_LAUNCH(k_gram_rhs, dim3((unsigned)((dp + 255) / 256), (unsigned)fs.k),
+  PICHOL_LAUNCH(k_gram_rhs, dim3((unsigned)(dp / 64), (unsigned)fs.k),
                      dim3(256), 0, s, X, ldx, Y, ldy, d, c, dp, fs, C);
   PICHOL_LAUNCH(k_gram_yy, dim3((unsigned)fs.k), dim3(256), 0, s, Y, ldy,
                      c, fs, yy);

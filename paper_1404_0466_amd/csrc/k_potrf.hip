@@ -46,67 +46,195 @@ __global__ void __launch_bounds__(256) k_shift_copy(int64_t d, int64_t S,
   if (blockIdx.x == 0 && threadIdx.x == 0) info[ms] = 0;
 }
 
-// Diagonal tile kk of factor f: unblocked right-looking Cholesky in LDS,
-// then the in-place inverse of the factor.  Writes the factor tile and the
-// inverse (column-major, zeros above the diagonal) to linv.
+__device__ inline double bcast_lane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One level of the recursive triangular inverse inside a 128 x 128 LDS
+// tile: for each pair of BS x BS diagonal blocks whose inverses are already
+// in place, replace the block below them, B, by -C^{-1} B A^{-1}.  All 256
+// threads take part; each computes a 4 x (BS/16) piece.
+template <int BS>
+__device__ inline void inv_combine(double* a, int tid) {
+  constexpr int CW = BS / 16, RB = BS / 4;
+  const int P = tid / (4 * BS), t = tid % (4 * BS);
+  const int i0 = 4 * (t % RB), j0 = CW * (t / RB);
+  const int o = 2 * BS * P;
+  double v[4][CW] = {};
+  // T = B A^{-1}: B at rows o+BS.., cols o..; A^{-1} lower at (o, o)
+  for (int p = j0; p < BS; ++p) {
+    const double* bc = a + (o + p) * NB + o + BS + i0;
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      const double ia = a[(o + j0 + c) * NB + o + p];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u][c] += bc[u] * ia;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CW; ++c)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[(o + j0 + c) * NB + o + BS + i0 + u] = v[u][c];
+  __syncthreads();
+  // X = -C^{-1} T: C^{-1} lower at (o+BS, o+BS)
+  double x[4][CW] = {};
+  for (int p = 0; p <= i0 + 3; ++p) {
+    const double* cc = a + (o + BS + p) * NB + o + BS + i0;
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      const double tv = a[(o + j0 + c) * NB + o + BS + p];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (p <= i0 + u) x[u][c] -= cc[u] * tv;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CW; ++c)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[(o + j0 + c) * NB + o + BS + i0 + u] = x[u][c];
+  __syncthreads();
+}
+
+// Diagonal tile kk of factor f, in LDS (column-major, a[c*128 + r]):
+//  factorization in four 32-column blocks -- the 32 x 32 diagonal block by
+//  one wavefront with its rows in registers (readlane broadcasts, no
+//  barriers), the rows below it by forward substitution one row per thread,
+//  the trailing part by 4 x 4 register-blocked updates;
+//  then the inverse of the factor, recursively: the eight 16 x 16 diagonal
+//  blocks inverted by half-wavefronts, combined pairwise with
+//  [[A,0],[B,C]]^{-1} = [[A^{-1},0],[-C^{-1} B A^{-1}, C^{-1}]].
+// Writes the factor tile (zeros above the diagonal) and its inverse to linv.
 __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
                                                     int kk, double* L,
                                                     int* info, double* linv) {
-  __shared__ double a[NB * LDS_LD];
-  __shared__ double tmp[NB];
+  __shared__ double a[NB2];
   const int f = blockIdx.x;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double* tile = L + (int64_t)f * S + tile_off(kk, kk);
-  for (int e = tid; e < NB2; e += blockDim.x)
-    a[(e >> 7) * LDS_LD + (e & (NB - 1))] = tile[e];
+  for (int e = tid; e < NB2; e += blockDim.x) a[e] = tile[e];
   __syncthreads();
 
-  const int i = tid & (NB - 1), grp = tid >> 7;
-  for (int j = 0; j < NB; ++j) {
-    const double piv = a[j * LDS_LD + j];
-    if (tid == 0 && !(piv > 0.0) && info[f] == 0 &&
-        (int64_t)kk * NB + j < d)
-      info[f] = kk * NB + j + 1;
-    const double ljj = sqrt(piv);
-    __syncthreads();  // every thread has read the pivot
-    if (tid < NB) {
-      if (i > j) a[j * LDS_LD + i] = a[j * LDS_LD + i] / ljj;
-      if (i == j) a[j * LDS_LD + j] = ljj;
+  for (int jb = 0; jb < 4; ++jb) {
+    const int j0 = 32 * jb;
+    // (1) diagonal 32 x 32 block, wave 0, lane = row j0 + lane
+    if (w == 0) {
+      double r[32];
+#pragma unroll
+      for (int k = 0; k < 32; ++k)
+        r[k] = (lane < 32 && k <= lane) ? a[(j0 + k) * NB + j0 + lane] : 0.0;
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        const double piv = bcast_lane(r[j], j);
+        if (lane == 0 && !(piv > 0.0) && info[f] == 0 &&
+            (int64_t)kk * NB + j0 + j < d)
+          info[f] = kk * NB + j0 + j + 1;
+        const double ljj = sqrt(piv);
+        if (lane == j) r[j] = ljj;
+        else if (lane > j) r[j] = r[j] / ljj;
+#pragma unroll
+        for (int k = j + 1; k < 32; ++k) {
+          const double lkj = bcast_lane(r[j], k);
+          if (lane >= k) r[k] -= r[j] * lkj;
+        }
+      }
+      if (lane < 32) {
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+          if (k <= lane) a[(j0 + k) * NB + j0 + lane] = r[k];
+      }
     }
     __syncthreads();
-    if (i > j) {
-      const double lij = a[j * LDS_LD + i];
-      for (int c = j + 1 + grp; c <= i; c += 2)
-        a[c * LDS_LD + i] -= lij * a[j * LDS_LD + c];
+    if (jb == 3) break;
+    // (2) rows below: X = A L_d^{-T}, one row per thread
+    const int nrow = NB - j0 - 32;
+    if (tid < nrow) {
+      const int i = j0 + 32 + tid;
+      double x[32];
+#pragma unroll
+      for (int k = 0; k < 32; ++k) x[k] = a[(j0 + k) * NB + i];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        x[j] = x[j] / a[(j0 + j) * NB + j0 + j];
+#pragma unroll
+        for (int p = j + 1; p < 32; ++p) x[p] -= x[j] * a[(j0 + j) * NB + j0 + p];
+      }
+#pragma unroll
+      for (int k = 0; k < 32; ++k) a[(j0 + k) * NB + i] = x[k];
+    }
+    __syncthreads();
+    // (3) trailing update of rows/columns [j0+32, 128), 4 x 4 blocks
+    const int nb4 = nrow / 4;
+    const int nblk = nb4 * (nb4 + 1) / 2;
+    for (int b = tid; b < nblk; b += blockDim.x) {
+      int bi = (int)((sqrtf(8.0f * (float)b + 1.0f) - 1.0f) * 0.5f);
+      while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+      while (bi * (bi + 1) / 2 > b) --bi;
+      const int bj = b - bi * (bi + 1) / 2;
+      const int r0 = j0 + 32 + 4 * bi, c0 = j0 + 32 + 4 * bj;
+      double acc[4][4] = {};
+#pragma unroll 8
+      for (int p = 0; p < 32; ++p) {
+        const double* col = a + (j0 + p) * NB;
+        double xr[4], xc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          xr[u] = col[r0 + u];
+          xc[u] = col[c0 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += xr[u] * xc[v];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (r0 + u >= c0 + v) a[(c0 + v) * NB + r0 + u] -= acc[u][v];
     }
     __syncthreads();
   }
 
   for (int e = tid; e < NB2; e += blockDim.x) {
     const int r = e & (NB - 1), c = e >> 7;
-    tile[e] = (r >= c) ? a[c * LDS_LD + r] : 0.0;
+    tile[e] = (r >= c) ? a[e] : 0.0;
   }
-  __syncthreads();
 
-  // In-place inverse, columns from last to first: with the trailing block
-  // already inverted, column j becomes -(1/L_jj) * Tinv * x.
-  for (int j = NB - 1; j >= 0; --j) {
-    if (tid > j && tid < NB) tmp[tid] = a[j * LDS_LD + tid];
-    __syncthreads();
-    const double inv = 1.0 / a[j * LDS_LD + j];
-    if (tid > j && tid < NB) {
-      double y = 0.0;
-      for (int p = j + 1; p <= tid; ++p) y += a[p * LDS_LD + tid] * tmp[p];
-      a[j * LDS_LD + tid] = -inv * y;
+  __syncthreads();
+  // inverse: eight 16 x 16 diagonal blocks (two per wavefront, lane =
+  // column), then three levels of pairwise combination
+  {
+    const int leaf = 2 * w + ((lane >> 4) & 1);
+    const int o = 16 * leaf, j = lane & 15;
+    double x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      const double* col = a + (o + p) * NB + o;
+      x[p] = x[p] / col[p];
+#pragma unroll
+      for (int i = p + 1; i < 16; ++i) x[i] -= col[i] * x[p];
     }
     __syncthreads();
-    if (tid == j) a[j * LDS_LD + j] = inv;
+    if (lane < 32) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) a[(o + j) * NB + o + i] = x[i];
+    }
   }
   __syncthreads();
+  inv_combine<16>(a, tid);
+  inv_combine<32>(a, tid);
+  inv_combine<64>(a, tid);
   double* li = linv + (int64_t)f * NB2;
   for (int e = tid; e < NB2; e += blockDim.x) {
     const int r = e & (NB - 1), c = e >> 7;
-    li[e] = (r >= c) ? a[c * LDS_LD + r] : 0.0;
+    li[e] = (r >= c) ? a[e] : 0.0;
   }
 }
 
@@ -137,38 +265,47 @@ __global__ void __launch_bounds__(256) k_potrf_panel(int64_t S, int kk,
 }
 
 // Trailing tile (I,J), kk < J <= I: A_IJ -= sum_{c in [c0,c1)} L_Ic L_Jc^T.
-// The wave computes D'(n,m) = sum_p L_Jc(n,p) L_Ic(m,p) = update(m,n).
+// The wave computes D'(n,m) = A_IJ(m,n) - sum_p L_Jc(n,p) L_Ic(m,p): the
+// accumulators start from the tile (its loads overlap the first operand
+// loads) and the products are subtracted, so the epilogue is a store.
+// Logical workgroup ids are laid out matrix by matrix and spread over the
+// XCDs in contiguous ranges.
 __global__ void __launch_bounds__(256) k_potrf_update(int64_t S, int kk,
                                                       int c0, int c1,
-                                                      double* L) {
-  const int f = blockIdx.y;
-  const int t = blockIdx.x;
+                                                      int ntile, double* L) {
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  const int f = id / ntile;
+  const int t = id - f * ntile;
   const int r = tri_row(t);
   const int I = kk + 1 + r, J = kk + 1 + (t - (int)tri(r));
   const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
   if (I == J && wi > wj) return;  // block strictly above the diagonal
   double* Lf = L + (int64_t)f * S;
-  Acc64 acc;
-  acc.zero();
-  for (int c = c0; c < c1; ++c)
-    mma_panel(acc, Lf + tile_off(J, c) + wi * 64, NB,
-              Lf + tile_off(I, c) + wj * 64, NB, NB);
   double* ct = Lf + tile_off(I, J);
   const LaneXY lx;
   const int m0 = wj * 64 + lx.col0();
+  Acc64 acc;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+      acc.set_row(v, bi, ld4(ct + (wi * 64 + lx.row(v, bi)) * NB + m0));
+  for (int c = c0; c < c1; ++c)
+    mma_panel_sub(acc, Lf + tile_off(J, c) + wi * 64, NB,
+                  Lf + tile_off(I, c) + wj * 64, NB, NB);
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi) {
       const int n = wi * 64 + lx.row(v, bi);
       double* p = ct + n * NB + m0;
-      const v4d upd = acc.row(v, bi);
+      const v4d val = acc.row(v, bi);
       if (I != J || wi != wj) {
-        st4(p, ld4(p) - upd);
+        st4(p, val);
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          if (m0 + e >= n) p[e] -= upd[e];
+          if (m0 + e >= n) p[e] = val[e];
       }
     }
 }
@@ -195,9 +332,9 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
     if (rest > 0) {
       PICHOL_LAUNCH(k_potrf_panel, dim3((unsigned)rest, (unsigned)nfac),
                          dim3(256), 0, s, S, kk, L, linv_ws);
-      PICHOL_LAUNCH(k_potrf_update,
-                         dim3((unsigned)tri(rest), (unsigned)nfac), dim3(256),
-                         0, s, S, kk, kk, kk + 1, L);
+      const int ntile = (int)tri(rest);
+      PICHOL_LAUNCH(k_potrf_update, dim3((unsigned)(ntile * nfac)), dim3(256),
+                    0, s, S, kk, kk, kk + 1, ntile, L);
     }
   }
   return hipGetLastError();
