@@ -169,7 +169,7 @@ pichol_status pichol_fit(int64_t d, int32_t nmat, int32_t g, int32_t r,
                          const double *lam_s, double lam_ref, const double *L,
                          double *theta, double *theta_t, hipStream_t stream);
 
-/* Scratch bytes for pichol_eval and pichol_solve_interp with nlam values. */
+/* Scratch bytes for pichol_eval with nlam values. */
 size_t pichol_lambda_workspace(int32_t nlam);
 
 /* Evaluate the fitted factor at nlam values (Sec. 3.3):
@@ -181,16 +181,23 @@ pichol_status pichol_eval(int64_t d, int32_t nmat, int32_t r,
                           const double *lam, double lam_ref, double *Lhat,
                           void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Scratch bytes for pichol_solve_interp: the q scaled lambdas and the
+ * inverses of every diagonal 128 x 128 block of every interpolated factor,
+ * in two layouts (2 * nmat * q * ceil(d/128) * 131072 bytes). */
+size_t pichol_solve_interp_workspace(int64_t d, int32_t nmat, int32_t q);
+
 /* Interpolated solves for all q grid values of nmat folds (Sec. 3.2 applied
  * to the evaluated factor of Sec. 3.3), without materialising the factors:
  * forward substitution Lhat_t U = B then back substitution Lhat_t^T W = U,
- * blocked over 128-row tiles, the off-diagonal updates of all q values done
- * as one FP64 MFMA product with the r+1 coefficient planes.
+ * blocked over 128-row tiles.  The diagonal blocks of every Lhat_t are
+ * evaluated and inverted once; each step multiplies by the stored inverses,
+ * and the off-diagonal updates of all q values are one FP64 MFMA product
+ * with the r+1 coefficient planes.
  * In:  theta, theta_t from pichol_fit (device); B nmat x dp x c row-major
  *      (device, padding rows 0); lam q values (host).
  * Out: Z nmat slabs of dp x pichol_slab_cols(q,c) (device): W for every
  *      (fold, lambda); flags nmat*q (device, int32), zeroed then set.
- * ws: pichol_lambda_workspace(q) bytes. */
+ * ws: pichol_solve_interp_workspace(d, nmat, q) bytes. */
 pichol_status pichol_solve_interp(int64_t d, int32_t nmat, int32_t c,
                                   int32_t r, const double *theta,
                                   const double *theta_t, const double *B,

@@ -66,6 +66,7 @@ _SIGNATURES = {
     "pichol_fit": (_i32, [_i64, _i32, _i32, _i32, _vp, _dbl, _vp, _vp, _vp,
                           _vp]),
     "pichol_lambda_workspace": (_sz, [_i32]),
+    "pichol_solve_interp_workspace": (_sz, [_i64, _i32, _i32]),
     "pichol_eval": (_i32, [_i64, _i32, _i32, _vp, _i32, _vp, _dbl, _vp, _vp,
                            _sz, _vp]),
     "pichol_solve_interp": (_i32, [_i64, _i32, _i32, _i32, _vp, _vp, _vp,
@@ -226,6 +227,10 @@ def pichol_fit(d, nmat, g, r, lam_s, lam_ref, L, theta, theta_t, stream=None):
 
 def pichol_lambda_workspace(nlam: int) -> int:
     return int(load().pichol_lambda_workspace(nlam))
+
+
+def pichol_solve_interp_workspace(d: int, nmat: int, q: int) -> int:
+    return int(load().pichol_solve_interp_workspace(d, nmat, q))
 
 
 def pichol_eval(d, nmat, r, theta, nlam, lam, lam_ref, Lhat, ws, ws_bytes,

@@ -164,7 +164,8 @@ struct Layout {
   int64_t d, nt, dp, S, ldz;
   size_t G, C, yy, H, B, region;  // byte offsets
   // interpolated region
-  size_t i_lam, i_tau, i_L, i_linv, i_th, i_tht, i_Z, i_part, i_end;
+  size_t i_lam, i_tau, i_L, i_linv, i_th, i_tht, i_Z, i_part, i_dinv, i_dinvr,
+      i_end;
   // exact region
   size_t e_lam, e_L, e_linv, e_Z, e_part, e_end;
 };
@@ -194,6 +195,8 @@ static Layout layout_of(const pichol_problem* p) {
   L.i_tht = a; a += align256(k * M * L.S * dbl);
   L.i_Z = a; a += align256(k * L.dp * L.ldz * dbl);
   L.i_part = a; a += align256(k * L.nt * L.ldz * dbl);
+  L.i_dinv = a; a += align256(k * q * L.nt * NB2 * dbl);
+  L.i_dinvr = a; a += align256(k * q * L.nt * NB2 * dbl);
   L.i_end = a;
   a = o;
   L.e_lam = a; a += align256(q * dbl);
@@ -374,6 +377,12 @@ size_t pichol_lambda_workspace(int32_t nlam) {
   return nlam < 1 ? 0 : align256((size_t)nlam * sizeof(double));
 }
 
+size_t pichol_solve_interp_workspace(int64_t d, int32_t nmat, int32_t q) {
+  if (d < 1 || nmat < 1 || q < 1) return 0;
+  return pichol_lambda_workspace(q) +
+         2 * align256((size_t)nmat * q * ntiles_of(d) * NB2 * sizeof(double));
+}
+
 static hipError_t upload_tau(const double* lam, int nlam, double lam_ref,
                              double* dst, hipStream_t stream) {
   std::vector<double> tau(nlam);
@@ -405,14 +414,18 @@ pichol_status pichol_solve_interp(int64_t d, int32_t nmat, int32_t c, int32_t r,
       !theta_t || !B || !lam || !Z || !flags || !(lam_ref > 0.0) ||
       !isfinite(lam_ref))
     return PICHOL_ERR_ARG;
-  if (!ws || ws_bytes < pichol_lambda_workspace(q)) return PICHOL_ERR_WORKSPACE;
+  if (!ws || ws_bytes < pichol_solve_interp_workspace(d, nmat, q))
+    return PICHOL_ERR_WORKSPACE;
   const int64_t ldz = pichol_slab_cols(q, c);
   double* tau = at<double>(ws, 0);
+  double* dinv = at<double>(ws, pichol_lambda_workspace(q));
+  double* dinv_r = dinv + (pichol_solve_interp_workspace(d, nmat, q) -
+                           pichol_lambda_workspace(q)) / 2 / sizeof(double);
   hipError_t e = upload_tau(lam, q, lam_ref, tau, stream);
   if (e == hipSuccess) e = launch_slab_init(d, nmat, q, c, ldz, B, Z, flags, stream);
   if (e == hipSuccess)
     e = launch_solve_interp(d, nmat, c, r + 1, theta, theta_t, q, tau, ldz, Z,
-                            flags, stream);
+                            flags, dinv, dinv_r, stream);
   return hip_status(e);
 }
 
@@ -527,6 +540,7 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
                          stream);
   if (e == hipSuccess)
     e = launch_solve_interp(p->d, k, c, M, th, tht, q, tau, L.ldz, Z, flags,
+                            at<double>(ws, L.i_dinv), at<double>(ws, L.i_dinvr),
                             stream);
   if (e == hipSuccess)
     e = launch_holdout(p->d, k, c, q, L.ldz, Z, at<double>(ws, L.G),

@@ -46,60 +46,6 @@ __global__ void __launch_bounds__(256) k_shift_copy(int64_t d, int64_t S,
   if (blockIdx.x == 0 && threadIdx.x == 0) info[ms] = 0;
 }
 
-__device__ inline double bcast_lane(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// One level of the recursive triangular inverse inside a 128 x 128 LDS
-// tile: for each pair of BS x BS diagonal blocks whose inverses are already
-// in place, replace the block below them, B, by -C^{-1} B A^{-1}.  All 256
-// threads take part; each computes a 4 x (BS/16) piece.
-template <int BS>
-__device__ inline void inv_combine(double* a, int tid) {
-  constexpr int CW = BS / 16, RB = BS / 4;
-  const int P = tid / (4 * BS), t = tid % (4 * BS);
-  const int i0 = 4 * (t % RB), j0 = CW * (t / RB);
-  const int o = 2 * BS * P;
-  double v[4][CW] = {};
-  // T = B A^{-1}: B at rows o+BS.., cols o..; A^{-1} lower at (o, o)
-  for (int p = j0; p < BS; ++p) {
-    const double* bc = a + (o + p) * NB + o + BS + i0;
-#pragma unroll
-    for (int c = 0; c < CW; ++c) {
-      const double ia = a[(o + j0 + c) * NB + o + p];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) v[u][c] += bc[u] * ia;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < CW; ++c)
-#pragma unroll
-    for (int u = 0; u < 4; ++u) a[(o + j0 + c) * NB + o + BS + i0 + u] = v[u][c];
-  __syncthreads();
-  // X = -C^{-1} T: C^{-1} lower at (o+BS, o+BS)
-  double x[4][CW] = {};
-  for (int p = 0; p <= i0 + 3; ++p) {
-    const double* cc = a + (o + BS + p) * NB + o + BS + i0;
-#pragma unroll
-    for (int c = 0; c < CW; ++c) {
-      const double tv = a[(o + j0 + c) * NB + o + BS + p];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (p <= i0 + u) x[u][c] -= cc[u] * tv;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < CW; ++c)
-#pragma unroll
-    for (int u = 0; u < 4; ++u) a[(o + j0 + c) * NB + o + BS + i0 + u] = x[u][c];
-  __syncthreads();
-}
-
 // Diagonal tile kk of factor f, in LDS (column-major, a[c*128 + r]):
 //  factorization in four 32-column blocks -- the 32 x 32 diagonal block by
 //  one wavefront with its rows in registers (readlane broadcasts, no
@@ -206,31 +152,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
   }
 
   __syncthreads();
-  // inverse: eight 16 x 16 diagonal blocks (two per wavefront, lane =
-  // column), then three levels of pairwise combination
-  {
-    const int leaf = 2 * w + ((lane >> 4) & 1);
-    const int o = 16 * leaf, j = lane & 15;
-    double x[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) x[i] = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-    for (int p = 0; p < 16; ++p) {
-      const double* col = a + (o + p) * NB + o;
-      x[p] = x[p] / col[p];
-#pragma unroll
-      for (int i = p + 1; i < 16; ++i) x[i] -= col[i] * x[p];
-    }
-    __syncthreads();
-    if (lane < 32) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) a[(o + j) * NB + o + i] = x[i];
-    }
-  }
-  __syncthreads();
-  inv_combine<16>(a, tid);
-  inv_combine<32>(a, tid);
-  inv_combine<64>(a, tid);
+  invert_lower_lds(a, tid);
   double* li = linv + (int64_t)f * NB2;
   for (int e = tid; e < NB2; e += blockDim.x) {
     const int r = e & (NB - 1), c = e >> 7;
@@ -264,20 +186,29 @@ __global__ void __launch_bounds__(256) k_potrf_panel(int64_t S, int kk,
     }
 }
 
-// Trailing tile (I,J), kk < J <= I: A_IJ -= sum_{c in [c0,c1)} L_Ic L_Jc^T.
+// Trailing tile (I,J): A_IJ -= sum_{c in [c0,c1)} L_Ic L_Jc^T, for the
+// tiles of the triangle j0 <= J <= I, or of the single column J = j0.
 // The wave computes D'(n,m) = A_IJ(m,n) - sum_p L_Jc(n,p) L_Ic(m,p): the
 // accumulators start from the tile (its loads overlap the first operand
 // loads) and the products are subtracted, so the epilogue is a store.
 // Logical workgroup ids are laid out matrix by matrix and spread over the
 // XCDs in contiguous ranges.
-__global__ void __launch_bounds__(256) k_potrf_update(int64_t S, int kk,
-                                                      int c0, int c1,
-                                                      int ntile, double* L) {
+__global__ void __launch_bounds__(256) k_potrf_update(int64_t S, int j0,
+                                                      int column, int c0,
+                                                      int c1, int ntile,
+                                                      double* L) {
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int f = id / ntile;
   const int t = id - f * ntile;
-  const int r = tri_row(t);
-  const int I = kk + 1 + r, J = kk + 1 + (t - (int)tri(r));
+  int I, J;
+  if (column) {  // tiles (j0 + t, j0)
+    I = j0 + t;
+    J = j0;
+  } else {       // tiles (I, J) with j0 <= J <= I
+    const int r = tri_row(t);
+    I = j0 + r;
+    J = j0 + (t - (int)tri(r));
+  }
   const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
   if (I == J && wi > wj) return;  // block strictly above the diagonal
   double* Lf = L + (int64_t)f * S;
@@ -321,21 +252,35 @@ hipError_t launch_shift_copy(int64_t d, int nmat, const double* H, int nshift,
   return hipGetLastError();
 }
 
+// Panels are factored in pairs with a delayed update: after panel kk only
+// the next panel column is updated, panel kk+1 is factored, and the rest of
+// the trailing matrix receives both panels' contributions in one rank-256
+// update.  This halves the read-modify-write traffic of the trailing tiles.
 hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
                                 double* linv_ws, hipStream_t s) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
-  for (int kk = 0; kk < nt; ++kk) {
-    PICHOL_LAUNCH(k_potrf_diag, dim3((unsigned)nfac), dim3(256), 0, s, d,
-                       S, kk, L, info, linv_ws);
+  auto diag_panel = [&](int kk) {
+    PICHOL_LAUNCH(k_potrf_diag, dim3((unsigned)nfac), dim3(256), 0, s, d, S,
+                  kk, L, info, linv_ws);
     const int rest = nt - kk - 1;
-    if (rest > 0) {
+    if (rest > 0)
       PICHOL_LAUNCH(k_potrf_panel, dim3((unsigned)rest, (unsigned)nfac),
-                         dim3(256), 0, s, S, kk, L, linv_ws);
-      const int ntile = (int)tri(rest);
-      PICHOL_LAUNCH(k_potrf_update, dim3((unsigned)(ntile * nfac)), dim3(256),
-                    0, s, S, kk, kk, kk + 1, ntile, L);
-    }
+                    dim3(256), 0, s, S, kk, L, linv_ws);
+  };
+  auto update = [&](int j0, int column, int c0, int c1) {
+    const int rest = nt - j0;
+    if (rest <= 0) return;
+    const int ntile = column ? rest : (int)tri(rest);
+    PICHOL_LAUNCH(k_potrf_update, dim3((unsigned)(ntile * nfac)), dim3(256),
+                  0, s, S, j0, column, c0, c1, ntile, L);
+  };
+  for (int kk = 0; kk < nt; kk += 2) {
+    diag_panel(kk);
+    if (kk + 1 >= nt) break;
+    update(kk + 1, 1, kk, kk + 1);   // next panel column only
+    diag_panel(kk + 1);
+    update(kk + 2, 0, kk, kk + 2);   // the rest, rank 256
   }
   return hipGetLastError();
 }

@@ -9,21 +9,16 @@
 // tile rows in reverse with the transposed blocks.
 //
 // Interpolated factors (Sec. 3.3) are never materialised.  Their diagonal
-// blocks are evaluated in LDS, and the off-diagonal update of all lambdas is
-// one FP64 MFMA product: Lhat_t(I,i) U_t = sum_p Theta_p(I,i) (tau_t^p U_t),
-// so each coefficient tile is read once per step for all q values.
+// blocks are evaluated and inverted once, up front, all in parallel
+// (k_diag_inv), so each sequential step applies a stored inverse; the
+// off-diagonal update of all lambdas is one FP64 MFMA product:
+// Lhat_t(I,i) U_t = sum_p Theta_p(I,i) (tau_t^p U_t), so each coefficient
+// tile is read once per step for all q values.
 // Exact factors (the per-lambda baseline) use one factor per lambda.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace pichol {
-
-__device__ inline double bcast_lane(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // Z[m][i][col] = B[m][i][col % c] for col < q*c, 0 beyond; flags cleared.
 __global__ void __launch_bounds__(256) k_slab_init(int64_t dp, int q, int c,
@@ -136,6 +131,77 @@ __global__ void __launch_bounds__(256) k_diag_solve(int64_t d, int i,
         zbase[(int64_t)r0 * ldz + cc] = z[u][0];
         zbase[(int64_t)r1 * ldz + cc] = z[u][1];
       }
+    }
+  }
+}
+
+// Inverse of diagonal block i of the interpolated factor for lambda t of
+// fold m: the block is evaluated from the coefficient planes into LDS and
+// inverted there.  Written twice: column-major to dinv (forward solves) and
+// row-major to dinv_r (the transpose, for back solves).  A non-positive
+// diagonal entry sets flag bit1.
+__global__ void __launch_bounds__(256) k_diag_inv(int64_t d, FactorSrc src,
+                                                  double* dinv, double* dinv_r,
+                                                  int* flags) {
+  __shared__ double a[NB2];
+  const int i = blockIdx.x, t = blockIdx.y;
+  const int64_t m = blockIdx.z;
+  const int nt = gridDim.x;
+  const int tid = threadIdx.x;
+  const double tv = src.tau[t];
+  const double* p = src.base + m * src.M * src.S + tile_off(i, i);
+  for (int e = tid; e < NB2; e += blockDim.x) {
+    double acc = 0.0, pw = 1.0;
+    for (int q = 0; q < src.M; ++q) {
+      acc += pw * p[q * src.S + e];
+      pw *= tv;
+    }
+    a[e] = acc;
+  }
+  __syncthreads();
+  if (tid < NB && (int64_t)i * NB + tid < d && !(a[tid * NB + tid] > 0.0))
+    atomicOr(flags + m * src.nper + t, 2);
+  invert_lower_lds(a, tid);
+  const int64_t off = ((m * src.nper + t) * nt + i) * (int64_t)NB2;
+  for (int e = tid; e < NB2; e += blockDim.x) dinv[off + e] = a[e];
+  for (int e = tid; e < NB2; e += blockDim.x)
+    dinv_r[off + e] = a[(e & (NB - 1)) * NB + (e >> 7)];
+}
+
+// Diagonal block solve of tile row i by multiplication with the stored
+// inverse: z <- M z for the c columns of lambda t = blockIdx.x of fold
+// m = blockIdx.y, where M(r,k) = mat[k*128 + r] (the inverse for forward
+// steps, its transpose for back steps).
+__global__ void __launch_bounds__(256) k_diag_apply(int64_t d, int i, int nper,
+                                                    int c, const double* mats,
+                                                    int64_t ldz, double* Z) {
+  __shared__ double zs[NB * 16];
+  const int t = blockIdx.x;
+  const int64_t m = blockIdx.y;
+  const int nt = (int)ntiles_of(d);
+  const int tid = threadIdx.x, row = tid & (NB - 1), half = tid >> 7;
+  const int64_t dp = (int64_t)nt * NB;
+  const double* M = mats + ((m * nper + t) * nt + i) * (int64_t)NB2;
+  double* zb = Z + (m * dp + (int64_t)i * NB) * ldz + (int64_t)t * c;
+  for (int cg = 0; cg < c; cg += 16) {
+    const int cn = (c - cg) < 16 ? (c - cg) : 16;
+    if (cg) __syncthreads();
+    for (int e = tid; e < NB * 16; e += blockDim.x) {
+      const int k = e >> 4, cc = e & 15;
+      zs[e] = cc < cn ? zb[(int64_t)k * ldz + cg + cc] : 0.0;
+    }
+    __syncthreads();
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 4
+    for (int k = 0; k < NB; ++k) {
+      const double mv = M[k * NB + row];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += mv * zs[k * 16 + half + 2 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int cc = half + 2 * u;
+      if (cc < cn) zb[(int64_t)row * ldz + cg + cc] = acc[u];
     }
   }
 }
@@ -268,27 +334,30 @@ hipError_t launch_slab_init(int64_t d, int nmat, int q, int c, int64_t ldz,
 hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
                                const double* theta, const double* theta_t,
                                int q, const double* tau_dev, int64_t ldz,
-                               double* Z, int* flags, hipStream_t s) {
+                               double* Z, int* flags, double* dinv,
+                               double* dinv_r, hipStream_t s) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
   const unsigned ncb = (unsigned)(ldz / NB);
   FactorSrc src{theta, S, M, 0, q, tau_dev};
+  PICHOL_LAUNCH(k_diag_inv, dim3((unsigned)nt, (unsigned)q, (unsigned)nmat),
+                dim3(256), 0, s, d, src, dinv, dinv_r, flags);
   for (int i = 0; i < nt; ++i) {
-    PICHOL_LAUNCH(k_diag_solve<true>, dim3((unsigned)q, (unsigned)nmat),
-                       dim3(256), 0, s, d, i, src, c, ldz, Z, flags);
+    PICHOL_LAUNCH(k_diag_apply, dim3((unsigned)q, (unsigned)nmat), dim3(256), 0,
+                  s, d, i, q, c, dinv, ldz, Z);
     if (i + 1 < nt)
       PICHOL_LAUNCH(k_update_interp<true>,
-                         dim3(ncb, (unsigned)(nt - i - 1), (unsigned)nmat),
-                         dim3(256), 0, s, d, i, theta, theta_t, S, M, q, c,
-                         tau_dev, ldz, Z);
+                    dim3(ncb, (unsigned)(nt - i - 1), (unsigned)nmat),
+                    dim3(256), 0, s, d, i, theta, theta_t, S, M, q, c,
+                    tau_dev, ldz, Z);
   }
   for (int i = nt - 1; i >= 0; --i) {
-    PICHOL_LAUNCH(k_diag_solve<false>, dim3((unsigned)q, (unsigned)nmat),
-                       dim3(256), 0, s, d, i, src, c, ldz, Z, flags);
+    PICHOL_LAUNCH(k_diag_apply, dim3((unsigned)q, (unsigned)nmat), dim3(256), 0,
+                  s, d, i, q, c, dinv_r, ldz, Z);
     if (i > 0)
       PICHOL_LAUNCH(k_update_interp<false>,
-                         dim3(ncb, (unsigned)i, (unsigned)nmat), dim3(256), 0,
-                         s, d, i, theta, theta_t, S, M, q, c, tau_dev, ldz, Z);
+                    dim3(ncb, (unsigned)i, (unsigned)nmat), dim3(256), 0, s,
+                    d, i, theta, theta_t, S, M, q, c, tau_dev, ldz, Z);
   }
   return hipGetLastError();
 }
