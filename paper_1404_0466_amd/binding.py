@@ -16,7 +16,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpichol.so")
+# PICHOL_LIB selects another build of the library (e.g. for A/B timing).
+LIB_PATH = os.environ.get("PICHOL_LIB") or os.path.join(_HERE, "libpichol.so")
 
 PICHOL_OK = 0
 PICHOL_ERR_ARG = -1

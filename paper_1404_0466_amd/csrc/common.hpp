@@ -225,6 +225,60 @@ __device__ inline void invert_lower_lds(double* a, int tid) {
   inv_combine<64>(a, tid);
 }
 
+// Whole-tile transfers by a 256-thread workgroup.  A tile is 16384 doubles
+// (32-byte aligned); each thread moves sixteen 32-byte pieces, with eight
+// global loads in flight at a time so that their latencies overlap.
+__device__ inline void tile_to_lds(double* lds, const double* g, int tid) {
+#pragma unroll
+  for (int it = 0; it < 16; it += 8) {
+    v4d v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = ld4(g + ((it + u) * 256 + tid) * 4);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) *(v4d*)(lds + ((it + u) * 256 + tid) * 4) = v[u];
+  }
+}
+
+// Writes the lower triangle of a column-major LDS tile (zeros above the
+// diagonal) to global memory.
+__device__ inline void tile_lower_from_lds(double* g, const double* lds,
+                                           int tid) {
+#pragma unroll
+  for (int it = 0; it < 16; ++it) {
+    const int e = (it * 256 + tid) * 4;
+    const int r = e & (NB - 1), c = e >> 7;
+    v4d v = *(const v4d*)(lds + e);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (r + u < c) v[u] = 0.0;
+    st4(g + e, v);
+  }
+}
+
+// Evaluates sum_p w^p planes[p*S + e] for a whole tile into LDS (Horner-free
+// power sum in p order), eight 32-byte pieces per plane in flight.
+__device__ inline void tile_eval_to_lds(double* lds, const double* planes,
+                                        int64_t S, int M, double w, int tid) {
+#pragma unroll
+  for (int it = 0; it < 16; it += 8) {
+    v4d acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+    double pw = 1.0;
+    for (int p = 0; p < M; ++p) {
+      v4d v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = ld4(planes + p * S + ((it + u) * 256 + tid) * 4);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += pw * v[u];
+      pw *= w;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) *(v4d*)(lds + ((it + u) * 256 + tid) * 4) = acc[u];
+  }
+}
+
 // Lane coordinates inside a 64 x 64 wave block.
 struct LaneXY {
   int lq;  // l / 16

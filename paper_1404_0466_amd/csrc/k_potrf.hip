@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
   const int f = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double* tile = L + (int64_t)f * S + tile_off(kk, kk);
-  for (int e = tid; e < NB2; e += blockDim.x) a[e] = tile[e];
+  tile_to_lds(a, tile, tid);
   __syncthreads();
 
   for (int jb = 0; jb < 4; ++jb) {
@@ -146,18 +146,12 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
     __syncthreads();
   }
 
-  for (int e = tid; e < NB2; e += blockDim.x) {
-    const int r = e & (NB - 1), c = e >> 7;
-    tile[e] = (r >= c) ? a[e] : 0.0;
-  }
+  tile_lower_from_lds(tile, a, tid);
 
   __syncthreads();
   invert_lower_lds(a, tid);
   double* li = linv + (int64_t)f * NB2;
-  for (int e = tid; e < NB2; e += blockDim.x) {
-    const int r = e & (NB - 1), c = e >> 7;
-    li[e] = (r >= c) ? a[e] : 0.0;
-  }
+  tile_lower_from_lds(li, a, tid);
 }
 
 // Panel tile (I, kk), I > kk: X = A L_kk^{-T}, in place.  The wave computes

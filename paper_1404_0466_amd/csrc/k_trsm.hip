@@ -60,20 +60,32 @@ __global__ void __launch_bounds__(256) k_diag_solve(int64_t d, int i,
   const int tid = threadIdx.x;
   const int64_t dp = ntiles_of(d) * NB;
   const int64_t toff = tile_off(i, i);
-  if (src.exact) {
-    const double* p = src.base + (m * src.nper + t) * src.S + toff;
-    for (int e = tid; e < NB2; e += blockDim.x)
-      a[(e >> 7) * LDS_LD + (e & (NB - 1))] = p[e];
-  } else {
-    const double tv = src.tau[t];
-    const double* p = src.base + m * src.M * src.S + toff;
-    for (int e = tid; e < NB2; e += blockDim.x) {
-      double acc = 0.0, pw = 1.0;
-      for (int q = 0; q < src.M; ++q) {
-        acc += pw * p[q * src.S + e];
+  {
+    const double* p = src.exact ? src.base + (m * src.nper + t) * src.S + toff
+                                : src.base + m * src.M * src.S + toff;
+    const int M = src.exact ? 1 : src.M;
+    const double tv = src.exact ? 1.0 : src.tau[t];
+#pragma unroll
+    for (int it = 0; it < 16; it += 8) {
+      v4d acc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+      double pw = 1.0;
+      for (int q = 0; q < M; ++q) {
+        v4d v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = ld4(p + q * src.S + ((it + u) * 256 + tid) * 4);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += pw * v[u];
         pw *= tv;
       }
-      a[(e >> 7) * LDS_LD + (e & (NB - 1))] = acc;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = ((it + u) * 256 + tid) * 4;
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+          a[(e >> 7) * LDS_LD + ((e + x) & (NB - 1))] = acc[u][x];
+      }
     }
   }
   __syncthreads();
@@ -148,24 +160,19 @@ __global__ void __launch_bounds__(256) k_diag_inv(int64_t d, FactorSrc src,
   const int64_t m = blockIdx.z;
   const int nt = gridDim.x;
   const int tid = threadIdx.x;
-  const double tv = src.tau[t];
-  const double* p = src.base + m * src.M * src.S + tile_off(i, i);
-  for (int e = tid; e < NB2; e += blockDim.x) {
-    double acc = 0.0, pw = 1.0;
-    for (int q = 0; q < src.M; ++q) {
-      acc += pw * p[q * src.S + e];
-      pw *= tv;
-    }
-    a[e] = acc;
-  }
+  tile_eval_to_lds(a, src.base + m * src.M * src.S + tile_off(i, i), src.S,
+                   src.M, src.tau[t], tid);
   __syncthreads();
   if (tid < NB && (int64_t)i * NB + tid < d && !(a[tid * NB + tid] > 0.0))
     atomicOr(flags + m * src.nper + t, 2);
   invert_lower_lds(a, tid);
   const int64_t off = ((m * src.nper + t) * nt + i) * (int64_t)NB2;
-  for (int e = tid; e < NB2; e += blockDim.x) dinv[off + e] = a[e];
-  for (int e = tid; e < NB2; e += blockDim.x)
+  tile_lower_from_lds(dinv + off, a, tid);
+#pragma unroll 8
+  for (int it = 0; it < 64; ++it) {
+    const int e = it * 256 + tid;
     dinv_r[off + e] = a[(e & (NB - 1)) * NB + (e >> 7)];
+  }
 }
 
 // Diagonal block solve of tile row i by multiplication with the stored
@@ -230,14 +237,21 @@ __device__ inline void mma_panel_scaled(Acc64& acc, const double* a,
 // Off-diagonal update for interpolated factors.  Forward step i: rows of
 // tile I > i lose sum_p Theta_p(I,i) (tau^p .* U_i); backward step i: rows
 // of tile I < i lose sum_p Theta_p(i,I)^T (tau^p .* W_i), read from the
-// row-major copy of the planes.
+// row-major copy of the planes.  The accumulators start from the slab rows
+// being updated and the products are subtracted (negative scale).  Logical
+// workgroup ids run over the column blocks fastest, so the blocks that
+// share a coefficient tile meet on one XCD.
 template <bool FWD>
 __global__ void __launch_bounds__(256) k_update_interp(
     int64_t d, int i, const double* theta, const double* theta_t, int64_t S,
-    int M, int q, int c, const double* tau, int64_t ldz, double* Z) {
-  const int cb = blockIdx.x;
-  const int I = FWD ? i + 1 + (int)blockIdx.y : (int)blockIdx.y;
-  const int64_t m = blockIdx.z;
+    int M, int q, int c, const double* tau, int64_t ldz, int ncb, int nrows,
+    double* Z) {
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  const int cb = id % ncb;
+  const int rest = id / ncb;
+  const int row = rest % nrows;
+  const int64_t m = rest / nrows;
+  const int I = FWD ? i + 1 + row : row;
   const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
   const int64_t dp = ntiles_of(d) * NB;
   const LaneXY lx;
@@ -251,66 +265,76 @@ __global__ void __launch_bounds__(256) k_update_interp(
   const double* planes = FWD ? theta + m * M * S + tile_off(I, i)
                              : theta_t + m * M * S + tile_off(i, I);
   const double* bsrc = Z + (m * dp + (int64_t)i * NB) * ldz + cb * NB + wj * 64;
+  double* zt = Z + (m * dp + (int64_t)I * NB + wi * 64) * ldz + col;
   Acc64 acc;
-  acc.zero();
-  v4d scale = {1.0, 1.0, 1.0, 1.0};
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+      acc.set_row(v, bi, ld4(zt + (int64_t)lx.row(v, bi) * ldz));
+  v4d scale = {-1.0, -1.0, -1.0, -1.0};
   for (int p = 0; p < M; ++p) {
     mma_panel_scaled(acc, planes + p * S + wi * 64, NB, bsrc, ldz, NB, scale);
     scale *= tau4;
   }
-  double* zt = Z + (m * dp + (int64_t)I * NB) * ldz + col;
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
-      const int r = wi * 64 + lx.row(v, bi);
-      double* p = zt + (int64_t)r * ldz;
-      st4(p, ld4(p) - acc.row(v, bi));
-    }
+    for (int bi = 0; bi < 4; ++bi)
+      st4(zt + (int64_t)lx.row(v, bi) * ldz, acc.row(v, bi));
 }
 
 // Off-diagonal update for exact factors, one factor per lambda t:
 // forward rows of tile I > i lose L_t(I,i) U_i, backward rows of tile I < i
-// lose L_t(i,I)^T W_i.  The tile is staged in LDS with a padded leading
-// dimension so that both orientations read without bank conflicts.
+// lose L_t(i,I)^T W_i.  One thread per row of tile I, all c columns; the
+// 128 x c right-hand-side rows sit in LDS.  Forward reads L(r,k) at
+// k*128 + r (coalesced across rows); backward reads column r of the tile,
+// contiguous per thread.  Small workgroups keep many tiles in flight: the
+// kernel streams every factor tile once per step.
 template <bool FWD>
-__global__ void __launch_bounds__(256) k_update_factors(int64_t d, int i,
+__global__ void __launch_bounds__(128) k_update_factors(int64_t d, int i,
                                                         const double* L,
                                                         int64_t S, int nper,
                                                         int c, int64_t ldz,
                                                         double* Z) {
-  __shared__ double lt[NB * LDS_LD];
   __shared__ double zs[NB * 16];
   const int I = FWD ? i + 1 + (int)blockIdx.x : (int)blockIdx.x;
   const int t = blockIdx.y;
   const int64_t m = blockIdx.z;
-  const int tid = threadIdx.x;
+  const int row = threadIdx.x;
   const int64_t dp = ntiles_of(d) * NB;
   const double* tile = L + (m * nper + t) * S + (FWD ? tile_off(I, i) : tile_off(i, I));
-  for (int e = tid; e < NB2; e += blockDim.x)
-    lt[(e >> 7) * LDS_LD + (e & (NB - 1))] = tile[e];
   const double* zsrc = Z + (m * dp + (int64_t)i * NB) * ldz + (int64_t)t * c;
-  double* zdst = Z + (m * dp + (int64_t)I * NB) * ldz + (int64_t)t * c;
-  const int row = tid & (NB - 1), half = tid >> 7;
+  double* zdst = Z + (m * dp + (int64_t)I * NB + row) * ldz + (int64_t)t * c;
   for (int cg = 0; cg < c; cg += 16) {
     const int cn = (c - cg) < 16 ? (c - cg) : 16;
-    __syncthreads();
-    for (int e = tid; e < NB * 16; e += blockDim.x) {
+    if (cg) __syncthreads();
+    for (int e = row; e < NB * 16; e += NB) {
       const int k = e >> 4, cc = e & 15;
       zs[e] = cc < cn ? zsrc[(int64_t)k * ldz + cg + cc] : 0.0;
     }
     __syncthreads();
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < NB; ++k) {
-      const double lv = FWD ? lt[k * LDS_LD + row] : lt[row * LDS_LD + k];
+    double acc[16] = {};
+    if (FWD) {
+#pragma unroll 4
+      for (int k = 0; k < NB; ++k) {
+        const double lv = tile[k * NB + row];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] += lv * zs[k * 16 + half + 2 * u];
+        for (int u = 0; u < 16; ++u) acc[u] += lv * zs[k * 16 + u];
+      }
+    } else {
+      const double* colr = tile + row * NB;
+      for (int k0 = 0; k0 < NB; k0 += 4) {
+        const v4d lv = ld4(colr + k0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int u = 0; u < 16; ++u) acc[u] += lv[e] * zs[(k0 + e) * 16 + u];
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int cc = half + 2 * u;
-      if (cc < cn) zdst[(int64_t)row * ldz + cg + cc] -= acc[u];
-    }
+    for (int u = 0; u < 16; ++u)
+      if (u < cn) zdst[cg + u] -= acc[u];
   }
 }
 
@@ -345,19 +369,20 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
   for (int i = 0; i < nt; ++i) {
     PICHOL_LAUNCH(k_diag_apply, dim3((unsigned)q, (unsigned)nmat), dim3(256), 0,
                   s, d, i, q, c, dinv, ldz, Z);
-    if (i + 1 < nt)
-      PICHOL_LAUNCH(k_update_interp<true>,
-                    dim3(ncb, (unsigned)(nt - i - 1), (unsigned)nmat),
-                    dim3(256), 0, s, d, i, theta, theta_t, S, M, q, c,
-                    tau_dev, ldz, Z);
+    if (i + 1 < nt) {
+      const int nrows = nt - i - 1;
+      PICHOL_LAUNCH(k_update_interp<true>, dim3(ncb * nrows * nmat), dim3(256),
+                    0, s, d, i, theta, theta_t, S, M, q, c, tau_dev, ldz,
+                    (int)ncb, nrows, Z);
+    }
   }
   for (int i = nt - 1; i >= 0; --i) {
     PICHOL_LAUNCH(k_diag_apply, dim3((unsigned)q, (unsigned)nmat), dim3(256), 0,
                   s, d, i, q, c, dinv_r, ldz, Z);
     if (i > 0)
-      PICHOL_LAUNCH(k_update_interp<false>,
-                    dim3(ncb, (unsigned)i, (unsigned)nmat), dim3(256), 0, s,
-                    d, i, theta, theta_t, S, M, q, c, tau_dev, ldz, Z);
+      PICHOL_LAUNCH(k_update_interp<false>, dim3(ncb * i * nmat), dim3(256), 0,
+                    s, d, i, theta, theta_t, S, M, q, c, tau_dev, ldz,
+                    (int)ncb, i, Z);
   }
   return hipGetLastError();
 }
@@ -373,16 +398,16 @@ hipError_t launch_solve_factors(int64_t d, int nmat, int nper, int c,
                        dim3(256), 0, s, d, i, src, c, ldz, Z, flags);
     if (i + 1 < nt)
       PICHOL_LAUNCH(k_update_factors<true>,
-                         dim3((unsigned)(nt - i - 1), (unsigned)nper, (unsigned)nmat),
-                         dim3(256), 0, s, d, i, L, S, nper, c, ldz, Z);
+                    dim3((unsigned)(nt - i - 1), (unsigned)nper, (unsigned)nmat),
+                    dim3(128), 0, s, d, i, L, S, nper, c, ldz, Z);
   }
   for (int i = nt - 1; i >= 0; --i) {
     PICHOL_LAUNCH(k_diag_solve<false>, dim3((unsigned)nper, (unsigned)nmat),
                        dim3(256), 0, s, d, i, src, c, ldz, Z, flags);
     if (i > 0)
       PICHOL_LAUNCH(k_update_factors<false>,
-                         dim3((unsigned)i, (unsigned)nper, (unsigned)nmat),
-                         dim3(256), 0, s, d, i, L, S, nper, c, ldz, Z);
+                    dim3((unsigned)i, (unsigned)nper, (unsigned)nmat),
+                    dim3(128), 0, s, d, i, L, S, nper, c, ldz, Z);
   }
   return hipGetLastError();
 }
