@@ -14,7 +14,7 @@ namespace pichol {
 //     W(r, col) * ((G W)(r, col) - 2 C(r, col mod c))
 // for the 128 slab columns of block cb; written to
 // partial[m][I][col].
-__global__ void __launch_bounds__(256) k_holdout_partial(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_holdout_partial(
     int64_t d, int q, int c, int64_t ldz, const double* Z, const double* G,
     const double* C, double* partial) {
   __shared__ double red[64 * 2];

@@ -31,17 +31,28 @@ __global__ void __launch_bounds__(256) k_shift_copy(int64_t d, int64_t S,
   const double shift = lam[s];
   const double* h = H + m * S + tile_off(I, J);
   double* l = L + ms * S + tile_off(I, J);
-  for (int e = threadIdx.x; e < NB2; e += blockDim.x) {
-    const int64_t i = (int64_t)I * NB + (e & (NB - 1));
-    const int64_t j = (int64_t)J * NB + (e >> 7);
-    double v;
-    if (i >= d || j >= d)
-      v = (i == j) ? 1.0 : 0.0;
-    else if (i < j)
-      v = 0.0;
-    else
-      v = h[e] + (i == j ? shift : 0.0);
-    l[e] = v;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < 16; it += 8) {
+    v4d v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = ld4(h + ((it + u) * 256 + tid) * 4);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = ((it + u) * 256 + tid) * 4;
+      const int64_t j = (int64_t)J * NB + (e >> 7);
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int64_t i = (int64_t)I * NB + ((e + x) & (NB - 1));
+        if (i >= d || j >= d)
+          v[u][x] = (i == j) ? 1.0 : 0.0;
+        else if (i < j)
+          v[u][x] = 0.0;
+        else if (i == j)
+          v[u][x] += shift;
+      }
+      st4(l + e, v[u]);
+    }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) info[ms] = 0;
 }
@@ -157,7 +168,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
 // Panel tile (I, kk), I > kk: X = A L_kk^{-T}, in place.  The wave computes
 // D'(n,m) = sum_p Linv(n,p) A(m,p) = X(m,n), stored at n*128 + m.  Linv is
 // lower triangular, so the sum stops at the wave's last n.
-__global__ void __launch_bounds__(256) k_potrf_panel(int64_t S, int kk,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_potrf_panel(int64_t S, int kk,
                                                      double* L,
                                                      const double* linv) {
   const int f = blockIdx.y;
@@ -182,12 +193,13 @@ __global__ void __launch_bounds__(256) k_potrf_panel(int64_t S, int kk,
 
 // Trailing tile (I,J): A_IJ -= sum_{c in [c0,c1)} L_Ic L_Jc^T, for the
 // tiles of the triangle j0 <= J <= I, or of the single column J = j0.
-// The wave computes D'(n,m) = A_IJ(m,n) - sum_p L_Jc(n,p) L_Ic(m,p): the
-// accumulators start from the tile (its loads overlap the first operand
-// loads) and the products are subtracted, so the epilogue is a store.
-// Logical workgroup ids are laid out matrix by matrix and spread over the
-// XCDs in contiguous ranges.
-__global__ void __launch_bounds__(256) k_potrf_update(int64_t S, int j0,
+// The wave computes D'(n,m) = sum_p L_Jc(n,p) L_Ic(m,p) = update(m,n) and
+// subtracts it from the tile in its epilogue.  Two workgroups share a CU
+// (the register budget is capped for two waves per SIMD), so one's
+// read-modify-write epilogue overlaps the other's products.  Logical
+// workgroup ids are laid out matrix by matrix and spread over the XCDs in
+// contiguous ranges.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_potrf_update(int64_t S, int j0,
                                                       int column, int c0,
                                                       int c1, int ntile,
                                                       double* L) {
@@ -210,14 +222,10 @@ __global__ void __launch_bounds__(256) k_potrf_update(int64_t S, int j0,
   const LaneXY lx;
   const int m0 = wj * 64 + lx.col0();
   Acc64 acc;
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
-      acc.set_row(v, bi, ld4(ct + (wi * 64 + lx.row(v, bi)) * NB + m0));
+  acc.zero();
   for (int c = c0; c < c1; ++c)
-    mma_panel_sub(acc, Lf + tile_off(J, c) + wi * 64, NB,
-                  Lf + tile_off(I, c) + wj * 64, NB, NB);
+    mma_panel(acc, Lf + tile_off(J, c) + wi * 64, NB,
+              Lf + tile_off(I, c) + wj * 64, NB, NB);
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -226,11 +234,11 @@ __global__ void __launch_bounds__(256) k_potrf_update(int64_t S, int j0,
       double* p = ct + n * NB + m0;
       const v4d val = acc.row(v, bi);
       if (I != J || wi != wj) {
-        st4(p, val);
+        st4(p, ld4(p) - val);
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          if (m0 + e >= n) p[e] = val[e];
+          if (m0 + e >= n) p[e] -= val[e];
       }
     }
 }
