@@ -54,6 +54,24 @@ def update_flops(d: int, nfac: int) -> float:
     return tot
 
 
+def measured_traffic(exact: bool, lookahead: int):
+    """HBM bytes per launch of k_potrf_update from the committed rocprofv3
+    counter record (profiles/k_potrf_update_traffic.json), or None when the
+    kernel's sources changed since the counters were taken or this run's
+    launch mix differs from the profiled one."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_potrf_update_traffic.json")
+    if not os.path.exists(path) or not exact or lookahead != 0:
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in rec["source_files"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def gaps(cp, ce, lam):
     tp = int(np.argmin(np.where(np.isfinite(cp), cp, np.inf)))
     te = int(np.argmin(np.where(np.isfinite(ce), ce, np.inf)))
@@ -109,6 +127,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-kernel event pass (no roofline)")
+    ap.add_argument("--lookahead", type=int, default=0, choices=[0, 1],
+                    help="side-stream look-ahead in the factorizations")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="finish with one plain device copy of this many MiB "
                          "(reference dispatch for hardware byte counters)")
@@ -128,6 +148,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     B.load()
+    B.pichol_set_option(B.PICHOL_OPT_LOOKAHEAD, args.lookahead)
     dev = torch.device("cuda:0")
 
     log(f"generating workload {args.config}")
@@ -232,7 +253,8 @@ def main():
             roofline = {
                 "kernel": "k_potrf_update", "bound": "mfma",
                 "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": measured_traffic(not args.no_exact, args.lookahead),
                 "flops_per_launch": avg_flops, "avg_launch_ms": avg_ms,
                 "launches_per_step": per_step_launches,
             }
@@ -260,7 +282,7 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": prob.name, "n": n, "d": d, "c": c, "k": k, "g": g,
                    "r": r, "q": q, "lam_range": list(prob.meta.get("lam_range", [])),
-                   "kind": prob.meta.get("kind")},
+                   "kind": prob.meta.get("kind"), "lookahead": args.lookahead},
         **result_extra,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -305,6 +305,24 @@ const char *pichol_status_string(pichol_status s);
 /* Text of the last HIP error the library saw on this thread ("" if none). */
 const char *pichol_last_error(void);
 
+/* ---------------------------------------------------------------- options */
+
+typedef enum {
+  /* 0 (default) or 1.  When 1, the blocked factorizations run the bulk of
+   * each trailing update on a library-owned side stream (default priority,
+   * created with a few events on first use on each device), joined back to
+   * the caller's stream by events, so the next panels' diagonal
+   * factorizations overlap it.  Results are identical either way. */
+  PICHOL_OPT_LOOKAHEAD = 1
+} pichol_option;
+
+/* Set a process-wide option; PICHOL_ERR_ARG for an unknown option or
+ * value. */
+pichol_status pichol_set_option(int32_t option, int32_t value);
+
+/* Current value of an option, or -1 for an unknown option. */
+int32_t pichol_get_option(int32_t option);
+
 /* ------------------------------------------------------------- profiling */
 
 /* Per-kernel timing with HIP events, for benchmarks and tuning.  While

@@ -27,6 +27,7 @@ PICHOL_ERR_NOT_PD = -4
 PICHOL_ERR_DATA = -5
 PICHOL_METHOD_INTERP = 1
 PICHOL_METHOD_EXACT = 2
+PICHOL_OPT_LOOKAHEAD = 1
 NB = 128
 
 _lib = None
@@ -89,6 +90,8 @@ _SIGNATURES = {
     "pichol_exact_cv": (_i32, [_pprob, _vp, _vp, _vp, _vp, _sz, _vp, _vp, _vp,
                                _vp, _vp]),
     "pichol_check": (_i32, [_vp, _i64, _vp, _i64, _vp]),
+    "pichol_set_option": (_i32, [_i32, _i32]),
+    "pichol_get_option": (_i32, [_i32]),
     "pichol_profile_start": (_i32, [_i32]),
     "pichol_profile_stop": (_i32, []),
     "pichol_profile_summary": (_i32, [_i32, ctypes.POINTER(ctypes.c_char_p),
@@ -333,6 +336,16 @@ def pichol_check(info, n_info, flags, n_flags, stream=None) -> int:
     return int(load().pichol_check(_dev(info, _i32t()), n_info,
                                    _dev(flags, _i32t()), n_flags,
                                    _stream(stream)))
+
+
+# ------------------------------------------------------------------ options
+
+def pichol_set_option(option: int, value: int):
+    _check("pichol_set_option", load().pichol_set_option(option, value))
+
+
+def pichol_get_option(option: int) -> int:
+    return int(load().pichol_get_option(option))
 
 
 # ------------------------------------------------------------------ profiling

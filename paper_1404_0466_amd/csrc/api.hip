@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -29,6 +30,9 @@ static pichol_status hip_status(hipError_t e) {
 }
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static std::atomic<int> g_opt_lookahead{0};
+int option_lookahead() { return g_opt_lookahead.load(); }
 
 // ---------------------------------------------------------------- profiling
 struct ProfState {
@@ -247,6 +251,23 @@ const char* pichol_status_string(pichol_status s) {
 }
 
 const char* pichol_last_error(void) { return g_last_error.c_str(); }
+
+pichol_status pichol_set_option(int32_t option, int32_t value) {
+  switch (option) {
+    case PICHOL_OPT_LOOKAHEAD:
+      if (value != 0 && value != 1) return PICHOL_ERR_ARG;
+      g_opt_lookahead.store(value);
+      return PICHOL_OK;
+  }
+  return PICHOL_ERR_ARG;
+}
+
+int32_t pichol_get_option(int32_t option) {
+  switch (option) {
+    case PICHOL_OPT_LOOKAHEAD: return g_opt_lookahead.load();
+  }
+  return -1;
+}
 
 pichol_status pichol_profile_start(int32_t capacity) {
   if (capacity < 1) return PICHOL_ERR_ARG;

@@ -11,6 +11,8 @@
 //                     (FP64 MFMA, the bulk of the flops).
 // One launch of each kernel covers the whole batch, so a batch of B
 // matrices of order d fills the GPU with B * (trailing tiles) workgroups.
+#include <mutex>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -192,28 +194,34 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 }
 
 // Trailing tile (I,J): A_IJ -= sum_{c in [c0,c1)} L_Ic L_Jc^T, for the
-// tiles of the triangle j0 <= J <= I, or of the single column J = j0.
+// tiles of the triangle j0 <= J <= I (mode 0), of the column J = j0
+// (mode 1), or of the two columns J = j0, j0+1 (mode 2).
 // The wave computes D'(n,m) = sum_p L_Jc(n,p) L_Ic(m,p) = update(m,n) and
 // subtracts it from the tile in its epilogue.  Two workgroups share a CU
 // (the register budget is capped for two waves per SIMD), so one's
 // read-modify-write epilogue overlaps the other's products.  Logical
 // workgroup ids are laid out matrix by matrix and spread over the XCDs in
 // contiguous ranges.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_potrf_update(int64_t S, int j0,
-                                                      int column, int c0,
-                                                      int c1, int ntile,
-                                                      double* L) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_potrf_update(int64_t S, int nt, int j0, int mode, int c0, int c1, int ntile,
+               double* L) {
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int f = id / ntile;
   const int t = id - f * ntile;
   int I, J;
-  if (column) {  // tiles (j0 + t, j0)
-    I = j0 + t;
-    J = j0;
-  } else {       // tiles (I, J) with j0 <= J <= I
+  if (mode == 0) {
     const int r = tri_row(t);
     I = j0 + r;
     J = j0 + (t - (int)tri(r));
+  } else {
+    const int n1 = nt - j0;  // tiles of column j0
+    if (t < n1) {
+      I = j0 + t;
+      J = j0;
+    } else {
+      I = j0 + 1 + (t - n1);
+      J = j0 + 1;
+    }
   }
   const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
   if (I == J && wi > wj) return;  // block strictly above the diagonal
@@ -254,14 +262,45 @@ hipError_t launch_shift_copy(int64_t d, int nmat, const double* H, int nshift,
   return hipGetLastError();
 }
 
+// Side stream for look-ahead: created once per device on first use, with
+// the default priority, and a small ring of events.
+struct SideStream {
+  bool ready = false;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[8] = {};
+};
+static std::mutex g_side_mu;
+static SideStream g_side[64];
+
+static SideStream* side_stream() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  SideStream& ss = g_side[dev];
+  if (!ss.ready) {
+    if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) != hipSuccess)
+      return nullptr;
+    for (hipEvent_t& e : ss.ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+        return nullptr;
+    ss.ready = true;
+  }
+  return &ss;
+}
+
 // Panels are factored in pairs with a delayed update: after panel kk only
 // the next panel column is updated, panel kk+1 is factored, and the rest of
 // the trailing matrix receives both panels' contributions in one rank-256
-// update.  This halves the read-modify-write traffic of the trailing tiles.
+// update.  With the look-ahead option on, that update is split: the two
+// columns the next pair factors first stay on the caller's stream, the
+// remainder runs on a side stream, so the next pair's diagonal
+// factorizations and panel solves (short, latency-bound launches) overlap
+// the bulk of the update.
 hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
                                 double* linv_ws, hipStream_t s) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  SideStream* side = option_lookahead() ? side_stream() : nullptr;
   auto diag_panel = [&](int kk) {
     PICHOL_LAUNCH(k_potrf_diag, dim3((unsigned)nfac), dim3(256), 0, s, d, S,
                   kk, L, info, linv_ws);
@@ -270,20 +309,43 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
       PICHOL_LAUNCH(k_potrf_panel, dim3((unsigned)rest, (unsigned)nfac),
                     dim3(256), 0, s, S, kk, L, linv_ws);
   };
-  auto update = [&](int j0, int column, int c0, int c1) {
+  auto update = [&](hipStream_t st, int j0, int mode, int c0, int c1) {
     const int rest = nt - j0;
     if (rest <= 0) return;
-    const int ntile = column ? rest : (int)tri(rest);
-    PICHOL_LAUNCH(k_potrf_update, dim3((unsigned)(ntile * nfac)), dim3(256),
-                  0, s, S, j0, column, c0, c1, ntile, L);
+    const int ntile = mode == 0 ? (int)tri(rest)
+                                : (mode == 1 || rest == 1 ? rest : 2 * rest - 1);
+    const int m = (mode == 2 && rest == 1) ? 1 : mode;
+    PICHOL_LAUNCH(k_potrf_update, dim3((unsigned)(ntile * nfac)), dim3(256), 0,
+                  st, S, nt, j0, m, c0, c1, ntile, L);
   };
+  int ring = 0;
+  bool pending = false;  // a side-stream update not yet joined
+  hipEvent_t joined = nullptr;
   for (int kk = 0; kk < nt; kk += 2) {
     diag_panel(kk);
     if (kk + 1 >= nt) break;
-    update(kk + 1, 1, kk, kk + 1);   // next panel column only
+    update(s, kk + 1, 1, kk, kk + 1);  // next panel column only
     diag_panel(kk + 1);
-    update(kk + 2, 0, kk, kk + 2);   // the rest, rank 256
+    if (kk + 2 >= nt) break;
+    // columns kk+2, kk+3 also received the previous pair's remainder
+    if (pending) {
+      hipStreamWaitEvent(s, joined, 0);
+      pending = false;
+    }
+    if (side && kk + 4 < nt) {
+      hipEvent_t ready = side->ev[ring++ & 7];
+      hipEventRecord(ready, s);
+      update(s, kk + 2, 2, kk, kk + 2);
+      hipStreamWaitEvent(side->stream, ready, 0);
+      update(side->stream, kk + 4, 0, kk, kk + 2);
+      joined = side->ev[ring++ & 7];
+      hipEventRecord(joined, side->stream);
+      pending = true;
+    } else {
+      update(s, kk + 2, 0, kk, kk + 2);
+    }
   }
+  if (pending) hipStreamWaitEvent(s, joined, 0);
   return hipGetLastError();
 }
 

@@ -26,6 +26,9 @@ struct ProfScope {
   } while (0)
 
 hipError_t record_hip_error_code(hipError_t e);
+
+// Library options (pichol_set_option).
+int option_lookahead();
 inline int record_hip_error(hipError_t e) {
   record_hip_error_code(e);
   return -3;  // PICHOL_ERR_HIP

@@ -83,3 +83,15 @@ def test_workspace_size_and_argument_checks(lib):
 def test_status_strings(lib):
     for s in [0, -1, -2, -3, -4, -5]:
         assert lib.pichol_status_string(s)
+
+
+def test_options(lib):
+    assert B.pichol_get_option(B.PICHOL_OPT_LOOKAHEAD) == 0
+    B.pichol_set_option(B.PICHOL_OPT_LOOKAHEAD, 1)
+    assert B.pichol_get_option(B.PICHOL_OPT_LOOKAHEAD) == 1
+    B.pichol_set_option(B.PICHOL_OPT_LOOKAHEAD, 0)
+    with pytest.raises(B.PicholError):
+        B.pichol_set_option(B.PICHOL_OPT_LOOKAHEAD, 7)
+    with pytest.raises(B.PicholError):
+        B.pichol_set_option(99, 0)
+    assert B.pichol_get_option(99) == -1

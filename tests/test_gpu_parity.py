@@ -363,3 +363,23 @@ def test_argument_errors(gu):
         B.pichol_cv_interp(p, [0.1, 0.1, 0.3], [0.1] * 4, 0.3, w, nbytes, err, None, info,
                            flags)
     assert e.value.status == B.PICHOL_ERR_ARG
+
+
+@pytest.mark.parametrize("method", ["interp", "exact"])
+def test_cv_with_lookahead_matches_without(gu, method):
+    """The side-stream look-ahead schedule gives bitwise the same results
+    (same kernels, same per-tile accumulation order)."""
+    B = gu.B
+    p = workloads.rff_problem(2000, 700, 10, seed=6, g=5, q=12)
+    B.pichol_set_option(B.PICHOL_OPT_LOOKAHEAD, 0)
+    a = gu.cv(p, method)
+    B.pichol_set_option(B.PICHOL_OPT_LOOKAHEAD, 1)
+    try:
+        b = gu.cv(p, method)
+    finally:
+        B.pichol_set_option(B.PICHOL_OPT_LOOKAHEAD, 0)
+    np.testing.assert_array_equal(a["mse"], b["mse"])
+    np.testing.assert_array_equal(a["W"], b["W"])
+    want = (oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r) if method == "interp"
+            else oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid))
+    np.testing.assert_allclose(b["mse"], want["mse"], rtol=1e-10)
