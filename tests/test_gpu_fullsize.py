@@ -1,0 +1,73 @@
+"""Parity at the benchmark's full size: random Fourier features, n=60000,
+d=4096, c=10, k=5, g=6, r=2, q=64, in the launch configuration bench.py
+times (the pipeline calls through the C-ABI).
+
+The oracle cannot redo the whole job in a test's time, so the checks are
+(1) fold 0 of the interpolated cross-validation, which the oracle computes
+in full from that fold's Gram matrices (about 20 s on 16 cores), and
+(2) properties checked entry by entry on samples: Gram entries against
+their definition, and L L^T = H + lambda I for exact factors.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def big(gpu):
+    import gpu_util
+    prob = workloads.config(3)
+    return gpu_util, prob
+
+
+def test_fullsize_fold0_matches_oracle(big):
+    gu, p = big
+    got = gu.cv(p, "interp", want_W=False)
+    assert np.all(got["info"] == 0) and np.all(got["flags"] == 0)
+    nv = len(np.array_split(np.arange(p.n), p.k)[0])
+    Xt, Yt = p.X[nv:], p.Y[nv:]
+    H = Xt.T @ Xt / Xt.shape[0]
+    Bm = Xt.T @ Yt / Xt.shape[0]
+    want = oracle.fold_interp(H, Bm, p.X[:nv], p.Y[:nv], p.lam_s, p.lam_grid, p.r)
+    assert np.all(want["info"] == 0) and np.all(want["flags"] == 0)
+    np.testing.assert_allclose(got["mse"][0], want["mse"], rtol=1e-10, atol=0)
+
+
+def test_fullsize_gram_and_factor_properties(big):
+    gu, p = big
+    B = gu.B
+    n, d, c, k = p.n, p.d, p.c, p.k
+    g = gu.gram(p.X, p.Y, k)
+    rng = np.random.default_rng(0)
+    idx = rng.integers(0, d, size=(40, 2))
+    H = gu.unpack(g["H"], d, k)  # lower triangles
+    starts = np.concatenate([[0], np.cumsum(gu.fold_sizes(n, k))])
+    for f in [0, 3]:
+        mask = np.ones(n, bool)
+        mask[starts[f]:starts[f + 1]] = False
+        ntr = mask.sum()
+        for i, j in idx:
+            i, j = max(i, j), min(i, j)
+            want = np.dot(p.X[mask, i], p.X[mask, j]) / ntr
+            np.testing.assert_allclose(H[f][i, j], want, rtol=1e-12, atol=1e-15)
+    # exact factors of fold 1 at two grid values: L L^T = H + lambda I
+    lam = p.lam_grid[[0, 40]]
+    S = B.pichol_packed_elems(d)
+    Lp = gu.empty(2 * S)
+    info = gu.empty(2, torch.int32)
+    nb = B.pichol_potrf_workspace(1, 2)
+    Hf = g["H"][S:2 * S].contiguous()
+    B.pichol_potrf_shifted_batched(d, 1, Hf, 2, lam, Lp, info, gu.ws(nb), nb)
+    L = gu.unpack(Lp, d, 2)
+    assert np.all(info.cpu().numpy() == 0)
+    for s in range(2):
+        for i, j in idx:
+            i, j = max(i, j), min(i, j)
+            lhs = np.dot(L[s][i, :j + 1], L[s][j, :j + 1])
+            rhs = H[1][i, j] + (lam[s] if i == j else 0.0)
+            assert abs(lhs - rhs) <= 1e-12 * (abs(H[1][i, i]) + lam[s])
