@@ -115,6 +115,67 @@ def cpu_baseline(prob, gpu_err_fold0):
     }
 
 
+def mixed_leg(args, B, p, ws, nbytes, prob, ei64, ee64, stream):
+    """Time the piCholesky (and exact) stages with PICHOL_PREC_MIXED on the
+    resident Gram matrices and compare the hold-out errors with the FP64
+    run of the same step."""
+    import torch
+    k, q, g = prob.k, prob.q, prob.g
+    pm = B.make_problem(p.n, p.d, p.c, k, g, p.r, q, True,
+                        precision=B.PICHOL_PREC_MIXED)
+    dev = torch.device("cuda:0")
+    err_i = torch.empty(k * q, dtype=torch.float64, device=dev)
+    err_e = torch.empty(k * q, dtype=torch.float64, device=dev)
+    info_i = torch.empty(k * g, dtype=torch.int32, device=dev)
+    info_e = torch.empty(k * q, dtype=torch.int32, device=dev)
+    flags_i = torch.empty(k * q, dtype=torch.int32, device=dev)
+    flags_e = torch.empty(k * q, dtype=torch.int32, device=dev)
+    exact = ee64 is not None
+
+    def run(ev):
+        ev[0].record(stream)
+        B.pichol_cv_interp(pm, prob.lam_s, prob.lam_grid, prob.lam_ref, ws, nbytes,
+                           err_i, None, info_i, flags_i)
+        ev[1].record(stream)
+        if exact:
+            B.pichol_cv_exact(pm, prob.lam_grid, ws, nbytes, err_e, None, info_e,
+                              flags_e)
+        ev[2].record(stream)
+
+    log("mixed-precision leg")
+    for _ in range(args.warmup):
+        run([torch.cuda.Event(enable_timing=True) for _ in range(3)])
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)]
+           for _ in range(args.steps)]
+    for e in evs:
+        run(e)
+    torch.cuda.synchronize()
+    t_int = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    t_ex = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    ei = err_i.cpu().numpy().reshape(k, q)
+    out = {
+        "precision": "FP32-MFMA trailing updates, FP64 elsewhere",
+        "interp_ms": t_int, "value": k * q / (t_int * 1e-3),
+        "interp_ok": bool((info_i.cpu().numpy() == 0).all()
+                          and (flags_i.cpu().numpy() == 0).all()),
+        "max_rel_err_vs_fp64_interp": float(np.max(np.abs(ei - ei64) / ei64)),
+    }
+    log(f"mixed: interp {t_int:.2f} ms -> {out['value']:.1f} lambda-solves/s, "
+        f"max rel diff vs FP64 {out['max_rel_err_vs_fp64_interp']:.2e}")
+    if exact:
+        ee = err_e.cpu().numpy().reshape(k, q)
+        out.update({
+            "exact_ms": t_ex, "exact_value": k * q / (t_ex * 1e-3),
+            "exact_ok": bool((info_e.cpu().numpy() == 0).all()
+                             and (flags_e.cpu().numpy() == 0).all()),
+            "max_rel_err_vs_fp64_exact": float(np.max(np.abs(ee - ee64) / ee64)),
+            "err_gap_vs_fp64_exact": gaps(ei.mean(0), ee64.mean(0), prob.lam_grid),
+        })
+        log(f"mixed: exact {t_ex:.2f} ms, max rel diff vs FP64 "
+            f"{out['max_rel_err_vs_fp64_exact']:.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +190,9 @@ def main():
                     help="skip the per-kernel event pass (no roofline)")
     ap.add_argument("--lookahead", type=int, default=0, choices=[0, 1],
                     help="side-stream look-ahead in the factorizations")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision leg (FP32-MFMA trailing "
+                         "updates, timed after the FP64 headline)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="finish with one plain device copy of this many MiB "
                          "(reference dispatch for hardware byte counters)")
@@ -227,6 +291,11 @@ def main():
             "err_gap": gaps(ei.mean(0), ee.mean(0), lam_grid),
         })
 
+    mixed = None
+    if not args.no_mixed:
+        mixed = mixed_leg(args, B, p, ws, nbytes, prob, ei,
+                          None if args.no_exact else ee, stream)
+
     roofline = None
     kernels = None
     if not args.no_profile:
@@ -284,6 +353,7 @@ def main():
                    "r": r, "q": q, "lam_range": list(prob.meta.get("lam_range", [])),
                    "kind": prob.meta.get("kind"), "lookahead": args.lookahead},
         **result_extra,
+        "mixed": mixed,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

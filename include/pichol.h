@@ -27,7 +27,8 @@
  *               bit1 = a diagonal entry of the (interpolated) factor is <= 0.
  *  - Results are bitwise reproducible from run to run (no floating-point
  *    atomics; every reduction has a fixed order).
- *  - All arithmetic is IEEE FP64.
+ *  - All arithmetic is IEEE FP64, except where a call is asked for
+ *    PICHOL_PREC_MIXED (below).
  *
  * Folds: k contiguous folds; fold f holds rows [start_f, start_{f+1}) with
  * sizes as numpy.array_split (the first n mod k folds get one extra row).
@@ -76,6 +77,22 @@ typedef enum {
   PICHOL_METHOD_EXACT = 2   /* one exact factorization per grid value       */
 } pichol_method;
 
+/* Arithmetic of the factorizations (Sec. 3.2; Algorithm 1 step 1).
+ *   PICHOL_PREC_FP64   everything in FP64 (FP64 MFMA).
+ *   PICHOL_PREC_MIXED  the trailing updates of the blocked factorization,
+ *                      which hold all but O(d^2 * 128) of its d^3/3 flops,
+ *                      take their products on FP32 MFMA: factor entries are
+ *                      rounded to FP32 as they are read and each 256-term
+ *                      product is accumulated in FP32, then subtracted from
+ *                      the FP64 trailing matrix.  Diagonal blocks, panels,
+ *                      the fit, the solves and the hold-out errors stay FP64.
+ *                      The factors then satisfy L L^T = H + lam I + E with
+ *                      |E_ij| of the order of 1e-7 * sum_p |L_ip L_jp|. */
+typedef enum {
+  PICHOL_PREC_FP64 = 0,
+  PICHOL_PREC_MIXED = 1
+} pichol_precision;
+
 /* Problem description shared by the pipeline calls.
  *   n, d, c   rows of X, features, right-hand sides (label columns);
  *             n >= k, d >= 1, 1 <= c
@@ -84,12 +101,14 @@ typedef enum {
  *             r <= 7), dense grid size (q >= 1)
  *   normalize 1: H_f = X_tr^T X_tr / n_tr and B_f = X_tr^T Y_tr / n_tr;
  *             0: no division (the paper's X^T X, X^T y)
+ *   precision a pichol_precision value for the factorizations
  *   ldx, ldy  row-major leading dimensions of X (n x d) and Y (n x c),
  *             ldx >= d, ldy >= c                                            */
 typedef struct {
   int64_t n, d, c;
   int32_t k, g, r, q;
   int32_t normalize;
+  int32_t precision;
   int64_t ldx, ldy;
 } pichol_problem;
 
@@ -144,12 +163,13 @@ size_t pichol_potrf_workspace(int32_t nmat, int32_t nshift);
  *      first d rows/columns, lower triangular with positive diagonal;
  *      info nmat*nshift (device, int32), see the conventions above.
  * Blocked right-looking algorithm on 128-wide panels; the trailing updates
- * run on FP64 MFMA.  ws: pichol_potrf_workspace(nmat, nshift) bytes. */
+ * run on FP64 MFMA, or on FP32 MFMA when precision is PICHOL_PREC_MIXED.
+ * ws: pichol_potrf_workspace(nmat, nshift) bytes. */
 pichol_status pichol_potrf_shifted_batched(int64_t d, int32_t nmat,
                                            const double *H, int32_t nshift,
                                            const double *lam, double *L,
                                            int32_t *info, void *ws,
-                                           size_t ws_bytes,
+                                           size_t ws_bytes, int32_t precision,
                                            hipStream_t stream);
 
 /* Least-squares polynomial fit of every factor entry (Algorithm 1 steps

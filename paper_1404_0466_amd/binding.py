@@ -28,6 +28,8 @@ PICHOL_ERR_DATA = -5
 PICHOL_METHOD_INTERP = 1
 PICHOL_METHOD_EXACT = 2
 PICHOL_OPT_LOOKAHEAD = 1
+PICHOL_PREC_FP64 = 0
+PICHOL_PREC_MIXED = 1
 NB = 128
 
 _lib = None
@@ -45,6 +47,7 @@ class Problem(ctypes.Structure):
                 ("c", ctypes.c_int64), ("k", ctypes.c_int32),
                 ("g", ctypes.c_int32), ("r", ctypes.c_int32),
                 ("q", ctypes.c_int32), ("normalize", ctypes.c_int32),
+                ("precision", ctypes.c_int32),
                 ("ldx", ctypes.c_int64), ("ldy", ctypes.c_int64)]
 
 
@@ -64,7 +67,7 @@ _SIGNATURES = {
     "pichol_gram": (_i32, [_pprob, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pichol_potrf_workspace": (_sz, [_i32, _i32]),
     "pichol_potrf_shifted_batched": (_i32, [_i64, _i32, _vp, _i32, _vp, _vp,
-                                            _vp, _vp, _sz, _vp]),
+                                            _vp, _vp, _sz, _i32, _vp]),
     "pichol_fit": (_i32, [_i64, _i32, _i32, _i32, _vp, _dbl, _vp, _vp, _vp,
                           _vp]),
     "pichol_lambda_workspace": (_sz, [_i32]),
@@ -198,8 +201,8 @@ def pichol_unpack(d, nmat, P, A, lda, stream=None):
 # ------------------------------------------------------------------ steps
 
 def make_problem(n, d, c, k, g=1, r=0, q=1, normalize=True, ldx=None,
-                 ldy=None) -> Problem:
-    return Problem(n, d, c, k, g, r, q, int(bool(normalize)),
+                 ldy=None, precision=PICHOL_PREC_FP64) -> Problem:
+    return Problem(n, d, c, k, g, r, q, int(bool(normalize)), int(precision),
                    d if ldx is None else ldx, c if ldy is None else ldy)
 
 
@@ -215,11 +218,13 @@ def pichol_potrf_workspace(nmat: int, nshift: int) -> int:
 
 
 def pichol_potrf_shifted_batched(d, nmat, H, nshift, lam, L, info, ws,
-                                 ws_bytes, stream=None):
+                                 ws_bytes, precision=PICHOL_PREC_FP64,
+                                 stream=None):
     lam_h = _Host(lam, np.float64)
     _check("pichol_potrf_shifted_batched", load().pichol_potrf_shifted_batched(
         d, nmat, _dev(H, _f64()), nshift, lam_h.ptr, _dev(L, _f64()),
-        _dev(info, _i32t()), _dev(ws), ws_bytes, _stream(stream)))
+        _dev(info, _i32t()), _dev(ws), ws_bytes, int(precision),
+        _stream(stream)))
 
 
 def pichol_fit(d, nmat, g, r, lam_s, lam_ref, L, theta, theta_t, stream=None):

@@ -127,10 +127,15 @@ static bool fold_split(int64_t n, int k, int normalize, FoldSplit* fs) {
   return true;
 }
 
+static bool precision_ok(int32_t precision) {
+  return precision == PICHOL_PREC_FP64 || precision == PICHOL_PREC_MIXED;
+}
+
 static bool problem_ok(const pichol_problem* p) {
   return p && p->n >= 1 && p->d >= 1 && p->c >= 1 && p->k >= 2 && p->k <= 64 &&
          p->n >= p->k && p->ldx >= p->d && p->ldy >= p->c && p->q >= 1 &&
-         p->g >= 1 && p->g <= 32 && p->r >= 0 && p->r <= 7 && p->r < p->g;
+         p->g >= 1 && p->g <= 32 && p->r >= 0 && p->r <= 7 && p->r < p->g &&
+         precision_ok(p->precision);
 }
 
 static bool samples_ok(const double* lam, int g) {
@@ -365,9 +370,10 @@ pichol_status pichol_potrf_shifted_batched(int64_t d, int32_t nmat,
                                            const double* H, int32_t nshift,
                                            const double* lam, double* L,
                                            int32_t* info, void* ws,
-                                           size_t ws_bytes,
+                                           size_t ws_bytes, int32_t precision,
                                            hipStream_t stream) {
-  if (d < 1 || nmat < 1 || nshift < 1 || !H || !lam || !L || !info)
+  if (d < 1 || nmat < 1 || nshift < 1 || !H || !lam || !L || !info ||
+      !precision_ok(precision))
     return PICHOL_ERR_ARG;
   for (int s = 0; s < nshift; ++s)
     if (!isfinite(lam[s])) return PICHOL_ERR_ARG;
@@ -379,7 +385,9 @@ pichol_status pichol_potrf_shifted_batched(int64_t d, int32_t nmat,
   if (e != hipSuccess) return hip_status(e);
   e = launch_shift_copy(d, nmat, H, nshift, lam_dev, L, info, stream);
   if (e != hipSuccess) return hip_status(e);
-  return hip_status(launch_potrf_blocked(d, nmat * nshift, L, info, linv, stream));
+  return hip_status(launch_potrf_blocked(d, nmat * nshift, L, info, linv,
+                                         precision == PICHOL_PREC_MIXED,
+                                         stream));
 }
 
 pichol_status pichol_fit(int64_t d, int32_t nmat, int32_t g, int32_t r,
@@ -554,7 +562,7 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
                           stream);
   if (e == hipSuccess)
     e = launch_potrf_blocked(p->d, k * g, Lf, info, at<double>(ws, L.i_linv),
-                             stream);
+                             p->precision == PICHOL_PREC_MIXED, stream);
   if (e == hipSuccess) e = launch_fit(p->d, k, fc, Lf, th, tht, stream);
   if (e == hipSuccess)
     e = launch_slab_init(p->d, k, q, c, L.ldz, at<double>(ws, L.B), Z, flags,
@@ -594,7 +602,7 @@ pichol_status pichol_cv_exact(const pichol_problem* p, const double* lam_grid,
                           stream);
   if (e == hipSuccess)
     e = launch_potrf_blocked(p->d, k * q, Lf, info, at<double>(ws, L.e_linv),
-                             stream);
+                             p->precision == PICHOL_PREC_MIXED, stream);
   if (e == hipSuccess)
     e = launch_slab_init(p->d, k, q, c, L.ldz, at<double>(ws, L.B), Z, flags,
                          stream);

@@ -14,6 +14,7 @@ constexpr int LDS_LD = NB + 1;   // padded leading dimension of LDS tiles
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 __host__ __device__ inline int64_t tri(int64_t I) { return I * (I + 1) / 2; }
 
@@ -61,6 +62,11 @@ __device__ inline void st4(double* p, v4d v) { *(v4d*)p = v; }
 // epilogue writes them with one 32-byte store.
 // ---------------------------------------------------------------------------
 struct Acc64 {
+  // Global row (within the 64-row block) of accumulator element v of block
+  // bi for a lane with l/16 = lq: element v holds D[4v + l/16][l%16].
+  __device__ static inline int row_of(int lq, int v, int bi) {
+    return 16 * v + 4 * lq + bi;
+  }
   v4d c[4][4];
   __device__ inline void zero() {
 #pragma unroll
@@ -105,6 +111,59 @@ __device__ inline void mma_panel(Acc64& acc, const double* a, int64_t lda,
     bv = bn;
   }
   acc.mma(av, bv);
+}
+
+// The same 64 x 64 wave block on FP32 MFMA.  v_mfma_f32_16x16x4f32 takes
+// its operands in the lane layout of the FP64 instruction, but element v of
+// lane l holds D[4(l/16) + v][l%16] (four consecutive rows per lane), so
+// the global row of (v, bi) is 16(l/16) + 4v + bi.  FP64 operands are
+// rounded to FP32 as they are loaded, products accumulate in FP32, and rows
+// are handed back in FP64.
+struct Acc64F {
+  __device__ static inline int row_of(int lq, int v, int bi) {
+    return 16 * lq + 4 * v + bi;
+  }
+  v4f c[4][4];
+  __device__ inline void zero() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) c[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+  __device__ inline void mma(const v4f& a, const v4f& b) {
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj)
+        c[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[bi], b[bj],
+                                                          c[bi][bj], 0, 0, 0);
+  }
+  __device__ inline v4d row(int v, int bi) const {
+    return v4d{(double)c[bi][0][v], (double)c[bi][1][v], (double)c[bi][2][v],
+               (double)c[bi][3][v]};
+  }
+};
+
+__device__ inline v4f to_f32(const v4d& x) {
+  return v4f{(float)x[0], (float)x[1], (float)x[2], (float)x[3]};
+}
+
+__device__ inline void mma_panel_f32(Acc64F& acc, const double* a, int64_t lda,
+                                     const double* b, int64_t ldb, int K) {
+  const int l = threadIdx.x & 63;
+  const double* pa = a + (int64_t)(l >> 4) * lda + 4 * (l & 15);
+  const double* pb = b + (int64_t)(l >> 4) * ldb + 4 * (l & 15);
+  const int64_t sa = 4 * lda, sb = 4 * ldb;
+  v4d av = ld4(pa), bv = ld4(pb);
+  for (int k0 = 4; k0 < K; k0 += 4) {
+    pa += sa;
+    pb += sb;
+    v4d an = ld4(pa), bn = ld4(pb);
+    acc.mma(to_f32(av), to_f32(bv));
+    av = an;
+    bv = bn;
+  }
+  acc.mma(to_f32(av), to_f32(bv));
 }
 
 // acc -= sum over k in [0,K) of A'(i,k) B'(k,j) (the A operand negated).

@@ -193,6 +193,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
     }
 }
 
+__device__ inline void mma_any(Acc64& acc, const double* a, int64_t lda,
+                               const double* b, int64_t ldb, int K) {
+  mma_panel(acc, a, lda, b, ldb, K);
+}
+__device__ inline void mma_any(Acc64F& acc, const double* a, int64_t lda,
+                               const double* b, int64_t ldb, int K) {
+  mma_panel_f32(acc, a, lda, b, ldb, K);
+}
+
 // Trailing tile (I,J): A_IJ -= sum_{c in [c0,c1)} L_Ic L_Jc^T, for the
 // tiles of the triangle j0 <= J <= I (mode 0), of the column J = j0
 // (mode 1), or of the two columns J = j0, j0+1 (mode 2).
@@ -202,8 +211,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 // read-modify-write epilogue overlaps the other's products.  Logical
 // workgroup ids are laid out matrix by matrix and spread over the XCDs in
 // contiguous ranges.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_potrf_update(int64_t S, int nt, int j0, int mode, int c0, int c1, int ntile,
+template <typename ACC>
+__device__ inline void potrf_update_body(int64_t S, int nt, int j0, int mode, int c0, int c1, int ntile,
                double* L) {
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int f = id / ntile;
@@ -229,16 +238,16 @@ k_potrf_update(int64_t S, int nt, int j0, int mode, int c0, int c1, int ntile,
   double* ct = Lf + tile_off(I, J);
   const LaneXY lx;
   const int m0 = wj * 64 + lx.col0();
-  Acc64 acc;
+  ACC acc;
   acc.zero();
   for (int c = c0; c < c1; ++c)
-    mma_panel(acc, Lf + tile_off(J, c) + wi * 64, NB,
-              Lf + tile_off(I, c) + wj * 64, NB, NB);
+    mma_any(acc, Lf + tile_off(J, c) + wi * 64, NB,
+            Lf + tile_off(I, c) + wj * 64, NB, NB);
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi) {
-      const int n = wi * 64 + lx.row(v, bi);
+      const int n = wi * 64 + ACC::row_of(lx.lq, v, bi);
       double* p = ct + n * NB + m0;
       const v4d val = acc.row(v, bi);
       if (I != J || wi != wj) {
@@ -260,6 +269,21 @@ hipError_t launch_shift_copy(int64_t d, int nmat, const double* H, int nshift,
                      dim3(256), 0, s, d, packed_elems_of(d), H, nshift,
                      lam_dev, L, info);
   return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_potrf_update(int64_t S, int nt, int j0, int mode, int c0, int c1, int ntile,
+               double* L) {
+  potrf_update_body<Acc64>(S, nt, j0, mode, c0, c1, ntile, L);
+}
+
+// Mixed precision: the same update with the products on FP32 MFMA (operands
+// rounded to FP32, FP32 accumulation over the 256-long sums); the tile
+// itself stays FP64.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_potrf_update_f32(int64_t S, int nt, int j0, int mode, int c0, int c1,
+                   int ntile, double* L) {
+  potrf_update_body<Acc64F>(S, nt, j0, mode, c0, c1, ntile, L);
 }
 
 // Side stream for look-ahead: created once per device on first use, with
@@ -296,7 +320,7 @@ static SideStream* side_stream() {
 // factorizations and panel solves (short, latency-bound launches) overlap
 // the bulk of the update.
 hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
-                                double* linv_ws, hipStream_t s) {
+                                double* linv_ws, int mixed, hipStream_t s) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
   std::lock_guard<std::mutex> lk(g_side_mu);
@@ -315,8 +339,12 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
     const int ntile = mode == 0 ? (int)tri(rest)
                                 : (mode == 1 || rest == 1 ? rest : 2 * rest - 1);
     const int m = (mode == 2 && rest == 1) ? 1 : mode;
-    PICHOL_LAUNCH(k_potrf_update, dim3((unsigned)(ntile * nfac)), dim3(256), 0,
-                  st, S, nt, j0, m, c0, c1, ntile, L);
+    if (mixed)
+      PICHOL_LAUNCH(k_potrf_update_f32, dim3((unsigned)(ntile * nfac)),
+                    dim3(256), 0, st, S, nt, j0, m, c0, c1, ntile, L);
+    else
+      PICHOL_LAUNCH(k_potrf_update, dim3((unsigned)(ntile * nfac)), dim3(256),
+                    0, st, S, nt, j0, m, c0, c1, ntile, L);
   };
   int ring = 0;
   bool pending = false;  // a side-stream update not yet joined

@@ -61,7 +61,7 @@ hipError_t launch_shift_copy(int64_t d, int nmat, const double* H, int nshift,
                              const double* lam_dev, double* L, int* info,
                              hipStream_t s);
 hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
-                                double* linv_ws, hipStream_t s);
+                                double* linv_ws, int mixed, hipStream_t s);
 
 // ---- fit / evaluate (k_fit.hip)
 struct FitCoef {

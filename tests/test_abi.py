@@ -67,7 +67,7 @@ def test_workspace_size_and_argument_checks(lib):
     S = B.pichol_packed_elems(4096)
     assert wi > 5 * 6 * S * 8 and we > 5 * 64 * S * 8
     for bad in [dict(r=6, g=6), dict(k=1), dict(k=65), dict(g=33), dict(r=8, g=9),
-                dict(q=0)]:
+                dict(q=0), dict(precision=2), dict(precision=-1)]:
         kw = dict(g=6, r=2, q=64, k=5)
         kw.update(bad)
         k = kw.pop("k")
@@ -78,6 +78,14 @@ def test_workspace_size_and_argument_checks(lib):
     p = B.make_problem(100, 10, 2, 5, g=3, r=2, q=4, ldx=9)  # ldx < d
     with pytest.raises(B.PicholError):
         B.pichol_workspace_size(p, B.PICHOL_METHOD_EXACT)
+
+
+def test_problem_struct_layout():
+    # int64 n, d, c; int32 k, g, r, q, normalize, precision; int64 ldx, ldy
+    assert ctypes.sizeof(B.Problem) == 3 * 8 + 6 * 4 + 2 * 8
+    assert B.Problem.ldx.offset == 48
+    p = B.make_problem(10, 3, 2, 2, precision=B.PICHOL_PREC_MIXED)
+    assert p.precision == 1 and p.ldx == 3 and p.ldy == 2
 
 
 def test_status_strings(lib):
