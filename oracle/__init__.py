@@ -81,14 +81,16 @@ def _load():
         "orc_holdout_sse": (_dbl, [_i64, _i64, _i64, _pd, _i64, _pd, _i64,
                                    _pd]),
         "orc_holdout_sst": (_dbl, [_i64, _i64, _pd, _i64]),
+        "orc_refine": (_i32, [_i64, _i64, _pd, _dbl, _pd, _pd, _pd, _i32]),
         "orc_cv_exact": (_i32, [_i64, _i64, _i64, _i32, _i32, ctypes.c_int,
-                                _pd, _pd, _pd, _pd, _pd, _pd, _pi32, _pi32]),
+                                _pd, _pd, _pd, _pd, _pd, _pd, _pi32, _pi32,
+                                _i32]),
         "orc_cv_interp": (_i32, [_i64, _i64, _i64, _i32, _i32, _i32, _i32,
                                  ctypes.c_int, _pd, _pd, _pd, _pd, _dbl, _pd,
-                                 _pd, _pd, _pd, _pi32, _pi32]),
+                                 _pd, _pd, _pd, _pi32, _pi32, _i32]),
         "orc_fold_interp": (_i32, [_i64, _i64, _i32, _i32, _i32, _pd, _pd,
                                    _i64, _pd, _i64, _pd, _i64, _pd, _pd, _dbl,
-                                   _pd, _pd, _pi32, _pi32]),
+                                   _pd, _pd, _pi32, _pi32, _i32]),
         "orc_num_threads": (_i32, []),
     }
     for name, (res, args) in sig.items():
@@ -230,9 +232,26 @@ def holdout_sst(Yv) -> float:
 
 # ---------------------------------------------------------------- pipelines
 
+def refine(H, lam: float, L, B, W, steps: int):
+    """Iterative refinement of (H + lam I) W = B with the factor L: returns
+    the refined copy of W and the OR of the correction solves' flags."""
+    H = _f64(H)
+    L = _f64(L)
+    B = _f64(B)
+    Wr = np.array(W, dtype=np.float64, copy=True, order="C")
+    if B.ndim == 1:
+        B = B[:, None].copy()
+        Wr = Wr.reshape(-1, 1)
+    d, c = B.shape
+    fl = _load().orc_refine(d, c, _p(H), float(lam), _p(L), _p(B), _p(Wr),
+                            int(steps))
+    return Wr.reshape(np.shape(W)), int(fl)
+
+
 def cv_exact(X, Y, k: int, lam_grid, normalize: bool = True,
-             want_W: bool = False) -> dict:
-    """k-fold CV with an exact Cholesky factorization at every grid value."""
+             want_W: bool = False, refine: int = 0) -> dict:
+    """k-fold CV with an exact Cholesky factorization at every grid value
+    (then `refine` steps of iterative refinement per solve)."""
     X = _f64(X)
     Y = _f64(Y)
     if Y.ndim == 1:
@@ -248,7 +267,7 @@ def cv_exact(X, Y, k: int, lam_grid, normalize: bool = True,
     flags = np.zeros((k, q), dtype=np.int32)
     rc = _load().orc_cv_exact(n, d, c, k, q, int(normalize), _p(X), _p(Y),
                               _p(lam_grid), _p(mse), _p(sse), _p(W),
-                              _p(info), _p(flags))
+                              _p(info), _p(flags), int(refine))
     if rc != 0:
         raise ValueError("oracle cv_exact rejected its arguments")
     return {"mse": mse, "sse": sse, "W": W, "info": info, "flags": flags}
@@ -256,9 +275,12 @@ def cv_exact(X, Y, k: int, lam_grid, normalize: bool = True,
 
 def cv_interp(X, Y, k: int, lam_s, lam_grid, r: int, lam_ref: float | None = None,
               normalize: bool = True, want_W: bool = False,
-              want_theta: bool = False) -> dict:
+              want_theta: bool = False, refine: int = 0) -> dict:
     """k-fold CV with piCholesky: Algorithm 1 on each fold, evaluation at
-    every grid value, then the same solves and hold-out errors."""
+    every grid value, then the same solves and hold-out errors.  With
+    refine > 0, that many steps of iterative refinement against
+    H_f + lambda_t I follow each solve (the interpolated factor serves as
+    the preconditioner)."""
     X = _f64(X)
     Y = _f64(Y)
     if Y.ndim == 1:
@@ -281,7 +303,7 @@ def cv_interp(X, Y, k: int, lam_s, lam_grid, r: int, lam_ref: float | None = Non
     rc = _load().orc_cv_interp(n, d, c, k, g, r, q, int(normalize), _p(X),
                                _p(Y), _p(lam_s), _p(lam_grid), float(lam_ref),
                                _p(mse), _p(sse), _p(W), _p(Theta), _p(info),
-                               _p(flags))
+                               _p(flags), int(refine))
     if rc != 0:
         raise ValueError("oracle cv_interp rejected its arguments")
     return {"mse": mse, "sse": sse, "W": W, "theta": Theta, "info": info,
@@ -289,8 +311,10 @@ def cv_interp(X, Y, k: int, lam_s, lam_grid, r: int, lam_ref: float | None = Non
 
 
 def fold_interp(H, B, Xv, Yv, lam_s, lam_grid, r: int,
-                lam_ref: float | None = None, want_W: bool = False) -> dict:
-    """The per-fold piCholesky path starting from that fold's H_f and B_f."""
+                lam_ref: float | None = None, want_W: bool = False,
+                refine: int = 0) -> dict:
+    """The per-fold piCholesky path starting from that fold's H_f (both
+    triangles) and B_f."""
     H = _f64(H)
     B = _f64(B)
     Xv = _f64(Xv)
@@ -315,7 +339,7 @@ def fold_interp(H, B, Xv, Yv, lam_s, lam_grid, r: int,
     rc = _load().orc_fold_interp(d, c, g, r, q, _p(H), _p(B), nv, _p(Xv), d,
                                  _p(Yv), c, _p(lam_s), _p(lam_grid),
                                  float(lam_ref), _p(mse), _p(W), _p(info),
-                                 _p(flags))
+                                 _p(flags), int(refine))
     if rc != 0:
         raise ValueError("oracle fold_interp rejected its arguments")
     return {"mse": mse, "W": W, "info": info, "flags": flags}

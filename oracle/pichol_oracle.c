@@ -213,6 +213,28 @@ int32_t orc_solve(int64_t d, int64_t c, const double *L, const double *B,
   return flags;
 }
 
+int32_t orc_refine(int64_t d, int64_t c, const double *H, double lam,
+                   const double *L, const double *B, double *W,
+                   int32_t steps) {
+  int32_t flags = 0;
+  double *R = (double *)malloc(sizeof(double) * (size_t)(d * c));
+  double *D = (double *)malloc(sizeof(double) * (size_t)(d * c));
+  for (int32_t it = 0; it < steps; ++it) {
+    for (int64_t i = 0; i < d; ++i)
+      for (int64_t cc = 0; cc < c; ++cc) {
+        double acc = 0.0; /* ((H + lam I) W)_{i,cc} */
+        for (int64_t p = 0; p < d; ++p) acc += H[i * d + p] * W[p * c + cc];
+        acc += lam * W[i * c + cc];
+        R[i * c + cc] = B[i * c + cc] - acc;
+      }
+    flags |= orc_solve(d, c, L, R, D);
+    for (int64_t e = 0; e < d * c; ++e) W[e] += D[e];
+  }
+  free(R);
+  free(D);
+  return flags;
+}
+
 /* Hold-out residual R = Y_v - X_v W and its sum of squares. */
 double orc_holdout_sse(int64_t nv, int64_t d, int64_t c, const double *Xv,
                        int64_t ldx, const double *Yv, int64_t ldy,
@@ -244,14 +266,17 @@ double orc_holdout_sst(int64_t nv, int64_t c, const double *Yv, int64_t ldy) {
   return sst;
 }
 
-/* One (fold, lambda) unit downstream of a factor: solve, then hold-out. */
+/* One (fold, lambda) unit downstream of a factor: solve (then `refine`
+ * steps of refinement against H + lam I), then hold-out. */
 static void unit_solve_holdout(int64_t d, int64_t c, const double *L,
-                               const double *B, int64_t nv, const double *Xv,
+                               const double *B, const double *H, double lam,
+                               int32_t refine, int64_t nv, const double *Xv,
                                int64_t ldx, const double *Yv, int64_t ldy,
                                double *Wout, double *mse, double *sse,
                                int32_t *flags) {
   double *W = Wout ? Wout : (double *)malloc(sizeof(double) * (size_t)(d * c));
   int32_t fl = orc_solve(d, c, L, B, W);
+  if (refine > 0) fl |= orc_refine(d, c, H, lam, L, B, W, refine);
   double s = orc_holdout_sse(nv, d, c, Xv, ldx, Yv, ldy, W);
   if (!isfinite(s)) fl |= 1;
   *flags = fl;
@@ -263,8 +288,9 @@ static void unit_solve_holdout(int64_t d, int64_t c, const double *L,
 int32_t orc_cv_exact(int64_t n, int64_t d, int64_t c, int32_t k, int32_t q,
                      int normalize, const double *X, const double *Y,
                      const double *lam_grid, double *mse, double *sse,
-                     double *W, int32_t *info, int32_t *flags) {
-  if (n < k || k < 2 || d < 1 || c < 1 || q < 1) return -1;
+                     double *W, int32_t *info, int32_t *flags,
+                     int32_t refine) {
+  if (n < k || k < 2 || d < 1 || c < 1 || q < 1 || refine < 0) return -1;
   int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k + 1));
   orc_fold_bounds(n, k, start);
   double *H = (double *)malloc(sizeof(double) * (size_t)(d * d));
@@ -287,8 +313,8 @@ int32_t orc_cv_exact(int64_t n, int64_t d, int64_t c, int32_t k, int32_t q,
         if (sse) sse[u] = NAN;
         flags[u] = 1;
       } else {
-        unit_solve_holdout(d, c, L, B, nv, Xv, d, Yv, c, Wt, &mse[u],
-                           sse ? &sse[u] : NULL, &flags[u]);
+        unit_solve_holdout(d, c, L, B, H, lam_grid[t], refine, nv, Xv, d, Yv,
+                           c, Wt, &mse[u], sse ? &sse[u] : NULL, &flags[u]);
       }
       free(L);
     }
@@ -304,7 +330,9 @@ int32_t orc_fold_interp(int64_t d, int64_t c, int32_t g, int32_t r, int32_t q,
                         const double *Xv, int64_t ldx, const double *Yv,
                         int64_t ldy, const double *lam_s,
                         const double *lam_grid, double lam_ref, double *mse,
-                        double *W, int32_t *info, int32_t *flags) {
+                        double *W, int32_t *info, int32_t *flags,
+                        int32_t refine) {
+  if (refine < 0) return -1;
   int64_t D = d * (d + 1) / 2;
   double *T = (double *)malloc(sizeof(double) * (size_t)(g * D));
   double *Theta = (double *)malloc(sizeof(double) * (size_t)((r + 1) * D));
@@ -331,8 +359,8 @@ int32_t orc_fold_interp(int64_t d, int64_t c, int32_t g, int32_t r, int32_t q,
     double *L = (double *)malloc(sizeof(double) * (size_t)(d * d));
     orc_eval(D, r, Theta, lam_grid[t], lam_ref, lt);
     orc_unpack_lower(d, lt, L);
-    unit_solve_holdout(d, c, L, B, nv, Xv, ldx, Yv, ldy,
-                       W ? W + (int64_t)t * d * c : NULL, &mse[t], NULL,
+    unit_solve_holdout(d, c, L, B, H, lam_grid[t], refine, nv, Xv, ldx, Yv,
+                       ldy, W ? W + (int64_t)t * d * c : NULL, &mse[t], NULL,
                        &flags[t]);
     free(L);
     free(lt);
@@ -346,9 +374,9 @@ int32_t orc_cv_interp(int64_t n, int64_t d, int64_t c, int32_t k, int32_t g,
                       const double *Y, const double *lam_s,
                       const double *lam_grid, double lam_ref, double *mse,
                       double *sse, double *W, double *Theta_out, int32_t *info,
-                      int32_t *flags) {
+                      int32_t *flags, int32_t refine) {
   if (n < k || k < 2 || d < 1 || c < 1 || q < 1 || r < 0 || g <= r ||
-      !(lam_ref > 0.0))
+      !(lam_ref > 0.0) || refine < 0)
     return -1;
   int64_t D = d * (d + 1) / 2;
   int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k + 1));
@@ -386,8 +414,8 @@ int32_t orc_cv_interp(int64_t n, int64_t d, int64_t c, int32_t k, int32_t g,
       double *L = (double *)malloc(sizeof(double) * (size_t)(d * d));
       orc_eval(D, r, Theta, lam_grid[t], lam_ref, lt);
       orc_unpack_lower(d, lt, L);
-      unit_solve_holdout(d, c, L, B, nv, Xv, d, Yv, c,
-                         W ? W + u * d * c : NULL, &mse[u],
+      unit_solve_holdout(d, c, L, B, H, lam_grid[t], refine, nv, Xv, d, Yv,
+                         c, W ? W + u * d * c : NULL, &mse[u],
                          sse ? &sse[u] : NULL, &flags[u]);
       free(L);
       free(lt);

@@ -87,6 +87,21 @@ double orc_holdout_sse(int64_t nv, int64_t d, int64_t c, const double *Xv,
  * means (the denominator of the normalised RMSE). */
 double orc_holdout_sst(int64_t nv, int64_t c, const double *Yv, int64_t ldy);
 
+/* Iterative refinement of the solution of (H + lam I) W = B (the classic
+ * residual-correction method, e.g. Higham, "Accuracy and Stability of
+ * Numerical Algorithms", ch. 12), reusing the factor L of the first solve:
+ * `steps` times, R = B - (H + lam I) W (FP64, row by row, terms in
+ * increasing column order), then W += the solution of L L^T D = R
+ * (orc_solve).  H: d x d symmetric (both triangles); L: d x d lower;
+ * B, W: d x c.  With an exact factor the corrections are rounding-sized;
+ * with an approximate one (an interpolated factor, a lower-precision one)
+ * W converges to (H + lam I)^{-1} B when the spectral radius of
+ * I - (L L^T)^{-1}(H + lam I) is below one.  Returns orc_solve's flags
+ * OR-ed over the correction solves. */
+int32_t orc_refine(int64_t d, int64_t c, const double *H, double lam,
+                   const double *L, const double *B, double *W,
+                   int32_t steps);
+
 /* Whole k-fold cross-validation, exact Cholesky at every grid value
  * (Sec. 3.2 and the exact baseline of Sec. 6.2).
  *   mse   k x q   sum(R^2)/(n_v c)
@@ -94,23 +109,27 @@ double orc_holdout_sst(int64_t nv, int64_t c, const double *Yv, int64_t ldy);
  *   W     k x q x d x c solutions               (may be NULL)
  *   info  k x q
  *   flags k x q
+ * refine >= 0 steps of orc_refine follow every solve.
  * Returns 0, or -1 on invalid arguments. */
 int32_t orc_cv_exact(int64_t n, int64_t d, int64_t c, int32_t k, int32_t q,
                      int normalize, const double *X, const double *Y,
                      const double *lam_grid, double *mse, double *sse,
-                     double *W, int32_t *info, int32_t *flags);
+                     double *W, int32_t *info, int32_t *flags,
+                     int32_t refine);
 
 /* Whole k-fold cross-validation with piCholesky (Algorithm 1 followed by
  * evaluation at every grid value and the same solves):
  *   info  k x g (one per sample factorization)
  *   flags k x q
- * Theta (k x (r+1) x D, may be NULL) receives the fitted coefficients. */
+ * Theta (k x (r+1) x D, may be NULL) receives the fitted coefficients.
+ * refine >= 0 steps of orc_refine against H_f + lambda_t I follow every
+ * solve, with the interpolated factor as the preconditioner. */
 int32_t orc_cv_interp(int64_t n, int64_t d, int64_t c, int32_t k, int32_t g,
                       int32_t r, int32_t q, int normalize, const double *X,
                       const double *Y, const double *lam_s,
                       const double *lam_grid, double lam_ref, double *mse,
                       double *sse, double *W, double *Theta, int32_t *info,
-                      int32_t *flags);
+                      int32_t *flags, int32_t refine);
 
 /* The per-fold part of orc_cv_interp starting from that fold's H_f, B_f and
  * validation rows (used to time one fold without the Gram step).
@@ -120,7 +139,8 @@ int32_t orc_fold_interp(int64_t d, int64_t c, int32_t g, int32_t r, int32_t q,
                         const double *Xv, int64_t ldx, const double *Yv,
                         int64_t ldy, const double *lam_s,
                         const double *lam_grid, double lam_ref, double *mse,
-                        double *W, int32_t *info, int32_t *flags);
+                        double *W, int32_t *info, int32_t *flags,
+                        int32_t refine);
 
 /* Number of OpenMP threads the oracle runs with. */
 int32_t orc_num_threads(void);

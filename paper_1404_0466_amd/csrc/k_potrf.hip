@@ -279,8 +279,9 @@ k_potrf_update(int64_t S, int nt, int j0, int mode, int c0, int c1, int ntile,
 
 // Mixed precision: the same update with the products on FP32 MFMA (operands
 // rounded to FP32, FP32 accumulation over the 256-long sums); the tile
-// itself stays FP64.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+// itself stays FP64.  FP32 accumulators take half the registers, so four
+// workgroups share a CU (measured faster than two at d = 4096).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_potrf_update_f32(int64_t S, int nt, int j0, int mode, int c0, int c1,
                    int ntile, double* L) {
   potrf_update_body<Acc64F>(S, nt, j0, mode, c0, c1, ntile, L);

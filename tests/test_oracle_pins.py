@@ -394,3 +394,82 @@ def test_cholesky_derivative_matches_frechet_form():
     Gamma = L @ Phi
     np.testing.assert_allclose(Gamma @ L.T + L @ Gamma.T, np.eye(7), atol=1e-12)
     np.testing.assert_allclose(fd, Gamma, rtol=0, atol=1e-8)
+
+
+# ------------------------------------------------------------------ iterative refinement
+
+def _perturbed_factor(H, lam, rel, seed):
+    L, info = oracle.cholesky(H, lam)
+    assert info == 0
+    rng = np.random.default_rng(seed)
+    return np.tril(L * (1.0 + rel * rng.standard_normal(L.shape)))
+
+
+@pytest.mark.parametrize("lam", [1e-3, 0.3])
+def test_refine_converges_to_lapack_solution(lam):
+    """Residual correction with an approximate factor converges
+    geometrically to the LAPACK solution of (H + lam I) W = B; a wrong
+    sign of the shift or a transposed product would stall it."""
+    d, c = 45, 3
+    H = spd(d, 7, cond=50.0)
+    rng = np.random.default_rng(8)
+    B = rng.standard_normal((d, c))
+    Lp = _perturbed_factor(H, lam, 1e-2, 9)
+    W0, fl = oracle.solve(Lp, B)
+    assert fl == 0
+    want = scipy.linalg.solve(H + lam * np.eye(d), B, assume_a="pos")
+    errs = []
+    for m in [0, 1, 2, 3, 12]:
+        W, fl = oracle.refine(H, lam, Lp, B, W0, m)
+        assert fl == 0
+        errs.append(np.max(np.abs(W - want)) / np.max(np.abs(want)))
+    assert errs[0] > 1e-3
+    for a, b in zip(errs[:3], errs[1:4]):
+        assert b < 0.3 * a
+    assert errs[-1] < 1e-12
+
+
+def test_refine_with_exact_factor_only_moves_by_rounding():
+    d, c, lam = 30, 2, 0.1
+    H = spd(d, 3)
+    B = np.random.default_rng(4).standard_normal((d, c))
+    L, _ = oracle.cholesky(H, lam)
+    W0, _ = oracle.solve(L, B)
+    W1, fl = oracle.refine(H, lam, L, B, W0, 3)
+    assert fl == 0
+    assert np.max(np.abs(W1 - W0)) <= 100 * EPS * np.max(np.abs(W0)) * 50.0
+    W2, _ = oracle.refine(H, lam, L, B, W0, 0)
+    np.testing.assert_array_equal(W2, W0)
+
+
+def test_refined_interp_cv_converges_to_exact_cv():
+    """Refinement against H_f + lambda_t I pulls the interpolated solutions
+    to the exact ones: after enough steps piCholesky CV equals exact CV."""
+    p = workloads.gaussian_problem(300, 24, 3, seed=6, g=4, q=9)
+    ex = oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid, want_W=True)
+    pi0 = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r, want_W=True)
+    pi2 = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r, want_W=True,
+                           refine=2)
+    # the worst grid value of this problem contracts by about 0.27 per step
+    pi30 = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r, want_W=True,
+                            refine=30)
+    scale = np.abs(ex["W"]).max()
+    e0 = np.abs(pi0["W"] - ex["W"]).max() / scale
+    e2 = np.abs(pi2["W"] - ex["W"]).max() / scale
+    e30 = np.abs(pi30["W"] - ex["W"]).max() / scale
+    assert e0 > 1e-3 and e2 < 0.1 * e0 and e30 < 1e-12
+    np.testing.assert_allclose(pi30["mse"], ex["mse"], rtol=1e-11)
+    # exact factors: refinement changes the hold-out errors only by rounding
+    ex2 = oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid, refine=2)
+    np.testing.assert_allclose(ex2["mse"], ex["mse"], rtol=1e-12)
+
+
+def test_refined_fold_interp_matches_cv_interp():
+    p = workloads.gaussian_problem(250, 20, 3, seed=2, g=4, q=9)
+    full = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r, want_W=True,
+                            refine=2)
+    b = oracle.fold_bounds(p.n, p.k)
+    H, B, _ = oracle.fold_gram(p.X, p.Y, p.k, 1)
+    one = oracle.fold_interp(H, B, p.X[b[1]:b[2]], p.Y[b[1]:b[2]], p.lam_s,
+                             p.lam_grid, p.r, want_W=True, refine=2)
+    np.testing.assert_array_equal(one["mse"], full["mse"][1])
