@@ -115,14 +115,16 @@ def cpu_baseline(prob, gpu_err_fold0):
     }
 
 
-def mixed_leg(args, B, p, ws, nbytes, prob, ei64, ee64, stream):
-    """Time the piCholesky (and exact) stages with PICHOL_PREC_MIXED on the
-    resident Gram matrices and compare the hold-out errors with the FP64
-    run of the same step."""
+def variant_leg(args, B, p, ws, nbytes, prob, ei64, ee64, stream, precision,
+                refine):
+    """Time the piCholesky (and exact) stages with another precision and/or
+    refinement count on the resident Gram matrices, and compare the hold-out
+    errors with the FP64 run of the same step (FP64 interpolated and FP64
+    exact)."""
     import torch
     k, q, g = prob.k, prob.q, prob.g
-    pm = B.make_problem(p.n, p.d, p.c, k, g, p.r, q, True,
-                        precision=B.PICHOL_PREC_MIXED)
+    pm = B.make_problem(p.n, p.d, p.c, k, g, p.r, q, True, precision=precision,
+                        refine=refine)
     dev = torch.device("cuda:0")
     err_i = torch.empty(k * q, dtype=torch.float64, device=dev)
     err_e = torch.empty(k * q, dtype=torch.float64, device=dev)
@@ -142,7 +144,8 @@ def mixed_leg(args, B, p, ws, nbytes, prob, ei64, ee64, stream):
                               flags_e)
         ev[2].record(stream)
 
-    log("mixed-precision leg")
+    name = ("mixed" if precision else "fp64") + f", refine={refine}"
+    log(f"leg {name}")
     for _ in range(args.warmup):
         run([torch.cuda.Event(enable_timing=True) for _ in range(3)])
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -154,25 +157,30 @@ def mixed_leg(args, B, p, ws, nbytes, prob, ei64, ee64, stream):
     t_ex = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     ei = err_i.cpu().numpy().reshape(k, q)
     out = {
-        "precision": "FP32-MFMA trailing updates, FP64 elsewhere",
+        "precision": ("FP32-MFMA trailing updates, FP64 elsewhere" if precision
+                      else "FP64"),
+        "refine": refine,
         "interp_ms": t_int, "value": k * q / (t_int * 1e-3),
         "interp_ok": bool((info_i.cpu().numpy() == 0).all()
                           and (flags_i.cpu().numpy() == 0).all()),
-        "max_rel_err_vs_fp64_interp": float(np.max(np.abs(ei - ei64) / ei64)),
+        "interp_max_rel_err_vs_fp64_interp": float(np.max(np.abs(ei - ei64) / ei64)),
     }
-    log(f"mixed: interp {t_int:.2f} ms -> {out['value']:.1f} lambda-solves/s, "
-        f"max rel diff vs FP64 {out['max_rel_err_vs_fp64_interp']:.2e}")
+    msg = (f"{name}: interp {t_int:.2f} ms -> {out['value']:.1f} lambda-solves/s, "
+           f"max rel diff vs FP64 interp {out['interp_max_rel_err_vs_fp64_interp']:.2e}")
     if exact:
         ee = err_e.cpu().numpy().reshape(k, q)
         out.update({
+            "interp_max_rel_err_vs_fp64_exact": float(np.max(np.abs(ei - ee64) / ee64)),
             "exact_ms": t_ex, "exact_value": k * q / (t_ex * 1e-3),
             "exact_ok": bool((info_e.cpu().numpy() == 0).all()
                              and (flags_e.cpu().numpy() == 0).all()),
-            "max_rel_err_vs_fp64_exact": float(np.max(np.abs(ee - ee64) / ee64)),
+            "exact_max_rel_err_vs_fp64_exact": float(np.max(np.abs(ee - ee64) / ee64)),
             "err_gap_vs_fp64_exact": gaps(ei.mean(0), ee64.mean(0), prob.lam_grid),
         })
-        log(f"mixed: exact {t_ex:.2f} ms, max rel diff vs FP64 "
-            f"{out['max_rel_err_vs_fp64_exact']:.2e}")
+        msg += (f"; vs FP64 exact {out['interp_max_rel_err_vs_fp64_exact']:.2e}; "
+                f"exact {t_ex:.2f} ms, max rel diff vs FP64 exact "
+                f"{out['exact_max_rel_err_vs_fp64_exact']:.2e}")
+    log(msg)
     return out
 
 
@@ -190,9 +198,12 @@ def main():
                     help="skip the per-kernel event pass (no roofline)")
     ap.add_argument("--lookahead", type=int, default=0, choices=[0, 1],
                     help="side-stream look-ahead in the factorizations")
-    ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the mixed-precision leg (FP32-MFMA trailing "
-                         "updates, timed after the FP64 headline)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the precision-form legs timed after the FP64 "
+                         "headline (FP32-MFMA trailing updates, iterative "
+                         "refinement)")
+    ap.add_argument("--refine", type=int, default=2,
+                    help="refinement steps of the refined legs")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="finish with one plain device copy of this many MiB "
                          "(reference dispatch for hardware byte counters)")
@@ -226,7 +237,10 @@ def main():
     Y = torch.from_numpy(prob.Y).to(dev)
     p = B.make_problem(n, d, c, k, g, r, q, True)
     methods = B.PICHOL_METHOD_INTERP | (0 if args.no_exact else B.PICHOL_METHOD_EXACT)
-    nbytes = B.pichol_workspace_size(p, methods)
+    # sized for the refined legs too (their scratch is appended at the end)
+    p_ws = B.make_problem(n, d, c, k, g, r, q, True,
+                          refine=0 if args.no_variants else args.refine)
+    nbytes = B.pichol_workspace_size(p_ws, methods)
     log(f"workspace {nbytes / 2**30:.2f} GiB")
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     err_i = torch.empty(k * q, dtype=torch.float64, device=dev)
@@ -291,10 +305,19 @@ def main():
             "err_gap": gaps(ei.mean(0), ee.mean(0), lam_grid),
         })
 
-    mixed = None
-    if not args.no_mixed:
-        mixed = mixed_leg(args, B, p, ws, nbytes, prob, ei,
-                          None if args.no_exact else ee, stream)
+    variants = None
+    if not args.no_variants:
+        ee64 = None if args.no_exact else ee
+        variants = {
+            "mixed": variant_leg(args, B, p, ws, nbytes, prob, ei, ee64, stream,
+                                 B.PICHOL_PREC_MIXED, 0),
+            f"mixed_refine{args.refine}": variant_leg(
+                args, B, p, ws, nbytes, prob, ei, ee64, stream,
+                B.PICHOL_PREC_MIXED, args.refine),
+            f"fp64_refine{args.refine}": variant_leg(
+                args, B, p, ws, nbytes, prob, ei, ee64, stream,
+                B.PICHOL_PREC_FP64, args.refine),
+        }
 
     roofline = None
     kernels = None
@@ -353,7 +376,7 @@ def main():
                    "r": r, "q": q, "lam_range": list(prob.meta.get("lam_range", [])),
                    "kind": prob.meta.get("kind"), "lookahead": args.lookahead},
         **result_extra,
-        "mixed": mixed,
+        "precision_forms": variants,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

@@ -102,6 +102,20 @@ typedef enum {
  *   normalize 1: H_f = X_tr^T X_tr / n_tr and B_f = X_tr^T Y_tr / n_tr;
  *             0: no division (the paper's X^T X, X^T y)
  *   precision a pichol_precision value for the factorizations
+ *   refine    0 .. PICHOL_MAX_REFINE steps of iterative refinement after
+ *             the solves of the pipeline calls (pichol_cv_interp,
+ *             pichol_cv_exact): R_t = B_f - (H_f + lambda_t I) W_t in FP64
+ *             (H_f from the fold Gram blocks), then W_t += the solution of
+ *             L L^T D = R_t with the same factor L (interpolated or
+ *             exact).  With exact factors this recovers FP64 accuracy
+ *             after a mixed-precision factorization.  With interpolated
+ *             factors it moves W_t toward the exact ridge solution at
+ *             lambda_t, i.e. toward exact cross-validation, converging
+ *             where the interpolated factor is a close enough
+ *             preconditioner (spectral radius of
+ *             I - (Lhat Lhat^T)^{-1}(H_f + lambda_t I) below one).  Each
+ *             step costs one residual product (2 d^2 q c flops per fold)
+ *             and one pair of triangular solves.
  *   ldx, ldy  row-major leading dimensions of X (n x d) and Y (n x c),
  *             ldx >= d, ldy >= c                                            */
 typedef struct {
@@ -109,8 +123,11 @@ typedef struct {
   int32_t k, g, r, q;
   int32_t normalize;
   int32_t precision;
+  int32_t refine;
   int64_t ldx, ldy;
 } pichol_problem;
+
+#define PICHOL_MAX_REFINE 16
 
 /* ---------------------------------------------------------------- layout */
 

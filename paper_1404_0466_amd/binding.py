@@ -30,6 +30,7 @@ PICHOL_METHOD_EXACT = 2
 PICHOL_OPT_LOOKAHEAD = 1
 PICHOL_PREC_FP64 = 0
 PICHOL_PREC_MIXED = 1
+PICHOL_MAX_REFINE = 16
 NB = 128
 
 _lib = None
@@ -47,7 +48,7 @@ class Problem(ctypes.Structure):
                 ("c", ctypes.c_int64), ("k", ctypes.c_int32),
                 ("g", ctypes.c_int32), ("r", ctypes.c_int32),
                 ("q", ctypes.c_int32), ("normalize", ctypes.c_int32),
-                ("precision", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("ldx", ctypes.c_int64), ("ldy", ctypes.c_int64)]
 
 
@@ -201,9 +202,10 @@ def pichol_unpack(d, nmat, P, A, lda, stream=None):
 # ------------------------------------------------------------------ steps
 
 def make_problem(n, d, c, k, g=1, r=0, q=1, normalize=True, ldx=None,
-                 ldy=None, precision=PICHOL_PREC_FP64) -> Problem:
+                 ldy=None, precision=PICHOL_PREC_FP64, refine=0) -> Problem:
     return Problem(n, d, c, k, g, r, q, int(bool(normalize)), int(precision),
-                   d if ldx is None else ldx, c if ldy is None else ldy)
+                   int(refine), d if ldx is None else ldx,
+                   c if ldy is None else ldy)
 
 
 def pichol_gram(p: Problem, X, Y, G, C, yy, H, B, stream=None):

@@ -135,7 +135,8 @@ static bool problem_ok(const pichol_problem* p) {
   return p && p->n >= 1 && p->d >= 1 && p->c >= 1 && p->k >= 2 && p->k <= 64 &&
          p->n >= p->k && p->ldx >= p->d && p->ldy >= p->c && p->q >= 1 &&
          p->g >= 1 && p->g <= 32 && p->r >= 0 && p->r <= 7 && p->r < p->g &&
-         precision_ok(p->precision);
+         precision_ok(p->precision) && p->refine >= 0 &&
+         p->refine <= PICHOL_MAX_REFINE;
 }
 
 static bool samples_ok(const double* lam, int g) {
@@ -177,6 +178,9 @@ struct Layout {
       i_end;
   // exact region
   size_t e_lam, e_L, e_linv, e_Z, e_part, e_end;
+  // refinement scratch (full-tile H_f and the correction slab), appended to
+  // each method's region when refine > 0
+  size_t i_rH, i_rZ, i_lamg, e_rH, e_rZ;
 };
 
 static Layout layout_of(const pichol_problem* p) {
@@ -206,6 +210,11 @@ static Layout layout_of(const pichol_problem* p) {
   L.i_part = a; a += align256(k * L.nt * L.ldz * dbl);
   L.i_dinv = a; a += align256(k * q * L.nt * NB2 * dbl);
   L.i_dinvr = a; a += align256(k * q * L.nt * NB2 * dbl);
+  L.i_lamg = a; a += align256(q * dbl);
+  const size_t rH = p->refine > 0 ? align256(k * L.dp * L.dp * dbl) : 0;
+  const size_t rZ = p->refine > 0 ? align256(k * L.dp * L.ldz * dbl) : 0;
+  L.i_rH = a; a += rH;
+  L.i_rZ = a; a += rZ;
   L.i_end = a;
   a = o;
   L.e_lam = a; a += align256(q * dbl);
@@ -213,6 +222,8 @@ static Layout layout_of(const pichol_problem* p) {
   L.e_linv = a; a += align256(k * q * NB2 * dbl);
   L.e_Z = a; a += align256(k * L.dp * L.ldz * dbl);
   L.e_part = a; a += align256(k * L.nt * L.ldz * dbl);
+  L.e_rH = a; a += rH;
+  L.e_rZ = a; a += rZ;
   L.e_end = a;
   return L;
 }
@@ -454,7 +465,7 @@ pichol_status pichol_solve_interp(int64_t d, int32_t nmat, int32_t c, int32_t r,
   if (e == hipSuccess) e = launch_slab_init(d, nmat, q, c, ldz, B, Z, flags, stream);
   if (e == hipSuccess)
     e = launch_solve_interp(d, nmat, c, r + 1, theta, theta_t, q, tau, ldz, Z,
-                            flags, dinv, dinv_r, stream);
+                            flags, dinv, dinv_r, 1, stream);
   return hip_status(e);
 }
 
@@ -570,7 +581,27 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
   if (e == hipSuccess)
     e = launch_solve_interp(p->d, k, c, M, th, tht, q, tau, L.ldz, Z, flags,
                             at<double>(ws, L.i_dinv), at<double>(ws, L.i_dinvr),
-                            stream);
+                            1, stream);
+  if (e == hipSuccess && p->refine > 0) {
+    // Residual correction against H_f + lambda_t I; the correction solves
+    // reuse the inverted diagonal blocks of the interpolated factors.
+    double* Hf = at<double>(ws, L.i_rH);
+    double* D = at<double>(ws, L.i_rZ);
+    double* lamg = at<double>(ws, L.i_lamg);
+    FoldSplit fs;
+    fold_split(p->n, p->k, p->normalize, &fs);
+    e = launch_store_doubles(lam_grid, q, lamg, stream);
+    if (e == hipSuccess) e = launch_full_h(p->d, fs, at<double>(ws, L.G), Hf, stream);
+    for (int it = 0; it < p->refine && e == hipSuccess; ++it) {
+      e = launch_residual(p->d, k, q, c, L.ldz, Hf, at<double>(ws, L.B), lamg,
+                          Z, D, stream);
+      if (e == hipSuccess)
+        e = launch_solve_interp(p->d, k, c, M, th, tht, q, tau, L.ldz, D,
+                                flags, at<double>(ws, L.i_dinv),
+                                at<double>(ws, L.i_dinvr), 0, stream);
+      if (e == hipSuccess) e = launch_slab_add(p->d, k, L.ldz, D, Z, stream);
+    }
+  }
   if (e == hipSuccess)
     e = launch_holdout(p->d, k, c, q, L.ldz, Z, at<double>(ws, L.G),
                        at<double>(ws, L.C), at<double>(ws, L.yy), hn,
@@ -608,6 +639,20 @@ pichol_status pichol_cv_exact(const pichol_problem* p, const double* lam_grid,
                          stream);
   if (e == hipSuccess)
     e = launch_solve_factors(p->d, k, q, c, Lf, L.ldz, Z, flags, stream);
+  if (e == hipSuccess && p->refine > 0) {
+    double* Hf = at<double>(ws, L.e_rH);
+    double* D = at<double>(ws, L.e_rZ);
+    FoldSplit fs;
+    fold_split(p->n, p->k, p->normalize, &fs);
+    e = launch_full_h(p->d, fs, at<double>(ws, L.G), Hf, stream);
+    for (int it = 0; it < p->refine && e == hipSuccess; ++it) {
+      e = launch_residual(p->d, k, q, c, L.ldz, Hf, at<double>(ws, L.B),
+                          lam_dev, Z, D, stream);
+      if (e == hipSuccess)
+        e = launch_solve_factors(p->d, k, q, c, Lf, L.ldz, D, flags, stream);
+      if (e == hipSuccess) e = launch_slab_add(p->d, k, L.ldz, D, Z, stream);
+    }
+  }
   if (e == hipSuccess)
     e = launch_holdout(p->d, k, c, q, L.ldz, Z, at<double>(ws, L.G),
                        at<double>(ws, L.C), at<double>(ws, L.yy), hn,

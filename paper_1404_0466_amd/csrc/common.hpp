@@ -166,6 +166,27 @@ __device__ inline void mma_panel_f32(Acc64F& acc, const double* a, int64_t lda,
   acc.mma(to_f32(av), to_f32(bv));
 }
 
+// acc += sum_k A'(i,k) (scale .* B'(k,j)); scale holds the factor of the
+// lane's four columns.
+__device__ inline void mma_panel_scaled(Acc64& acc, const double* a,
+                                        int64_t lda, const double* b,
+                                        int64_t ldb, int K, v4d scale) {
+  const int l = threadIdx.x & 63;
+  const double* pa = a + (int64_t)(l >> 4) * lda + 4 * (l & 15);
+  const double* pb = b + (int64_t)(l >> 4) * ldb + 4 * (l & 15);
+  const int64_t sa = 4 * lda, sb = 4 * ldb;
+  v4d av = ld4(pa), bv = ld4(pb);
+  for (int k0 = 4; k0 < K; k0 += 4) {
+    pa += sa;
+    pb += sb;
+    v4d an = ld4(pa), bn = ld4(pb);
+    acc.mma(av, bv * scale);
+    av = an;
+    bv = bn;
+  }
+  acc.mma(av, bv * scale);
+}
+
 // acc -= sum over k in [0,K) of A'(i,k) B'(k,j) (the A operand negated).
 __device__ inline void mma_panel_sub(Acc64& acc, const double* a, int64_t lda,
                                      const double* b, int64_t ldb, int K) {

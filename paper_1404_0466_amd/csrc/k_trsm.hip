@@ -213,27 +213,6 @@ __global__ void __launch_bounds__(256) k_diag_apply(int64_t d, int i, int nper,
   }
 }
 
-// acc += sum_k A'(i,k) (scale .* B'(k,j)); scale holds the factor of the
-// lane's four columns.
-__device__ inline void mma_panel_scaled(Acc64& acc, const double* a,
-                                        int64_t lda, const double* b,
-                                        int64_t ldb, int K, v4d scale) {
-  const int l = threadIdx.x & 63;
-  const double* pa = a + (int64_t)(l >> 4) * lda + 4 * (l & 15);
-  const double* pb = b + (int64_t)(l >> 4) * ldb + 4 * (l & 15);
-  const int64_t sa = 4 * lda, sb = 4 * ldb;
-  v4d av = ld4(pa), bv = ld4(pb);
-  for (int k0 = 4; k0 < K; k0 += 4) {
-    pa += sa;
-    pb += sb;
-    v4d an = ld4(pa), bn = ld4(pb);
-    acc.mma(av, bv * scale);
-    av = an;
-    bv = bn;
-  }
-  acc.mma(av, bv * scale);
-}
-
 // Off-diagonal update for interpolated factors.  Forward step i: rows of
 // tile I > i lose sum_p Theta_p(I,i) (tau^p .* U_i); backward step i: rows
 // of tile I < i lose sum_p Theta_p(i,I)^T (tau^p .* W_i), read from the
@@ -359,13 +338,14 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
                                const double* theta, const double* theta_t,
                                int q, const double* tau_dev, int64_t ldz,
                                double* Z, int* flags, double* dinv,
-                               double* dinv_r, hipStream_t s) {
+                               double* dinv_r, int prepare, hipStream_t s) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
   const unsigned ncb = (unsigned)(ldz / NB);
   FactorSrc src{theta, S, M, 0, q, tau_dev};
-  PICHOL_LAUNCH(k_diag_inv, dim3((unsigned)nt, (unsigned)q, (unsigned)nmat),
-                dim3(256), 0, s, d, src, dinv, dinv_r, flags);
+  if (prepare)
+    PICHOL_LAUNCH(k_diag_inv, dim3((unsigned)nt, (unsigned)q, (unsigned)nmat),
+                  dim3(256), 0, s, d, src, dinv, dinv_r, flags);
   for (int i = 0; i < nt; ++i) {
     PICHOL_LAUNCH(k_diag_apply, dim3((unsigned)q, (unsigned)nmat), dim3(256), 0,
                   s, d, i, q, c, dinv, ldz, Z);

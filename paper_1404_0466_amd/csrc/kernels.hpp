@@ -82,7 +82,7 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int m,
                                const double* theta, const double* theta_t,
                                int q, const double* tau_dev, int64_t ldz,
                                double* Z, int* flags, double* dinv,
-                               double* dinv_r, hipStream_t s);
+                               double* dinv_r, int prepare, hipStream_t s);
 hipError_t launch_solve_factors(int64_t d, int nmat, int nper, int c,
                                 const double* L, int64_t ldz, double* Z,
                                 int* flags, hipStream_t s);
@@ -97,5 +97,15 @@ hipError_t launch_holdout(int64_t d, int nmat, int c, int q, int64_t ldz,
                           const double* yy, const HoldoutNorm& hn,
                           double* partial, double* err, int* flags,
                           hipStream_t s);
+
+// ---- iterative refinement (k_refine.hip)
+hipError_t launch_full_h(int64_t d, const FoldSplit& fs, const double* G,
+                         double* Hf, hipStream_t s);
+hipError_t launch_residual(int64_t d, int nmat, int q, int c, int64_t ldz,
+                           const double* Hf, const double* B,
+                           const double* lam_dev, const double* Z, double* R,
+                           hipStream_t s);
+hipError_t launch_slab_add(int64_t d, int nmat, int64_t ldz, const double* D,
+                           double* Z, hipStream_t s);
 
 }  // namespace pichol

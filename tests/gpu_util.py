@@ -68,7 +68,7 @@ def gram(X, Y, k, normalize=True):
 
 
 def cv(prob, method, X=None, Y=None, lam_s=None, lam_grid=None, r=None,
-       want_W=True, normalize=True, k=None, precision=0):
+       want_W=True, normalize=True, k=None, precision=0, refine=0):
     """Run the pipeline (gram + interp or exact) on the GPU."""
     X = prob.X if X is None else X
     Y = prob.Y if Y is None else Y
@@ -79,7 +79,8 @@ def cv(prob, method, X=None, Y=None, lam_s=None, lam_grid=None, r=None,
     n, d = X.shape
     c = Y.shape[1]
     g, q = len(lam_s), len(lam_grid)
-    p = B.make_problem(n, d, c, k, g, r, q, normalize, precision=precision)
+    p = B.make_problem(n, d, c, k, g, r, q, normalize, precision=precision,
+                       refine=refine)
     m = B.PICHOL_METHOD_INTERP if method == "interp" else B.PICHOL_METHOD_EXACT
     nbytes = B.pichol_workspace_size(p, m)
     w = ws(nbytes)
