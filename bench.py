@@ -116,7 +116,7 @@ def cpu_baseline(prob, gpu_err_fold0):
 
 
 def variant_leg(args, B, p, ws, nbytes, prob, ei64, ee64, stream, precision,
-                refine):
+                refine, W64):
     """Time the piCholesky (and exact) stages with another precision and/or
     refinement count on the resident Gram matrices, and compare the hold-out
     errors with the FP64 run of the same step (FP64 interpolated and FP64
@@ -156,6 +156,20 @@ def variant_leg(args, B, p, ws, nbytes, prob, ei64, ee64, stream, precision,
     t_int = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     t_ex = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     ei = err_i.cpu().numpy().reshape(k, q)
+    # relative weight error against the FP64 runs (one more, untimed call)
+    Wv = torch.empty_like(W64["interp"])
+    B.pichol_cv_interp(pm, prob.lam_s, prob.lam_grid, prob.lam_ref, ws, nbytes,
+                       err_i, Wv, info_i, flags_i)
+    wscale_i = float(W64["interp"].abs().max())
+    w_rel_i = float((Wv - W64["interp"]).abs().max()) / wscale_i
+    w_rel_ie = None
+    w_rel_e = None
+    if exact:
+        wscale_e = float(W64["exact"].abs().max())
+        w_rel_ie = float((Wv - W64["exact"]).abs().max()) / wscale_e
+        B.pichol_cv_exact(pm, prob.lam_grid, ws, nbytes, err_e, Wv, info_e, flags_e)
+        w_rel_e = float((Wv - W64["exact"]).abs().max()) / wscale_e
+    del Wv
     out = {
         "precision": ("FP32-MFMA trailing updates, FP64 elsewhere" if precision
                       else "FP64"),
@@ -164,6 +178,7 @@ def variant_leg(args, B, p, ws, nbytes, prob, ei64, ee64, stream, precision,
         "interp_ok": bool((info_i.cpu().numpy() == 0).all()
                           and (flags_i.cpu().numpy() == 0).all()),
         "interp_max_rel_err_vs_fp64_interp": float(np.max(np.abs(ei - ei64) / ei64)),
+        "interp_weight_rel_err_vs_fp64_interp": w_rel_i,
     }
     msg = (f"{name}: interp {t_int:.2f} ms -> {out['value']:.1f} lambda-solves/s, "
            f"max rel diff vs FP64 interp {out['interp_max_rel_err_vs_fp64_interp']:.2e}")
@@ -175,12 +190,120 @@ def variant_leg(args, B, p, ws, nbytes, prob, ei64, ee64, stream, precision,
             "exact_ok": bool((info_e.cpu().numpy() == 0).all()
                              and (flags_e.cpu().numpy() == 0).all()),
             "exact_max_rel_err_vs_fp64_exact": float(np.max(np.abs(ee - ee64) / ee64)),
+            "interp_weight_rel_err_vs_fp64_exact": w_rel_ie,
+            "exact_weight_rel_err_vs_fp64_exact": w_rel_e,
+            "interp_speedup_vs_fp64_exact": None,
             "err_gap_vs_fp64_exact": gaps(ei.mean(0), ee64.mean(0), prob.lam_grid),
         })
         msg += (f"; vs FP64 exact {out['interp_max_rel_err_vs_fp64_exact']:.2e}; "
                 f"exact {t_ex:.2f} ms, max rel diff vs FP64 exact "
                 f"{out['exact_max_rel_err_vs_fp64_exact']:.2e}")
     log(msg)
+    return out
+
+
+def batching_leg(args, B, stream):
+    """The many-problem workload (48 ridge problems of uneven d, k=5, g=5,
+    r=2, q=32, FP64): every problem, fold and lambda through pichol_cv_batch
+    (Gram included), eager and as one replayed HIP graph with an autotuned
+    schedule, against the same problems run one after another through the
+    single-problem pipeline, and against the batched exact method."""
+    import torch
+    import workloads
+    from paper_1404_0466_amd import autotune
+
+    t0 = time.perf_counter()
+    probs = workloads.batch_problems()
+    log(f"many-problem workload: {len(probs)} problems "
+        f"({time.perf_counter() - t0:.1f} s to generate)")
+    dev = torch.device("cuda:0")
+    ents_i, ents_e, keep = [], [], []
+    for pb in probs:
+        k, q, g = pb.k, pb.q, pb.g
+        X = torch.from_numpy(pb.X).to(dev)
+        Y = torch.from_numpy(pb.Y).to(dev)
+        bi = dict(err=torch.empty(k * q, dtype=torch.float64, device=dev),
+                  info=torch.empty(k * g, dtype=torch.int32, device=dev),
+                  flags=torch.empty(k * q, dtype=torch.int32, device=dev))
+        be = dict(err=torch.empty(k * q, dtype=torch.float64, device=dev),
+                  info=torch.empty(k * q, dtype=torch.int32, device=dev),
+                  flags=torch.empty(k * q, dtype=torch.int32, device=dev))
+        keep.append((X, Y, bi, be))
+        prob = B.make_problem(pb.n, pb.d, pb.c, k, g, pb.r, q, True)
+        ents_i.append(dict(p=prob, X=X, Y=Y, lam_s=pb.lam_s, lam_grid=pb.lam_grid,
+                           lam_ref=pb.lam_ref, W=None, **bi))
+        ents_e.append(dict(p=prob, X=X, Y=Y, lam_s=None, lam_grid=pb.lam_grid,
+                           lam_ref=pb.lam_ref, W=None, **be))
+    bat_i, bat_e = B.Batch(ents_i), B.Batch(ents_e)
+    nb_i = B.pichol_batch_workspace_size(bat_i, B.PICHOL_METHOD_INTERP)
+    nb_e = B.pichol_batch_workspace_size(bat_e, B.PICHOL_METHOD_EXACT)
+    nbytes = max(nb_i, nb_e)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    nsolves = sum(pb.k * pb.q for pb in probs)
+
+    def timed(fn, reps):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        for _ in range(reps):
+            fn()
+        e.record(stream)
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / reps
+
+    reps = args.steps
+    tune_i, times_i = autotune.tune(bat_i, B.PICHOL_METHOD_INTERP, ws, nbytes, cache=None)
+    log(f"autotuned schedule {tune_i}: "
+        + ", ".join(f"{k_}={v:.2f} ms" for k_, v in (times_i or {}).items()))
+    t_eager = timed(lambda: B.pichol_cv_batch(bat_i, B.PICHOL_METHOD_INTERP, tune_i,
+                                              ws, nbytes), reps)
+    gi = B.pichol_cv_batch_graph(bat_i, B.PICHOL_METHOD_INTERP, tune_i, ws, nbytes)
+    t_graph = timed(lambda: B.pichol_graph_launch(gi), reps)
+    B.pichol_graph_destroy(gi)
+    ei = [b[2]["err"].cpu().numpy().reshape(pb.k, pb.q) for b, pb in zip(keep, probs)]
+    ok_i = all(bool((b[2]["info"] == 0).all()) and bool((b[2]["flags"] == 0).all())
+               for b in keep)
+    # the same problems one after another through the single-problem pipeline
+    err1 = torch.empty(max(pb.k * pb.q for pb in probs), dtype=torch.float64, device=dev)
+    inf1 = torch.empty(max(pb.k * pb.g for pb in probs), dtype=torch.int32, device=dev)
+    fl1 = torch.empty(max(pb.k * pb.q for pb in probs), dtype=torch.int32, device=dev)
+
+    def sequential():
+        for (X, Y, _, _), e in zip(keep, ents_i):
+            B.pichol_cv(e["p"], X, Y, e["lam_s"], e["lam_grid"], e["lam_ref"], ws,
+                        nbytes, err1, None, inf1, fl1)
+    t_seq = timed(sequential, max(1, reps // 2))
+    # the exact method, batched
+    tune_e, _ = autotune.tune(bat_e, B.PICHOL_METHOD_EXACT, ws, nbytes, cache=None, reps=2)
+    ge = B.pichol_cv_batch_graph(bat_e, B.PICHOL_METHOD_EXACT, tune_e, ws, nbytes)
+    t_exact = timed(lambda: B.pichol_graph_launch(ge), reps)
+    B.pichol_graph_destroy(ge)
+    ee = [b[3]["err"].cpu().numpy().reshape(pb.k, pb.q) for b, pb in zip(keep, probs)]
+    ok_e = all(bool((b[3]["info"] == 0).all()) and bool((b[3]["flags"] == 0).all())
+               for b in keep)
+    gap = [float(np.max(np.abs(a.mean(0) - b.mean(0)) / b.mean(0))) for a, b in zip(ei, ee)]
+    same_sel = sum(int(np.argmin(a.mean(0)) == np.argmin(b.mean(0))) for a, b in zip(ei, ee))
+    out = {
+        "workload": "48 power-law Gaussian problems, d in {256..2048}, n=8d, c in {1,10}, "
+                    "k=5, g=5, r=2, q=32, lambda in [1e-4,1e1]*s",
+        "lambda_solves": nsolves, "buckets": B.pichol_batch_buckets(bat_i, B.PICHOL_METHOD_INTERP),
+        "tuning": tune_i,
+        "graph_ms": t_graph, "value": nsolves / (t_graph * 1e-3),
+        "eager_ms": t_eager, "sequential_single_ms": t_seq,
+        "speedup_vs_sequential": t_seq / t_graph,
+        "exact_graph_ms": t_exact, "exact_value": nsolves / (t_exact * 1e-3),
+        "speedup_vs_exact": t_exact / t_graph,
+        "interp_ok": ok_i, "exact_ok": ok_e,
+        "curve_gap_max_rel": max(gap), "curve_gap_median_rel": float(np.median(gap)),
+        "same_selection": f"{same_sel}/{len(probs)}",
+        "note": "times include the Gram step of every problem",
+    }
+    log(f"many problems: graph {t_graph:.2f} ms ({out['value']:.0f} lambda-solves/s), "
+        f"eager {t_eager:.2f} ms, one by one {t_seq:.2f} ms, exact {t_exact:.2f} ms; "
+        f"gap max {max(gap):.2e}, same selection {same_sel}/{len(probs)}")
+    del ws
     return out
 
 
@@ -202,6 +325,8 @@ def main():
                     help="skip the precision-form legs timed after the FP64 "
                          "headline (FP32-MFMA trailing updates, iterative "
                          "refinement)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the many-problem (batching form) leg")
     ap.add_argument("--refine", type=int, default=2,
                     help="refinement steps of the refined legs")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -308,16 +433,35 @@ def main():
     variants = None
     if not args.no_variants:
         ee64 = None if args.no_exact else ee
+        # FP64 weights of both methods (untimed), the reference of the
+        # variants' relative weight errors
+        W64 = {"interp": torch.empty(k * q * d * c, dtype=torch.float64, device=dev),
+               "exact": None}
+        B.pichol_cv_interp(p, lam_s, lam_grid, lam_ref, ws, nbytes, err_i, W64["interp"],
+                           info_i, flags_i)
+        if not args.no_exact:
+            W64["exact"] = torch.empty_like(W64["interp"])
+            B.pichol_cv_exact(p, lam_grid, ws, nbytes, err_e, W64["exact"], info_e,
+                              flags_e)
+        torch.cuda.synchronize()
         variants = {
             "mixed": variant_leg(args, B, p, ws, nbytes, prob, ei, ee64, stream,
-                                 B.PICHOL_PREC_MIXED, 0),
+                                 B.PICHOL_PREC_MIXED, 0, W64),
             f"mixed_refine{args.refine}": variant_leg(
                 args, B, p, ws, nbytes, prob, ei, ee64, stream,
-                B.PICHOL_PREC_MIXED, args.refine),
+                B.PICHOL_PREC_MIXED, args.refine, W64),
             f"fp64_refine{args.refine}": variant_leg(
                 args, B, p, ws, nbytes, prob, ei, ee64, stream,
-                B.PICHOL_PREC_FP64, args.refine),
+                B.PICHOL_PREC_FP64, args.refine, W64),
         }
+        if not args.no_exact:
+            for v in variants.values():
+                v["interp_speedup_vs_fp64_exact"] = t_ex / v["interp_ms"]
+        del W64
+
+    batching = None
+    if not args.no_batch:
+        batching = batching_leg(args, B, stream)
 
     roofline = None
     kernels = None
@@ -377,6 +521,7 @@ def main():
                    "kind": prob.meta.get("kind"), "lookahead": args.lookahead},
         **result_extra,
         "precision_forms": variants,
+        "batching_form": batching,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

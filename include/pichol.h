@@ -327,6 +327,81 @@ pichol_status pichol_exact_cv(const pichol_problem *p, const double *X,
                               double *W, int32_t *info, int32_t *flags,
                               hipStream_t stream);
 
+/* ---------------------------------------------------------------- batching */
+
+/* One independent ridge problem of a batch: the arguments of the
+ * single-problem pipeline (pichol_cv_gram followed by pichol_cv_interp or
+ * pichol_cv_exact) gathered in one record.  p.refine must be 0; p.precision
+ * applies to the problem's factorizations.  X, Y, err, W, info, flags are
+ * device pointers as in those calls; lam_s (g values, interpolated method
+ * only) and lam_grid (q values) are host arrays read during the call. */
+typedef struct {
+  pichol_problem p;
+  const double *X, *Y;
+  const double *lam_s;
+  const double *lam_grid;
+  double lam_ref;
+  double *err;     /* k*q                                              */
+  double *W;       /* k*q*d*c, or NULL                                 */
+  int32_t *info;   /* k*g (interpolated) or k*q (exact)                */
+  int32_t *flags;  /* k*q                                              */
+} pichol_batch_item;
+
+/* Scheduling knobs of a batch (pass NULL for the defaults; the values an
+ * autotuner picks per batch signature).
+ *   streams  concurrent streams for independent buckets, 1..4 (0 = 4)
+ *   order    0: buckets by decreasing estimated work (d^3 x factorizations),
+ *               assigned to the least-loaded stream; 1: input order,
+ *               round-robin over the streams */
+typedef struct {
+  int32_t streams;
+  int32_t order;
+} pichol_batch_tuning;
+
+/* Many independent problems of uneven size in one call (Sec. 3.3's method
+ * applied to a workload of many ridge problems).  Problems that share d, c,
+ * k, g, r, q, precision and, for the interpolated method, the scaled sample
+ * and grid values lambda/lam_ref to within 8 ulps (so the fit's
+ * pseudo-inverse and the evaluation weights are shared; the bucket uses its
+ * first problem's scaled values) form a bucket: every fold, lambda and
+ * problem of a bucket runs in the same launches (the stacked matrices of
+ * the bucket are one batch for the factorization, fit, solve and hold-out
+ * kernels; each problem keeps its own shifts lambda_s, fold split and hold-out
+ * counts).  Buckets are independent and run concurrently on library-owned
+ * streams (default priority, created on first use per device), forked from
+ * and joined back to `stream` with events, so the call is capturable into a
+ * HIP graph (pichol_cv_batch_graph).  Results equal those of the
+ * single-problem pipeline bit for bit when the scaled values agree exactly,
+ * and to within the effect of those few ulps otherwise.
+ *   method  PICHOL_METHOD_INTERP or PICHOL_METHOD_EXACT (one of them)
+ *   ws      pichol_batch_workspace_size bytes: each bucket has its own
+ *           region, laid out as the single-problem workspace of its stacked
+ *           problems. */
+pichol_status pichol_batch_workspace_size(int32_t nprob,
+                                          const pichol_batch_item *items,
+                                          int32_t method, size_t *bytes);
+pichol_status pichol_cv_batch(int32_t nprob, const pichol_batch_item *items,
+                              int32_t method, const pichol_batch_tuning *tune,
+                              void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Number of buckets the call above forms (host only, for inspection). */
+int32_t pichol_batch_buckets(int32_t nprob, const pichol_batch_item *items,
+                             int32_t method);
+
+/* The whole batch as one HIP graph: pichol_cv_batch captured on a private
+ * stream and instantiated.  The graph records the items' pointers and the
+ * lambda values as they are at this call; each pichol_graph_launch replays
+ * every launch of the batch with one host call.  Per-kernel profiling must
+ * be off while a graph is built. */
+typedef struct pichol_graph_s *pichol_graph;
+pichol_status pichol_cv_batch_graph(int32_t nprob,
+                                    const pichol_batch_item *items,
+                                    int32_t method,
+                                    const pichol_batch_tuning *tune, void *ws,
+                                    size_t ws_bytes, pichol_graph *graph);
+pichol_status pichol_graph_launch(pichol_graph graph, hipStream_t stream);
+pichol_status pichol_graph_destroy(pichol_graph graph);
+
 /* ------------------------------------------------------------------ misc */
 
 /* Synchronise the stream and inspect info/flags (device arrays, either may

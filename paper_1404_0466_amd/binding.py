@@ -59,6 +59,22 @@ _dbl = ctypes.c_double
 _sz = ctypes.c_size_t
 _pprob = ctypes.POINTER(Problem)
 
+
+class BatchItem(ctypes.Structure):
+    """pichol_batch_item."""
+    _fields_ = [("p", Problem), ("X", _vp), ("Y", _vp), ("lam_s", _vp),
+                ("lam_grid", _vp), ("lam_ref", _dbl), ("err", _vp), ("W", _vp),
+                ("info", _vp), ("flags", _vp)]
+
+
+class BatchTuning(ctypes.Structure):
+    """pichol_batch_tuning."""
+    _fields_ = [("streams", _i32), ("order", _i32)]
+
+
+_pitem = ctypes.POINTER(BatchItem)
+_ptune = ctypes.POINTER(BatchTuning)
+
 _SIGNATURES = {
     "pichol_packed_elems": (_i64, [_i64]),
     "pichol_padded_order": (_i64, [_i64]),
@@ -93,6 +109,14 @@ _SIGNATURES = {
                          _vp, _vp, _vp]),
     "pichol_exact_cv": (_i32, [_pprob, _vp, _vp, _vp, _vp, _sz, _vp, _vp, _vp,
                                _vp, _vp]),
+    "pichol_batch_workspace_size": (_i32, [_i32, _pitem, _i32,
+                                           ctypes.POINTER(_sz)]),
+    "pichol_cv_batch": (_i32, [_i32, _pitem, _i32, _ptune, _vp, _sz, _vp]),
+    "pichol_batch_buckets": (_i32, [_i32, _pitem, _i32]),
+    "pichol_cv_batch_graph": (_i32, [_i32, _pitem, _i32, _ptune, _vp, _sz,
+                                     ctypes.POINTER(_vp)]),
+    "pichol_graph_launch": (_i32, [_vp, _vp]),
+    "pichol_graph_destroy": (_i32, [_vp]),
     "pichol_check": (_i32, [_vp, _i64, _vp, _i64, _vp]),
     "pichol_set_option": (_i32, [_i32, _i32]),
     "pichol_get_option": (_i32, [_i32]),
@@ -381,3 +405,85 @@ def pichol_profile_summary(max_kernels: int = 256) -> dict:
 
 def pichol_profile_reset():
     _check("pichol_profile_reset", load().pichol_profile_reset())
+
+
+# ------------------------------------------------------------------ batching
+
+def _ptr(t, dtype=None):
+    """Device pointer of a tensor, or an integer address passed through (for
+    host-only calls such as the workspace size), or NULL for None."""
+    if t is None or isinstance(t, int):
+        return t
+    return _dev(t, dtype)
+
+
+class Batch:
+    """A ctypes array of pichol_batch_item built from dicts with the keys
+    p (Problem), X, Y, err, W, info, flags (device tensors, W may be None),
+    lam_s (host, interpolated method), lam_grid (host), lam_ref.  Keeps the
+    host lambda arrays alive as long as the batch object lives."""
+
+    def __init__(self, entries):
+        self.n = len(entries)
+        self.items = (BatchItem * max(1, self.n))()
+        self._keep = []
+        for i, e in enumerate(entries):
+            ls = _Host(e["lam_s"], np.float64) if e.get("lam_s") is not None else None
+            lg = _Host(e["lam_grid"], np.float64)
+            self._keep += [ls, lg]
+            it = self.items[i]
+            it.p = e["p"]
+            it.X = _ptr(e["X"], _f64() if not isinstance(e["X"], int) else None)
+            it.Y = _ptr(e["Y"], _f64() if not isinstance(e["Y"], int) else None)
+            it.lam_s = ls.ptr if ls is not None else None
+            it.lam_grid = lg.ptr
+            it.lam_ref = float(e.get("lam_ref", 0.0))
+            for name in ("err", "W"):
+                v = e.get(name)
+                setattr(it, name, _ptr(v, _f64() if v is not None and not isinstance(v, int) else None))
+            for name in ("info", "flags"):
+                v = e.get(name)
+                setattr(it, name, _ptr(v, _i32t() if v is not None and not isinstance(v, int) else None))
+
+
+def _tune(tune):
+    if tune is None:
+        return None
+    if isinstance(tune, BatchTuning):
+        return ctypes.byref(tune)
+    return ctypes.byref(BatchTuning(int(tune.get("streams", 0)), int(tune.get("order", 0))))
+
+
+def pichol_batch_workspace_size(batch: Batch, method: int) -> int:
+    out = _sz(0)
+    _check("pichol_batch_workspace_size", load().pichol_batch_workspace_size(
+        batch.n, batch.items, method, ctypes.byref(out)))
+    return int(out.value)
+
+
+def pichol_batch_buckets(batch: Batch, method: int) -> int:
+    return int(load().pichol_batch_buckets(batch.n, batch.items, method))
+
+
+def pichol_cv_batch(batch: Batch, method: int, tune, ws, ws_bytes, stream=None):
+    _check("pichol_cv_batch", load().pichol_cv_batch(
+        batch.n, batch.items, method, _tune(tune), _dev(ws), ws_bytes,
+        _stream(stream)))
+
+
+def pichol_cv_batch_graph(batch: Batch, method: int, tune, ws, ws_bytes):
+    """Returns the graph handle (pass it to pichol_graph_launch / _destroy)."""
+    g = _vp(None)
+    _check("pichol_cv_batch_graph", load().pichol_cv_batch_graph(
+        batch.n, batch.items, method, _tune(tune), _dev(ws), ws_bytes,
+        ctypes.byref(g)))
+    return g
+
+
+def pichol_graph_launch(graph, stream=None):
+    _check("pichol_graph_launch", load().pichol_graph_launch(graph, _stream(stream)))
+
+
+def pichol_graph_destroy(graph):
+    _check("pichol_graph_destroy", load().pichol_graph_destroy(graph))
+

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "api_internal.hpp"
 #include "kernels.hpp"
 #include "pichol.h"
 
@@ -23,13 +24,13 @@ hipError_t record_hip_error_code(hipError_t e) {
   return e;
 }
 
-static pichol_status hip_status(hipError_t e) {
+pichol_status hip_status(hipError_t e) {
   if (e == hipSuccess) return PICHOL_OK;
   record_hip_error_code(e);
   return PICHOL_ERR_HIP;
 }
 
-static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static std::atomic<int> g_opt_lookahead{0};
 int option_lookahead() { return g_opt_lookahead.load(); }
@@ -44,6 +45,7 @@ struct ProfState {
   std::vector<std::string> names_out;
 };
 static ProfState g_prof;
+bool profiling_on() { return g_prof.on; }
 
 ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), stream(s), slot(-1) {
   if (!g_prof.on) return;
@@ -113,7 +115,7 @@ static bool pseudo_inverse(int g, int m, const double* V, double* P) {
   return true;
 }
 
-static bool fold_split(int64_t n, int k, int normalize, FoldSplit* fs) {
+bool fold_split(int64_t n, int k, int normalize, FoldSplit* fs) {
   if (k < 2 || k > 64 || n < k) return false;
   memset(fs, 0, sizeof(*fs));
   fs->k = k;
@@ -127,11 +129,11 @@ static bool fold_split(int64_t n, int k, int normalize, FoldSplit* fs) {
   return true;
 }
 
-static bool precision_ok(int32_t precision) {
+bool precision_ok(int32_t precision) {
   return precision == PICHOL_PREC_FP64 || precision == PICHOL_PREC_MIXED;
 }
 
-static bool problem_ok(const pichol_problem* p) {
+bool problem_ok(const pichol_problem* p) {
   return p && p->n >= 1 && p->d >= 1 && p->c >= 1 && p->k >= 2 && p->k <= 64 &&
          p->n >= p->k && p->ldx >= p->d && p->ldy >= p->c && p->q >= 1 &&
          p->g >= 1 && p->g <= 32 && p->r >= 0 && p->r <= 7 && p->r < p->g &&
@@ -139,7 +141,7 @@ static bool problem_ok(const pichol_problem* p) {
          p->refine <= PICHOL_MAX_REFINE;
 }
 
-static bool samples_ok(const double* lam, int g) {
+bool samples_ok(const double* lam, int g) {
   for (int s = 0; s < g; ++s) {
     if (!isfinite(lam[s])) return false;
     for (int t = 0; t < s; ++t)
@@ -148,7 +150,7 @@ static bool samples_ok(const double* lam, int g) {
   return true;
 }
 
-static bool fit_coef(int g, int r, const double* lam_s, double lam_ref,
+bool fit_coef(int g, int r, const double* lam_s, double lam_ref,
                      FitCoef* fc) {
   const int m = r + 1;
   memset(fc, 0, sizeof(*fc));
@@ -233,13 +235,20 @@ static T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
-static void holdout_norm(const pichol_problem* p, HoldoutNorm* hn) {
+void holdout_norm(const pichol_problem* p, HoldoutNorm* hn) {
   FoldSplit fs;
   fold_split(p->n, p->k, p->normalize, &fs);
   memset(hn, 0, sizeof(*hn));
   hn->nmat = p->k;
   for (int f = 0; f < p->k; ++f)
     hn->count[f] = (double)(fs.start[f + 1] - fs.start[f]) * (double)p->c;
+}
+
+hipError_t upload_tau(const double* lam, int nlam, double lam_ref,
+                             double* dst, hipStream_t stream) {
+  std::vector<double> tau(nlam);
+  for (int t = 0; t < nlam; ++t) tau[t] = lam[t] / lam_ref;
+  return launch_store_doubles(tau.data(), nlam, dst, stream);
 }
 
 }  // namespace pichol
@@ -394,11 +403,11 @@ pichol_status pichol_potrf_shifted_batched(int64_t d, int32_t nmat,
   double* linv = at<double>(ws, align256((size_t)nshift * sizeof(double)));
   hipError_t e = launch_store_doubles(lam, nshift, lam_dev, stream);
   if (e != hipSuccess) return hip_status(e);
-  e = launch_shift_copy(d, nmat, H, nshift, lam_dev, L, info, stream);
+  e = launch_shift_copy(d, nmat, H, nshift, lam_dev, nmat, L, info, stream);
   if (e != hipSuccess) return hip_status(e);
   return hip_status(launch_potrf_blocked(d, nmat * nshift, L, info, linv,
                                          precision == PICHOL_PREC_MIXED,
-                                         stream));
+                                         option_lookahead(), stream));
 }
 
 pichol_status pichol_fit(int64_t d, int32_t nmat, int32_t g, int32_t r,
@@ -423,12 +432,6 @@ size_t pichol_solve_interp_workspace(int64_t d, int32_t nmat, int32_t q) {
          2 * align256((size_t)nmat * q * ntiles_of(d) * NB2 * sizeof(double));
 }
 
-static hipError_t upload_tau(const double* lam, int nlam, double lam_ref,
-                             double* dst, hipStream_t stream) {
-  std::vector<double> tau(nlam);
-  for (int t = 0; t < nlam; ++t) tau[t] = lam[t] / lam_ref;
-  return launch_store_doubles(tau.data(), nlam, dst, stream);
-}
 
 pichol_status pichol_eval(int64_t d, int32_t nmat, int32_t r,
                           const double* theta, int32_t nlam, const double* lam,
@@ -569,11 +572,12 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
   hipError_t e = launch_store_doubles(lam_s, g, lam_dev, stream);
   if (e == hipSuccess) e = upload_tau(lam_grid, q, lam_ref, tau, stream);
   if (e == hipSuccess)
-    e = launch_shift_copy(p->d, k, at<double>(ws, L.H), g, lam_dev, Lf, info,
-                          stream);
+    e = launch_shift_copy(p->d, k, at<double>(ws, L.H), g, lam_dev, k, Lf,
+                          info, stream);
   if (e == hipSuccess)
     e = launch_potrf_blocked(p->d, k * g, Lf, info, at<double>(ws, L.i_linv),
-                             p->precision == PICHOL_PREC_MIXED, stream);
+                             p->precision == PICHOL_PREC_MIXED,
+                             option_lookahead(), stream);
   if (e == hipSuccess) e = launch_fit(p->d, k, fc, Lf, th, tht, stream);
   if (e == hipSuccess)
     e = launch_slab_init(p->d, k, q, c, L.ldz, at<double>(ws, L.B), Z, flags,
@@ -629,11 +633,12 @@ pichol_status pichol_cv_exact(const pichol_problem* p, const double* lam_grid,
   double* Z = at<double>(ws, L.e_Z);
   hipError_t e = launch_store_doubles(lam_grid, q, lam_dev, stream);
   if (e == hipSuccess)
-    e = launch_shift_copy(p->d, k, at<double>(ws, L.H), q, lam_dev, Lf, info,
-                          stream);
+    e = launch_shift_copy(p->d, k, at<double>(ws, L.H), q, lam_dev, k, Lf,
+                          info, stream);
   if (e == hipSuccess)
     e = launch_potrf_blocked(p->d, k * q, Lf, info, at<double>(ws, L.e_linv),
-                             p->precision == PICHOL_PREC_MIXED, stream);
+                             p->precision == PICHOL_PREC_MIXED,
+                             option_lookahead(), stream);
   if (e == hipSuccess)
     e = launch_slab_init(p->d, k, q, c, L.ldz, at<double>(ws, L.B), Z, flags,
                          stream);

@@ -93,19 +93,37 @@ __global__ void __launch_bounds__(64) k_holdout_final(int64_t nt, int q, int c,
   if (!isfinite(e)) flags[m * q + t] |= 1;
 }
 
+hipError_t launch_holdout_partial(int64_t d, int nmat, int c, int q,
+                                  int64_t ldz, const double* Z,
+                                  const double* G, const double* C,
+                                  double* partial, hipStream_t s) {
+  const int64_t nt = ntiles_of(d);
+  PICHOL_LAUNCH(k_holdout_partial,
+                     dim3((unsigned)(ldz / NB), (unsigned)nt, (unsigned)nmat),
+                     dim3(256), 0, s, d, q, c, ldz, Z, G, C, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_holdout_final(int64_t d, int nmat, int c, int q, int64_t ldz,
+                                const double* partial, const double* yy,
+                                const HoldoutNorm& hn, double* err, int* flags,
+                                hipStream_t s) {
+  const int64_t nt = ntiles_of(d);
+  PICHOL_LAUNCH(k_holdout_final,
+                     dim3((unsigned)((q + 63) / 64), (unsigned)nmat), dim3(64),
+                     0, s, nt, q, c, ldz, partial, yy, hn, err, flags);
+  return hipGetLastError();
+}
+
 hipError_t launch_holdout(int64_t d, int nmat, int c, int q, int64_t ldz,
                           const double* Z, const double* G, const double* C,
                           const double* yy, const HoldoutNorm& hn,
                           double* partial, double* err, int* flags,
                           hipStream_t s) {
-  const int64_t nt = ntiles_of(d);
-  PICHOL_LAUNCH(k_holdout_partial,
-                     dim3((unsigned)(ldz / NB), (unsigned)nt, (unsigned)nmat),
-                     dim3(256), 0, s, d, q, c, ldz, Z, G, C, partial);
-  PICHOL_LAUNCH(k_holdout_final,
-                     dim3((unsigned)((q + 63) / 64), (unsigned)nmat), dim3(64),
-                     0, s, nt, q, c, ldz, partial, yy, hn, err, flags);
-  return hipGetLastError();
+  hipError_t e = launch_holdout_partial(d, nmat, c, q, ldz, Z, G, C, partial, s);
+  if (e != hipSuccess) return e;
+  return launch_holdout_final(d, nmat, c, q, ldz, partial, yy, hn, err, flags,
+                              s);
 }
 
 }  // namespace pichol

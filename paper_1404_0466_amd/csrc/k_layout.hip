@@ -117,4 +117,21 @@ hipError_t launch_slab_to_weights(int64_t d, int nmat, int q, int c,
   return hipGetLastError();
 }
 
+// dst[i] = src[i] (int32), through vector stores: gathers per-problem
+// status words out of a batch's stacked arrays.
+__global__ void __launch_bounds__(256) k_copy_i32(int64_t n, const int* src,
+                                                  int* dst) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+
+hipError_t launch_copy_i32(int64_t n, const int* src, int* dst, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t bx = (n + 255) / 256;
+  if (bx > 1024) bx = 1024;
+  PICHOL_LAUNCH(k_copy_i32, dim3((unsigned)bx), dim3(256), 0, s, n, src, dst);
+  return hipGetLastError();
+}
+
 }  // namespace pichol

@@ -20,17 +20,19 @@ namespace pichol {
 
 // L(m*nshift + s) = H(m) + lam_s I: lower part copied, shift on the first d
 // diagonal entries, identity padding, zeros above the diagonal of diagonal
-// tiles.  Also clears info.
+// tiles.  Also clears info.  Matrices m share their shift set in groups of
+// lam_group: matrix m uses lam[(m / lam_group) * nshift + s].
 __global__ void __launch_bounds__(256) k_shift_copy(int64_t d, int64_t S,
                                                     const double* H,
                                                     int nshift,
                                                     const double* lam,
+                                                    int lam_group,
                                                     double* L, int* info) {
   const int64_t ms = blockIdx.y;
   const int64_t m = ms / nshift;
   const int s = (int)(ms % nshift);
   const int I = tri_row(blockIdx.x), J = blockIdx.x - (int)tri(I);
-  const double shift = lam[s];
+  const double shift = lam[(m / lam_group) * nshift + s];
   const double* h = H + m * S + tile_off(I, J);
   double* l = L + ms * S + tile_off(I, J);
   const int tid = threadIdx.x;
@@ -261,13 +263,13 @@ __device__ inline void potrf_update_body(int64_t S, int nt, int j0, int mode, in
 }
 
 hipError_t launch_shift_copy(int64_t d, int nmat, const double* H, int nshift,
-                             const double* lam_dev, double* L, int* info,
-                             hipStream_t s) {
+                             const double* lam_dev, int lam_group, double* L,
+                             int* info, hipStream_t s) {
   const int64_t nt = ntiles_of(d);
   PICHOL_LAUNCH(k_shift_copy,
                      dim3((unsigned)tri(nt), (unsigned)(nmat * nshift)),
                      dim3(256), 0, s, d, packed_elems_of(d), H, nshift,
-                     lam_dev, L, info);
+                     lam_dev, lam_group, L, info);
   return hipGetLastError();
 }
 
@@ -321,11 +323,13 @@ static SideStream* side_stream() {
 // factorizations and panel solves (short, latency-bound launches) overlap
 // the bulk of the update.
 hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
-                                double* linv_ws, int mixed, hipStream_t s) {
+                                double* linv_ws, int mixed, int lookahead,
+                                hipStream_t s) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
-  std::lock_guard<std::mutex> lk(g_side_mu);
-  SideStream* side = option_lookahead() ? side_stream() : nullptr;
+  std::unique_lock<std::mutex> lk(g_side_mu, std::defer_lock);
+  if (lookahead) lk.lock();
+  SideStream* side = lookahead ? side_stream() : nullptr;
   auto diag_panel = [&](int kk) {
     PICHOL_LAUNCH(k_potrf_diag, dim3((unsigned)nfac), dim3(256), 0, s, d, S,
                   kk, L, info, linv_ws);

@@ -44,6 +44,7 @@ hipError_t launch_unpack(int64_t d, int nmat, const double* P, double* A,
 hipError_t launch_slab_to_weights(int64_t d, int nmat, int q, int c,
                                   int64_t ldz, const double* Z, double* W,
                                   hipStream_t s);
+hipError_t launch_copy_i32(int64_t n, const int* src, int* dst, hipStream_t s);
 
 // ---- Gram (k_gram.hip)
 struct FoldSplit {
@@ -58,10 +59,13 @@ hipError_t launch_gram(const double* X, int64_t ldx, const double* Y,
 
 // ---- POTRF (k_potrf.hip)
 hipError_t launch_shift_copy(int64_t d, int nmat, const double* H, int nshift,
-                             const double* lam_dev, double* L, int* info,
-                             hipStream_t s);
+                             const double* lam_dev, int lam_group, double* L,
+                             int* info, hipStream_t s);
+// lookahead: 1 runs the bulk of each trailing update on the library's side
+// stream (see k_potrf.hip), 0 keeps everything on s.
 hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
-                                double* linv_ws, int mixed, hipStream_t s);
+                                double* linv_ws, int mixed, int lookahead,
+                                hipStream_t s);
 
 // ---- fit / evaluate (k_fit.hip)
 struct FitCoef {
@@ -92,6 +96,14 @@ struct HoldoutNorm {
   int nmat;
   double count[64];  // n_v * c per fold
 };
+hipError_t launch_holdout_partial(int64_t d, int nmat, int c, int q,
+                                  int64_t ldz, const double* Z,
+                                  const double* G, const double* C,
+                                  double* partial, hipStream_t s);
+hipError_t launch_holdout_final(int64_t d, int nmat, int c, int q, int64_t ldz,
+                                const double* partial, const double* yy,
+                                const HoldoutNorm& hn, double* err, int* flags,
+                                hipStream_t s);
 hipError_t launch_holdout(int64_t d, int nmat, int c, int q, int64_t ldz,
                           const double* Z, const double* G, const double* C,
                           const double* yy, const HoldoutNorm& hn,

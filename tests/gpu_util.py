@@ -102,3 +102,57 @@ def cv(prob, method, X=None, Y=None, lam_s=None, lam_grid=None, r=None,
         "info": info.cpu().numpy().reshape(k, -1),
         "flags": flags.cpu().numpy().reshape(k, q),
     }
+
+
+class BatchRun:
+    """Device buffers and the ctypes batch for a list of workloads.Problem
+    (pichol_cv_batch)."""
+
+    def __init__(self, probs, method, precision=0, want_W=True):
+        self.probs = probs
+        self.method = B.PICHOL_METHOD_INTERP if method == "interp" else B.PICHOL_METHOD_EXACT
+        self.interp = method == "interp"
+        self.want_W = want_W
+        self.bufs = []
+        ents = []
+        for p in probs:
+            k, q = p.k, p.q
+            nf = p.g if self.interp else q
+            b = {
+                "X": dev(p.X), "Y": dev(p.Y), "err": empty(k * q),
+                "W": empty(k * q * p.d * p.c) if want_W else None,
+                "info": empty(k * nf, torch.int32), "flags": empty(k * q, torch.int32),
+            }
+            self.bufs.append(b)
+            ents.append(dict(p=B.make_problem(p.n, p.d, p.c, k, p.g, p.r, q, True,
+                                              precision=precision),
+                             lam_s=p.lam_s if self.interp else None,
+                             lam_grid=p.lam_grid, lam_ref=p.lam_ref, **b))
+        self.batch = B.Batch(ents)
+        self.nbytes = B.pichol_batch_workspace_size(self.batch, self.method)
+        self.ws = ws(self.nbytes)
+
+    def run(self, tune=None):
+        B.pichol_cv_batch(self.batch, self.method, tune, self.ws, self.nbytes)
+        torch.cuda.synchronize()
+        return self.results()
+
+    def clear(self):
+        for b in self.bufs:
+            b["err"].fill_(float("nan"))
+            b["info"].fill_(-7)
+            b["flags"].fill_(-7)
+            if b["W"] is not None:
+                b["W"].fill_(float("nan"))
+        torch.cuda.synchronize()
+
+    def results(self):
+        out = []
+        for p, b in zip(self.probs, self.bufs):
+            out.append({
+                "mse": b["err"].cpu().numpy().reshape(p.k, p.q),
+                "W": b["W"].cpu().numpy().reshape(p.k, p.q, p.d, p.c) if self.want_W else None,
+                "info": b["info"].cpu().numpy().reshape(p.k, -1),
+                "flags": b["flags"].cpu().numpy().reshape(p.k, p.q),
+            })
+        return out

@@ -71,3 +71,39 @@ def test_fullsize_gram_and_factor_properties(big):
             lhs = np.dot(L[s][i, :j + 1], L[s][j, :j + 1])
             rhs = H[1][i, j] + (lam[s] if i == j else 0.0)
             assert abs(lhs - rhs) <= 1e-12 * (abs(H[1][i, i]) + lam[s])
+
+
+# ---------------------------------------------------------------- many problems
+
+@pytest.fixture(scope="module")
+def manyprob(gpu):
+    import gpu_util
+    probs = workloads.batch_problems()
+    run = gpu_util.BatchRun(probs, "interp", want_W=False)
+    return gpu_util, probs, run, run.run()
+
+
+def test_batch_fullsize_buckets_and_status(manyprob):
+    gu, probs, run, got = manyprob
+    assert len(probs) == 48
+    shapes = {(p.d, p.c) for p in probs}
+    assert gu.B.pichol_batch_buckets(run.batch, run.method) == len(shapes)
+    for i, o in enumerate(got):
+        assert np.all(o["info"] == 0) and np.all(o["flags"] == 0), i
+        assert np.all(np.isfinite(o["mse"])) and np.all(o["mse"] > 0), i
+
+
+def test_batch_fullsize_matches_oracle_and_single(manyprob):
+    gu, probs, run, got = manyprob
+    order = sorted(range(len(probs)), key=lambda i: (probs[i].d, i))
+    for i in order[:2]:  # the two smallest problems against the oracle
+        p = probs[i]
+        want = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r)
+        np.testing.assert_allclose(got[i]["mse"], want["mse"], rtol=1e-10, atol=0)
+    seen = set()
+    for i in range(len(probs)):  # one problem of every d against its own run
+        if probs[i].d in seen:
+            continue
+        seen.add(probs[i].d)
+        one = gu.cv(probs[i], "interp", want_W=False)
+        np.testing.assert_allclose(got[i]["mse"], one["mse"], rtol=1e-13, atol=0)

@@ -128,6 +128,54 @@ def rff_problem(n: int, d: int, c: int = 10, seed: int = 0, k: int = 5,
                     "lam_range": lam_range})
 
 
+def powerlaw_problem(d: int, c: int, seed: int, k: int = 5, g: int = 5,
+                     r: int = 2, q: int = 32, lam_range=(1e-4, 1e1),
+                     name: str | None = None) -> Problem:
+    """One problem of the many-problem workload: n = 8 d rows,
+    X ~ N(0,1)^{n x d} with column j (1-based) scaled by j^{-1/2};
+    teacher W0 ~ N(0,1)^{d x c}; c = 10: one-vs-all labels of
+    argmax(X W0); c = 1: sign(X w0).  Draw order: X, then W0."""
+    return _powerlaw(np.random.default_rng(seed), d, c, seed, k, g, r, q,
+                     lam_range, name)
+
+
+def _powerlaw(rng, d, c, seed, k, g, r, q, lam_range, name):
+    n = 8 * d
+    X = rng.standard_normal((n, d))
+    X *= 1.0 / np.sqrt(np.arange(1, d + 1, dtype=np.float64))
+    W0 = rng.standard_normal((d, c))
+    if c == 1:
+        Y = np.where(X @ W0 >= 0.0, 1.0, -1.0)
+    else:
+        Y = one_vs_all(np.argmax(X @ W0, axis=1), c)
+    s = lam_scale(X)
+    return Problem(name or f"plaw_d{d}_c{c}_s{seed}", np.ascontiguousarray(X),
+                   np.ascontiguousarray(Y), k, g, r,
+                   log_grid(s, *lam_range, g), log_grid(s, *lam_range, q), s,
+                   {"kind": "powerlaw", "seed": seed, "lam_range": lam_range})
+
+
+BATCH_DS = (256, 384, 512, 768, 1024, 1536, 2048)
+
+
+def batch_problems(count: int = 48, seed0: int = 1000, ds=BATCH_DS,
+                   cs=(1, 10), **kw) -> list[Problem]:
+    """The many-problem workload: problem p uses one generator seeded
+    seed0 + p, which draws d uniformly from ds, then c uniformly from cs,
+    then the problem's arrays as in powerlaw_problem (X, then W0)."""
+    opts = dict(k=5, g=5, r=2, q=32, lam_range=(1e-4, 1e1))
+    opts.update(kw)
+    out = []
+    for p in range(count):
+        rng = np.random.default_rng(seed0 + p)
+        d = int(rng.choice(ds))
+        c = int(rng.choice(cs))
+        out.append(_powerlaw(rng, d, c, seed0 + p, opts["k"], opts["g"],
+                             opts["r"], opts["q"], opts["lam_range"],
+                             f"plaw{p}_d{d}_c{c}"))
+    return out
+
+
 def config(i: int) -> Problem:
     """The workloads of the parity tests and the benchmark.
 
