@@ -82,6 +82,10 @@ def _load():
                                    _pd]),
         "orc_holdout_sst": (_dbl, [_i64, _i64, _pd, _i64]),
         "orc_refine": (_i32, [_i64, _i64, _pd, _dbl, _pd, _pd, _pd, _i32]),
+        "orc_eval_deriv": (None, [_i64, _i32, _pd, _dbl, _dbl, _pd]),
+        "orc_cv_grad": (_i32, [_i64, _i64, _i64, _i32, _i32, _i32, _i32,
+                               ctypes.c_int, ctypes.c_int, _pd, _pd, _pd, _pd,
+                               _dbl, _pd, _pd, _pi32, _pi32]),
         "orc_cv_exact": (_i32, [_i64, _i64, _i64, _i32, _i32, ctypes.c_int,
                                 _pd, _pd, _pd, _pd, _pd, _pd, _pi32, _pi32,
                                 _i32]),
@@ -246,6 +250,46 @@ def refine(H, lam: float, L, B, W, steps: int):
     fl = _load().orc_refine(d, c, _p(H), float(lam), _p(L), _p(B), _p(Wr),
                             int(steps))
     return Wr.reshape(np.shape(W)), int(fl)
+
+
+def evaluate_deriv(Theta, lam: float, lam_ref: float) -> np.ndarray:
+    """d Lhat / d lambda of the fitted polynomials (packed vector)."""
+    Theta = _f64(Theta)
+    r = Theta.shape[0] - 1
+    D = Theta.shape[1]
+    out = np.zeros(D)
+    _load().orc_eval_deriv(D, r, _p(Theta), float(lam), float(lam_ref), _p(out))
+    return out
+
+
+def cv_grad(X, Y, k: int, lam_grid, lam_s=None, r: int = 0,
+            lam_ref: float | None = None, normalize: bool = True) -> dict:
+    """Hold-out error and its derivative with respect to log lambda at every
+    grid value and fold: piCholesky when lam_s is given (degree r), the
+    exact method otherwise."""
+    X = _f64(X)
+    Y = _f64(Y)
+    if Y.ndim == 1:
+        Y = Y[:, None].copy()
+    lam_grid = _f64(lam_grid)
+    interp = lam_s is not None
+    lam_s = _f64(lam_s) if interp else np.zeros(1)
+    if lam_ref is None:
+        lam_ref = float(np.max(lam_s)) if interp else 1.0
+    n, d = X.shape
+    c = Y.shape[1]
+    g = lam_s.shape[0]
+    q = lam_grid.shape[0]
+    mse = np.zeros((k, q))
+    dlog = np.zeros((k, q))
+    info = np.zeros((k, g if interp else q), dtype=np.int32)
+    flags = np.zeros((k, q), dtype=np.int32)
+    rc = _load().orc_cv_grad(n, d, c, k, g, r, q, int(normalize), int(interp),
+                             _p(X), _p(Y), _p(lam_s), _p(lam_grid), float(lam_ref),
+                             _p(mse), _p(dlog), _p(info), _p(flags))
+    if rc != 0:
+        raise ValueError("oracle cv_grad rejected its arguments")
+    return {"mse": mse, "dlog": dlog, "info": info, "flags": flags}
 
 
 def cv_exact(X, Y, k: int, lam_grid, normalize: bool = True,

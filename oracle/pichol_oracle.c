@@ -184,6 +184,19 @@ void orc_eval(int64_t D, int32_t r, const double *Theta, double lam,
   }
 }
 
+void orc_eval_deriv(int64_t D, int32_t r, const double *Theta, double lam,
+                    double lam_ref, double *out) {
+  double tau = lam / lam_ref;
+  for (int64_t e = 0; e < D; ++e) {
+    double acc = 0.0, p = 1.0; /* p = tau^(j-1) */
+    for (int32_t j = 1; j <= r; ++j) {
+      acc += (double)j * p * Theta[(int64_t)j * D + e];
+      p *= tau;
+    }
+    out[e] = acc / lam_ref;
+  }
+}
+
 /* Sec. 3.2: L w = g by forward substitution, then L^T theta = w by back
  * substitution, for each of the c columns. */
 int32_t orc_solve(int64_t d, int64_t c, const double *L, const double *B,
@@ -428,3 +441,137 @@ int32_t orc_cv_interp(int64_t n, int64_t d, int64_t c, int32_t k, int32_t g,
   free(start);
   return rc;
 }
+
+/* out = M^T x for a dense lower d x d M (row-major) and x d x c. */
+static void lower_t_times(int64_t d, int64_t c, const double *M,
+                          const double *x, double *out) {
+  for (int64_t i = 0; i < d; ++i)
+    for (int64_t cc = 0; cc < c; ++cc) {
+      double acc = 0.0;
+      for (int64_t p = i; p < d; ++p) acc += M[p * d + i] * x[p * c + cc];
+      out[i * c + cc] = acc;
+    }
+}
+
+/* One (fold, lambda) of the gradient, given the factor L of A and, for
+ * piCholesky, dL = dLhat/dlambda (NULL for the exact method, dA = I). */
+static void unit_grad(int64_t d, int64_t c, const double *L, const double *dL,
+                      const double *B, int64_t nv, const double *Xv,
+                      const double *Yv, double lam, double *mse, double *dlog,
+                      int32_t *flags) {
+  size_t dc = (size_t)(d * c);
+  double *th = (double *)malloc(sizeof(double) * dc);
+  double *s = (double *)malloc(sizeof(double) * dc);
+  double *z = (double *)malloc(sizeof(double) * dc);
+  int32_t fl = orc_solve(d, c, L, B, th);
+  /* s = X_v^T R, R = Y_v - X_v theta, row by row */
+  for (size_t e = 0; e < dc; ++e) s[e] = 0.0;
+  double sse = 0.0;
+  for (int64_t row = 0; row < nv; ++row) {
+    const double *x = Xv + row * d;
+    for (int64_t cc = 0; cc < c; ++cc) {
+      double pred = 0.0;
+      for (int64_t p = 0; p < d; ++p) pred += x[p] * th[p * c + cc];
+      double res = Yv[row * c + cc] - pred;
+      sse += res * res;
+      for (int64_t p = 0; p < d; ++p) s[p * c + cc] += x[p] * res;
+    }
+  }
+  fl |= orc_solve(d, c, L, s, z);
+  double dot = 0.0;
+  if (dL) {
+    double *a1 = (double *)malloc(sizeof(double) * dc); /* Lhat^T theta */
+    double *b1 = (double *)malloc(sizeof(double) * dc); /* dLhat^T theta */
+    double *a2 = (double *)malloc(sizeof(double) * dc); /* Lhat^T z */
+    double *b2 = (double *)malloc(sizeof(double) * dc); /* dLhat^T z */
+    lower_t_times(d, c, L, th, a1);
+    lower_t_times(d, c, dL, th, b1);
+    lower_t_times(d, c, L, z, a2);
+    lower_t_times(d, c, dL, z, b2);
+    for (size_t e = 0; e < dc; ++e) dot += b2[e] * a1[e] + a2[e] * b1[e];
+    free(a1);
+    free(b1);
+    free(a2);
+    free(b2);
+  } else {
+    for (size_t e = 0; e < dc; ++e) dot += z[e] * th[e];
+  }
+  double cnt = (double)nv * (double)c;
+  *mse = sse / cnt;
+  *dlog = lam * 2.0 * dot / cnt;
+  if (!isfinite(*mse) || !isfinite(*dlog)) fl |= 1;
+  *flags = fl;
+  free(th);
+  free(s);
+  free(z);
+}
+
+int32_t orc_cv_grad(int64_t n, int64_t d, int64_t c, int32_t k, int32_t g,
+                    int32_t r, int32_t q, int normalize, int interp,
+                    const double *X, const double *Y, const double *lam_s,
+                    const double *lam_grid, double lam_ref, double *mse,
+                    double *dlog, int32_t *info, int32_t *flags) {
+  if (n < k || k < 2 || d < 1 || c < 1 || q < 1) return -1;
+  if (interp && (r < 0 || g <= r || !(lam_ref > 0.0))) return -1;
+  int64_t D = d * (d + 1) / 2;
+  int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k + 1));
+  orc_fold_bounds(n, k, start);
+  double *H = (double *)malloc(sizeof(double) * (size_t)(d * d));
+  double *B = (double *)malloc(sizeof(double) * (size_t)(d * c));
+  double *T = interp ? (double *)malloc(sizeof(double) * (size_t)(g * D)) : NULL;
+  double *Theta =
+      interp ? (double *)malloc(sizeof(double) * (size_t)((r + 1) * D)) : NULL;
+  int32_t rc = 0;
+  for (int32_t f = 0; f < k && rc == 0; ++f) {
+    orc_fold_gram(n, d, c, k, f, X, Y, normalize, H, B);
+    int64_t nv = start[f + 1] - start[f];
+    const double *Xv = X + start[f] * d, *Yv = Y + start[f] * c;
+    if (interp) {
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int32_t s = 0; s < g; ++s) {
+        double *L = (double *)malloc(sizeof(double) * (size_t)(d * d));
+        info[(int64_t)f * g + s] = orc_cholesky(d, H, lam_s[s], L);
+        if (info[(int64_t)f * g + s] != 0)
+          for (int64_t e = 0; e < d * d; ++e) L[e] = NAN;
+        orc_pack_lower(d, L, T + (int64_t)s * D);
+        free(L);
+      }
+      rc = orc_fit(D, g, r, lam_s, lam_ref, T, Theta);
+      if (rc != 0) break;
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t t = 0; t < q; ++t) {
+      int64_t u = (int64_t)f * q + t;
+      double *L = (double *)malloc(sizeof(double) * (size_t)(d * d));
+      double *dL = NULL;
+      if (interp) {
+        double *lt = (double *)malloc(sizeof(double) * (size_t)D);
+        dL = (double *)malloc(sizeof(double) * (size_t)(d * d));
+        orc_eval(D, r, Theta, lam_grid[t], lam_ref, lt);
+        orc_unpack_lower(d, lt, L);
+        orc_eval_deriv(D, r, Theta, lam_grid[t], lam_ref, lt);
+        orc_unpack_lower(d, lt, dL);
+        free(lt);
+      } else {
+        info[u] = orc_cholesky(d, H, lam_grid[t], L);
+      }
+      if (!interp && info[u] != 0) {
+        mse[u] = NAN;
+        dlog[u] = NAN;
+        flags[u] = 1;
+      } else {
+        unit_grad(d, c, L, dL, B, nv, Xv, Yv, lam_grid[t], &mse[u], &dlog[u],
+                  &flags[u]);
+      }
+      free(L);
+      free(dL);
+    }
+  }
+  free(H);
+  free(B);
+  free(T);
+  free(Theta);
+  free(start);
+  return rc;
+}
+

@@ -70,6 +70,11 @@ int32_t orc_fit(int64_t D, int32_t g, int32_t r, const double *lam_s,
 void orc_eval(int64_t D, int32_t r, const double *Theta, double lam,
               double lam_ref, double *out);
 
+/* Derivative of the interpolated factor with respect to lambda:
+ * sum_j j tau^(j-1) / lam_ref Theta_j, tau = lam / lam_ref. */
+void orc_eval_deriv(int64_t D, int32_t r, const double *Theta, double lam,
+                    double lam_ref, double *out);
+
 /* Forward substitution L U = B, then back substitution L^T W = U
  * (Sec. 3.2).  L is d x d lower (only the lower triangle is read), B and W are
  * d x c.  Never aborts.  Returns flag bits (bit1: some L_ii <= 0, bit0: some
@@ -141,6 +146,24 @@ int32_t orc_fold_interp(int64_t d, int64_t c, int32_t g, int32_t r, int32_t q,
                         const double *lam_grid, double lam_ref, double *mse,
                         double *W, int32_t *info, int32_t *flags,
                         int32_t refine);
+
+/* Derivative of the hold-out error with respect to log lambda, for every
+ * fold and grid value (the differentiation form).  With A the matrix whose
+ * Cholesky factor the method uses at lambda (Lhat Lhat^T for piCholesky,
+ * H_f + lambda I for the exact method), theta = A^{-1} B_f,
+ * R = Y_v - X_v theta and z = A^{-1} X_v^T R:
+ *   d mse / d lambda = 2/(n_v c) <z, (dA/dlambda) theta>,
+ * with dA = dLhat Lhat^T + Lhat dLhat^T and dLhat = orc_eval_deriv for
+ * piCholesky, so the product is <dLhat^T z, Lhat^T theta> +
+ * <Lhat^T z, dLhat^T theta>; dA = I for the exact method.
+ * dlog = lambda * d mse / d lambda.  mse as in the CV calls.
+ * interp != 0: piCholesky (lam_s, r used); interp == 0: exact factors.
+ * Returns 0, or -1 on invalid arguments. */
+int32_t orc_cv_grad(int64_t n, int64_t d, int64_t c, int32_t k, int32_t g,
+                    int32_t r, int32_t q, int normalize, int interp,
+                    const double *X, const double *Y, const double *lam_s,
+                    const double *lam_grid, double lam_ref, double *mse,
+                    double *dlog, int32_t *info, int32_t *flags);
 
 /* Number of OpenMP threads the oracle runs with. */
 int32_t orc_num_threads(void);

@@ -473,3 +473,72 @@ def test_refined_fold_interp_matches_cv_interp():
     one = oracle.fold_interp(H, B, p.X[b[1]:b[2]], p.Y[b[1]:b[2]], p.lam_s,
                              p.lam_grid, p.r, want_W=True, refine=2)
     np.testing.assert_array_equal(one["mse"], full["mse"][1])
+
+
+# ------------------------------------------------------------------ gradient of the hold-out error
+
+def test_eval_deriv_is_the_polynomial_derivative():
+    rng = np.random.default_rng(3)
+    Theta = rng.standard_normal((3, 11))
+    lam_ref, lam, h = 2.0, 0.7, 1e-5
+    num = (oracle.evaluate(Theta, lam + h, lam_ref)
+           - oracle.evaluate(Theta, lam - h, lam_ref)) / (2 * h)
+    # a quadratic: the central difference is exact up to rounding
+    np.testing.assert_allclose(oracle.evaluate_deriv(Theta, lam, lam_ref), num,
+                               rtol=1e-8, atol=1e-9)
+    tau = lam / lam_ref
+    want = (Theta[1] + 2 * tau * Theta[2]) / lam_ref
+    np.testing.assert_allclose(oracle.evaluate_deriv(Theta, lam, lam_ref), want,
+                               rtol=1e-14, atol=1e-15)
+
+
+def _fd_dlog(fn, lam_grid, h=1e-4):
+    return (fn(lam_grid * np.exp(h)) - fn(lam_grid * np.exp(-h))) / (2 * h)
+
+
+def test_interp_gradient_matches_central_differences():
+    p = workloads.gaussian_problem(300, 24, 3, seed=6, g=4, q=9)
+    got = oracle.cv_grad(p.X, p.Y, p.k, p.lam_grid, p.lam_s, p.r)
+    assert np.all(got["flags"] == 0)
+    fd = _fd_dlog(lambda lg: oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, lg, p.r,
+                                              lam_ref=p.lam_ref)["mse"], p.lam_grid)
+    scale = np.abs(got["dlog"]).max()
+    assert np.abs(fd - got["dlog"]).max() <= 1e-6 * scale
+    ref = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r)
+    np.testing.assert_array_equal(got["mse"], ref["mse"])
+
+
+def test_exact_gradient_matches_svd_closed_form():
+    """d mse / d lambda from the SVD form of ridge regression:
+    theta = V diag(s/(s^2+lam)) U^T y, d theta/d lam = -V diag(s/(s^2+lam)^2) U^T y."""
+    n, d, c, k = 203, 17, 4, 5
+    p = workloads.gaussian_problem(n, d, c, seed=21, k=k, q=7)
+    got = oracle.cv_grad(p.X, p.Y, k, p.lam_grid)
+    b = oracle.fold_bounds(n, k)
+    for f in range(k):
+        mask = np.ones(n, bool)
+        mask[b[f]:b[f + 1]] = False
+        Xt, Yt = p.X[mask] / np.sqrt(mask.sum()), p.Y[mask] / np.sqrt(mask.sum())
+        Xv, Yv = p.X[~mask], p.Y[~mask]
+        U, sig, Vt = np.linalg.svd(Xt, full_matrices=False)
+        UtY = U.T @ Yt
+        for t, lam in enumerate(p.lam_grid):
+            th = Vt.T @ ((sig / (sig ** 2 + lam))[:, None] * UtY)
+            dth = -Vt.T @ ((sig / (sig ** 2 + lam) ** 2)[:, None] * UtY)
+            R = Yv - Xv @ th
+            dmse = -2.0 * np.sum(R * (Xv @ dth)) / Yv.size
+            np.testing.assert_allclose(got["dlog"][f, t], lam * dmse, rtol=1e-8,
+                                       atol=1e-12)
+    fd = _fd_dlog(lambda lg: oracle.cv_exact(p.X, p.Y, k, lg)["mse"], p.lam_grid)
+    assert np.abs(fd - got["dlog"]).max() <= 1e-6 * np.abs(got["dlog"]).max()
+
+
+def test_gradient_scale_error_would_be_caught():
+    """The central-difference check is sharp: a gradient off by a factor of
+    two (as from a dropped symmetric term of dA = dL L^T + L dL^T when the
+    two terms are close) misses it by far more than its tolerance."""
+    p = workloads.gaussian_problem(300, 24, 3, seed=6, g=4, q=9)
+    got = oracle.cv_grad(p.X, p.Y, p.k, p.lam_grid, p.lam_s, p.r)
+    fd = _fd_dlog(lambda lg: oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, lg, p.r,
+                                              lam_ref=p.lam_ref)["mse"], p.lam_grid)
+    assert np.abs(fd - 0.5 * got["dlog"]).max() > 1e-2 * np.abs(fd).max()
