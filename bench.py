@@ -307,6 +307,94 @@ def batching_leg(args, B, stream):
     return out
 
 
+def differentiation_leg(args, B, stream):
+    """d(hold-out error)/d(log lambda) at 64 grid values on the d = 2048
+    random-Fourier-feature workload (n = 20000, k = 5, g = 6, r = 2):
+    the forward piCholesky stage alone, forward + adjoint, the exact
+    method's gradient, a central-difference check of the adjoint and its gap
+    to the exact gradient."""
+    import torch
+    import workloads
+
+    t0 = time.perf_counter()
+    pb = workloads.config(2)
+    log(f"differentiation workload {pb.name} ({time.perf_counter() - t0:.1f} s)")
+    dev = torch.device("cuda:0")
+    n, d, c, k, g, r, q = pb.n, pb.d, pb.c, pb.k, pb.g, pb.r, pb.q
+    p = B.make_problem(n, d, c, k, g, r, q, True)
+    nbytes = B.pichol_workspace_size(
+        p, B.PICHOL_METHOD_INTERP | B.PICHOL_METHOD_EXACT | B.PICHOL_METHOD_GRAD)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    X = torch.from_numpy(pb.X).to(dev)
+    Y = torch.from_numpy(pb.Y).to(dev)
+    err = torch.empty(k * q, dtype=torch.float64, device=dev)
+    dlog = torch.empty(k * q, dtype=torch.float64, device=dev)
+    err_e = torch.empty(k * q, dtype=torch.float64, device=dev)
+    dlog_e = torch.empty(k * q, dtype=torch.float64, device=dev)
+    info = torch.empty(k * q, dtype=torch.int32, device=dev)
+    flags = torch.empty(k * q, dtype=torch.int32, device=dev)
+    B.pichol_cv_gram(p, X, Y, ws, nbytes)
+
+    def timed(fn):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        s1.record(stream)
+        torch.cuda.synchronize()
+        return s0.elapsed_time(s1) / args.steps
+
+    fwd = lambda lam: B.pichol_cv_interp(p, pb.lam_s, lam, pb.lam_ref, ws, nbytes, err,
+                                         None, info, flags)
+    t_fwd = timed(lambda: fwd(pb.lam_grid))
+    t_grad = timed(lambda: B.pichol_cv_interp_grad(p, pb.lam_s, pb.lam_grid, pb.lam_ref,
+                                                   ws, nbytes, err, dlog, None, info,
+                                                   flags))
+    ok = bool((info[:k * g] == 0).all()) and bool((flags == 0).all())
+    gi = dlog.cpu().numpy().reshape(k, q)
+    mi = err.cpu().numpy().reshape(k, q)
+    t_ex = timed(lambda: B.pichol_cv_exact_grad(p, pb.lam_grid, ws, nbytes, err_e, dlog_e,
+                                                None, info, flags))
+    ge = dlog_e.cpu().numpy().reshape(k, q)
+    h = 1e-4
+    fwd(pb.lam_grid * np.exp(h))
+    up = err.cpu().numpy().reshape(k, q)
+    fwd(pb.lam_grid * np.exp(-h))
+    dn = err.cpu().numpy().reshape(k, q)
+    fd = (up - dn) / (2 * h)
+    fd_err = float(np.abs(fd - gi).max() / np.abs(gi).max())
+    cm_i, cm_e = gi.mean(0), ge.mean(0)
+
+    def zero_cross(v):
+        idx = np.nonzero((v[:-1] < 0) & (v[1:] >= 0))[0]
+        return float(pb.lam_grid[idx[0]]) if idx.size else None
+
+    out = {
+        "workload": f"{pb.name}: random Fourier features n={n}, d={d}, c={c}, k={k}, "
+                    f"g={g}, r={r}, q={q}",
+        "forward_ms": t_fwd, "forward_plus_grad_ms": t_grad,
+        "grad_overhead": t_grad / t_fwd - 1.0,
+        "exact_grad_ms": t_ex,
+        "value": k * q / (t_grad * 1e-3), "unit": "λ-solves with d err/d log λ per s",
+        "ok": ok, "dtype": "f64",
+        "fd_check_max_rel": fd_err,
+        "grad_gap_vs_exact_max_rel": float(np.abs(cm_i - cm_e).max() / np.abs(cm_e).max()),
+        "stationary_lambda_interp": zero_cross(cm_i),
+        "stationary_lambda_exact": zero_cross(cm_e),
+        "mse_gap_vs_exact_max_rel": float(np.max(np.abs(mi.mean(0) - err_e.cpu().numpy()
+                                                        .reshape(k, q).mean(0))
+                                                 / err_e.cpu().numpy().reshape(k, q).mean(0))),
+    }
+    log(f"differentiation: forward {t_fwd:.2f} ms, forward+grad {t_grad:.2f} ms, exact grad "
+        f"{t_ex:.2f} ms; FD check {fd_err:.2e}; gap to exact gradient "
+        f"{out['grad_gap_vs_exact_max_rel']:.2e}")
+    del ws
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +413,8 @@ def main():
                     help="skip the precision-form legs timed after the FP64 "
                          "headline (FP32-MFMA trailing updates, iterative "
                          "refinement)")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the differentiation-form leg (d=2048 workload)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the many-problem (batching form) leg")
     ap.add_argument("--refine", type=int, default=2,
@@ -463,6 +553,10 @@ def main():
     if not args.no_batch:
         batching = batching_leg(args, B, stream)
 
+    differentiation = None
+    if not args.no_grad:
+        differentiation = differentiation_leg(args, B, stream)
+
     roofline = None
     kernels = None
     if not args.no_profile:
@@ -522,6 +616,7 @@ def main():
         **result_extra,
         "precision_forms": variants,
         "batching_form": batching,
+        "differentiation_form": differentiation,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

@@ -74,7 +74,8 @@ typedef enum {
 
 typedef enum {
   PICHOL_METHOD_INTERP = 1, /* piCholesky: Algorithm 1 + evaluation         */
-  PICHOL_METHOD_EXACT = 2   /* one exact factorization per grid value       */
+  PICHOL_METHOD_EXACT = 2,  /* one exact factorization per grid value       */
+  PICHOL_METHOD_GRAD = 4    /* workspace flag: room for the *_grad calls    */
 } pichol_method;
 
 /* Arithmetic of the factorizations (Sec. 3.2; Algorithm 1 step 1).
@@ -312,6 +313,37 @@ pichol_status pichol_cv_exact(const pichol_problem *p, const double *lam_grid,
                               void *ws, size_t ws_bytes, double *err,
                               double *W, int32_t *info, int32_t *flags,
                               hipStream_t stream);
+
+/* Differentiation form: pichol_cv_interp, then the derivative of every
+ * hold-out error with respect to log lambda through the interpolated factor
+ * (the polynomial of Sec. 3.3 is differentiable in lambda):
+ *   A = Lhat Lhat^T, theta = A^{-1} B_f, R = Y_v - X_v theta,
+ *   z = A^{-1} X_v^T R (X_v^T R = C_v - G_v theta from the validation
+ *   block's Gram matrices; one more pair of interpolated solves),
+ *   d err / d lambda = 2/(n_v c) (<dLhat^T z, Lhat^T theta>
+ *                                + <Lhat^T z, dLhat^T theta>),
+ *   dLhat = sum_j j tau^(j-1) / lam_ref Theta_j,
+ *   dlog = lambda * d err / d lambda.
+ * lam_ref and the samples stay fixed (they define the fit).  All FP64.
+ * Out: dlog k*q (device) besides the outputs of pichol_cv_interp.
+ * p->refine must be 0.  ws: pichol_workspace_size with
+ * PICHOL_METHOD_INTERP | PICHOL_METHOD_GRAD. */
+pichol_status pichol_cv_interp_grad(const pichol_problem *p,
+                                    const double *lam_s,
+                                    const double *lam_grid, double lam_ref,
+                                    void *ws, size_t ws_bytes, double *err,
+                                    double *dlog, double *W, int32_t *info,
+                                    int32_t *flags, hipStream_t stream);
+
+/* The same derivative for the exact method (dA/dlambda = I):
+ * d err / d lambda = 2/(n_v c) <z, theta>, z = (H_f + lambda I)^{-1} X_v^T R,
+ * i.e. the exact gradient the interpolated one approximates.
+ * ws: pichol_workspace_size with PICHOL_METHOD_EXACT | PICHOL_METHOD_GRAD. */
+pichol_status pichol_cv_exact_grad(const pichol_problem *p,
+                                   const double *lam_grid, void *ws,
+                                   size_t ws_bytes, double *err, double *dlog,
+                                   double *W, int32_t *info, int32_t *flags,
+                                   hipStream_t stream);
 
 /* pichol_cv_gram followed by pichol_cv_interp. */
 pichol_status pichol_cv(const pichol_problem *p, const double *X,

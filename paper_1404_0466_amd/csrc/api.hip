@@ -183,6 +183,11 @@ struct Layout {
   // refinement scratch (full-tile H_f and the correction slab), appended to
   // each method's region when refine > 0
   size_t i_rH, i_rZ, i_lamg, e_rH, e_rZ;
+  // gradient scratch (pichol_cv_interp_grad / pichol_cv_exact_grad): the
+  // adjoint right-hand sides, four transposed products, plane weights, a
+  // zero shift and per-tile partial sums
+  size_t i_gS, i_ga1, i_gb1, i_ga2, i_gb2, i_gw, i_gzero, i_gpart, i_gend;
+  size_t e_gS, e_gzero, e_gpart, e_gend;
 };
 
 static Layout layout_of(const pichol_problem* p) {
@@ -218,6 +223,16 @@ static Layout layout_of(const pichol_problem* p) {
   L.i_rH = a; a += rH;
   L.i_rZ = a; a += rZ;
   L.i_end = a;
+  const size_t slab = align256(k * L.dp * L.ldz * dbl);
+  L.i_gS = a; a += slab;
+  L.i_ga1 = a; a += slab;
+  L.i_gb1 = a; a += slab;
+  L.i_ga2 = a; a += slab;
+  L.i_gb2 = a; a += slab;
+  L.i_gw = a; a += align256(2 * 8 * q * dbl);
+  L.i_gzero = a; a += align256(q * dbl);
+  L.i_gpart = a; a += align256(k * L.nt * q * dbl);
+  L.i_gend = a;
   a = o;
   L.e_lam = a; a += align256(q * dbl);
   L.e_L = a; a += align256(k * q * L.S * dbl);
@@ -227,6 +242,10 @@ static Layout layout_of(const pichol_problem* p) {
   L.e_rH = a; a += rH;
   L.e_rZ = a; a += rZ;
   L.e_end = a;
+  L.e_gS = a; a += slab;
+  L.e_gzero = a; a += align256(q * dbl);
+  L.e_gpart = a; a += align256(k * L.nt * q * dbl);
+  L.e_gend = a;
   return L;
 }
 
@@ -524,12 +543,16 @@ pichol_status pichol_slab_to_weights(int64_t d, int32_t nmat, int32_t q,
 pichol_status pichol_workspace_size(const pichol_problem* p, int32_t methods,
                                     size_t* bytes) {
   if (!bytes || !problem_ok(p) ||
-      (methods & ~(PICHOL_METHOD_INTERP | PICHOL_METHOD_EXACT)) || !methods)
+      (methods & ~(PICHOL_METHOD_INTERP | PICHOL_METHOD_EXACT |
+                   PICHOL_METHOD_GRAD)) ||
+      !(methods & (PICHOL_METHOD_INTERP | PICHOL_METHOD_EXACT)))
     return PICHOL_ERR_ARG;
   const Layout L = layout_of(p);
+  const bool grad = (methods & PICHOL_METHOD_GRAD) != 0;
   size_t end = L.region;
-  if (methods & PICHOL_METHOD_INTERP) end = end > L.i_end ? end : L.i_end;
-  if (methods & PICHOL_METHOD_EXACT) end = end > L.e_end ? end : L.e_end;
+  const size_t ie = grad ? L.i_gend : L.i_end, ee = grad ? L.e_gend : L.e_end;
+  if (methods & PICHOL_METHOD_INTERP) end = end > ie ? end : ie;
+  if (methods & PICHOL_METHOD_EXACT) end = end > ee ? end : ee;
   *bytes = end;
   return PICHOL_OK;
 }
@@ -664,6 +687,109 @@ pichol_status pichol_cv_exact(const pichol_problem* p, const double* lam_grid,
                        at<double>(ws, L.e_part), err, flags, stream);
   if (e == hipSuccess && W)
     e = launch_slab_to_weights(p->d, k, q, c, L.ldz, Z, W, stream);
+  return hip_status(e);
+}
+
+pichol_status pichol_cv_interp_grad(const pichol_problem* p,
+                                    const double* lam_s,
+                                    const double* lam_grid, double lam_ref,
+                                    void* ws, size_t ws_bytes, double* err,
+                                    double* dlog, double* W, int32_t* info,
+                                    int32_t* flags, hipStream_t stream) {
+  if (!problem_ok(p) || p->refine != 0 || !dlog) return PICHOL_ERR_ARG;
+  const Layout L = layout_of(p);
+  if (!ws || ws_bytes < L.i_gend) return PICHOL_ERR_WORKSPACE;
+  // forward: the piCholesky stage (solutions in the slab, hold-out errors)
+  pichol_status st = pichol_cv_interp(p, lam_s, lam_grid, lam_ref, ws, ws_bytes,
+                                      err, W, info, flags, stream);
+  if (st != PICHOL_OK) return st;
+  const int k = p->k, q = p->q, c = (int)p->c, M = p->r + 1;
+  double* Z = at<double>(ws, L.i_Z);
+  double* Sg = at<double>(ws, L.i_gS);
+  double* th_t = at<double>(ws, L.i_tht);
+  double* wts = at<double>(ws, L.i_gw);
+  // plane weights per lambda: tau^p (value) and p tau^(p-1) / lam_ref
+  std::vector<double> w(2 * 8 * (size_t)q, 0.0), zero(q, 0.0);
+  for (int t = 0; t < q; ++t) {
+    const double tau = lam_grid[t] / lam_ref;
+    double pw = 1.0, pwm1 = 0.0;  // tau^p, tau^(p-1)
+    for (int pp = 0; pp < M; ++pp) {
+      w[(size_t)pp * q + t] = pw;
+      w[(size_t)(8 + pp) * q + t] = pp == 0 ? 0.0 : (double)pp * pwm1 / lam_ref;
+      pwm1 = pw;
+      pw *= tau;
+    }
+  }
+  HoldoutNorm hn;
+  holdout_norm(p, &hn);
+  double* lamg = at<double>(ws, L.i_lamg);
+  hipError_t e = launch_store_doubles(w.data(), 16 * q, wts, stream);
+  if (e == hipSuccess)
+    e = launch_store_doubles(zero.data(), q, at<double>(ws, L.i_gzero), stream);
+  if (e == hipSuccess) e = launch_store_doubles(lam_grid, q, lamg, stream);
+  // X_v^T R = C_v - G_v theta for every lambda (a zero shift)
+  if (e == hipSuccess)
+    e = launch_residual(p->d, k, q, c, L.ldz, at<double>(ws, L.G),
+                        at<double>(ws, L.C), at<double>(ws, L.i_gzero), Z, Sg,
+                        stream);
+  // z = A^{-1} X_v^T R with the stored diagonal-block inverses
+  if (e == hipSuccess)
+    e = launch_solve_interp(p->d, k, c, M, at<double>(ws, L.i_th), th_t, q,
+                            at<double>(ws, L.i_tau), L.ldz, Sg, flags,
+                            at<double>(ws, L.i_dinv), at<double>(ws, L.i_dinvr),
+                            0, stream);
+  double* a1 = at<double>(ws, L.i_ga1);
+  double* b1 = at<double>(ws, L.i_gb1);
+  double* a2 = at<double>(ws, L.i_ga2);
+  double* b2 = at<double>(ws, L.i_gb2);
+  if (e == hipSuccess)
+    e = launch_trmv_interp(p->d, k, M, q, c, L.ldz, th_t, wts, Z, a1, stream);
+  if (e == hipSuccess)
+    e = launch_trmv_interp(p->d, k, M, q, c, L.ldz, th_t, wts + 8 * q, Z, b1,
+                           stream);
+  if (e == hipSuccess)
+    e = launch_trmv_interp(p->d, k, M, q, c, L.ldz, th_t, wts, Sg, a2, stream);
+  if (e == hipSuccess)
+    e = launch_trmv_interp(p->d, k, M, q, c, L.ldz, th_t, wts + 8 * q, Sg, b2,
+                           stream);
+  // <dLhat^T z, Lhat^T theta> + <Lhat^T z, dLhat^T theta>
+  if (e == hipSuccess)
+    e = launch_grad_dot(p->d, k, q, c, L.ldz, b2, a1, a2, b1, lamg, hn,
+                        at<double>(ws, L.i_gpart), dlog, flags, stream);
+  return hip_status(e);
+}
+
+pichol_status pichol_cv_exact_grad(const pichol_problem* p,
+                                   const double* lam_grid, void* ws,
+                                   size_t ws_bytes, double* err, double* dlog,
+                                   double* W, int32_t* info, int32_t* flags,
+                                   hipStream_t stream) {
+  if (!problem_ok(p) || p->refine != 0 || !dlog) return PICHOL_ERR_ARG;
+  const Layout L = layout_of(p);
+  if (!ws || ws_bytes < L.e_gend) return PICHOL_ERR_WORKSPACE;
+  pichol_status st =
+      pichol_cv_exact(p, lam_grid, ws, ws_bytes, err, W, info, flags, stream);
+  if (st != PICHOL_OK) return st;
+  const int k = p->k, q = p->q, c = (int)p->c;
+  double* Z = at<double>(ws, L.e_Z);
+  double* Sg = at<double>(ws, L.e_gS);
+  std::vector<double> zero(q, 0.0);
+  HoldoutNorm hn;
+  holdout_norm(p, &hn);
+  hipError_t e =
+      launch_store_doubles(zero.data(), q, at<double>(ws, L.e_gzero), stream);
+  if (e == hipSuccess)
+    e = launch_residual(p->d, k, q, c, L.ldz, at<double>(ws, L.G),
+                        at<double>(ws, L.C), at<double>(ws, L.e_gzero), Z, Sg,
+                        stream);
+  if (e == hipSuccess)
+    e = launch_solve_factors(p->d, k, q, c, at<double>(ws, L.e_L), L.ldz, Sg,
+                             flags, stream);
+  // dA/dlambda = I: <z, theta>
+  if (e == hipSuccess)
+    e = launch_grad_dot(p->d, k, q, c, L.ldz, Sg, Z, nullptr, nullptr,
+                        at<double>(ws, L.e_lam), hn, at<double>(ws, L.e_gpart),
+                        dlog, flags, stream);
   return hip_status(e);
 }
 

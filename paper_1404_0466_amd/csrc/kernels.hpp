@@ -120,4 +120,16 @@ hipError_t launch_residual(int64_t d, int nmat, int q, int c, int64_t ldz,
 hipError_t launch_slab_add(int64_t d, int nmat, int64_t ldz, const double* D,
                            double* Z, hipStream_t s);
 
+// ---- derivative of the hold-out error (k_grad.hip)
+hipError_t launch_trmv_interp(int64_t d, int nmat, int M, int q, int c,
+                              int64_t ldz, const double* theta_t,
+                              const double* w_dev, const double* X, double* Out,
+                              hipStream_t s);
+hipError_t launch_grad_dot(int64_t d, int nmat, int q, int c, int64_t ldz,
+                           const double* x1, const double* y1,
+                           const double* x2, const double* y2,
+                           const double* lam_dev, const HoldoutNorm& hn,
+                           double* partial, double* dlog, int* flags,
+                           hipStream_t s);
+
 }  // namespace pichol

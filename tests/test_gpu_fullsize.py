@@ -107,3 +107,38 @@ def test_batch_fullsize_matches_oracle_and_single(manyprob):
         seen.add(probs[i].d)
         one = gu.cv(probs[i], "interp", want_W=False)
         np.testing.assert_allclose(got[i]["mse"], one["mse"], rtol=1e-13, atol=0)
+
+
+# ---------------------------------------------------------------- derivative at d=2048
+
+@pytest.fixture(scope="module")
+def c5(gpu):
+    import gpu_util
+    return gpu_util, workloads.config(2)
+
+
+def _grad(gu, prob, lam_grid, method="interp"):
+    from test_gpu_grad import gpu_grad
+    return gpu_grad(gu, prob, method, lam_grid)
+
+
+def test_fullsize_grad_sampled_against_oracle(c5):
+    """d = 2048 random Fourier features (n = 20000, k = 5, g = 6, r = 2):
+    the derivative at four of the 64 grid values against the oracle."""
+    gu, p = c5
+    lam = p.lam_grid[[0, 21, 42, 63]]
+    got = _grad(gu, p, lam)
+    want = oracle.cv_grad(p.X, p.Y, p.k, lam, p.lam_s, p.r)
+    assert np.all(got["flags"] == 0) and np.all(want["flags"] == 0)
+    np.testing.assert_allclose(got["mse"], want["mse"], rtol=1e-10, atol=0)
+    assert np.abs(got["dlog"] - want["dlog"]).max() <= 1e-9 * np.abs(want["dlog"]).max()
+
+
+def test_fullsize_grad_matches_central_differences(c5):
+    gu, p = c5
+    got = _grad(gu, p, p.lam_grid)
+    h = 1e-4
+    up = gu.cv(p, "interp", lam_grid=p.lam_grid * np.exp(h), want_W=False)["mse"]
+    dn = gu.cv(p, "interp", lam_grid=p.lam_grid * np.exp(-h), want_W=False)["mse"]
+    fd = (up - dn) / (2 * h)
+    assert np.abs(fd - got["dlog"]).max() <= 1e-6 * np.abs(got["dlog"]).max()
