@@ -75,7 +75,8 @@ typedef enum {
 typedef enum {
   PICHOL_METHOD_INTERP = 1, /* piCholesky: Algorithm 1 + evaluation         */
   PICHOL_METHOD_EXACT = 2,  /* one exact factorization per grid value       */
-  PICHOL_METHOD_GRAD = 4    /* workspace flag: room for the *_grad calls    */
+  PICHOL_METHOD_GRAD = 4,   /* workspace flag: room for the *_grad calls    */
+  PICHOL_METHOD_PINRMSE = 8 /* hold-out errors interpolated directly        */
 } pichol_method;
 
 /* Arithmetic of the factorizations (Sec. 3.2; Algorithm 1 step 1).
@@ -344,6 +345,22 @@ pichol_status pichol_cv_exact_grad(const pichol_problem *p,
                                    size_t ws_bytes, double *err, double *dlog,
                                    double *W, int32_t *info, int32_t *flags,
                                    hipStream_t stream);
+
+/* The hold-out-error variant of Algorithm 1 (PINRMSE, Sec. 6.5 and its
+ * supplement): the exact hold-out errors at the g samples (exact Cholesky,
+ * as pichol_cv_exact at lambda = lam_s) take the place of the g x D matrix
+ * T, i.e. the polynomial of degree r in tau = lambda/lam_ref is fitted to
+ * the g errors of each fold and evaluated at the q grid values.
+ * Needs the Gram matrices in ws (pichol_cv_gram).
+ * Out: err k*q (device) the interpolated hold-out errors; err_s k*g
+ *      (device, may be NULL) the exact errors at the samples; info, flags
+ *      k*g (device) the status of the sample factorizations and solves.
+ * ws: pichol_workspace_size with PICHOL_METHOD_PINRMSE. */
+pichol_status pichol_cv_pinrmse(const pichol_problem *p, const double *lam_s,
+                                const double *lam_grid, double lam_ref,
+                                void *ws, size_t ws_bytes, double *err,
+                                double *err_s, int32_t *info, int32_t *flags,
+                                hipStream_t stream);
 
 /* pichol_cv_gram followed by pichol_cv_interp. */
 pichol_status pichol_cv(const pichol_problem *p, const double *X,

@@ -389,6 +389,49 @@ def fold_interp(H, B, Xv, Yv, lam_s, lam_grid, r: int,
     return {"mse": mse, "W": W, "info": info, "flags": flags}
 
 
+# ---------------------------------------------------------------- the paper's variants (Sec. 6.2, 6.5)
+
+def pinrmse(X, Y, k: int, lam_s, lam_grid, r: int, lam_ref: float | None = None,
+            normalize: bool = True) -> dict:
+    """PINRMSE (Sec. 6.5): Algorithm 1 with the g x D matrix T replaced by
+    the g-vector of exact hold-out errors at the samples, fold by fold; the
+    fitted polynomial is evaluated at the grid."""
+    lam_s = _f64(lam_s)
+    lam_grid = _f64(lam_grid)
+    if lam_ref is None:
+        lam_ref = float(np.max(lam_s))
+    ex = cv_exact(X, Y, k, lam_s, normalize=normalize)
+    mse = np.zeros((k, lam_grid.shape[0]))
+    for f in range(k):
+        t = ex["mse"][f][:, None].copy()          # g x 1 in place of T
+        theta = fit(t, lam_s, r, lam_ref)          # (r+1) x 1
+        for j, lam in enumerate(lam_grid):
+            mse[f, j] = evaluate(theta, lam, lam_ref)[0]
+    return {"mse": mse, "mse_samples": ex["mse"], "info": ex["info"],
+            "flags": ex["flags"]}
+
+
+def mchol(X, Y, k: int, c0: float, s: float = 1.5, s0: float = 0.0025,
+          normalize: bool = True) -> dict:
+    """Multi-level Cholesky search (MChol, Sec. 6.2): starting from the
+    range [10^(c-s), 10^(c+s)], evaluate the fold-mean hold-out error with
+    exact factors at 10^(c-s), 10^c, 10^(c+s), move c to the best of the
+    three (ties: the smallest lambda), halve s, and stop once s <= s0.
+    Returns the final lambda = 10^c and the visited points."""
+    c = float(c0)
+    trace = []
+    while True:
+        lams = 10.0 ** np.array([c - s, c, c + s])
+        cvv = cv_exact(X, Y, k, lams, normalize=normalize)["mse"].mean(axis=0)
+        j = int(np.argmin(cvv))
+        trace.append((lams, cvv))
+        c = float(np.log10(lams[j]))
+        s = s / 2.0
+        if s <= s0:
+            break
+    return {"lam": 10.0 ** c, "log10_lam": c, "trace": trace}
+
+
 # ---------------------------------------------------------------- selection (Sec. 6)
 
 def cv_curve(mse) -> np.ndarray:

@@ -28,6 +28,7 @@ PICHOL_ERR_DATA = -5
 PICHOL_METHOD_INTERP = 1
 PICHOL_METHOD_EXACT = 2
 PICHOL_METHOD_GRAD = 4
+PICHOL_METHOD_PINRMSE = 8
 PICHOL_OPT_LOOKAHEAD = 1
 PICHOL_PREC_FP64 = 0
 PICHOL_PREC_MIXED = 1
@@ -110,6 +111,8 @@ _SIGNATURES = {
                                      _vp, _vp, _vp, _vp, _vp]),
     "pichol_cv_exact_grad": (_i32, [_pprob, _vp, _vp, _sz, _vp, _vp, _vp, _vp,
                                     _vp, _vp]),
+    "pichol_cv_pinrmse": (_i32, [_pprob, _vp, _vp, _dbl, _vp, _sz, _vp, _vp,
+                                 _vp, _vp, _vp]),
     "pichol_cv": (_i32, [_pprob, _vp, _vp, _vp, _vp, _dbl, _vp, _sz, _vp, _vp,
                          _vp, _vp, _vp]),
     "pichol_exact_cv": (_i32, [_pprob, _vp, _vp, _vp, _vp, _sz, _vp, _vp, _vp,
@@ -364,6 +367,16 @@ def pichol_cv_exact_grad(p: Problem, lam_grid, ws, ws_bytes, err, dlog, W, info,
     _check("pichol_cv_exact_grad", load().pichol_cv_exact_grad(
         ctypes.byref(p), lg.ptr, _dev(ws), ws_bytes, _dev(err, _f64()),
         _dev(dlog, _f64()), _dev(W, _f64()), _dev(info, _i32t()),
+        _dev(flags, _i32t()), _stream(stream)))
+
+
+def pichol_cv_pinrmse(p: Problem, lam_s, lam_grid, lam_ref, ws, ws_bytes, err,
+                      err_s, info, flags, stream=None):
+    ls = _Host(lam_s, np.float64)
+    lg = _Host(lam_grid, np.float64)
+    _check("pichol_cv_pinrmse", load().pichol_cv_pinrmse(
+        ctypes.byref(p), ls.ptr, lg.ptr, float(lam_ref), _dev(ws), ws_bytes,
+        _dev(err, _f64()), _dev(err_s, _f64()), _dev(info, _i32t()),
         _dev(flags, _i32t()), _stream(stream)))
 
 

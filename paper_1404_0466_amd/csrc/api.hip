@@ -540,13 +540,42 @@ pichol_status pichol_slab_to_weights(int64_t d, int32_t nmat, int32_t q,
                                            Z, W, stream));
 }
 
+// PINRMSE workspace: the exact pipeline's layout at the g samples, then the
+// sample errors and the scaled grid values.
+static size_t pinrmse_es(const pichol_problem* p) {
+  pichol_problem ps = *p;
+  ps.q = p->g;
+  ps.refine = 0;
+  return layout_of(&ps).e_end;
+}
+static size_t pinrmse_tau(const pichol_problem* p) {
+  return pinrmse_es(p) + align256((size_t)p->k * p->g * sizeof(double));
+}
+static size_t pinrmse_end(const pichol_problem* p) {
+  return pinrmse_tau(p) + align256((size_t)p->q * sizeof(double));
+}
+
 pichol_status pichol_workspace_size(const pichol_problem* p, int32_t methods,
                                     size_t* bytes) {
   if (!bytes || !problem_ok(p) ||
       (methods & ~(PICHOL_METHOD_INTERP | PICHOL_METHOD_EXACT |
-                   PICHOL_METHOD_GRAD)) ||
-      !(methods & (PICHOL_METHOD_INTERP | PICHOL_METHOD_EXACT)))
+                   PICHOL_METHOD_GRAD | PICHOL_METHOD_PINRMSE)) ||
+      !(methods & (PICHOL_METHOD_INTERP | PICHOL_METHOD_EXACT |
+                   PICHOL_METHOD_PINRMSE)))
     return PICHOL_ERR_ARG;
+  if (methods & PICHOL_METHOD_PINRMSE) {
+    size_t pe = pinrmse_end(p);
+    if ((methods & ~PICHOL_METHOD_PINRMSE) == 0) {
+      *bytes = pe;
+      return PICHOL_OK;
+    }
+    size_t rest = 0;
+    pichol_status st = pichol_workspace_size(p, methods & ~PICHOL_METHOD_PINRMSE,
+                                             &rest);
+    if (st != PICHOL_OK) return st;
+    *bytes = pe > rest ? pe : rest;
+    return PICHOL_OK;
+  }
   const Layout L = layout_of(p);
   const bool grad = (methods & PICHOL_METHOD_GRAD) != 0;
   size_t end = L.region;
@@ -790,6 +819,33 @@ pichol_status pichol_cv_exact_grad(const pichol_problem* p,
     e = launch_grad_dot(p->d, k, q, c, L.ldz, Sg, Z, nullptr, nullptr,
                         at<double>(ws, L.e_lam), hn, at<double>(ws, L.e_gpart),
                         dlog, flags, stream);
+  return hip_status(e);
+}
+
+pichol_status pichol_cv_pinrmse(const pichol_problem* p, const double* lam_s,
+                                const double* lam_grid, double lam_ref,
+                                void* ws, size_t ws_bytes, double* err,
+                                double* err_s, int32_t* info, int32_t* flags,
+                                hipStream_t stream) {
+  if (!problem_ok(p) || p->refine != 0 || !lam_s || !lam_grid || !err ||
+      !info || !flags || !(lam_ref > 0.0) || !isfinite(lam_ref))
+    return PICHOL_ERR_ARG;
+  if (!samples_ok(lam_s, p->g)) return PICHOL_ERR_ARG;
+  for (int t = 0; t < p->q; ++t)
+    if (!isfinite(lam_grid[t])) return PICHOL_ERR_ARG;
+  if (!ws || ws_bytes < pinrmse_end(p)) return PICHOL_ERR_WORKSPACE;
+  FitCoef fc;
+  if (!fit_coef(p->g, p->r, lam_s, lam_ref, &fc)) return PICHOL_ERR_ARG;
+  // exact hold-out errors at the g samples (the Gram blocks are shared)
+  pichol_problem ps = *p;
+  ps.q = p->g;
+  double* es = err_s ? err_s : at<double>(ws, pinrmse_es(p));
+  pichol_status st = pichol_cv_exact(&ps, lam_s, ws, ws_bytes, es, nullptr,
+                                     info, flags, stream);
+  if (st != PICHOL_OK) return st;
+  double* tau = at<double>(ws, pinrmse_tau(p));
+  hipError_t e = upload_tau(lam_grid, p->q, lam_ref, tau, stream);
+  if (e == hipSuccess) e = launch_pinrmse(p->k, fc, p->q, tau, es, err, stream);
   return hip_status(e);
 }
 

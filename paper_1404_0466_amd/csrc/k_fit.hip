@@ -116,4 +116,42 @@ hipError_t launch_eval(int64_t d, int nmat, int m, const double* theta,
   return hipGetLastError();
 }
 
+// The hold-out-error variant of Algorithm 1 (PINRMSE): the g-vector of
+// exact hold-out errors of fold m at the samples takes the place of T, so
+// the fitted coefficients are theta_j = sum_s P[j][s] e[m][s] and the curve
+// at grid value t is sum_j tau_t^j theta_j.
+__global__ void __launch_bounds__(64) k_pinrmse(FitCoef fc, int q,
+                                                const double* tau,
+                                                const double* es,
+                                                double* err) {
+  const int64_t m = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= q) return;
+  double th[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    double acc = 0.0;
+    if (j < fc.m)
+      for (int s = 0; s < fc.g; ++s) acc += fc.P[j][s] * es[m * fc.g + s];
+    th[j] = acc;
+  }
+  double out = 0.0, pw = 1.0;
+  const double tv = tau[t];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < fc.m) {
+      out += pw * th[j];
+      pw *= tv;
+    }
+  err[m * q + t] = out;
+}
+
+hipError_t launch_pinrmse(int nmat, const FitCoef& fc, int q,
+                          const double* tau_dev, const double* es, double* err,
+                          hipStream_t s) {
+  PICHOL_LAUNCH(k_pinrmse, dim3((unsigned)((q + 63) / 64), (unsigned)nmat),
+                dim3(64), 0, s, fc, q, tau_dev, es, err);
+  return hipGetLastError();
+}
+
 }  // namespace pichol

@@ -74,6 +74,9 @@ struct FitCoef {
 };
 hipError_t launch_fit(int64_t d, int nmat, const FitCoef& fc, const double* L,
                       double* theta, double* theta_t, hipStream_t s);
+hipError_t launch_pinrmse(int nmat, const FitCoef& fc, int q,
+                          const double* tau_dev, const double* es, double* err,
+                          hipStream_t s);
 hipError_t launch_eval(int64_t d, int nmat, int m, const double* theta,
                        int nlam, const double* tau_dev, double* Lhat,
                        hipStream_t s);

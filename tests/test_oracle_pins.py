@@ -542,3 +542,49 @@ def test_gradient_scale_error_would_be_caught():
     fd = _fd_dlog(lambda lg: oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, lg, p.r,
                                               lam_ref=p.lam_ref)["mse"], p.lam_grid)
     assert np.abs(fd - 0.5 * got["dlog"]).max() > 1e-2 * np.abs(fd).max()
+
+
+# ------------------------------------------------------------------ the paper's variants (PINRMSE, MChol)
+
+def test_pinrmse_matches_numpy_polyfit():
+    """PINRMSE replaces T by the g-vector of sample hold-out errors: per
+    fold, the least-squares polynomial in tau through those errors, which
+    numpy's polyfit computes independently."""
+    from numpy.polynomial import polynomial as P
+    p = workloads.gaussian_problem(300, 24, 3, seed=6, g=4, q=9)
+    pr = oracle.pinrmse(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r)
+    ex = oracle.cv_exact(p.X, p.Y, p.k, p.lam_s)
+    np.testing.assert_allclose(pr["mse_samples"], ex["mse"], rtol=1e-14)
+    tau_s, tau_t = p.lam_s / p.lam_ref, p.lam_grid / p.lam_ref
+    for f in range(p.k):
+        co = P.polyfit(tau_s, pr["mse_samples"][f], p.r)
+        np.testing.assert_allclose(pr["mse"][f], P.polyval(tau_t, co), rtol=1e-11)
+
+
+def test_pinrmse_interpolates_when_degree_is_g_minus_1():
+    p = workloads.gaussian_problem(250, 20, 2, seed=7, g=4, q=10, lam_range=(1e-3, 1.0))
+    lam_s = p.lam_grid[[0, 3, 6, 9]]
+    pr = oracle.pinrmse(p.X, p.Y, p.k, lam_s, p.lam_grid, 3)
+    ex = oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid)
+    np.testing.assert_allclose(pr["mse"][:, [0, 3, 6, 9]], ex["mse"][:, [0, 3, 6, 9]],
+                               rtol=1e-9)
+
+
+def test_mchol_bracketing_search():
+    """MChol halves s from 1.5 until s <= 0.0025 (10 levels), recentres on
+    the best of three points at every level, and ends next to the minimiser
+    of a dense exact search over the initial range."""
+    p = workloads.gaussian_problem(300, 24, 3, seed=6, g=4, q=9)
+    c0 = np.log10(p.scale) - 1.5
+    m = oracle.mchol(p.X, p.Y, p.k, c0, 1.5, 0.0025)
+    assert len(m["trace"]) == 10
+    s = 1.5
+    for lvl, (lams, cvv) in enumerate(m["trace"]):
+        np.testing.assert_allclose(np.log10(lams[2]) - np.log10(lams[1]), s, rtol=1e-12)
+        if lvl > 0:
+            prev_l, prev_v = m["trace"][lvl - 1]
+            np.testing.assert_allclose(lams[1], prev_l[np.argmin(prev_v)], rtol=1e-12)
+        s /= 2
+    dense = np.logspace(c0 - 1.5, c0 + 1.5, 601)
+    cv = oracle.cv_exact(p.X, p.Y, p.k, dense)["mse"].mean(0)
+    assert abs(m["log10_lam"] - np.log10(dense[np.argmin(cv)])) <= 0.01
