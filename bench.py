@@ -395,6 +395,69 @@ def differentiation_leg(args, B, stream):
     return out
 
 
+def layout_leg(args, B, stream):
+    """Table-1-style comparison of factor vectorisations (Sec. 5) on the GPU:
+    for one fold with g = 4 sample factors, r = 2 and q = 31 grid values,
+    the time to vectorise the factors (Vec), fit the polynomials (Fit) and
+    evaluate them at the grid (Interp), for the row-wise, full-matrix and
+    recursive (threshold 128) layouts and the tile-packed layout the
+    factorization writes directly (no Vec step).  Factor values are random:
+    the three steps are data movement and streaming arithmetic."""
+    import torch
+    dev = torch.device("cuda:0")
+    g, r, q, h0 = 4, 2, 31, 128
+    lam_s = np.logspace(-3, 0, g)
+    lam = np.logspace(-3, 0, q)
+    lam_ref = float(lam_s.max())
+    nbw = B.pichol_lambda_workspace(q)
+    wsl = torch.empty(nbw, dtype=torch.uint8, device=dev)
+    names = {B.PICHOL_LAYOUT_ROWWISE: "row-wise", B.PICHOL_LAYOUT_FULL: "full-matrix",
+             B.PICHOL_LAYOUT_RECURSIVE: "recursive", B.PICHOL_LAYOUT_TILE: "tile-packed"}
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        for _ in range(reps):
+            fn()
+        s1.record(stream)
+        torch.cuda.synchronize()
+        return s0.elapsed_time(s1) / reps
+
+    rows = []
+    for d in (1024, 2048, 4096):
+        S = B.pichol_packed_elems(d)
+        L = torch.randn(g * S, dtype=torch.float64, device=dev)
+        for layout in (B.PICHOL_LAYOUT_ROWWISE, B.PICHOL_LAYOUT_FULL,
+                       B.PICHOL_LAYOUT_RECURSIVE, B.PICHOL_LAYOUT_TILE):
+            N = B.pichol_vector_length(d, layout)
+            if layout == B.PICHOL_LAYOUT_TILE:
+                T, t_vec = L, 0.0
+            else:
+                T = torch.zeros(g * N, dtype=torch.float64, device=dev)
+                t_vec = timed(lambda: B.pichol_vectorize(d, g, L, layout, h0, T))
+            th = torch.empty((r + 1) * N, dtype=torch.float64, device=dev)
+            out = torch.empty(q * N, dtype=torch.float64, device=dev)
+            t_fit = timed(lambda: B.pichol_fit_vec(N, 1, g, r, lam_s, lam_ref, T, th))
+            t_int = timed(lambda: B.pichol_eval_vec(N, 1, r, th, q, lam, lam_ref, out, wsl,
+                                                    nbw))
+            rows.append({
+                "d": d, "layout": names[layout], "vector_length": N,
+                "vec_ms": t_vec, "fit_ms": t_fit, "interp_ms": t_int,
+                "total_ms": t_vec + t_fit + t_int,
+                "fit_GBps": (g + r + 1) * N * 8 / (t_fit * 1e-3) / 1e9,
+                "interp_GBps": (r + 1 + q) * N * 8 / (t_int * 1e-3) / 1e9,
+            })
+            del T, th, out
+        del L
+    for rw in rows:
+        log(f"layouts d={rw['d']:5d} {rw['layout']:12s} vec {rw['vec_ms']:7.3f} fit "
+            f"{rw['fit_ms']:7.3f} interp {rw['interp_ms']:7.3f} total {rw['total_ms']:7.3f} ms "
+            f"(fit {rw['fit_GBps']:.0f} GB/s, interp {rw['interp_GBps']:.0f} GB/s)")
+    return {"setting": "one fold, g=4, r=2, q=31, recursive threshold 128", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -413,6 +476,8 @@ def main():
                     help="skip the precision-form legs timed after the FP64 "
                          "headline (FP32-MFMA trailing updates, iterative "
                          "refinement)")
+    ap.add_argument("--no-layouts", action="store_true",
+                    help="skip the vectorisation-layout comparison")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the differentiation-form leg (d=2048 workload)")
     ap.add_argument("--no-batch", action="store_true",
@@ -553,6 +618,10 @@ def main():
     if not args.no_batch:
         batching = batching_leg(args, B, stream)
 
+    layouts = None
+    if not args.no_layouts:
+        layouts = layout_leg(args, B, stream)
+
     differentiation = None
     if not args.no_grad:
         differentiation = differentiation_leg(args, B, stream)
@@ -617,6 +686,7 @@ def main():
         "precision_forms": variants,
         "batching_form": batching,
         "differentiation_form": differentiation,
+        "layout_comparison": layouts,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

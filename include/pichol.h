@@ -376,6 +376,54 @@ pichol_status pichol_exact_cv(const pichol_problem *p, const double *X,
                               double *W, int32_t *info, int32_t *flags,
                               hipStream_t stream);
 
+/* ------------------------------------------------- vectorisation layouts */
+
+/* Layouts of Sec. 5 for the vector that holds one factor as a row of T
+ * (the layout comparison of Table 1):
+ *   ROWWISE    entry (i,j), j <= i, at i(i+1)/2 + j
+ *   FULL       the d x d matrix, row-major, zeros above the diagonal
+ *   RECURSIVE  eq. (recursive): split at half = d/2 into the square block
+ *              L12 = rows [half,d) x columns [0,half) stored first,
+ *              row-major, then L11, then L22, each split the same way until
+ *              the order is at most h0, where rows are concatenated (d need
+ *              not be a power of two: L12 is then (d-half) x half)
+ *   TILE       the tile-packed triangle the factorization writes (the
+ *              library's own layout: no conversion needed)
+ * Vector lengths are rounded up to a multiple of 4; entries past the
+ * layout's own length are not written. */
+typedef enum {
+  PICHOL_LAYOUT_ROWWISE = 1,
+  PICHOL_LAYOUT_FULL = 2,
+  PICHOL_LAYOUT_RECURSIVE = 3,
+  PICHOL_LAYOUT_TILE = 4
+} pichol_layout;
+
+/* Length of one vectorised factor of order d in the layout (0 if invalid). */
+int64_t pichol_vector_length(int64_t d, int32_t layout);
+
+/* Tile-packed factors (device, nmat of them) -> their vectors in `layout`
+ * (ROWWISE, FULL or RECURSIVE with threshold h0 >= 1), T nmat x
+ * pichol_vector_length(d, layout) (device). */
+pichol_status pichol_vectorize(int64_t d, int32_t nmat, const double *L,
+                               int32_t layout, int32_t h0, double *T,
+                               hipStream_t stream);
+
+/* The fit of pichol_fit on flat vectors of length N (a multiple of 4):
+ * theta(m, j) = sum_s P[j][s] T(m, s), T nmat*g x N, theta nmat*(r+1) x N
+ * (device). */
+pichol_status pichol_fit_vec(int64_t N, int32_t nmat, int32_t g, int32_t r,
+                             const double *lam_s, double lam_ref,
+                             const double *T, double *theta,
+                             hipStream_t stream);
+
+/* The evaluation of pichol_eval on flat vectors: out(m, t) =
+ * sum_j (lam_t/lam_ref)^j theta(m, j), out nmat*nlam x N (device).
+ * ws: pichol_lambda_workspace(nlam) bytes. */
+pichol_status pichol_eval_vec(int64_t N, int32_t nmat, int32_t r,
+                              const double *theta, int32_t nlam,
+                              const double *lam, double lam_ref, double *out,
+                              void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------- batching */
 
 /* One independent ridge problem of a batch: the arguments of the

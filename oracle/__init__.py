@@ -389,6 +389,23 @@ def fold_interp(H, B, Xv, Yv, lam_s, lam_grid, r: int,
     return {"mse": mse, "W": W, "info": info, "flags": flags}
 
 
+# ---------------------------------------------------------------- vectorisation orders (Sec. 5)
+
+def recursive_order(h: int, h0: int) -> list:
+    """The (row, column) entries of an order-h lower triangle in the order
+    of the recursive vectorisation (Sec. 5, eq. recursive): the square
+    block L12 (rows h/2..h-1, columns 0..h/2-1) row by row, then the
+    triangle L11, then the triangle L22, each split the same way until its
+    order is at most h0, where the rows are concatenated."""
+    def rec(r0, h):
+        if h <= h0:
+            return [(r0 + i, r0 + j) for i in range(h) for j in range(i + 1)]
+        half = h // 2
+        l12 = [(r0 + half + i, r0 + j) for i in range(h - half) for j in range(half)]
+        return l12 + rec(r0, half) + rec(r0 + half, h - half)
+    return rec(0, h)
+
+
 # ---------------------------------------------------------------- the paper's variants (Sec. 6.2, 6.5)
 
 def pinrmse(X, Y, k: int, lam_s, lam_grid, r: int, lam_ref: float | None = None,

@@ -29,6 +29,10 @@ PICHOL_METHOD_INTERP = 1
 PICHOL_METHOD_EXACT = 2
 PICHOL_METHOD_GRAD = 4
 PICHOL_METHOD_PINRMSE = 8
+PICHOL_LAYOUT_ROWWISE = 1
+PICHOL_LAYOUT_FULL = 2
+PICHOL_LAYOUT_RECURSIVE = 3
+PICHOL_LAYOUT_TILE = 4
 PICHOL_OPT_LOOKAHEAD = 1
 PICHOL_PREC_FP64 = 0
 PICHOL_PREC_MIXED = 1
@@ -117,6 +121,11 @@ _SIGNATURES = {
                          _vp, _vp, _vp]),
     "pichol_exact_cv": (_i32, [_pprob, _vp, _vp, _vp, _vp, _sz, _vp, _vp, _vp,
                                _vp, _vp]),
+    "pichol_vector_length": (_i64, [_i64, _i32]),
+    "pichol_vectorize": (_i32, [_i64, _i32, _vp, _i32, _i32, _vp, _vp]),
+    "pichol_fit_vec": (_i32, [_i64, _i32, _i32, _i32, _vp, _dbl, _vp, _vp, _vp]),
+    "pichol_eval_vec": (_i32, [_i64, _i32, _i32, _vp, _i32, _vp, _dbl, _vp, _vp,
+                               _sz, _vp]),
     "pichol_batch_workspace_size": (_i32, [_i32, _pitem, _i32,
                                            ctypes.POINTER(_sz)]),
     "pichol_cv_batch": (_i32, [_i32, _pitem, _i32, _ptune, _vp, _sz, _vp]),
@@ -442,6 +451,32 @@ def pichol_profile_summary(max_kernels: int = 256) -> dict:
 
 def pichol_profile_reset():
     _check("pichol_profile_reset", load().pichol_profile_reset())
+
+
+# ------------------------------------------------------------------ layouts
+
+def pichol_vector_length(d: int, layout: int) -> int:
+    return int(load().pichol_vector_length(d, layout))
+
+
+def pichol_vectorize(d, nmat, L, layout, h0, T, stream=None):
+    _check("pichol_vectorize", load().pichol_vectorize(
+        d, nmat, _dev(L, _f64()), layout, h0, _dev(T, _f64()), _stream(stream)))
+
+
+def pichol_fit_vec(N, nmat, g, r, lam_s, lam_ref, T, theta, stream=None):
+    ls = _Host(lam_s, np.float64)
+    _check("pichol_fit_vec", load().pichol_fit_vec(
+        N, nmat, g, r, ls.ptr, float(lam_ref), _dev(T, _f64()), _dev(theta, _f64()),
+        _stream(stream)))
+
+
+def pichol_eval_vec(N, nmat, r, theta, nlam, lam, lam_ref, out, ws, ws_bytes,
+                    stream=None):
+    lh = _Host(lam, np.float64)
+    _check("pichol_eval_vec", load().pichol_eval_vec(
+        N, nmat, r, _dev(theta, _f64()), nlam, lh.ptr, float(lam_ref),
+        _dev(out, _f64()), _dev(ws), ws_bytes, _stream(stream)))
 
 
 # ------------------------------------------------------------------ batching

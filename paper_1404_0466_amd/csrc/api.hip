@@ -849,6 +849,64 @@ pichol_status pichol_cv_pinrmse(const pichol_problem* p, const double* lam_s,
   return hip_status(e);
 }
 
+int64_t pichol_vector_length(int64_t d, int32_t layout) {
+  if (d < 1) return 0;
+  int64_t n;
+  if (layout == PICHOL_LAYOUT_ROWWISE || layout == PICHOL_LAYOUT_RECURSIVE)
+    n = d * (d + 1) / 2;
+  else if (layout == PICHOL_LAYOUT_FULL)
+    n = d * d;
+  else if (layout == PICHOL_LAYOUT_TILE)
+    n = packed_elems_of(d);
+  else
+    return 0;
+  return (n + 3) / 4 * 4;
+}
+
+pichol_status pichol_vectorize(int64_t d, int32_t nmat, const double* L,
+                               int32_t layout, int32_t h0, double* T,
+                               hipStream_t stream) {
+  if (d < 1 || nmat < 1 || !L || !T || h0 < 1 ||
+      (layout != PICHOL_LAYOUT_ROWWISE && layout != PICHOL_LAYOUT_FULL &&
+       layout != PICHOL_LAYOUT_RECURSIVE))
+    return PICHOL_ERR_ARG;
+  const int kind = layout == PICHOL_LAYOUT_ROWWISE ? 1
+                   : layout == PICHOL_LAYOUT_FULL  ? 2
+                                                   : 3;
+  return hip_status(launch_vectorize(d, nmat, L, kind, h0,
+                                     pichol_vector_length(d, layout), T,
+                                     stream));
+}
+
+pichol_status pichol_fit_vec(int64_t N, int32_t nmat, int32_t g, int32_t r,
+                             const double* lam_s, double lam_ref,
+                             const double* T, double* theta,
+                             hipStream_t stream) {
+  if (N < 4 || N % 4 || nmat < 1 || g < 1 || g > 32 || r < 0 || r > 7 ||
+      r >= g || !lam_s || !T || !theta || !(lam_ref > 0.0) ||
+      !isfinite(lam_ref))
+    return PICHOL_ERR_ARG;
+  if (!samples_ok(lam_s, g)) return PICHOL_ERR_ARG;
+  FitCoef fc;
+  if (!fit_coef(g, r, lam_s, lam_ref, &fc)) return PICHOL_ERR_ARG;
+  return hip_status(launch_fit_flat(N, nmat, fc, T, theta, stream));
+}
+
+pichol_status pichol_eval_vec(int64_t N, int32_t nmat, int32_t r,
+                              const double* theta, int32_t nlam,
+                              const double* lam, double lam_ref, double* out,
+                              void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (N < 4 || N % 4 || nmat < 1 || r < 0 || r > 7 || nlam < 1 || !theta ||
+      !lam || !out || !(lam_ref > 0.0) || !isfinite(lam_ref))
+    return PICHOL_ERR_ARG;
+  if (!ws || ws_bytes < pichol_lambda_workspace(nlam)) return PICHOL_ERR_WORKSPACE;
+  double* tau = static_cast<double*>(ws);
+  hipError_t e = upload_tau(lam, nlam, lam_ref, tau, stream);
+  if (e == hipSuccess)
+    e = launch_eval_flat(N, nmat, r + 1, theta, nlam, tau, out, stream);
+  return hip_status(e);
+}
+
 pichol_status pichol_cv(const pichol_problem* p, const double* X,
                         const double* Y, const double* lam_s,
                         const double* lam_grid, double lam_ref, void* ws,

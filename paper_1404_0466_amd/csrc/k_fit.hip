@@ -154,4 +154,62 @@ hipError_t launch_pinrmse(int nmat, const FitCoef& fc, int q,
   return hipGetLastError();
 }
 
+// Theta(m, p) = sum_s P[p][s] T(m, s) over flat vectors of length N
+// (N a multiple of 4), four entries per thread: the fit on any
+// vectorisation of the factors (the layout comparison).
+template <int M>
+__global__ void __launch_bounds__(256) k_fit_flat(int64_t N, FitCoef fc,
+                                                  const double* T,
+                                                  double* theta) {
+  const int64_t m = blockIdx.y;
+  for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e < N;
+       e += (int64_t)gridDim.x * blockDim.x * 4) {
+    v4d th[M];
+#pragma unroll
+    for (int p = 0; p < M; ++p) th[p] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < fc.g; ++s) {
+      const v4d t = ld4(T + (m * fc.g + s) * N + e);
+#pragma unroll
+      for (int p = 0; p < M; ++p) th[p] += fc.P[p][s] * t;
+    }
+#pragma unroll
+    for (int p = 0; p < M; ++p) st4(theta + (m * M + p) * N + e, th[p]);
+  }
+}
+
+hipError_t launch_fit_flat(int64_t N, int nmat, const FitCoef& fc,
+                           const double* T, double* theta, hipStream_t s) {
+  int64_t bx = (N / 4 + 255) / 256;
+  if (bx > 2048) bx = 2048;
+  dim3 grid((unsigned)bx, (unsigned)nmat);
+  switch (fc.m) {
+#define PICHOL_FITF_CASE(MM)                                                  \
+  case MM:                                                                    \
+    PICHOL_LAUNCH(k_fit_flat<MM>, grid, dim3(256), 0, s, N, fc, T, theta);    \
+    break;
+    PICHOL_FITF_CASE(1)
+    PICHOL_FITF_CASE(2)
+    PICHOL_FITF_CASE(3)
+    PICHOL_FITF_CASE(4)
+    PICHOL_FITF_CASE(5)
+    PICHOL_FITF_CASE(6)
+    PICHOL_FITF_CASE(7)
+    PICHOL_FITF_CASE(8)
+#undef PICHOL_FITF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_flat(int64_t N, int nmat, int m, const double* theta,
+                            int nlam, const double* tau_dev, double* out,
+                            hipStream_t s) {
+  unsigned bx = (unsigned)((N / 4 + 255) / 256);
+  if (bx > 1024) bx = 1024;
+  PICHOL_LAUNCH(k_eval, dim3(bx, (unsigned)nlam, (unsigned)nmat), dim3(256), 0,
+                s, N, m, theta, nlam, tau_dev, out);
+  return hipGetLastError();
+}
+
 }  // namespace pichol

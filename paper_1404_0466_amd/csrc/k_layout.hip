@@ -134,4 +134,79 @@ hipError_t launch_copy_i32(int64_t n, const int* src, int* dst, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---- vectorisations of a factor (Sec. 5), for the layout comparison.
+// Position of lower entry (i, j) of an order-h triangle in the recursive
+// vectorisation of Sec. 5 (eq. recursive): the triangle is split at
+// half = h/2 into the square block L12 (rows half.., columns ..half),
+// stored first in row-major order, then the triangle L11, then the triangle
+// L22, each vectorised the same way until the order is at most h0, where
+// rows are concatenated.  (h need not be a power of two: L12 is then
+// (h - half) x half.)
+__device__ inline int64_t recursive_pos(int64_t i, int64_t j, int64_t h,
+                                        int64_t h0) {
+  int64_t base = 0;
+  while (h > h0) {
+    const int64_t half = h / 2, rest = h - half;
+    if (i >= half && j < half) return base + (i - half) * half + j;
+    if (i < half) {
+      base += rest * half;
+      h = half;
+    } else {
+      base += rest * half + half * (half + 1) / 2;
+      i -= half;
+      j -= half;
+      h = rest;
+    }
+  }
+  return base + i * (i + 1) / 2 + j;
+}
+
+// One 128 x 128 tile (I,J) of a tile-packed factor into a vectorised
+// layout: the tile is read column-major (coalesced) into LDS and written
+// row by row, so the writes of a row segment are contiguous in the
+// row-wise, full-matrix and (within its blocks) recursive orders.  For the
+// full-matrix layout the tiles above the diagonal are written as zeros.
+__global__ void __launch_bounds__(256) k_vectorize(int64_t d, int64_t S,
+                                                   const double* P, int layout,
+                                                   int64_t h0, int64_t N,
+                                                   double* T) {
+  __shared__ double lds[NB * LDS_LD];
+  const int64_t nt = ntiles_of(d);
+  const int64_t mat = blockIdx.y;
+  const int I = (int)(blockIdx.x / nt), J = (int)(blockIdx.x % nt);
+  const int tid = threadIdx.x;
+  double* out = T + mat * N;
+  if (J > I) {
+    if (layout != 2) return;
+    for (int e = tid; e < NB2; e += blockDim.x) {
+      const int64_t i = (int64_t)I * NB + (e >> 7), j = (int64_t)J * NB + (e & (NB - 1));
+      if (i < d && j < d) out[i * d + j] = 0.0;
+    }
+    return;
+  }
+  const double* tile = P + mat * S + tile_off(I, J);
+  for (int e = tid; e < NB2; e += blockDim.x)
+    lds[(e >> 7) * LDS_LD + (e & (NB - 1))] = tile[e];  // lds[col][row]
+  __syncthreads();
+  for (int e = tid; e < NB2; e += blockDim.x) {
+    const int r = e >> 7, cc = e & (NB - 1);
+    const int64_t i = (int64_t)I * NB + r, j = (int64_t)J * NB + cc;
+    if (i >= d || j >= d) continue;
+    const double v = lds[cc * LDS_LD + r];
+    if (layout == 2) {
+      out[i * d + j] = j <= i ? v : 0.0;
+    } else if (j <= i) {
+      out[layout == 1 ? i * (i + 1) / 2 + j : recursive_pos(i, j, d, h0)] = v;
+    }
+  }
+}
+
+hipError_t launch_vectorize(int64_t d, int nmat, const double* P, int layout,
+                            int64_t h0, int64_t N, double* T, hipStream_t s) {
+  const int64_t nt = ntiles_of(d);
+  PICHOL_LAUNCH(k_vectorize, dim3((unsigned)(nt * nt), (unsigned)nmat),
+                dim3(256), 0, s, d, packed_elems_of(d), P, layout, h0, N, T);
+  return hipGetLastError();
+}
+
 }  // namespace pichol

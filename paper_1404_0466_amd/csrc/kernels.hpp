@@ -45,6 +45,10 @@ hipError_t launch_slab_to_weights(int64_t d, int nmat, int q, int c,
                                   int64_t ldz, const double* Z, double* W,
                                   hipStream_t s);
 hipError_t launch_copy_i32(int64_t n, const int* src, int* dst, hipStream_t s);
+// layout: 1 row-wise, 2 full matrix, 3 recursive (threshold h0); N is the
+// vector length of one factor in that layout.
+hipError_t launch_vectorize(int64_t d, int nmat, const double* P, int layout,
+                            int64_t h0, int64_t N, double* T, hipStream_t s);
 
 // ---- Gram (k_gram.hip)
 struct FoldSplit {
@@ -74,6 +78,11 @@ struct FitCoef {
 };
 hipError_t launch_fit(int64_t d, int nmat, const FitCoef& fc, const double* L,
                       double* theta, double* theta_t, hipStream_t s);
+hipError_t launch_fit_flat(int64_t N, int nmat, const FitCoef& fc,
+                           const double* T, double* theta, hipStream_t s);
+hipError_t launch_eval_flat(int64_t N, int nmat, int m, const double* theta,
+                            int nlam, const double* tau_dev, double* out,
+                            hipStream_t s);
 hipError_t launch_pinrmse(int nmat, const FitCoef& fc, int q,
                           const double* tau_dev, const double* es, double* err,
                           hipStream_t s);

@@ -1,6 +1,12 @@
 """The paper's other procedures on the GPU path: PINRMSE
 (pichol_cv_pinrmse) and the multi-level Cholesky search (MChol driver over
-pichol_cv_exact), against the oracle's versions."""
+pichol_cv_exact), against the oracle's versions.
+
+PINRMSE tolerance: the oracle fits through Algorithm 1's normal equations,
+which lose accuracy as cond(V)^2 eps, while the library applies V^+ from a
+Householder QR; the curve is held to max(1e-9, 10 cond(V)^2 eps) of its
+largest value (1.2e-11 for g=5, r=2 over five decades; 5e-4 for the
+interpolating g=4, r=3 case, whose cond(V) is 4.8e5)."""
 import numpy as np
 import pytest
 
@@ -24,8 +30,11 @@ def test_pinrmse_matches_oracle(gu, n, d, c, g, r, q):
     want = oracle.pinrmse(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r)
     assert np.all(got["info"] == 0) and np.all(got["flags"] == 0)
     np.testing.assert_allclose(got["mse_samples"], want["mse_samples"], rtol=1e-10, atol=0)
+    tau = p.lam_s / p.lam_ref
+    cond = np.linalg.cond(np.vander(tau, p.r + 1, increasing=True))
+    tol = max(1e-9, 10 * cond ** 2 * np.finfo(float).eps)
     scale = np.abs(want["mse"]).max()
-    assert np.abs(got["mse"] - want["mse"]).max() <= 1e-9 * scale
+    assert np.abs(got["mse"] - want["mse"]).max() <= tol * scale
 
 
 def test_mchol_matches_oracle(gu):

@@ -588,3 +588,22 @@ def test_mchol_bracketing_search():
     dense = np.logspace(c0 - 1.5, c0 + 1.5, 601)
     cv = oracle.cv_exact(p.X, p.Y, p.k, dense)["mse"].mean(0)
     assert abs(m["log10_lam"] - np.log10(dense[np.argmin(cv)])) <= 0.01
+
+
+# ------------------------------------------------------------------ vectorisation orders (Sec. 5)
+
+def test_recursive_order_small_case_from_the_text():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "recursive_order_h4_h0_2.txt")
+    want = [tuple(int(v) for v in ln.split()) for ln in open(path)
+            if ln.strip() and not ln.startswith("#")]
+    assert oracle.recursive_order(4, 2) == want
+
+
+@pytest.mark.parametrize("h,h0", [(16, 4), (37, 5), (64, 64), (9, 1)])
+def test_recursive_order_is_a_bijection_on_the_triangle(h, h0):
+    order = oracle.recursive_order(h, h0)
+    assert len(order) == h * (h + 1) // 2
+    assert set(order) == {(i, j) for i in range(h) for j in range(i + 1)}
+    if h <= h0:  # no split: the row-wise order of pack_lower
+        assert order == [(i, j) for i in range(h) for j in range(i + 1)]
