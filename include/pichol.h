@@ -499,6 +499,16 @@ pichol_status pichol_cv_batch_graph(int32_t nprob,
 pichol_status pichol_graph_launch(pichol_graph graph, hipStream_t stream);
 pichol_status pichol_graph_destroy(pichol_graph graph);
 
+/* Capture any sequence of library calls made on `stream` (which must not be
+ * the legacy null stream) between these two calls into one HIP graph, e.g.
+ * the piCholesky stage of a repeated cross-validation: every launch of the
+ * sequence then replays with one pichol_graph_launch.  Host arrays
+ * (lambda values) are read during the capture and recorded in the graph.
+ * The look-ahead side stream and per-kernel profiling must be off during a
+ * capture; other threads' work is not captured (thread-local capture). */
+pichol_status pichol_graph_begin(hipStream_t stream);
+pichol_status pichol_graph_end(hipStream_t stream, pichol_graph *graph);
+
 /* ------------------------------------------------------------------ misc */
 
 /* Synchronise the stream and inspect info/flags (device arrays, either may

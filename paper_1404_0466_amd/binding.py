@@ -133,6 +133,8 @@ _SIGNATURES = {
     "pichol_cv_batch_graph": (_i32, [_i32, _pitem, _i32, _ptune, _vp, _sz,
                                      ctypes.POINTER(_vp)]),
     "pichol_graph_launch": (_i32, [_vp, _vp]),
+    "pichol_graph_begin": (_i32, [_vp]),
+    "pichol_graph_end": (_i32, [_vp, ctypes.POINTER(_vp)]),
     "pichol_graph_destroy": (_i32, [_vp]),
     "pichol_check": (_i32, [_vp, _i64, _vp, _i64, _vp]),
     "pichol_set_option": (_i32, [_i32, _i32]),
@@ -549,6 +551,16 @@ def pichol_cv_batch_graph(batch: Batch, method: int, tune, ws, ws_bytes):
     _check("pichol_cv_batch_graph", load().pichol_cv_batch_graph(
         batch.n, batch.items, method, _tune(tune), _dev(ws), ws_bytes,
         ctypes.byref(g)))
+    return g
+
+
+def pichol_graph_begin(stream=None):
+    _check("pichol_graph_begin", load().pichol_graph_begin(_stream(stream)))
+
+
+def pichol_graph_end(stream=None):
+    g = _vp(None)
+    _check("pichol_graph_end", load().pichol_graph_end(_stream(stream), ctypes.byref(g)))
     return g
 
 

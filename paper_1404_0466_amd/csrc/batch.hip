@@ -416,6 +416,36 @@ pichol_status pichol_cv_batch_graph(int32_t nprob,
   return PICHOL_OK;
 }
 
+pichol_status pichol_graph_begin(hipStream_t stream) {
+  if (!stream || profiling_on() || option_lookahead()) return PICHOL_ERR_ARG;
+  {
+    // the batch streams must exist before any capture that may use them
+    std::lock_guard<std::mutex> lk(g_bs_mu);
+    BatchStreams* S = nullptr;
+    hipError_t e = batch_streams(&S);
+    if (e != hipSuccess) return hip_status(e);
+  }
+  return hip_status(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+}
+
+pichol_status pichol_graph_end(hipStream_t stream, pichol_graph* graph) {
+  if (!stream || !graph) return PICHOL_ERR_ARG;
+  *graph = nullptr;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(stream, &g);
+  hipGraphExec_t exec = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_status(e);
+  pichol_graph out = new (std::nothrow) pichol_graph_s{exec};
+  if (!out) {
+    (void)hipGraphExecDestroy(exec);
+    return PICHOL_ERR_ARG;
+  }
+  *graph = out;
+  return PICHOL_OK;
+}
+
 pichol_status pichol_graph_launch(pichol_graph graph, hipStream_t stream) {
   if (!graph) return PICHOL_ERR_ARG;
   return hip_status(hipGraphLaunch(graph->exec, stream));

@@ -193,17 +193,28 @@ __global__ void __launch_bounds__(256) k_diag_apply(int64_t d, int i, int nper,
   for (int cg = 0; cg < c; cg += 16) {
     const int cn = (c - cg) < 16 ? (c - cg) : 16;
     if (cg) __syncthreads();
-    for (int e = tid; e < NB * 16; e += blockDim.x) {
-      const int k = e >> 4, cc = e & 15;
-      zs[e] = cc < cn ? zb[(int64_t)k * ldz + cg + cc] : 0.0;
-    }
-    __syncthreads();
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll 4
-    for (int k = 0; k < NB; ++k) {
-      const double mv = M[k * NB + row];
+    // the 128 x 16 right-hand-side block into LDS: eight loads in flight
+    double zv[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] += mv * zs[k * 16 + half + 2 * u];
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + 256 * u, k = e >> 4, cc = e & 15;
+      zv[u] = cc < cn ? zb[(int64_t)k * ldz + cg + cc] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) zs[tid + 256 * u] = zv[u];
+    __syncthreads();
+    // M z in chunks of 32 columns of M, each chunk's loads issued together
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+    for (int k0 = 0; k0 < NB; k0 += 32) {
+      double mv[32];
+#pragma unroll
+      for (int kk = 0; kk < 32; ++kk) mv[kk] = M[(k0 + kk) * NB + row];
+#pragma unroll
+      for (int kk = 0; kk < 32; ++kk)
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          acc[u] += mv[kk] * zs[(k0 + kk) * 16 + half + 2 * u];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {

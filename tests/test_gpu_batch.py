@@ -141,3 +141,42 @@ def test_batch_rejects_bad_items(gu):
     assert e.value.status == gu.B.PICHOL_ERR_WORKSPACE
     with pytest.raises(gu.B.PicholError):
         gu.B.pichol_cv_batch(run.batch, run.method, dict(streams=5), run.ws, run.nbytes)
+
+
+def test_captured_single_problem_stage_replays_match_eager(gu):
+    """pichol_graph_begin/end around the piCholesky stage of one problem:
+    replays equal the eager call bit for bit, with eager work between."""
+    B = gu.B
+    p = workloads.gaussian_problem(900, 300, 3, seed=31, g=5, r=2, q=11)
+    prob = B.make_problem(p.n, p.d, p.c, p.k, p.g, p.r, p.q, True)
+    nb = B.pichol_workspace_size(prob, B.PICHOL_METHOD_INTERP)
+    w = gu.ws(nb)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        err = gu.empty(p.k * p.q)
+        W = gu.empty(p.k * p.q * p.d * p.c)
+        info = gu.empty(p.k * p.g, torch.int32)
+        flags = gu.empty(p.k * p.q, torch.int32)
+        B.pichol_cv_gram(prob, gu.dev(p.X), gu.dev(p.Y), w, nb)
+        B.pichol_cv_interp(prob, p.lam_s, p.lam_grid, p.lam_ref, w, nb, err, W, info, flags)
+        s.synchronize()
+        ref = (err.cpu().numpy(), W.cpu().numpy(), flags.cpu().numpy())
+        B.pichol_graph_begin()
+        B.pichol_cv_interp(prob, p.lam_s, p.lam_grid, p.lam_ref, w, nb, err, W, info, flags)
+        g = B.pichol_graph_end()
+    try:
+        for rep in range(3):
+            err.fill_(float("nan"))
+            W.fill_(float("nan"))
+            torch.cuda.synchronize()
+            junk = torch.randn(1 << 20, device="cuda:0", dtype=torch.float64)
+            float(junk.sum())
+            B.pichol_graph_launch(g, s)
+            s.synchronize()
+            np.testing.assert_array_equal(err.cpu().numpy(), ref[0], err_msg=f"replay {rep}")
+            np.testing.assert_array_equal(W.cpu().numpy(), ref[1])
+            np.testing.assert_array_equal(flags.cpu().numpy(), ref[2])
+    finally:
+        B.pichol_graph_destroy(g)
+    want = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r)
+    np.testing.assert_allclose(ref[0].reshape(p.k, p.q), want["mse"], rtol=1e-10, atol=0)
