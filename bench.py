@@ -255,8 +255,11 @@ def batching_leg(args, B, stream):
 
     reps = args.steps
     tune_i, times_i = autotune.tune(bat_i, B.PICHOL_METHOD_INTERP, ws, nbytes, cache=None)
-    log(f"autotuned schedule {tune_i}: "
-        + ", ".join(f"{k_}={v:.2f} ms" for k_, v in (times_i or {}).items()))
+    log(f"autotuned: {tune_i}; schedules "
+        + ", ".join(f"{k_}={v:.2f} ms" for k_, v in times_i["schedule"].items())
+        + "; panel groups per nt "
+        + "; ".join(f"{nt}: " + ", ".join(f"{g_}={v:.2f}" for g_, v in tv.items())
+                    for nt, tv in times_i["panel_group"].items()))
     t_eager = timed(lambda: B.pichol_cv_batch(bat_i, B.PICHOL_METHOD_INTERP, tune_i,
                                               ws, nbytes), reps)
     gi = B.pichol_cv_batch_graph(bat_i, B.PICHOL_METHOD_INTERP, tune_i, ws, nbytes)
@@ -289,7 +292,7 @@ def batching_leg(args, B, stream):
         "workload": "48 power-law Gaussian problems, d in {256..2048}, n=8d, c in {1,10}, "
                     "k=5, g=5, r=2, q=32, lambda in [1e-4,1e1]*s",
         "lambda_solves": nsolves, "buckets": B.pichol_batch_buckets(bat_i, B.PICHOL_METHOD_INTERP),
-        "tuning": tune_i,
+        "tuning": tune_i, "tuning_times_ms": times_i,
         "graph_ms": t_graph, "value": nsolves / (t_graph * 1e-3),
         "eager_ms": t_eager, "sequential_single_ms": t_seq,
         "speedup_vs_sequential": t_seq / t_graph,

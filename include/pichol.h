@@ -446,13 +446,17 @@ typedef struct {
 
 /* Scheduling knobs of a batch (pass NULL for the defaults; the values an
  * autotuner picks per batch signature).
- *   streams  concurrent streams for independent buckets, 1..4 (0 = 4)
- *   order    0: buckets by decreasing estimated work (d^3 x factorizations),
- *               assigned to the least-loaded stream; 1: input order,
- *               round-robin over the streams */
+ *   streams      concurrent streams for independent buckets, 1..4 (0 = 4)
+ *   order        0: buckets by decreasing estimated work (d^3 x
+ *                factorizations), assigned to the least-loaded stream;
+ *                1: input order, round-robin over the streams
+ *   panel_group  per d bucket: panel_group[nt-1] (nt = ceil(d/128) <= 32)
+ *                panels per delayed trailing update in that bucket's
+ *                factorizations, 1..8, or 0 for PICHOL_OPT_PANEL_GROUP */
 typedef struct {
   int32_t streams;
   int32_t order;
+  int32_t panel_group[32];
 } pichol_batch_tuning;
 
 /* Many independent problems of uneven size in one call (Sec. 3.3's method
@@ -532,7 +536,16 @@ typedef enum {
    * created with a few events on first use on each device), joined back to
    * the caller's stream by events, so the next panels' diagonal
    * factorizations overlap it.  Results are identical either way. */
-  PICHOL_OPT_LOOKAHEAD = 1
+  PICHOL_OPT_LOOKAHEAD = 1,
+  /* 1..8 (default 4): the blocked factorizations take their 128-wide
+   * panels in groups of this many.  Inside a group, each panel's column
+   * first receives the group's earlier panels (a rank-128u update of that
+   * column); after the group, one rank-(128 x group) update reaches the
+   * rest of the trailing matrix, so larger groups read and write the
+   * trailing matrix fewer times.  The look-ahead schedule applies to groups
+   * of 2 only (other sizes run without it).  Results differ only by the
+   * rounding order of the trailing sums. */
+  PICHOL_OPT_PANEL_GROUP = 2
 } pichol_option;
 
 /* Set a process-wide option; PICHOL_ERR_ARG for an unknown option or

@@ -1,15 +1,19 @@
-"""Schedule autotuner for batched cross-validation (pichol_cv_batch).
+"""Autotuner for batched cross-validation (pichol_cv_batch).
 
-The kernels' tile shape is fixed by the tile-packed layout (128 x 128
-tiles), so what is left to choose for a batch of uneven problems is its
-schedule: how many library streams run the independent buckets
-concurrently, and whether buckets are dealt out by decreasing work or in
-input order.  ``tune`` times every candidate on the caller's batch (a few
-replays of a captured HIP graph each, so host launch cost does not blur the
-comparison) and keeps the fastest.  Results are cached in a JSON file keyed
-by the batch's signature (the multiset of problem shapes, the method and the
-device name), so a batch of the same shapes reuses the choice without
-timing again.
+The kernels' tile edge is fixed at 128 by the tile-packed layout; what is
+tuned is how the tiles are scheduled:
+  1. per d bucket, the number of 128-wide panels taken per delayed
+     trailing update of the factorizations (the panel group: a larger group
+     reads and writes the trailing tiles fewer times but lengthens the
+     per-column updates inside the group) -- each bucket's problems are
+     timed alone for every candidate group size;
+  2. for the whole batch, how many library streams run the independent
+     buckets concurrently and whether buckets are dealt out by decreasing
+     work or in input order.
+Every candidate is timed as a few replays of a captured HIP graph on the
+caller's own batch, so host launch cost does not blur the comparison.
+Choices are cached in a JSON file keyed by the batch's signature (the
+multiset of problem shapes, the method and the device name).
 """
 from __future__ import annotations
 
@@ -21,6 +25,18 @@ from . import binding as B
 CANDIDATES = [
     {"streams": s, "order": o} for s in (1, 2, 4) for o in (0, 1)
 ]
+GROUPS = (2, 4, 6)
+
+
+class _Subset:
+    """The items of a batch whose indices are given (same host arrays)."""
+
+    def __init__(self, batch, idx):
+        self.n = len(idx)
+        self.items = (B.BatchItem * self.n)(*[batch.items[i] for i in idx])
+        self._parent = batch
+
+
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pichol_autotune.json")
 
 
@@ -72,21 +88,46 @@ def time_schedule(batch, method, tune, ws, nbytes, reps=3):
         B.pichol_graph_destroy(g)
 
 
+def tune_groups(batch, method, ws, nbytes, reps=3, groups=GROUPS):
+    """Best panel group per d bucket: {nt: group}, and the timings
+    {nt: {group: ms}}."""
+    by_nt = {}
+    for i in range(batch.n):
+        nt = (batch.items[i].p.d + 127) // 128
+        by_nt.setdefault(nt, []).append(i)
+    best, times = {}, {}
+    for nt, idx in sorted(by_nt.items()):
+        if nt > 32:
+            continue
+        sub = _Subset(batch, idx)
+        times[nt] = {}
+        for gsz in groups:
+            tune_ = {"streams": 1, "order": 0, "panel_group": {nt: gsz}}
+            times[nt][gsz] = time_schedule(sub, method, tune_, ws, nbytes, reps)
+        best[nt] = min(times[nt], key=times[nt].get)
+    return best, times
+
+
 def tune(batch: B.Batch, method: int, ws, nbytes, cache: str | None = DEFAULT_CACHE,
-         reps: int = 3, force: bool = False):
-    """Returns (best tuning dict, {candidate: ms} timings or None when the
-    cached choice was used)."""
+         reps: int = 3, force: bool = False, groups=GROUPS):
+    """Returns (best tuning dict, timings or None when the cached choice was
+    used).  The tuning dict has streams, order and panel_group
+    ({nt: group})."""
     key = signature(batch, method)
     table = _load(cache) if cache else {}
     if not force and key in table:
-        return table[key]["tune"], None
+        choice = table[key]["tune"]
+        choice["panel_group"] = {int(k): v for k, v in choice.get("panel_group", {}).items()}
+        return choice, None
+    best_groups, group_times = tune_groups(batch, method, ws, nbytes, reps, groups)
     times = {}
     for cand in CANDIDATES:
-        times[json.dumps(cand, sort_keys=True)] = time_schedule(batch, method, cand, ws,
+        c = dict(cand, panel_group=best_groups)
+        times[json.dumps(cand, sort_keys=True)] = time_schedule(batch, method, c, ws,
                                                                nbytes, reps)
     best = min(times, key=times.get)
-    choice = json.loads(best)
+    choice = dict(json.loads(best), panel_group=best_groups)
     if cache:
         table[key] = {"tune": choice, "ms": times[best]}
         _store(cache, table)
-    return choice, times
+    return choice, {"schedule": times, "panel_group": group_times}

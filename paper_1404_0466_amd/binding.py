@@ -34,6 +34,7 @@ PICHOL_LAYOUT_FULL = 2
 PICHOL_LAYOUT_RECURSIVE = 3
 PICHOL_LAYOUT_TILE = 4
 PICHOL_OPT_LOOKAHEAD = 1
+PICHOL_OPT_PANEL_GROUP = 2
 PICHOL_PREC_FP64 = 0
 PICHOL_PREC_MIXED = 1
 PICHOL_MAX_REFINE = 16
@@ -75,7 +76,7 @@ class BatchItem(ctypes.Structure):
 
 class BatchTuning(ctypes.Structure):
     """pichol_batch_tuning."""
-    _fields_ = [("streams", _i32), ("order", _i32)]
+    _fields_ = [("streams", _i32), ("order", _i32), ("panel_group", _i32 * 32)]
 
 
 _pitem = ctypes.POINTER(BatchItem)
@@ -525,7 +526,10 @@ def _tune(tune):
         return None
     if isinstance(tune, BatchTuning):
         return ctypes.byref(tune)
-    return ctypes.byref(BatchTuning(int(tune.get("streams", 0)), int(tune.get("order", 0))))
+    t = BatchTuning(int(tune.get("streams", 0)), int(tune.get("order", 0)))
+    for nt, gsz in (tune.get("panel_group") or {}).items():
+        t.panel_group[int(nt) - 1] = int(gsz)
+    return ctypes.byref(t)
 
 
 def pichol_batch_workspace_size(batch: Batch, method: int) -> int:

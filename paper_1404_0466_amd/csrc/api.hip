@@ -34,6 +34,8 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static std::atomic<int> g_opt_lookahead{0};
 int option_lookahead() { return g_opt_lookahead.load(); }
+static std::atomic<int> g_opt_group{4};
+int option_panel_group() { return g_opt_group.load(); }
 
 // ---------------------------------------------------------------- profiling
 struct ProfState {
@@ -302,6 +304,10 @@ pichol_status pichol_set_option(int32_t option, int32_t value) {
       if (value != 0 && value != 1) return PICHOL_ERR_ARG;
       g_opt_lookahead.store(value);
       return PICHOL_OK;
+    case PICHOL_OPT_PANEL_GROUP:
+      if (value < 1 || value > 8) return PICHOL_ERR_ARG;
+      g_opt_group.store(value);
+      return PICHOL_OK;
   }
   return PICHOL_ERR_ARG;
 }
@@ -309,6 +315,7 @@ pichol_status pichol_set_option(int32_t option, int32_t value) {
 int32_t pichol_get_option(int32_t option) {
   switch (option) {
     case PICHOL_OPT_LOOKAHEAD: return g_opt_lookahead.load();
+    case PICHOL_OPT_PANEL_GROUP: return g_opt_group.load();
   }
   return -1;
 }
@@ -426,7 +433,7 @@ pichol_status pichol_potrf_shifted_batched(int64_t d, int32_t nmat,
   if (e != hipSuccess) return hip_status(e);
   return hip_status(launch_potrf_blocked(d, nmat * nshift, L, info, linv,
                                          precision == PICHOL_PREC_MIXED,
-                                         option_lookahead(), stream));
+                                         option_lookahead(), 0, stream));
 }
 
 pichol_status pichol_fit(int64_t d, int32_t nmat, int32_t g, int32_t r,
@@ -629,7 +636,7 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
   if (e == hipSuccess)
     e = launch_potrf_blocked(p->d, k * g, Lf, info, at<double>(ws, L.i_linv),
                              p->precision == PICHOL_PREC_MIXED,
-                             option_lookahead(), stream);
+                             option_lookahead(), 0, stream);
   if (e == hipSuccess) e = launch_fit(p->d, k, fc, Lf, th, tht, stream);
   if (e == hipSuccess)
     e = launch_slab_init(p->d, k, q, c, L.ldz, at<double>(ws, L.B), Z, flags,
@@ -690,7 +697,7 @@ pichol_status pichol_cv_exact(const pichol_problem* p, const double* lam_grid,
   if (e == hipSuccess)
     e = launch_potrf_blocked(p->d, k * q, Lf, info, at<double>(ws, L.e_linv),
                              p->precision == PICHOL_PREC_MIXED,
-                             option_lookahead(), stream);
+                             option_lookahead(), 0, stream);
   if (e == hipSuccess)
     e = launch_slab_init(p->d, k, q, c, L.ldz, at<double>(ws, L.B), Z, flags,
                          stream);

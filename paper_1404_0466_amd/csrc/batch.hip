@@ -167,7 +167,7 @@ T* at(void* ws, size_t off) {
 
 // One bucket's pipeline on stream st.
 hipError_t run_bucket(const Bucket& b, const pichol_batch_item* items,
-                      int method, void* ws, hipStream_t st) {
+                      int method, int group, void* ws, hipStream_t st) {
   const bool interp = method == PICHOL_METHOD_INTERP;
   const int64_t d = b.d, nt = ntiles_of(d), dp = nt * NB;
   const int64_t S = packed_elems_of(d);
@@ -207,7 +207,7 @@ hipError_t run_bucket(const Bucket& b, const pichol_batch_item* items,
     e = launch_shift_copy(d, nmat, H, nf, lam, k, L, info, st);
   if (e == hipSuccess)
     e = launch_potrf_blocked(d, nmat * nf, L, info, linv,
-                             b.precision == PICHOL_PREC_MIXED, 0, st);
+                             b.precision == PICHOL_PREC_MIXED, 0, group, st);
   if (e == hipSuccess)
     e = launch_slab_init(d, nmat, q, c, ldz, Bm, Z, flags, st);
   if (interp) {
@@ -335,9 +335,17 @@ pichol_status pichol_cv_batch(int32_t nprob, const pichol_batch_item* items,
     if (tune->streams < 0 || tune->streams > kMaxStreams || tune->order < 0 ||
         tune->order > 1)
       return PICHOL_ERR_ARG;
+    for (int i = 0; i < 32; ++i)
+      if (tune->panel_group[i] < 0 || tune->panel_group[i] > 8)
+        return PICHOL_ERR_ARG;
     if (tune->streams > 0) nstreams = tune->streams;
     order = tune->order;
   }
+  // panels per delayed update for a bucket of nt tile rows (0: option)
+  auto group_of = [&](const Bucket& b) {
+    const int64_t nt = ntiles_of(b.d);
+    return (tune && nt >= 1 && nt <= 32) ? tune->panel_group[nt - 1] : 0;
+  };
   if (!ws || ws_bytes < total) return PICHOL_ERR_WORKSPACE;
   if (nstreams > (int)bs.size()) nstreams = (int)bs.size();
   std::vector<int> run_order;
@@ -345,7 +353,7 @@ pichol_status pichol_cv_batch(int32_t nprob, const pichol_batch_item* items,
   if (nstreams == 1) {
     hipError_t e = hipSuccess;
     for (int j : run_order) {
-      e = run_bucket(bs[j], items, method, ws, stream);
+      e = run_bucket(bs[j], items, method, group_of(bs[j]), ws, stream);
       if (e != hipSuccess) break;
     }
     return hip_status(e);
@@ -359,7 +367,8 @@ pichol_status pichol_cv_batch(int32_t nprob, const pichol_batch_item* items,
     e = hipStreamWaitEvent(S->st[i], S->fork, 0);
   for (int j : run_order) {
     if (e != hipSuccess) break;
-    e = run_bucket(bs[j], items, method, ws, S->st[bs[j].stream]);
+    e = run_bucket(bs[j], items, method, group_of(bs[j]), ws,
+                   S->st[bs[j].stream]);
   }
   // join every forked stream back, also after a failure, so that no stream
   // is left depending on work the caller does not wait for

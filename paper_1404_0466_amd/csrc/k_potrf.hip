@@ -74,6 +74,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
                                                     int kk, double* L,
                                                     int* info, double* linv) {
   __shared__ double a[NB2];
+  __shared__ double grp[32 * 4];  // one 4-column group of the 32 x 32 block
   const int f = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double* tile = L + (int64_t)f * S + tile_off(kk, kk);
@@ -82,25 +83,49 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
 
   for (int jb = 0; jb < 4; ++jb) {
     const int j0 = 32 * jb;
-    // (1) diagonal 32 x 32 block, wave 0, lane = row j0 + lane
+    // (1) diagonal 32 x 32 block, wave 0, lane = row j0 + lane.  Columns
+    // are factored in groups of four: inside a group by rank-1 updates with
+    // readlane broadcasts; then each lane publishes its row of the group in
+    // LDS and the trailing columns take the group's four contributions from
+    // there (one broadcast read per row instead of four readlane pairs).
+    // The subtractions keep the order of plain right-looking elimination.
     if (w == 0) {
       double r[32];
 #pragma unroll
       for (int k = 0; k < 32; ++k)
         r[k] = (lane < 32 && k <= lane) ? a[(j0 + k) * NB + j0 + lane] : 0.0;
 #pragma unroll
-      for (int j = 0; j < 32; ++j) {
-        const double piv = bcast_lane(r[j], j);
-        if (lane == 0 && !(piv > 0.0) && info[f] == 0 &&
-            (int64_t)kk * NB + j0 + j < d)
-          info[f] = kk * NB + j0 + j + 1;
-        const double ljj = sqrt(piv);
-        if (lane == j) r[j] = ljj;
-        else if (lane > j) r[j] = r[j] / ljj;
+      for (int jg = 0; jg < 32; jg += 4) {
 #pragma unroll
-        for (int k = j + 1; k < 32; ++k) {
-          const double lkj = bcast_lane(r[j], k);
-          if (lane >= k) r[k] -= r[j] * lkj;
+        for (int j = jg; j < jg + 4; ++j) {
+          const double piv = bcast_lane(r[j], j);
+          if (lane == 0 && !(piv > 0.0) && info[f] == 0 &&
+              (int64_t)kk * NB + j0 + j < d)
+            info[f] = kk * NB + j0 + j + 1;
+          const double ljj = sqrt(piv);
+          if (lane == j) r[j] = ljj;
+          else if (lane > j) r[j] = r[j] / ljj;
+#pragma unroll
+          for (int k = j + 1; k < jg + 4; ++k) {
+            const double lkj = bcast_lane(r[j], k);
+            if (lane >= k) r[k] -= r[j] * lkj;
+          }
+        }
+        if (jg + 4 < 32) {
+          if (lane < 32)
+            *(v4d*)(grp + 4 * lane) = v4d{r[jg], r[jg + 1], r[jg + 2], r[jg + 3]};
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int k = jg + 4; k < 32; ++k) {
+            const v4d lk = *(const v4d*)(grp + 4 * k);
+            if (lane >= k) {
+              r[k] -= r[jg] * lk[0];
+              r[k] -= r[jg + 1] * lk[1];
+              r[k] -= r[jg + 2] * lk[2];
+              r[k] -= r[jg + 3] * lk[3];
+            }
+          }
+          __builtin_amdgcn_wave_barrier();
         }
       }
       if (lane < 32) {
@@ -225,14 +250,14 @@ __device__ inline void potrf_update_body(int64_t S, int nt, int j0, int mode, in
     I = j0 + r;
     J = j0 + (t - (int)tri(r));
   } else {
-    const int n1 = nt - j0;  // tiles of column j0
-    if (t < n1) {
-      I = j0 + t;
-      J = j0;
-    } else {
-      I = j0 + 1 + (t - n1);
-      J = j0 + 1;
+    // `mode` whole columns j0, j0+1, ..., enumerated column by column
+    int J0 = j0, tt = t;
+    while (tt >= nt - J0) {
+      tt -= nt - J0;
+      ++J0;
     }
+    I = J0 + tt;
+    J = J0;
   }
   const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
   if (I == J && wi > wj) return;  // block strictly above the diagonal
@@ -324,7 +349,7 @@ static SideStream* side_stream() {
 // the bulk of the update.
 hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
                                 double* linv_ws, int mixed, int lookahead,
-                                hipStream_t s) {
+                                int group, hipStream_t s) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
   std::unique_lock<std::mutex> lk(g_side_mu, std::defer_lock);
@@ -341,9 +366,8 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
   auto update = [&](hipStream_t st, int j0, int mode, int c0, int c1) {
     const int rest = nt - j0;
     if (rest <= 0) return;
-    const int ntile = mode == 0 ? (int)tri(rest)
-                                : (mode == 1 || rest == 1 ? rest : 2 * rest - 1);
-    const int m = (mode == 2 && rest == 1) ? 1 : mode;
+    const int m = mode == 0 ? 0 : (mode < rest ? mode : rest);
+    const int ntile = m == 0 ? (int)tri(rest) : m * rest - m * (m - 1) / 2;
     if (mixed)
       PICHOL_LAUNCH(k_potrf_update_f32, dim3((unsigned)(ntile * nfac)),
                     dim3(256), 0, st, S, nt, j0, m, c0, c1, ntile, L);
@@ -351,6 +375,20 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
       PICHOL_LAUNCH(k_potrf_update, dim3((unsigned)(ntile * nfac)), dim3(256),
                     0, st, S, nt, j0, m, c0, c1, ntile, L);
   };
+  const int G = group > 0 ? group : option_panel_group();
+  if (!side || G != 2) {
+    // Panels in groups of G: before its diagonal factorization, column
+    // kk+u receives the group's earlier panels (K = 128 u); after the group,
+    // one update of rank 128 G reaches the rest of the trailing matrix.
+    for (int kk = 0; kk < nt; kk += G) {
+      for (int u = 0; u < G && kk + u < nt; ++u) {
+        if (u > 0) update(s, kk + u, 1, kk, kk + u);
+        diag_panel(kk + u);
+      }
+      if (kk + G < nt) update(s, kk + G, 0, kk, kk + G);
+    }
+    return hipGetLastError();
+  }
   int ring = 0;
   bool pending = false;  // a side-stream update not yet joined
   hipEvent_t joined = nullptr;

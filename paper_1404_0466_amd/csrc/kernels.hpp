@@ -29,6 +29,7 @@ hipError_t record_hip_error_code(hipError_t e);
 
 // Library options (pichol_set_option).
 int option_lookahead();
+int option_panel_group();
 inline int record_hip_error(hipError_t e) {
   record_hip_error_code(e);
   return -3;  // PICHOL_ERR_HIP
@@ -66,10 +67,11 @@ hipError_t launch_shift_copy(int64_t d, int nmat, const double* H, int nshift,
                              const double* lam_dev, int lam_group, double* L,
                              int* info, hipStream_t s);
 // lookahead: 1 runs the bulk of each trailing update on the library's side
-// stream (see k_potrf.hip), 0 keeps everything on s.
+// stream (see k_potrf.hip), 0 keeps everything on s.  group: panels per
+// delayed trailing update (0: the library option).
 hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
                                 double* linv_ws, int mixed, int lookahead,
-                                hipStream_t s);
+                                int group, hipStream_t s);
 
 // ---- fit / evaluate (k_fit.hip)
 struct FitCoef {

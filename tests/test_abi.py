@@ -116,3 +116,10 @@ def test_options(lib):
     with pytest.raises(B.PicholError):
         B.pichol_set_option(99, 0)
     assert B.pichol_get_option(99) == -1
+    assert B.pichol_get_option(B.PICHOL_OPT_PANEL_GROUP) == 4
+    for gsz in [1, 3, 8, 4]:
+        B.pichol_set_option(B.PICHOL_OPT_PANEL_GROUP, gsz)
+        assert B.pichol_get_option(B.PICHOL_OPT_PANEL_GROUP) == gsz
+    for bad in [0, 9]:
+        with pytest.raises(B.PicholError):
+            B.pichol_set_option(B.PICHOL_OPT_PANEL_GROUP, bad)

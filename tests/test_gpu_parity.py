@@ -107,6 +107,30 @@ def test_potrf_matches_oracle(gu, d):
             close(Lg[m * len(lam) + s], Lo, 1e-11, f"L d={d} m={m} s={s}")
 
 
+@pytest.mark.parametrize("group", [1, 2, 3, 8])
+@pytest.mark.parametrize("d", [300, 1000])
+def test_potrf_panel_groups_match_oracle(gu, d, group):
+    nmat, lam = 2, np.array([1e-3, 0.4])
+    H = np.stack([spd(d, 7 * d + m, cond=1e3) for m in range(nmat)])
+    S = gu.B.pichol_packed_elems(d)
+    L = gu.empty(nmat * len(lam) * S)
+    info = gu.empty(nmat * len(lam), torch.int32)
+    nb = gu.B.pichol_potrf_workspace(nmat, len(lam))
+    old = gu.B.pichol_get_option(gu.B.PICHOL_OPT_PANEL_GROUP)
+    gu.B.pichol_set_option(gu.B.PICHOL_OPT_PANEL_GROUP, group)
+    try:
+        gu.B.pichol_potrf_shifted_batched(d, nmat, gu.pack(H, d), len(lam), lam, L, info,
+                                          gu.ws(nb), nb)
+        Lg = gu.unpack(L, d, nmat * len(lam))
+    finally:
+        gu.B.pichol_set_option(gu.B.PICHOL_OPT_PANEL_GROUP, old)
+    assert np.all(info.cpu().numpy() == 0)
+    for m in range(nmat):
+        for s, l in enumerate(lam):
+            Lo, io = oracle.cholesky(H[m], l)
+            close(Lg[m * len(lam) + s], Lo, 1e-11, f"L d={d} group={group}")
+
+
 def test_potrf_padding_and_upper_zero(gu):
     d = 200
     H = spd(d, 3)
