@@ -175,25 +175,28 @@ __global__ void __launch_bounds__(256) k_diag_inv(int64_t d, FactorSrc src,
   }
 }
 
-// Diagonal block solve of tile row i by multiplication with the stored
-// inverse: z <- M z for the c columns of lambda t = blockIdx.x of fold
-// m = blockIdx.y, where M(r,k) = mat[k*128 + r] (the inverse for forward
-// steps, its transpose for back steps).
+// Apply the stored inverse of diagonal block i to the slab rows of tile i:
+// z <- M z for the c columns of lambda t = blockIdx.x of fold m =
+// blockIdx.y, where M(r,k) = mat[k*128 + r] (the inverse for forward steps,
+// its transpose for back steps).  One workgroup per (fold, lambda) owns the
+// whole block (the update is in place); its threads split the 128-long sums
+// into two halves of two 32-load rounds each, and the halves are added in
+// LDS.
 __global__ void __launch_bounds__(256) k_diag_apply(int64_t d, int i, int nper,
                                                     int c, const double* mats,
                                                     int64_t ldz, double* Z) {
   __shared__ double zs[NB * 16];
+  __shared__ double part[NB * 17];
   const int t = blockIdx.x;
   const int64_t m = blockIdx.y;
   const int nt = (int)ntiles_of(d);
-  const int tid = threadIdx.x, row = tid & (NB - 1), half = tid >> 7;
+  const int tid = threadIdx.x, row = tid & (NB - 1), kh = tid >> 7;
   const int64_t dp = (int64_t)nt * NB;
   const double* M = mats + ((m * nper + t) * nt + i) * (int64_t)NB2;
   double* zb = Z + (m * dp + (int64_t)i * NB) * ldz + (int64_t)t * c;
   for (int cg = 0; cg < c; cg += 16) {
     const int cn = (c - cg) < 16 ? (c - cg) : 16;
     if (cg) __syncthreads();
-    // the 128 x 16 right-hand-side block into LDS: eight loads in flight
     double zv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -203,23 +206,28 @@ __global__ void __launch_bounds__(256) k_diag_apply(int64_t d, int i, int nper,
 #pragma unroll
     for (int u = 0; u < 8; ++u) zs[tid + 256 * u] = zv[u];
     __syncthreads();
-    // M z in chunks of 32 columns of M, each chunk's loads issued together
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
 #pragma unroll 1
-    for (int k0 = 0; k0 < NB; k0 += 32) {
+    for (int k0 = 64 * kh; k0 < 64 * kh + 64; k0 += 32) {
       double mv[32];
 #pragma unroll
       for (int kk = 0; kk < 32; ++kk) mv[kk] = M[(k0 + kk) * NB + row];
 #pragma unroll
       for (int kk = 0; kk < 32; ++kk)
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          acc[u] += mv[kk] * zs[(k0 + kk) * 16 + half + 2 * u];
+        for (int u = 0; u < 16; ++u) acc[u] += mv[kk] * zs[(k0 + kk) * 16 + u];
     }
+    if (kh == 1) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int cc = half + 2 * u;
-      if (cc < cn) zb[(int64_t)row * ldz + cg + cc] = acc[u];
+      for (int u = 0; u < 16; ++u) part[row * 17 + u] = acc[u];
+    }
+    __syncthreads();  // every read of the block's rows precedes the writes
+    if (kh == 0) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (u < cn) zb[(int64_t)row * ldz + cg + u] = acc[u] + part[row * 17 + u];
     }
   }
 }
@@ -299,28 +307,41 @@ __global__ void __launch_bounds__(128) k_update_factors(int64_t d, int i,
   for (int cg = 0; cg < c; cg += 16) {
     const int cn = (c - cg) < 16 ? (c - cg) : 16;
     if (cg) __syncthreads();
-    for (int e = row; e < NB * 16; e += NB) {
-      const int k = e >> 4, cc = e & 15;
-      zs[e] = cc < cn ? zsrc[(int64_t)k * ldz + cg + cc] : 0.0;
+    {
+      double zv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = row + NB * u, k = e >> 4, cc = e & 15;
+        zv[u] = cc < cn ? zsrc[(int64_t)k * ldz + cg + cc] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) zs[row + NB * u] = zv[u];
     }
     __syncthreads();
     double acc[16] = {};
-    if (FWD) {
-#pragma unroll 4
-      for (int k = 0; k < NB; ++k) {
-        const double lv = tile[k * NB + row];
+    // 32 entries of the lane's row of the tile are loaded together, so that
+    // many loads are in flight per thread (the kernel streams the tiles)
+#pragma unroll 1
+    for (int k0 = 0; k0 < NB; k0 += 32) {
+      double lv[32];
+      if (FWD) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) acc[u] += lv * zs[k * 16 + u];
+        for (int kk = 0; kk < 32; ++kk) lv[kk] = tile[(k0 + kk) * NB + row];
+      } else {
+        const double* colr = tile + row * NB + k0;
+#pragma unroll
+        for (int kk = 0; kk < 32; kk += 4) {
+          const v4d v = ld4(colr + kk);
+          lv[kk] = v[0];
+          lv[kk + 1] = v[1];
+          lv[kk + 2] = v[2];
+          lv[kk + 3] = v[3];
+        }
       }
-    } else {
-      const double* colr = tile + row * NB;
-      for (int k0 = 0; k0 < NB; k0 += 4) {
-        const v4d lv = ld4(colr + k0);
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+      for (int kk = 0; kk < 32; ++kk)
 #pragma unroll
-          for (int u = 0; u < 16; ++u) acc[u] += lv[e] * zs[(k0 + e) * 16 + u];
-      }
+        for (int u = 0; u < 16; ++u) acc[u] += lv[kk] * zs[(k0 + kk) * 16 + u];
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u)
