@@ -395,13 +395,16 @@ def test_cv_with_lookahead_matches_without(gu, method):
     (same kernels, same per-tile accumulation order)."""
     B = gu.B
     p = workloads.rff_problem(2000, 700, 10, seed=6, g=5, q=12)
+    old_group = B.pichol_get_option(B.PICHOL_OPT_PANEL_GROUP)
+    B.pichol_set_option(B.PICHOL_OPT_PANEL_GROUP, 2)  # the look-ahead schedule's group
     B.pichol_set_option(B.PICHOL_OPT_LOOKAHEAD, 0)
-    a = gu.cv(p, method)
-    B.pichol_set_option(B.PICHOL_OPT_LOOKAHEAD, 1)
     try:
+        a = gu.cv(p, method)
+        B.pichol_set_option(B.PICHOL_OPT_LOOKAHEAD, 1)
         b = gu.cv(p, method)
     finally:
         B.pichol_set_option(B.PICHOL_OPT_LOOKAHEAD, 0)
+        B.pichol_set_option(B.PICHOL_OPT_PANEL_GROUP, old_group)
     np.testing.assert_array_equal(a["mse"], b["mse"])
     np.testing.assert_array_equal(a["W"], b["W"])
     want = (oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r) if method == "interp"
