@@ -216,6 +216,24 @@ __device__ inline int xcd_remap(int id, int n) {
   return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
 }
 
+// s ~ sqrt(x) and y ~ 1/sqrt(x) for a positive x: the hardware
+// reciprocal-square-root estimate refined by two Newton steps
+// y <- y + y (1 - x y^2) / 2, then s = x y corrected once by
+// s <- s + y (x - s^2) / 2.  A few-ulp replacement for a correctly rounded
+// square root followed by divisions, with a much shorter dependency chain;
+// a non-positive or NaN x gives non-finite results.
+__device__ inline void sqrt_rsqrt(double x, double& s, double& y) {
+  double r = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * r, r, 1.0);
+  r = fma(0.5 * r, e, r);
+  e = fma(-x * r, r, 1.0);
+  r = fma(0.5 * r, e, r);
+  double t = x * r;
+  t = fma(0.5 * r, fma(-t, t, x), t);
+  s = t;
+  y = r;
+}
+
 __device__ inline double bcast_lane(double v, int lane) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
@@ -277,7 +295,8 @@ __device__ inline void inv_combine(double* a, int tid) {
 // pairs of blocks are combined at sizes 16, 32 and 64.  On return the lower
 // triangle holds the inverse and the strict upper part is still zero.
 // Ends with a barrier.
-__device__ inline void invert_lower_lds(double* a, int tid) {
+__device__ inline void invert_lower_lds(double* a, int tid,
+                                        const double* rdiag = nullptr) {
   __syncthreads();
   {
     const int lane = tid & 63, w = tid >> 6;
@@ -289,7 +308,7 @@ __device__ inline void invert_lower_lds(double* a, int tid) {
 #pragma unroll
     for (int p = 0; p < 16; ++p) {
       const double* col = a + (o + p) * NB + o;
-      x[p] = x[p] / col[p];
+      x[p] = rdiag ? x[p] * rdiag[o + p] : x[p] / col[p];
 #pragma unroll
       for (int i = p + 1; i < 16; ++i) x[i] -= col[i] * x[p];
     }

@@ -75,6 +75,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
                                                     int* info, double* linv) {
   __shared__ double a[NB2];
   __shared__ double grp[32 * 4];  // one 4-column group of the 32 x 32 block
+  __shared__ double rdiag[NB];    // reciprocals of the factor's diagonal
   const int f = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double* tile = L + (int64_t)f * S + tile_off(kk, kk);
@@ -91,6 +92,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
     // The subtractions keep the order of plain right-looking elimination.
     if (w == 0) {
       double r[32];
+      double myinv = 0.0;  // 1 / L(j0+lane, j0+lane)
 #pragma unroll
       for (int k = 0; k < 32; ++k)
         r[k] = (lane < 32 && k <= lane) ? a[(j0 + k) * NB + j0 + lane] : 0.0;
@@ -102,9 +104,14 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
           if (lane == 0 && !(piv > 0.0) && info[f] == 0 &&
               (int64_t)kk * NB + j0 + j < d)
             info[f] = kk * NB + j0 + j + 1;
-          const double ljj = sqrt(piv);
-          if (lane == j) r[j] = ljj;
-          else if (lane > j) r[j] = r[j] / ljj;
+          double ljj, inv;
+          sqrt_rsqrt(piv, ljj, inv);
+          if (lane == j) {
+            r[j] = ljj;
+            myinv = inv;
+          } else if (lane > j) {
+            r[j] = r[j] * inv;
+          }
 #pragma unroll
           for (int k = j + 1; k < jg + 4; ++k) {
             const double lkj = bcast_lane(r[j], k);
@@ -132,6 +139,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
 #pragma unroll
         for (int k = 0; k < 32; ++k)
           if (k <= lane) a[(j0 + k) * NB + j0 + lane] = r[k];
+        rdiag[j0 + lane] = myinv;
       }
     }
     __syncthreads();
@@ -145,7 +153,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
       for (int k = 0; k < 32; ++k) x[k] = a[(j0 + k) * NB + i];
 #pragma unroll
       for (int j = 0; j < 32; ++j) {
-        x[j] = x[j] / a[(j0 + j) * NB + j0 + j];
+        x[j] = x[j] * rdiag[j0 + j];
 #pragma unroll
         for (int p = j + 1; p < 32; ++p) x[p] -= x[j] * a[(j0 + j) * NB + j0 + p];
       }
@@ -189,7 +197,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
   tile_lower_from_lds(tile, a, tid);
 
   __syncthreads();
-  invert_lower_lds(a, tid);
+  invert_lower_lds(a, tid, rdiag);
   double* li = linv + (int64_t)f * NB2;
   tile_lower_from_lds(li, a, tid);
 }
