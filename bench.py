@@ -54,16 +54,19 @@ def update_flops(d: int, nfac: int) -> float:
     return tot
 
 
-def measured_traffic(exact: bool, lookahead: int):
+def measured_traffic(exact: bool, lookahead: int, group: int):
     """HBM bytes per launch of k_potrf_update from the committed rocprofv3
     counter record (profiles/k_potrf_update_traffic.json), or None when the
     kernel's sources changed since the counters were taken or this run's
-    launch mix differs from the profiled one."""
+    launch mix (methods, look-ahead, panel group) differs from the profiled
+    one."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_potrf_update_traffic.json")
     if not os.path.exists(path) or not exact or lookahead != 0:
         return None
     rec = json.load(open(path))
+    if rec.get("panel_group") != group:
+        return None
     h = hashlib.sha256()
     for f in rec["source_files"]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
@@ -656,7 +659,8 @@ def main():
                 "kernel": "k_potrf_update", "bound": "mfma",
                 "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": measured_traffic(not args.no_exact, args.lookahead),
+                "traffic": measured_traffic(not args.no_exact, args.lookahead,
+                                            B.pichol_get_option(B.PICHOL_OPT_PANEL_GROUP)),
                 "flops_per_launch": avg_flops, "avg_launch_ms": avg_ms,
                 "launches_per_step": per_step_launches,
             }
