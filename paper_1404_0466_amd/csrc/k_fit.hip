@@ -24,29 +24,40 @@ __global__ void __launch_bounds__(256) k_fit(int64_t S, FitCoef fc,
   const int64_t toff = tile_off(I, J);
   const int g = fc.g;
   const int tid = threadIdx.x;
+  // the tile in eight chunks of 16 columns; each thread owns two runs of
+  // four consecutive entries of a chunk (32-byte loads and stores)
   for (int cb = 0; cb < NB / 16; ++cb) {
-    double th[8][M];
+    v4d th[2][M];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = cb * 16 * NB + tid + 256 * u;
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int p = 0; p < M; ++p) th[u][p] = 0.0;
-      for (int s = 0; s < g; ++s) {
-        const double t = L[(m * g + s) * S + toff + e];
+      for (int p = 0; p < M; ++p) th[h][p] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int64_t base = toff + cb * 16 * NB;
+    for (int s = 0; s < g; ++s) {
+      const double* src = L + (m * g + s) * S + base;
+      const v4d x0 = ld4(src + 4 * tid), x1 = ld4(src + 4 * (tid + 256));
 #pragma unroll
-        for (int p = 0; p < M; ++p) th[u][p] += fc.P[p][s] * t;
+      for (int p = 0; p < M; ++p) {
+        th[0][p] += fc.P[p][s] * x0;
+        th[1][p] += fc.P[p][s] * x1;
       }
+    }
 #pragma unroll
-      for (int p = 0; p < M; ++p) theta[(m * M + p) * S + toff + e] = th[u][p];
+    for (int p = 0; p < M; ++p) {
+      double* dst = theta + (m * M + p) * S + base;
+      st4(dst + 4 * tid, th[0][p]);
+      st4(dst + 4 * (tid + 256), th[1][p]);
     }
     if (theta_t == nullptr) continue;
 #pragma unroll
     for (int p = 0; p < M; ++p) {
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = tid + 256 * u;  // within the 16-column chunk
-        lds[(e >> 7) * LDS_LD + (e & (NB - 1))] = th[u][p];
+      for (int h = 0; h < 2; ++h) {
+        const int e = 4 * (tid + 256 * h);  // within the chunk
+        const int col = e >> 7, row = e & (NB - 1);
+#pragma unroll
+        for (int x = 0; x < 4; ++x) lds[col * LDS_LD + row + x] = th[h][p][x];
       }
       __syncthreads();
       double* dst = theta_t + (m * M + p) * S + toff + cb * 16;

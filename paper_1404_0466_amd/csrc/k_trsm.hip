@@ -156,6 +156,7 @@ __global__ void __launch_bounds__(256) k_diag_inv(int64_t d, FactorSrc src,
                                                   double* dinv, double* dinv_r,
                                                   int* flags) {
   __shared__ double a[NB2];
+  __shared__ double rdiag[NB];
   const int i = blockIdx.x, t = blockIdx.y;
   const int64_t m = blockIdx.z;
   const int nt = gridDim.x;
@@ -163,9 +164,13 @@ __global__ void __launch_bounds__(256) k_diag_inv(int64_t d, FactorSrc src,
   tile_eval_to_lds(a, src.base + m * src.M * src.S + tile_off(i, i), src.S,
                    src.M, src.tau[t], tid);
   __syncthreads();
-  if (tid < NB && (int64_t)i * NB + tid < d && !(a[tid * NB + tid] > 0.0))
-    atomicOr(flags + m * src.nper + t, 2);
-  invert_lower_lds(a, tid);
+  if (tid < NB) {
+    const double dg = a[tid * NB + tid];
+    if ((int64_t)i * NB + tid < d && !(dg > 0.0))
+      atomicOr(flags + m * src.nper + t, 2);
+    rdiag[tid] = 1.0 / dg;  // the leaves of the inverse multiply by these
+  }
+  invert_lower_lds(a, tid, rdiag);
   const int64_t off = ((m * src.nper + t) * nt + i) * (int64_t)NB2;
   tile_lower_from_lds(dinv + off, a, tid);
 #pragma unroll 8
