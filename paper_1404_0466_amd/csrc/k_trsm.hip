@@ -240,22 +240,32 @@ __global__ void __launch_bounds__(256) k_diag_apply(int64_t d, int i, int nper,
 // Off-diagonal update for interpolated factors.  Forward step i: rows of
 // tile I > i lose sum_p Theta_p(I,i) (tau^p .* U_i); backward step i: rows
 // of tile I < i lose sum_p Theta_p(i,I)^T (tau^p .* W_i), read from the
-// row-major copy of the planes.  The accumulators start from the slab rows
-// being updated and the products are subtracted (negative scale).  Logical
-// workgroup ids run over the column blocks fastest, so the blocks that
-// share a coefficient tile meet on one XCD.
+// row-major copy of the planes.  A workgroup owns a 64 x 128 block (half of
+// the tile's rows, one 128-column block of the slab); its four waves split
+// it into two 64-column halves and the 128-long sums of every plane into two
+// 64-long halves, so a launch has twice as many, twice as short workgroups
+// (the last round of a launch is less empty).  The first half's
+// accumulators start from the slab rows being updated, the second half's
+// from zero; the second hands its partial sums over in LDS and the first
+// adds them (a fixed order).  Products are subtracted (negative scale).
+// Logical workgroup ids run over the column blocks fastest, so the blocks
+// that share a coefficient tile meet on one XCD.
 template <bool FWD>
-__global__ void __launch_bounds__(256) k_update_interp(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_update_interp(
     int64_t d, int i, const double* theta, const double* theta_t, int64_t S,
     int M, int q, int c, const double* tau, int64_t ldz, int ncb, int nrows,
     double* Z) {
+  __shared__ v4d xch[2][16][64];  // partial sums of the k-second-half waves
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int cb = id % ncb;
   const int rest = id / ncb;
-  const int row = rest % nrows;
-  const int64_t m = rest / nrows;
+  const int rh = rest & 1;  // row half of the tile
+  const int row = (rest >> 1) % nrows;
+  const int64_t m = (rest >> 1) / nrows;
   const int I = FWD ? i + 1 + row : row;
-  const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
+  const int w = threadIdx.x >> 6, wj = w & 1, kh = w >> 1;
+  const int l = threadIdx.x & 63;
   const int64_t dp = ntiles_of(d) * NB;
   const LaneXY lx;
   const int64_t col = (int64_t)cb * NB + wj * 64 + lx.col0();
@@ -268,23 +278,41 @@ __global__ void __launch_bounds__(256) k_update_interp(
   const double* planes = FWD ? theta + m * M * S + tile_off(I, i)
                              : theta_t + m * M * S + tile_off(i, I);
   const double* bsrc = Z + (m * dp + (int64_t)i * NB) * ldz + cb * NB + wj * 64;
-  double* zt = Z + (m * dp + (int64_t)I * NB + wi * 64) * ldz + col;
+  double* zt = Z + (m * dp + (int64_t)I * NB + rh * 64) * ldz + col;
   Acc64 acc;
+  if (kh == 0) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v)
+    for (int v = 0; v < 4; ++v)
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
-      acc.set_row(v, bi, ld4(zt + (int64_t)lx.row(v, bi) * ldz));
+      for (int bi = 0; bi < 4; ++bi)
+        acc.set_row(v, bi, ld4(zt + (int64_t)lx.row(v, bi) * ldz));
+  } else {
+    acc.zero();
+  }
   v4d scale = {-1.0, -1.0, -1.0, -1.0};
   for (int p = 0; p < M; ++p) {
-    mma_panel_scaled(acc, planes + p * S + wi * 64, NB, bsrc, ldz, NB, scale);
+    mma_panel_scaled(acc, planes + p * S + rh * 64 + (int64_t)kh * 64 * NB, NB,
+                     bsrc + (int64_t)kh * 64 * ldz, ldz, 64, scale);
     scale *= tau4;
   }
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
+  if (kh == 1) {
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
-      st4(zt + (int64_t)lx.row(v, bi) * ldz, acc.row(v, bi));
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) xch[wj][bi * 4 + bj][l] = acc.c[bi][bj];
+  }
+  __syncthreads();
+  if (kh == 0) {
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) acc.c[bi][bj] += xch[wj][bi * 4 + bj][l];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+        st4(zt + (int64_t)lx.row(v, bi) * ldz, acc.row(v, bi));
+  }
 }
 
 // Off-diagonal update for exact factors, one factor per lambda t:
@@ -388,17 +416,17 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
                   s, d, i, q, c, dinv, ldz, Z);
     if (i + 1 < nt) {
       const int nrows = nt - i - 1;
-      PICHOL_LAUNCH(k_update_interp<true>, dim3(ncb * nrows * nmat), dim3(256),
-                    0, s, d, i, theta, theta_t, S, M, q, c, tau_dev, ldz,
-                    (int)ncb, nrows, Z);
+      PICHOL_LAUNCH(k_update_interp<true>, dim3(ncb * 2 * nrows * nmat),
+                    dim3(256), 0, s, d, i, theta, theta_t, S, M, q, c, tau_dev,
+                    ldz, (int)ncb, nrows, Z);
     }
   }
   for (int i = nt - 1; i >= 0; --i) {
     PICHOL_LAUNCH(k_diag_apply, dim3((unsigned)q, (unsigned)nmat), dim3(256), 0,
                   s, d, i, q, c, dinv_r, ldz, Z);
     if (i > 0)
-      PICHOL_LAUNCH(k_update_interp<false>, dim3(ncb * i * nmat), dim3(256), 0,
-                    s, d, i, theta, theta_t, S, M, q, c, tau_dev, ldz,
+      PICHOL_LAUNCH(k_update_interp<false>, dim3(ncb * 2 * i * nmat), dim3(256),
+                    0, s, d, i, theta, theta_t, S, M, q, c, tau_dev, ldz,
                     (int)ncb, i, Z);
   }
   return hipGetLastError();
