@@ -216,7 +216,7 @@ static Layout layout_of(const pichol_problem* p) {
   L.i_th = a; a += align256(k * M * L.S * dbl);
   L.i_tht = a; a += align256(k * M * L.S * dbl);
   L.i_Z = a; a += align256(k * L.dp * L.ldz * dbl);
-  L.i_part = a; a += align256(k * L.nt * L.ldz * dbl);
+  L.i_part = a; a += align256(k * L.nt * HOLDOUT_KSPLIT * L.ldz * dbl);
   L.i_dinv = a; a += align256(k * q * L.nt * NB2 * dbl);
   L.i_dinvr = a; a += align256(k * q * L.nt * NB2 * dbl);
   L.i_lamg = a; a += align256(q * dbl);
@@ -240,7 +240,7 @@ static Layout layout_of(const pichol_problem* p) {
   L.e_L = a; a += align256(k * q * L.S * dbl);
   L.e_linv = a; a += align256(k * q * NB2 * dbl);
   L.e_Z = a; a += align256(k * L.dp * L.ldz * dbl);
-  L.e_part = a; a += align256(k * L.nt * L.ldz * dbl);
+  L.e_part = a; a += align256(k * L.nt * HOLDOUT_KSPLIT * L.ldz * dbl);
   L.e_rH = a; a += rH;
   L.e_rZ = a; a += rZ;
   L.e_end = a;
@@ -513,8 +513,8 @@ pichol_status pichol_solve_factors(int64_t d, int32_t nmat, int32_t nper,
 
 size_t pichol_holdout_workspace(int64_t d, int32_t nmat, int32_t q, int32_t c) {
   if (d < 1 || nmat < 1 || q < 1 || c < 1) return 0;
-  return align256((size_t)nmat * ntiles_of(d) * pichol_slab_cols(q, c) *
-                  sizeof(double));
+  return align256((size_t)nmat * ntiles_of(d) * HOLDOUT_KSPLIT *
+                  pichol_slab_cols(q, c) * sizeof(double));
 }
 
 pichol_status pichol_holdout(int64_t d, int32_t nmat, int32_t c, int32_t q,

@@ -106,7 +106,7 @@ void layout_bucket(Bucket& b, int method) {
   b.th = o; o += interp ? align256(nmat * M * S * dbl) : 0;
   b.tht = o; o += interp ? align256(nmat * M * S * dbl) : 0;
   b.Z = o; o += align256(nmat * dp * ldz * dbl);
-  b.part = o; o += align256(nmat * nt * ldz * dbl);
+  b.part = o; o += align256(nmat * nt * HOLDOUT_KSPLIT * ldz * dbl);
   b.dinv = o; o += interp ? align256(nmat * q * nt * NB2 * dbl) : 0;
   b.dinvr = o; o += interp ? align256(nmat * q * nt * NB2 * dbl) : 0;
   b.info = o; o += align256(nmat * nf * i32);
@@ -235,7 +235,8 @@ hipError_t run_bucket(const Bucket& b, const pichol_batch_item* items,
     const int64_t m0 = (int64_t)li * k;
     HoldoutNorm hn;
     holdout_norm(&it.p, &hn);
-    e = launch_holdout_final(d, k, c, q, ldz, part + m0 * nt * ldz, yy + m0, hn,
+    e = launch_holdout_final(d, k, c, q, ldz,
+                             part + m0 * nt * HOLDOUT_KSPLIT * ldz, yy + m0, hn,
                              it.err, flags + m0 * q, st);
     if (e == hipSuccess)
       e = launch_copy_i32((int64_t)k * nf, info + m0 * nf, it.info, st);

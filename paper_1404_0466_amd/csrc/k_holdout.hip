@@ -11,26 +11,31 @@
 namespace pichol {
 
 // Partial sums over the rows of tile row I of
-//     W(r, col) * ((G W)(r, col) - 2 C(r, col mod c))
-// for the 128 slab columns of block cb; written to
-// partial[m][I][col].
+//     W(r, col) * ((G W)_h(r, col) - [h == 0] 2 C(r, col mod c))
+// for the 128 slab columns of block cb, where (G W)_h sums over the h-th of
+// HOLDOUT_KSPLIT ranges of column blocks J (the expansion is linear in
+// G W); written to partial[m][I][h][col].
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_holdout_partial(
     int64_t d, int q, int c, int64_t ldz, const double* Z, const double* G,
     const double* C, double* partial) {
   __shared__ double red[64 * 2];
   const int cb = blockIdx.x;
   const int I = blockIdx.y;
-  const int64_t m = blockIdx.z;
+  const int64_t m = blockIdx.z / HOLDOUT_KSPLIT;
+  const int h = blockIdx.z % HOLDOUT_KSPLIT;
   const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
   const int64_t nt = ntiles_of(d), dp = nt * NB;
+  const int J0 = (int)(nt * h / HOLDOUT_KSPLIT);
+  const int J1 = (int)(nt * (h + 1) / HOLDOUT_KSPLIT);
   const LaneXY lx;
   const double* gm = G + m * dp * dp + (int64_t)I * nt * NB2 + wi * 64;
   const double* zm = Z + m * dp * ldz + (int64_t)cb * NB + wj * 64;
   Acc64 acc;
   acc.zero();
-  for (int J = 0; J < nt; ++J)
+  for (int J = J0; J < J1; ++J)
     mma_panel(acc, gm + (int64_t)J * NB2, NB, zm + (int64_t)J * NB * ldz, ldz,
               NB);
+  const double c2 = h == 0 ? 2.0 : 0.0;
 
   const int64_t col = (int64_t)cb * NB + wj * 64 + lx.col0();
   const int64_t qc = (int64_t)q * c;
@@ -48,7 +53,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
       const double* cr = C + (m * dp + r) * c;
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        part[e] += wv[e] * (gw[e] - 2.0 * cr[cmod[e]]);
+        part[e] += wv[e] * (gw[e] - c2 * cr[cmod[e]]);
     }
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -64,7 +69,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
   }
   __syncthreads();
   if (wi == 0 && lx.lq == 0) {
-    double* out = partial + (m * nt + I) * ldz + col;
+    double* out = partial + ((m * nt + I) * HOLDOUT_KSPLIT + h) * ldz + col;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const double v = (col + e) < qc ? part[e] + red[wj * 64 + lx.col0() + e] : 0.0;
@@ -84,8 +89,8 @@ __global__ void __launch_bounds__(64) k_holdout_final(int64_t nt, int q, int c,
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= q) return;
   double sse = yy[m];
-  for (int64_t I = 0; I < nt; ++I) {
-    const double* p = partial + (m * nt + I) * ldz + (int64_t)t * c;
+  for (int64_t I = 0; I < nt * HOLDOUT_KSPLIT; ++I) {
+    const double* p = partial + (m * nt * HOLDOUT_KSPLIT + I) * ldz + (int64_t)t * c;
     for (int j = 0; j < c; ++j) sse += p[j];
   }
   const double e = sse / hn.count[m];
@@ -99,7 +104,8 @@ hipError_t launch_holdout_partial(int64_t d, int nmat, int c, int q,
                                   double* partial, hipStream_t s) {
   const int64_t nt = ntiles_of(d);
   PICHOL_LAUNCH(k_holdout_partial,
-                     dim3((unsigned)(ldz / NB), (unsigned)nt, (unsigned)nmat),
+                     dim3((unsigned)(ldz / NB), (unsigned)nt,
+                          (unsigned)(nmat * HOLDOUT_KSPLIT)),
                      dim3(256), 0, s, d, q, c, ldz, Z, G, C, partial);
   return hipGetLastError();
 }

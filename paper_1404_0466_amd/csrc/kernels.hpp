@@ -110,6 +110,10 @@ struct HoldoutNorm {
   int nmat;
   double count[64];  // n_v * c per fold
 };
+// The hold-out products split their 128-row-block sums over this many
+// ranges of column blocks (more, shorter workgroups); partial sums hold
+// nmat * nt * HOLDOUT_KSPLIT * ldz doubles.
+constexpr int HOLDOUT_KSPLIT = 2;
 hipError_t launch_holdout_partial(int64_t d, int nmat, int c, int q,
                                   int64_t ldz, const double* Z,
                                   const double* G, const double* C,
