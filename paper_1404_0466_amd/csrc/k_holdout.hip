@@ -85,17 +85,24 @@ __global__ void __launch_bounds__(64) k_holdout_final(int64_t nt, int q, int c,
                                                       const double* yy,
                                                       HoldoutNorm hn,
                                                       double* err, int* flags) {
+  // one wavefront per (lambda t, fold m): lane l sums the partial rows
+  // l, l + 64, ... in order, then a fixed butterfly adds the 64 lanes
+  const int t = blockIdx.x;
   const int64_t m = blockIdx.y;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= q) return;
-  double sse = yy[m];
-  for (int64_t I = 0; I < nt * HOLDOUT_KSPLIT; ++I) {
-    const double* p = partial + (m * nt * HOLDOUT_KSPLIT + I) * ldz + (int64_t)t * c;
-    for (int j = 0; j < c; ++j) sse += p[j];
+  const int l = threadIdx.x;
+  const int64_t nI = nt * HOLDOUT_KSPLIT;
+  double s = 0.0;
+  for (int64_t I = l; I < nI; I += 64) {
+    const double* p = partial + (m * nI + I) * ldz + (int64_t)t * c;
+    for (int j = 0; j < c; ++j) s += p[j];
   }
-  const double e = sse / hn.count[m];
-  err[m * q + t] = e;
-  if (!isfinite(e)) flags[m * q + t] |= 1;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (l == 0) {
+    const double e = (yy[m] + s) / hn.count[m];
+    err[m * q + t] = e;
+    if (!isfinite(e)) flags[m * q + t] |= 1;
+  }
 }
 
 hipError_t launch_holdout_partial(int64_t d, int nmat, int c, int q,
@@ -115,8 +122,7 @@ hipError_t launch_holdout_final(int64_t d, int nmat, int c, int q, int64_t ldz,
                                 const HoldoutNorm& hn, double* err, int* flags,
                                 hipStream_t s) {
   const int64_t nt = ntiles_of(d);
-  PICHOL_LAUNCH(k_holdout_final,
-                     dim3((unsigned)((q + 63) / 64), (unsigned)nmat), dim3(64),
+  PICHOL_LAUNCH(k_holdout_final, dim3((unsigned)q, (unsigned)nmat), dim3(64),
                      0, s, nt, q, c, ldz, partial, yy, hn, err, flags);
   return hipGetLastError();
 }
