@@ -75,26 +75,26 @@ def _load():
         "orc_cholesky": (_i32, [_i64, _pd, _dbl, _pd]),
         "orc_pack_lower": (None, [_i64, _pd, _pd]),
         "orc_unpack_lower": (None, [_i64, _pd, _pd]),
-        "orc_fit": (_i32, [_i64, _i32, _i32, _pd, _dbl, _pd, _pd]),
-        "orc_eval": (None, [_i64, _i32, _pd, _dbl, _dbl, _pd]),
+        "orc_fit": (_i32, [_i64, _i32, _i32, _pd, _dbl, _pd, _pd, _i32]),
+        "orc_eval": (None, [_i64, _i32, _pd, _dbl, _dbl, _pd, _i32]),
         "orc_solve": (_i32, [_i64, _i64, _pd, _pd, _pd]),
         "orc_holdout_sse": (_dbl, [_i64, _i64, _i64, _pd, _i64, _pd, _i64,
                                    _pd]),
         "orc_holdout_sst": (_dbl, [_i64, _i64, _pd, _i64]),
         "orc_refine": (_i32, [_i64, _i64, _pd, _dbl, _pd, _pd, _pd, _i32]),
-        "orc_eval_deriv": (None, [_i64, _i32, _pd, _dbl, _dbl, _pd]),
+        "orc_eval_deriv": (None, [_i64, _i32, _pd, _dbl, _dbl, _pd, _i32]),
         "orc_cv_grad": (_i32, [_i64, _i64, _i64, _i32, _i32, _i32, _i32,
                                ctypes.c_int, ctypes.c_int, _pd, _pd, _pd, _pd,
-                               _dbl, _pd, _pd, _pi32, _pi32]),
+                               _dbl, _pd, _pd, _pi32, _pi32, _i32]),
         "orc_cv_exact": (_i32, [_i64, _i64, _i64, _i32, _i32, ctypes.c_int,
                                 _pd, _pd, _pd, _pd, _pd, _pd, _pi32, _pi32,
                                 _i32]),
         "orc_cv_interp": (_i32, [_i64, _i64, _i64, _i32, _i32, _i32, _i32,
                                  ctypes.c_int, _pd, _pd, _pd, _pd, _dbl, _pd,
-                                 _pd, _pd, _pd, _pi32, _pi32, _i32]),
+                                 _pd, _pd, _pd, _pi32, _pi32, _i32, _i32]),
         "orc_fold_interp": (_i32, [_i64, _i64, _i32, _i32, _i32, _pd, _pd,
                                    _i64, _pd, _i64, _pd, _i64, _pd, _pd, _dbl,
-                                   _pd, _pd, _pi32, _pi32, _i32]),
+                                   _pd, _pd, _pi32, _pi32, _i32, _i32]),
         "orc_num_threads": (_i32, []),
     }
     for name, (res, args) in sig.items():
@@ -174,26 +174,28 @@ def unpack_lower(t, d: int) -> np.ndarray:
     return L
 
 
-def fit(T, lam_s, r: int, lam_ref: float) -> np.ndarray:
-    """Algorithm 1 steps 3-6: Theta ((r+1) x D) from the g x D targets T."""
+def fit(T, lam_s, r: int, lam_ref: float, basis: int = 0) -> np.ndarray:
+    """Algorithm 1 steps 3-6: Theta ((r+1) x D) from the g x D targets T
+    (basis 0: polynomials in lam/lam_ref; 1: in log(lam/lam_ref))."""
     T = _f64(T)
     lam_s = _f64(lam_s)
     g, D = T.shape
     Theta = np.zeros((r + 1, D))
-    rc = _load().orc_fit(D, g, r, _p(lam_s), float(lam_ref), _p(T), _p(Theta))
+    rc = _load().orc_fit(D, g, r, _p(lam_s), float(lam_ref), _p(T), _p(Theta),
+                         int(basis))
     if rc != 0:
         raise ValueError("oracle fit rejected its arguments (r >= g, "
                          "lam_ref <= 0 or repeated samples)")
     return Theta
 
 
-def evaluate(Theta, lam: float, lam_ref: float) -> np.ndarray:
+def evaluate(Theta, lam: float, lam_ref: float, basis: int = 0) -> np.ndarray:
     """The D fitted polynomials at lam (Sec. 3.3), as a packed vector."""
     Theta = _f64(Theta)
     r = Theta.shape[0] - 1
     D = Theta.shape[1]
     out = np.zeros(D)
-    _load().orc_eval(D, r, _p(Theta), float(lam), float(lam_ref), _p(out))
+    _load().orc_eval(D, r, _p(Theta), float(lam), float(lam_ref), _p(out), int(basis))
     return out
 
 
@@ -252,18 +254,20 @@ def refine(H, lam: float, L, B, W, steps: int):
     return Wr.reshape(np.shape(W)), int(fl)
 
 
-def evaluate_deriv(Theta, lam: float, lam_ref: float) -> np.ndarray:
+def evaluate_deriv(Theta, lam: float, lam_ref: float, basis: int = 0) -> np.ndarray:
     """d Lhat / d lambda of the fitted polynomials (packed vector)."""
     Theta = _f64(Theta)
     r = Theta.shape[0] - 1
     D = Theta.shape[1]
     out = np.zeros(D)
-    _load().orc_eval_deriv(D, r, _p(Theta), float(lam), float(lam_ref), _p(out))
+    _load().orc_eval_deriv(D, r, _p(Theta), float(lam), float(lam_ref), _p(out),
+                           int(basis))
     return out
 
 
 def cv_grad(X, Y, k: int, lam_grid, lam_s=None, r: int = 0,
-            lam_ref: float | None = None, normalize: bool = True) -> dict:
+            lam_ref: float | None = None, normalize: bool = True,
+            basis: int = 0) -> dict:
     """Hold-out error and its derivative with respect to log lambda at every
     grid value and fold: piCholesky when lam_s is given (degree r), the
     exact method otherwise."""
@@ -286,7 +290,7 @@ def cv_grad(X, Y, k: int, lam_grid, lam_s=None, r: int = 0,
     flags = np.zeros((k, q), dtype=np.int32)
     rc = _load().orc_cv_grad(n, d, c, k, g, r, q, int(normalize), int(interp),
                              _p(X), _p(Y), _p(lam_s), _p(lam_grid), float(lam_ref),
-                             _p(mse), _p(dlog), _p(info), _p(flags))
+                             _p(mse), _p(dlog), _p(info), _p(flags), int(basis))
     if rc != 0:
         raise ValueError("oracle cv_grad rejected its arguments")
     return {"mse": mse, "dlog": dlog, "info": info, "flags": flags}
@@ -319,7 +323,7 @@ def cv_exact(X, Y, k: int, lam_grid, normalize: bool = True,
 
 def cv_interp(X, Y, k: int, lam_s, lam_grid, r: int, lam_ref: float | None = None,
               normalize: bool = True, want_W: bool = False,
-              want_theta: bool = False, refine: int = 0) -> dict:
+              want_theta: bool = False, refine: int = 0, basis: int = 0) -> dict:
     """k-fold CV with piCholesky: Algorithm 1 on each fold, evaluation at
     every grid value, then the same solves and hold-out errors.  With
     refine > 0, that many steps of iterative refinement against
@@ -347,7 +351,7 @@ def cv_interp(X, Y, k: int, lam_s, lam_grid, r: int, lam_ref: float | None = Non
     rc = _load().orc_cv_interp(n, d, c, k, g, r, q, int(normalize), _p(X),
                                _p(Y), _p(lam_s), _p(lam_grid), float(lam_ref),
                                _p(mse), _p(sse), _p(W), _p(Theta), _p(info),
-                               _p(flags), int(refine))
+                               _p(flags), int(refine), int(basis))
     if rc != 0:
         raise ValueError("oracle cv_interp rejected its arguments")
     return {"mse": mse, "sse": sse, "W": W, "theta": Theta, "info": info,
@@ -356,7 +360,7 @@ def cv_interp(X, Y, k: int, lam_s, lam_grid, r: int, lam_ref: float | None = Non
 
 def fold_interp(H, B, Xv, Yv, lam_s, lam_grid, r: int,
                 lam_ref: float | None = None, want_W: bool = False,
-                refine: int = 0) -> dict:
+                refine: int = 0, basis: int = 0) -> dict:
     """The per-fold piCholesky path starting from that fold's H_f (both
     triangles) and B_f."""
     H = _f64(H)
@@ -383,7 +387,7 @@ def fold_interp(H, B, Xv, Yv, lam_s, lam_grid, r: int,
     rc = _load().orc_fold_interp(d, c, g, r, q, _p(H), _p(B), nv, _p(Xv), d,
                                  _p(Yv), c, _p(lam_s), _p(lam_grid),
                                  float(lam_ref), _p(mse), _p(W), _p(info),
-                                 _p(flags), int(refine))
+                                 _p(flags), int(refine), int(basis))
     if rc != 0:
         raise ValueError("oracle fold_interp rejected its arguments")
     return {"mse": mse, "W": W, "info": info, "flags": flags}

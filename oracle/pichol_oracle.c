@@ -112,8 +112,16 @@ void orc_unpack_lower(int64_t d, const double *t, double *L) {
  * by the diagonal change of basis diag(lam_ref^-j) (Sec. 4, proof of the
  * stability theorem), chosen so that V stays well conditioned when the
  * sample values are small. */
+/* The variable of the fitted polynomials: tau = lam / lam_ref (basis 0, the
+ * paper's polynomials in lambda) or u = log(lam / lam_ref) (basis 1,
+ * polynomials in log lambda). */
+static double basis_var(double lam, double lam_ref, int32_t basis) {
+  return basis ? log(lam / lam_ref) : lam / lam_ref;
+}
+
 int32_t orc_fit(int64_t D, int32_t g, int32_t r, const double *lam_s,
-                double lam_ref, const double *T, double *Theta) {
+                double lam_ref, const double *T, double *Theta,
+                int32_t basis) {
   if (r < 0 || r > 63 || g <= r || !(lam_ref > 0.0)) return -1;
   int32_t m = r + 1;
   double *V = (double *)malloc(sizeof(double) * (size_t)(g * m));
@@ -121,7 +129,7 @@ int32_t orc_fit(int64_t D, int32_t g, int32_t r, const double *lam_s,
   double *Rl = (double *)malloc(sizeof(double) * (size_t)(m * m));
   /* step 3-4: leftmost r+1 columns of the g x g Vandermonde matrix */
   for (int32_t s = 0; s < g; ++s) {
-    double tau = lam_s[s] / lam_ref, p = 1.0;
+    double tau = basis_var(lam_s[s], lam_ref, basis), p = 1.0;
     for (int32_t j = 0; j < m; ++j) {
       V[s * m + j] = p;
       p *= tau;
@@ -172,8 +180,8 @@ int32_t orc_fit(int64_t D, int32_t g, int32_t r, const double *lam_s,
 /* Sec. 3.3: the interpolated factor at a new lambda is every fitted
  * polynomial evaluated there. */
 void orc_eval(int64_t D, int32_t r, const double *Theta, double lam,
-              double lam_ref, double *out) {
-  double tau = lam / lam_ref;
+              double lam_ref, double *out, int32_t basis) {
+  double tau = basis_var(lam, lam_ref, basis);
   for (int64_t e = 0; e < D; ++e) {
     double acc = 0.0, p = 1.0;
     for (int32_t j = 0; j <= r; ++j) {
@@ -185,15 +193,17 @@ void orc_eval(int64_t D, int32_t r, const double *Theta, double lam,
 }
 
 void orc_eval_deriv(int64_t D, int32_t r, const double *Theta, double lam,
-                    double lam_ref, double *out) {
-  double tau = lam / lam_ref;
+                    double lam_ref, double *out, int32_t basis) {
+  double tau = basis_var(lam, lam_ref, basis);
+  /* d(var)/d(lam): 1/lam_ref for tau, 1/lam for log(lam/lam_ref) */
+  double dvar = basis ? 1.0 / lam : 1.0 / lam_ref;
   for (int64_t e = 0; e < D; ++e) {
     double acc = 0.0, p = 1.0; /* p = tau^(j-1) */
     for (int32_t j = 1; j <= r; ++j) {
       acc += (double)j * p * Theta[(int64_t)j * D + e];
       p *= tau;
     }
-    out[e] = acc / lam_ref;
+    out[e] = acc * dvar;
   }
 }
 
@@ -344,7 +354,7 @@ int32_t orc_fold_interp(int64_t d, int64_t c, int32_t g, int32_t r, int32_t q,
                         int64_t ldy, const double *lam_s,
                         const double *lam_grid, double lam_ref, double *mse,
                         double *W, int32_t *info, int32_t *flags,
-                        int32_t refine) {
+                        int32_t refine, int32_t basis) {
   if (refine < 0) return -1;
   int64_t D = d * (d + 1) / 2;
   double *T = (double *)malloc(sizeof(double) * (size_t)(g * D));
@@ -360,7 +370,7 @@ int32_t orc_fold_interp(int64_t d, int64_t c, int32_t g, int32_t r, int32_t q,
     orc_pack_lower(d, L, T + (int64_t)s * D);
     free(L);
   }
-  int32_t rc = orc_fit(D, g, r, lam_s, lam_ref, T, Theta);
+  int32_t rc = orc_fit(D, g, r, lam_s, lam_ref, T, Theta, basis);
   free(T);
   if (rc != 0) {
     free(Theta);
@@ -370,7 +380,7 @@ int32_t orc_fold_interp(int64_t d, int64_t c, int32_t g, int32_t r, int32_t q,
   for (int32_t t = 0; t < q; ++t) {
     double *lt = (double *)malloc(sizeof(double) * (size_t)D);
     double *L = (double *)malloc(sizeof(double) * (size_t)(d * d));
-    orc_eval(D, r, Theta, lam_grid[t], lam_ref, lt);
+    orc_eval(D, r, Theta, lam_grid[t], lam_ref, lt, basis);
     orc_unpack_lower(d, lt, L);
     unit_solve_holdout(d, c, L, B, H, lam_grid[t], refine, nv, Xv, ldx, Yv,
                        ldy, W ? W + (int64_t)t * d * c : NULL, &mse[t], NULL,
@@ -387,7 +397,7 @@ int32_t orc_cv_interp(int64_t n, int64_t d, int64_t c, int32_t k, int32_t g,
                       const double *Y, const double *lam_s,
                       const double *lam_grid, double lam_ref, double *mse,
                       double *sse, double *W, double *Theta_out, int32_t *info,
-                      int32_t *flags, int32_t refine) {
+                      int32_t *flags, int32_t refine, int32_t basis) {
   if (n < k || k < 2 || d < 1 || c < 1 || q < 1 || r < 0 || g <= r ||
       !(lam_ref > 0.0) || refine < 0)
     return -1;
@@ -414,7 +424,7 @@ int32_t orc_cv_interp(int64_t n, int64_t d, int64_t c, int32_t k, int32_t g,
       free(L);
     }
     /* Algorithm 1 step 3-6 */
-    rc = orc_fit(D, g, r, lam_s, lam_ref, T, Theta);
+    rc = orc_fit(D, g, r, lam_s, lam_ref, T, Theta, basis);
     if (rc != 0) break;
     if (Theta_out)
       memcpy(Theta_out + (int64_t)f * (r + 1) * D, Theta,
@@ -425,7 +435,7 @@ int32_t orc_cv_interp(int64_t n, int64_t d, int64_t c, int32_t k, int32_t g,
       int64_t u = (int64_t)f * q + t;
       double *lt = (double *)malloc(sizeof(double) * (size_t)D);
       double *L = (double *)malloc(sizeof(double) * (size_t)(d * d));
-      orc_eval(D, r, Theta, lam_grid[t], lam_ref, lt);
+      orc_eval(D, r, Theta, lam_grid[t], lam_ref, lt, basis);
       orc_unpack_lower(d, lt, L);
       unit_solve_holdout(d, c, L, B, H, lam_grid[t], refine, nv, Xv, d, Yv,
                          c, W ? W + u * d * c : NULL, &mse[u],
@@ -510,7 +520,8 @@ int32_t orc_cv_grad(int64_t n, int64_t d, int64_t c, int32_t k, int32_t g,
                     int32_t r, int32_t q, int normalize, int interp,
                     const double *X, const double *Y, const double *lam_s,
                     const double *lam_grid, double lam_ref, double *mse,
-                    double *dlog, int32_t *info, int32_t *flags) {
+                    double *dlog, int32_t *info, int32_t *flags,
+                    int32_t basis) {
   if (n < k || k < 2 || d < 1 || c < 1 || q < 1) return -1;
   if (interp && (r < 0 || g <= r || !(lam_ref > 0.0))) return -1;
   int64_t D = d * (d + 1) / 2;
@@ -536,7 +547,7 @@ int32_t orc_cv_grad(int64_t n, int64_t d, int64_t c, int32_t k, int32_t g,
         orc_pack_lower(d, L, T + (int64_t)s * D);
         free(L);
       }
-      rc = orc_fit(D, g, r, lam_s, lam_ref, T, Theta);
+      rc = orc_fit(D, g, r, lam_s, lam_ref, T, Theta, basis);
       if (rc != 0) break;
     }
 #pragma omp parallel for schedule(dynamic, 1)
@@ -547,9 +558,9 @@ int32_t orc_cv_grad(int64_t n, int64_t d, int64_t c, int32_t k, int32_t g,
       if (interp) {
         double *lt = (double *)malloc(sizeof(double) * (size_t)D);
         dL = (double *)malloc(sizeof(double) * (size_t)(d * d));
-        orc_eval(D, r, Theta, lam_grid[t], lam_ref, lt);
+        orc_eval(D, r, Theta, lam_grid[t], lam_ref, lt, basis);
         orc_unpack_lower(d, lt, L);
-        orc_eval_deriv(D, r, Theta, lam_grid[t], lam_ref, lt);
+        orc_eval_deriv(D, r, Theta, lam_grid[t], lam_ref, lt, basis);
         orc_unpack_lower(d, lt, dL);
         free(lt);
       } else {

@@ -63,17 +63,25 @@ void orc_unpack_lower(int64_t d, const double *t, double *L);
  * Returns 0, or -1 when the arguments are invalid (r >= g, lam_ref <= 0) or
  * H_l is singular (repeated sample values). */
 int32_t orc_fit(int64_t D, int32_t g, int32_t r, const double *lam_s,
-                double lam_ref, const double *T, double *Theta);
+                double lam_ref, const double *T, double *Theta,
+                int32_t basis);
 
 /* Evaluate the D fitted polynomials at lam (Sec. 3.3): out[e] =
  * sum_j (lam/lam_ref)^j Theta[j][e]. */
 void orc_eval(int64_t D, int32_t r, const double *Theta, double lam,
-              double lam_ref, double *out);
+              double lam_ref, double *out,
+              int32_t basis);
+
+/* Basis of the fitted polynomials (the last argument of the fit, evaluation
+ * and interpolated-CV functions): 0 = monomials in tau = lam / lam_ref, the
+ * polynomial space of Algorithm 1 (polynomials in lambda); 1 = monomials in
+ * u = log(lam / lam_ref), polynomials in log lambda (all lambdas > 0). */
 
 /* Derivative of the interpolated factor with respect to lambda:
  * sum_j j tau^(j-1) / lam_ref Theta_j, tau = lam / lam_ref. */
 void orc_eval_deriv(int64_t D, int32_t r, const double *Theta, double lam,
-                    double lam_ref, double *out);
+                    double lam_ref, double *out,
+                    int32_t basis);
 
 /* Forward substitution L U = B, then back substitution L^T W = U
  * (Sec. 3.2).  L is d x d lower (only the lower triangle is read), B and W are
@@ -134,7 +142,8 @@ int32_t orc_cv_interp(int64_t n, int64_t d, int64_t c, int32_t k, int32_t g,
                       const double *Y, const double *lam_s,
                       const double *lam_grid, double lam_ref, double *mse,
                       double *sse, double *W, double *Theta, int32_t *info,
-                      int32_t *flags, int32_t refine);
+                      int32_t *flags, int32_t refine,
+                      int32_t basis);
 
 /* The per-fold part of orc_cv_interp starting from that fold's H_f, B_f and
  * validation rows (used to time one fold without the Gram step).
@@ -145,7 +154,8 @@ int32_t orc_fold_interp(int64_t d, int64_t c, int32_t g, int32_t r, int32_t q,
                         int64_t ldy, const double *lam_s,
                         const double *lam_grid, double lam_ref, double *mse,
                         double *W, int32_t *info, int32_t *flags,
-                        int32_t refine);
+                        int32_t refine,
+                      int32_t basis);
 
 /* Derivative of the hold-out error with respect to log lambda, for every
  * fold and grid value (the differentiation form).  With A the matrix whose
@@ -163,7 +173,8 @@ int32_t orc_cv_grad(int64_t n, int64_t d, int64_t c, int32_t k, int32_t g,
                     int32_t r, int32_t q, int normalize, int interp,
                     const double *X, const double *Y, const double *lam_s,
                     const double *lam_grid, double lam_ref, double *mse,
-                    double *dlog, int32_t *info, int32_t *flags);
+                    double *dlog, int32_t *info, int32_t *flags,
+                      int32_t basis);
 
 /* Number of OpenMP threads the oracle runs with. */
 int32_t orc_num_threads(void);

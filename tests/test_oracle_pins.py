@@ -607,3 +607,50 @@ def test_recursive_order_is_a_bijection_on_the_triangle(h, h0):
     assert set(order) == {(i, j) for i in range(h) for j in range(i + 1)}
     if h <= h0:  # no split: the row-wise order of pack_lower
         assert order == [(i, j) for i in range(h) for j in range(i + 1)]
+
+
+# ------------------------------------------------------------------ log-lambda basis (optional variant)
+
+def test_log_basis_fit_matches_polyfit_and_reproduces_polynomials():
+    from numpy.polynomial import polynomial as P
+    rng = np.random.default_rng(11)
+    g, r, D = 6, 2, 9
+    lam_s = np.logspace(-6, 0, g) * 3e-4
+    lam_ref = lam_s.max()
+    u = np.log(lam_s / lam_ref)
+    T = rng.standard_normal((g, D))
+    th = oracle.fit(T, lam_s, r, lam_ref, basis=1)
+    for e in range(D):
+        np.testing.assert_allclose(th[:, e], P.polyfit(u, T[:, e], r), rtol=1e-9, atol=1e-12)
+    # targets that are quadratics in log(lambda) are reproduced anywhere
+    coef = rng.standard_normal((3, D))
+    Tq = np.stack([coef[0] + coef[1] * x + coef[2] * x * x for x in u])
+    thq = oracle.fit(Tq, lam_s, r, lam_ref, basis=1)
+    lam = 7.3e-7
+    x = np.log(lam / lam_ref)
+    np.testing.assert_allclose(oracle.evaluate(thq, lam, lam_ref, basis=1),
+                               coef[0] + coef[1] * x + coef[2] * x * x, rtol=1e-9)
+
+
+def test_log_basis_derivative_matches_central_differences():
+    rng = np.random.default_rng(12)
+    Theta = rng.standard_normal((3, 7))
+    lam_ref, lam, h = 2.0, 0.03, 1e-7
+    num = (oracle.evaluate(Theta, lam + h, lam_ref, basis=1)
+           - oracle.evaluate(Theta, lam - h, lam_ref, basis=1)) / (2 * h)
+    np.testing.assert_allclose(oracle.evaluate_deriv(Theta, lam, lam_ref, basis=1), num,
+                               rtol=1e-6)
+
+
+def test_log_basis_cv_interpolates_samples_and_gradient_matches_differences():
+    p = workloads.gaussian_problem(400, 30, 2, seed=9, g=4, q=10, lam_range=(1e-3, 1.0))
+    lam_s = p.lam_grid[[0, 3, 6, 9]]
+    pi = oracle.cv_interp(p.X, p.Y, p.k, lam_s, p.lam_grid, 3, basis=1)
+    ex = oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid)
+    np.testing.assert_allclose(pi["mse"][:, [0, 3, 6, 9]], ex["mse"][:, [0, 3, 6, 9]],
+                               rtol=1e-8)
+    q = workloads.gaussian_problem(300, 24, 3, seed=6, g=4, q=9)
+    got = oracle.cv_grad(q.X, q.Y, q.k, q.lam_grid, q.lam_s, q.r, basis=1)
+    fd = _fd_dlog(lambda lg: oracle.cv_interp(q.X, q.Y, q.k, q.lam_s, lg, q.r,
+                                              lam_ref=q.lam_ref, basis=1)["mse"], q.lam_grid)
+    assert np.abs(fd - got["dlog"]).max() <= 1e-6 * np.abs(got["dlog"]).max()
