@@ -104,6 +104,14 @@ typedef enum {
  *   normalize 1: H_f = X_tr^T X_tr / n_tr and B_f = X_tr^T Y_tr / n_tr;
  *             0: no division (the paper's X^T X, X^T y)
  *   precision a pichol_precision value for the factorizations
+ *   basis     variable of the fitted polynomials in the pipeline calls:
+ *             0 = tau = lambda / lam_ref (the polynomial space of Algorithm
+ *             1: polynomials in lambda); 1 = log(lambda / lam_ref)
+ *             (polynomials in log lambda, an alternative to the paper's
+ *             basis for grids spanning many decades; every lambda must be
+ *             positive).  The step calls pichol_fit, pichol_eval,
+ *             pichol_solve_interp, pichol_fit_vec and pichol_eval_vec use
+ *             basis 0.
  *   refine    0 .. PICHOL_MAX_REFINE steps of iterative refinement after
  *             the solves of the pipeline calls (pichol_cv_interp,
  *             pichol_cv_exact): R_t = B_f - (H_f + lambda_t I) W_t in FP64
@@ -126,6 +134,7 @@ typedef struct {
   int32_t normalize;
   int32_t precision;
   int32_t refine;
+  int32_t basis;
   int64_t ldx, ldy;
 } pichol_problem;
 

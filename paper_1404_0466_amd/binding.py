@@ -56,6 +56,7 @@ class Problem(ctypes.Structure):
                 ("g", ctypes.c_int32), ("r", ctypes.c_int32),
                 ("q", ctypes.c_int32), ("normalize", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("basis", ctypes.c_int32),
                 ("ldx", ctypes.c_int64), ("ldy", ctypes.c_int64)]
 
 
@@ -246,9 +247,10 @@ def pichol_unpack(d, nmat, P, A, lda, stream=None):
 # ------------------------------------------------------------------ steps
 
 def make_problem(n, d, c, k, g=1, r=0, q=1, normalize=True, ldx=None,
-                 ldy=None, precision=PICHOL_PREC_FP64, refine=0) -> Problem:
+                 ldy=None, precision=PICHOL_PREC_FP64, refine=0,
+                 basis=0) -> Problem:
     return Problem(n, d, c, k, g, r, q, int(bool(normalize)), int(precision),
-                   int(refine), d if ldx is None else ldx,
+                   int(refine), int(basis), d if ldx is None else ldx,
                    c if ldy is None else ldy)
 
 

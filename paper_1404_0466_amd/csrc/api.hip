@@ -140,7 +140,7 @@ bool problem_ok(const pichol_problem* p) {
          p->n >= p->k && p->ldx >= p->d && p->ldy >= p->c && p->q >= 1 &&
          p->g >= 1 && p->g <= 32 && p->r >= 0 && p->r <= 7 && p->r < p->g &&
          precision_ok(p->precision) && p->refine >= 0 &&
-         p->refine <= PICHOL_MAX_REFINE;
+         p->refine <= PICHOL_MAX_REFINE && (p->basis == 0 || p->basis == 1);
 }
 
 bool samples_ok(const double* lam, int g) {
@@ -152,15 +152,30 @@ bool samples_ok(const double* lam, int g) {
   return true;
 }
 
-bool fit_coef(int g, int r, const double* lam_s, double lam_ref,
-                     FitCoef* fc) {
+// The variable of the fitted polynomials: lambda / lam_ref (basis 0) or
+// log(lambda / lam_ref) (basis 1).
+double basis_var(double lam, double lam_ref, int basis) {
+  return basis ? log(lam / lam_ref) : lam / lam_ref;
+}
+
+bool basis_ok(int basis, const double* lam, int n) {
+  if (basis == 0) return true;
+  if (basis != 1) return false;
+  for (int i = 0; i < n; ++i)
+    if (!(lam[i] > 0.0)) return false;
+  return true;
+}
+
+bool fit_coef(int g, int r, const double* lam_s, double lam_ref, int basis,
+              FitCoef* fc) {
   const int m = r + 1;
   memset(fc, 0, sizeof(*fc));
   fc->g = g;
   fc->m = m;
   std::vector<double> V((size_t)g * m), P((size_t)m * g);
   for (int s = 0; s < g; ++s) {
-    const double tau = lam_s[s] / lam_ref;
+    const double tau = basis_var(lam_s[s], lam_ref, basis);
+    if (!isfinite(tau)) return false;
     double pw = 1.0;
     for (int j = 0; j < m; ++j) {
       V[(size_t)s * m + j] = pw;
@@ -265,10 +280,10 @@ void holdout_norm(const pichol_problem* p, HoldoutNorm* hn) {
     hn->count[f] = (double)(fs.start[f + 1] - fs.start[f]) * (double)p->c;
 }
 
-hipError_t upload_tau(const double* lam, int nlam, double lam_ref,
-                             double* dst, hipStream_t stream) {
+hipError_t upload_tau(const double* lam, int nlam, double lam_ref, int basis,
+                      double* dst, hipStream_t stream) {
   std::vector<double> tau(nlam);
-  for (int t = 0; t < nlam; ++t) tau[t] = lam[t] / lam_ref;
+  for (int t = 0; t < nlam; ++t) tau[t] = basis_var(lam[t], lam_ref, basis);
   return launch_store_doubles(tau.data(), nlam, dst, stream);
 }
 
@@ -444,7 +459,7 @@ pichol_status pichol_fit(int64_t d, int32_t nmat, int32_t g, int32_t r,
     return PICHOL_ERR_ARG;
   if (!samples_ok(lam_s, g)) return PICHOL_ERR_ARG;
   FitCoef fc;
-  if (!fit_coef(g, r, lam_s, lam_ref, &fc)) return PICHOL_ERR_ARG;
+  if (!fit_coef(g, r, lam_s, lam_ref, 0, &fc)) return PICHOL_ERR_ARG;
   return hip_status(launch_fit(d, nmat, fc, L, theta, theta_t, stream));
 }
 
@@ -468,7 +483,7 @@ pichol_status pichol_eval(int64_t d, int32_t nmat, int32_t r,
     return PICHOL_ERR_ARG;
   if (!ws || ws_bytes < pichol_lambda_workspace(nlam)) return PICHOL_ERR_WORKSPACE;
   double* tau = at<double>(ws, 0);
-  hipError_t e = upload_tau(lam, nlam, lam_ref, tau, stream);
+  hipError_t e = upload_tau(lam, nlam, lam_ref, 0, tau, stream);
   if (e != hipSuccess) return hip_status(e);
   return hip_status(launch_eval(d, nmat, r + 1, theta, nlam, tau, Lhat, stream));
 }
@@ -490,7 +505,7 @@ pichol_status pichol_solve_interp(int64_t d, int32_t nmat, int32_t c, int32_t r,
   double* dinv = at<double>(ws, pichol_lambda_workspace(q));
   double* dinv_r = dinv + (pichol_solve_interp_workspace(d, nmat, q) -
                            pichol_lambda_workspace(q)) / 2 / sizeof(double);
-  hipError_t e = upload_tau(lam, q, lam_ref, tau, stream);
+  hipError_t e = upload_tau(lam, q, lam_ref, 0, tau, stream);
   if (e == hipSuccess) e = launch_slab_init(d, nmat, q, c, ldz, B, Z, flags, stream);
   if (e == hipSuccess)
     e = launch_solve_interp(d, nmat, c, r + 1, theta, theta_t, q, tau, ldz, Z,
@@ -618,7 +633,9 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
   const Layout L = layout_of(p);
   if (!ws || ws_bytes < L.i_end) return PICHOL_ERR_WORKSPACE;
   FitCoef fc;
-  if (!fit_coef(p->g, p->r, lam_s, lam_ref, &fc)) return PICHOL_ERR_ARG;
+  if (!basis_ok(p->basis, lam_s, p->g) || !basis_ok(p->basis, lam_grid, p->q))
+    return PICHOL_ERR_ARG;
+  if (!fit_coef(p->g, p->r, lam_s, lam_ref, p->basis, &fc)) return PICHOL_ERR_ARG;
   HoldoutNorm hn;
   holdout_norm(p, &hn);
   const int k = p->k, g = p->g, q = p->q, c = (int)p->c, M = p->r + 1;
@@ -629,7 +646,8 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
   double* tht = at<double>(ws, L.i_tht);
   double* Z = at<double>(ws, L.i_Z);
   hipError_t e = launch_store_doubles(lam_s, g, lam_dev, stream);
-  if (e == hipSuccess) e = upload_tau(lam_grid, q, lam_ref, tau, stream);
+  if (e == hipSuccess)
+    e = upload_tau(lam_grid, q, lam_ref, p->basis, tau, stream);
   if (e == hipSuccess)
     e = launch_shift_copy(p->d, k, at<double>(ws, L.H), g, lam_dev, k, Lf,
                           info, stream);
@@ -747,11 +765,13 @@ pichol_status pichol_cv_interp_grad(const pichol_problem* p,
   // plane weights per lambda: tau^p (value) and p tau^(p-1) / lam_ref
   std::vector<double> w(2 * 8 * (size_t)q, 0.0), zero(q, 0.0);
   for (int t = 0; t < q; ++t) {
-    const double tau = lam_grid[t] / lam_ref;
+    const double tau = basis_var(lam_grid[t], lam_ref, p->basis);
+    // d(variable)/d(lambda)
+    const double dvar = p->basis ? 1.0 / lam_grid[t] : 1.0 / lam_ref;
     double pw = 1.0, pwm1 = 0.0;  // tau^p, tau^(p-1)
     for (int pp = 0; pp < M; ++pp) {
       w[(size_t)pp * q + t] = pw;
-      w[(size_t)(8 + pp) * q + t] = pp == 0 ? 0.0 : (double)pp * pwm1 / lam_ref;
+      w[(size_t)(8 + pp) * q + t] = pp == 0 ? 0.0 : (double)pp * pwm1 * dvar;
       pwm1 = pw;
       pw *= tau;
     }
@@ -842,7 +862,9 @@ pichol_status pichol_cv_pinrmse(const pichol_problem* p, const double* lam_s,
     if (!isfinite(lam_grid[t])) return PICHOL_ERR_ARG;
   if (!ws || ws_bytes < pinrmse_end(p)) return PICHOL_ERR_WORKSPACE;
   FitCoef fc;
-  if (!fit_coef(p->g, p->r, lam_s, lam_ref, &fc)) return PICHOL_ERR_ARG;
+  if (!basis_ok(p->basis, lam_s, p->g) || !basis_ok(p->basis, lam_grid, p->q))
+    return PICHOL_ERR_ARG;
+  if (!fit_coef(p->g, p->r, lam_s, lam_ref, p->basis, &fc)) return PICHOL_ERR_ARG;
   // exact hold-out errors at the g samples (the Gram blocks are shared)
   pichol_problem ps = *p;
   ps.q = p->g;
@@ -851,7 +873,7 @@ pichol_status pichol_cv_pinrmse(const pichol_problem* p, const double* lam_s,
                                      info, flags, stream);
   if (st != PICHOL_OK) return st;
   double* tau = at<double>(ws, pinrmse_tau(p));
-  hipError_t e = upload_tau(lam_grid, p->q, lam_ref, tau, stream);
+  hipError_t e = upload_tau(lam_grid, p->q, lam_ref, p->basis, tau, stream);
   if (e == hipSuccess) e = launch_pinrmse(p->k, fc, p->q, tau, es, err, stream);
   return hip_status(e);
 }
@@ -895,7 +917,7 @@ pichol_status pichol_fit_vec(int64_t N, int32_t nmat, int32_t g, int32_t r,
     return PICHOL_ERR_ARG;
   if (!samples_ok(lam_s, g)) return PICHOL_ERR_ARG;
   FitCoef fc;
-  if (!fit_coef(g, r, lam_s, lam_ref, &fc)) return PICHOL_ERR_ARG;
+  if (!fit_coef(g, r, lam_s, lam_ref, 0, &fc)) return PICHOL_ERR_ARG;
   return hip_status(launch_fit_flat(N, nmat, fc, T, theta, stream));
 }
 
@@ -908,7 +930,7 @@ pichol_status pichol_eval_vec(int64_t N, int32_t nmat, int32_t r,
     return PICHOL_ERR_ARG;
   if (!ws || ws_bytes < pichol_lambda_workspace(nlam)) return PICHOL_ERR_WORKSPACE;
   double* tau = static_cast<double*>(ws);
-  hipError_t e = upload_tau(lam, nlam, lam_ref, tau, stream);
+  hipError_t e = upload_tau(lam, nlam, lam_ref, 0, tau, stream);
   if (e == hipSuccess)
     e = launch_eval_flat(N, nmat, r + 1, theta, nlam, tau, out, stream);
   return hip_status(e);

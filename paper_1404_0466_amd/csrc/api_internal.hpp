@@ -17,9 +17,12 @@ bool fold_split(int64_t n, int k, int normalize, FoldSplit* fs);
 bool precision_ok(int32_t precision);
 bool problem_ok(const pichol_problem* p);
 bool samples_ok(const double* lam, int g);
-bool fit_coef(int g, int r, const double* lam_s, double lam_ref, FitCoef* fc);
+double basis_var(double lam, double lam_ref, int basis);
+bool basis_ok(int basis, const double* lam, int n);
+bool fit_coef(int g, int r, const double* lam_s, double lam_ref, int basis,
+              FitCoef* fc);
 void holdout_norm(const pichol_problem* p, HoldoutNorm* hn);
-hipError_t upload_tau(const double* lam, int nlam, double lam_ref, double* dst,
-                      hipStream_t stream);
+hipError_t upload_tau(const double* lam, int nlam, double lam_ref, int basis,
+                      double* dst, hipStream_t stream);
 
 }  // namespace pichol

@@ -55,7 +55,7 @@ bool same_bucket(const pichol_batch_item& a, const pichol_batch_item& b,
                  int method) {
   const pichol_problem &p = a.p, &o = b.p;
   if (p.d != o.d || p.c != o.c || p.k != o.k || p.q != o.q ||
-      p.precision != o.precision)
+      p.precision != o.precision || p.basis != o.basis)
     return false;
   if (method != PICHOL_METHOD_INTERP) return true;
   if (p.g != o.g || p.r != o.r) return false;
@@ -78,8 +78,10 @@ bool item_ok(const pichol_batch_item& it, int method) {
   if (method == PICHOL_METHOD_INTERP) {
     if (!it.lam_s || !(it.lam_ref > 0.0) || !isfinite(it.lam_ref)) return false;
     if (!samples_ok(it.lam_s, p.g)) return false;
+    if (!basis_ok(p.basis, it.lam_s, p.g) || !basis_ok(p.basis, it.lam_grid, p.q))
+      return false;
     FitCoef fc;
-    if (!fit_coef(p.g, p.r, it.lam_s, it.lam_ref, &fc)) return false;
+    if (!fit_coef(p.g, p.r, it.lam_s, it.lam_ref, p.basis, &fc)) return false;
   }
   return true;
 }
@@ -213,10 +215,11 @@ hipError_t run_bucket(const Bucket& b, const pichol_batch_item* items,
   if (interp) {
     const pichol_batch_item& it0 = items[b.items[0]];
     FitCoef fc;
-    fit_coef(b.g, b.r, it0.lam_s, it0.lam_ref, &fc);
+    fit_coef(b.g, b.r, it0.lam_s, it0.lam_ref, it0.p.basis, &fc);
     double* th = at<double>(base, b.th);
     double* tht = at<double>(base, b.tht);
-    if (e == hipSuccess) e = upload_tau(it0.lam_grid, q, it0.lam_ref, tau, st);
+    if (e == hipSuccess)
+      e = upload_tau(it0.lam_grid, q, it0.lam_ref, it0.p.basis, tau, st);
     if (e == hipSuccess) e = launch_fit(d, nmat, fc, L, th, tht, st);
     if (e == hipSuccess)
       e = launch_solve_interp(d, nmat, c, M, th, tht, q, tau, ldz, Z, flags,

@@ -68,7 +68,7 @@ def gram(X, Y, k, normalize=True):
 
 
 def cv(prob, method, X=None, Y=None, lam_s=None, lam_grid=None, r=None,
-       want_W=True, normalize=True, k=None, precision=0, refine=0):
+       want_W=True, normalize=True, k=None, precision=0, refine=0, basis=0):
     """Run the pipeline (gram + interp or exact) on the GPU."""
     X = prob.X if X is None else X
     Y = prob.Y if Y is None else Y
@@ -80,7 +80,7 @@ def cv(prob, method, X=None, Y=None, lam_s=None, lam_grid=None, r=None,
     c = Y.shape[1]
     g, q = len(lam_s), len(lam_grid)
     p = B.make_problem(n, d, c, k, g, r, q, normalize, precision=precision,
-                       refine=refine)
+                       refine=refine, basis=basis)
     m = B.PICHOL_METHOD_INTERP if method == "interp" else B.PICHOL_METHOD_EXACT
     nbytes = B.pichol_workspace_size(p, m)
     w = ws(nbytes)
@@ -108,7 +108,7 @@ class BatchRun:
     """Device buffers and the ctypes batch for a list of workloads.Problem
     (pichol_cv_batch)."""
 
-    def __init__(self, probs, method, precision=0, want_W=True):
+    def __init__(self, probs, method, precision=0, want_W=True, basis=0):
         self.probs = probs
         self.method = B.PICHOL_METHOD_INTERP if method == "interp" else B.PICHOL_METHOD_EXACT
         self.interp = method == "interp"
@@ -125,7 +125,7 @@ class BatchRun:
             }
             self.bufs.append(b)
             ents.append(dict(p=B.make_problem(p.n, p.d, p.c, k, p.g, p.r, q, True,
-                                              precision=precision),
+                                              precision=precision, basis=basis),
                              lam_s=p.lam_s if self.interp else None,
                              lam_grid=p.lam_grid, lam_ref=p.lam_ref, **b))
         self.batch = B.Batch(ents)

@@ -68,7 +68,7 @@ def test_workspace_size_and_argument_checks(lib):
     assert wi > 5 * 6 * S * 8 and we > 5 * 64 * S * 8
     for bad in [dict(r=6, g=6), dict(k=1), dict(k=65), dict(g=33), dict(r=8, g=9),
                 dict(q=0), dict(precision=2), dict(precision=-1), dict(refine=-1),
-                dict(refine=B.PICHOL_MAX_REFINE + 1)]:
+                dict(refine=B.PICHOL_MAX_REFINE + 1), dict(basis=2), dict(basis=-1)]:
         kw = dict(g=6, r=2, q=64, k=5)
         kw.update(bad)
         k = kw.pop("k")
@@ -82,12 +82,13 @@ def test_workspace_size_and_argument_checks(lib):
 
 
 def test_problem_struct_layout():
-    # int64 n, d, c; int32 k, g, r, q, normalize, precision, refine;
-    # (4 bytes of padding) int64 ldx, ldy
+    # int64 n, d, c; int32 k, g, r, q, normalize, precision, refine, basis;
+    # int64 ldx, ldy
     assert ctypes.sizeof(B.Problem) == 3 * 8 + 8 * 4 + 2 * 8
     assert B.Problem.ldx.offset == 56
-    p = B.make_problem(10, 3, 2, 2, precision=B.PICHOL_PREC_MIXED, refine=3)
-    assert p.precision == 1 and p.refine == 3 and p.ldx == 3 and p.ldy == 2
+    p = B.make_problem(10, 3, 2, 2, precision=B.PICHOL_PREC_MIXED, refine=3, basis=1)
+    assert p.precision == 1 and p.refine == 3 and p.basis == 1
+    assert p.ldx == 3 and p.ldy == 2
     text = open(HEADER).read()
     assert "#define PICHOL_MAX_REFINE %d" % B.PICHOL_MAX_REFINE in text
 

@@ -106,3 +106,39 @@ def test_batch_of_one(gu):
     got = run.run()[0]
     want = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r)
     _check(got, want)
+
+
+@pytest.mark.parametrize("r", [2, 3])
+def test_log_lambda_basis(gu, r):
+    """Polynomials in log(lambda / lam_ref) instead of lambda / lam_ref:
+    the pipeline, the batch call and PINRMSE follow the oracle's log-basis
+    fit."""
+    p = workloads.gaussian_problem(1003, 300, 3, seed=50 + r, g=5, r=r, q=11)
+    got = gu.cv(p, "interp", basis=1)
+    want = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, r, want_W=True, basis=1)
+    u = np.log(p.lam_s / p.lam_ref)
+    cond = np.linalg.cond(np.vander(u, r + 1, increasing=True))
+    tol = max(1e-10, 10 * cond ** 2 * np.finfo(float).eps)
+    _check(got, want, rtol=tol)
+    run = gu.BatchRun([p], "interp", basis=1)
+    np.testing.assert_array_equal(run.run()[0]["mse"], got["mse"])
+    # the two bases differ (the interpolation is not the same function)
+    lin = gu.cv(p, "interp", want_W=False)
+    assert np.max(np.abs(lin["mse"] - got["mse"]) / got["mse"]) > 1e-8
+
+
+def test_log_basis_rejects_nonpositive_lambda(gu):
+    B = gu.B
+    p = workloads.gaussian_problem(300, 100, 2, seed=52, g=4, q=5)
+    prob = B.make_problem(p.n, p.d, p.c, p.k, p.g, p.r, p.q, True, basis=1)
+    nb = B.pichol_workspace_size(prob, B.PICHOL_METHOD_INTERP)
+    w = gu.ws(nb)
+    B.pichol_cv_gram(prob, gu.dev(p.X), gu.dev(p.Y), w, nb)
+    lam_grid = p.lam_grid.copy()
+    lam_grid[0] = 0.0
+    with pytest.raises(B.PicholError) as e:
+        B.pichol_cv_interp(prob, p.lam_s, lam_grid, p.lam_ref, w, nb, gu.empty(p.k * p.q),
+                           None, gu.empty(p.k * p.g, torch.int32),
+                           gu.empty(p.k * p.q, torch.int32))
+    assert e.value.status == B.PICHOL_ERR_ARG
+

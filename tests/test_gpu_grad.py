@@ -25,11 +25,11 @@ def gu(gpu):
     return gpu_util
 
 
-def gpu_grad(gu, prob, method, lam_grid=None):
+def gpu_grad(gu, prob, method, lam_grid=None, basis=0):
     B = gu.B
     lam_grid = prob.lam_grid if lam_grid is None else np.asarray(lam_grid)
     n, d, c, k, g, q = prob.n, prob.d, prob.c, prob.k, prob.g, len(lam_grid)
-    p = B.make_problem(n, d, c, k, g, prob.r, q, True)
+    p = B.make_problem(n, d, c, k, g, prob.r, q, True, basis=basis)
     m = (B.PICHOL_METHOD_INTERP if method == "interp" else B.PICHOL_METHOD_EXACT)
     nb = B.pichol_workspace_size(p, m | B.PICHOL_METHOD_GRAD)
     w = gu.ws(nb)
@@ -102,3 +102,13 @@ def test_autograd_wrapper(gu):
     ok = torch.autograd.gradcheck(lambda x: f(x), (log_lam.detach().requires_grad_(),),
                                   eps=1e-5, atol=1e-7, rtol=1e-4)
     assert ok
+
+
+def test_log_basis_grad_matches_oracle(gu):
+    prob = workloads.gaussian_problem(900, 260, 3, seed=14, g=5, r=2, q=9)
+    got = gpu_grad(gu, prob, "interp", basis=1)
+    want = oracle.cv_grad(prob.X, prob.Y, prob.k, prob.lam_grid, prob.lam_s, prob.r, basis=1)
+    assert np.all(got["info"] == 0) and np.all(got["flags"] == 0)
+    np.testing.assert_allclose(got["mse"], want["mse"], rtol=1e-10, atol=0)
+    assert np.abs(got["dlog"] - want["dlog"]).max() <= 1e-9 * np.abs(want["dlog"]).max()
+
