@@ -119,7 +119,7 @@ def cpu_baseline(prob, gpu_err_fold0):
 
 
 def variant_leg(args, B, p, ws, nbytes, prob, ei64, ee64, stream, precision,
-                refine, W64):
+                refine, W64, basis=0):
     """Time the piCholesky (and exact) stages with another precision and/or
     refinement count on the resident Gram matrices, and compare the hold-out
     errors with the FP64 run of the same step (FP64 interpolated and FP64
@@ -127,7 +127,7 @@ def variant_leg(args, B, p, ws, nbytes, prob, ei64, ee64, stream, precision,
     import torch
     k, q, g = prob.k, prob.q, prob.g
     pm = B.make_problem(p.n, p.d, p.c, k, g, p.r, q, True, precision=precision,
-                        refine=refine)
+                        refine=refine, basis=basis)
     dev = torch.device("cuda:0")
     err_i = torch.empty(k * q, dtype=torch.float64, device=dev)
     err_e = torch.empty(k * q, dtype=torch.float64, device=dev)
@@ -147,7 +147,8 @@ def variant_leg(args, B, p, ws, nbytes, prob, ei64, ee64, stream, precision,
                               flags_e)
         ev[2].record(stream)
 
-    name = ("mixed" if precision else "fp64") + f", refine={refine}"
+    name = (("mixed" if precision else "fp64") + f", refine={refine}"
+            + (", log-lambda basis" if basis else ""))
     log(f"leg {name}")
     for _ in range(args.warmup):
         run([torch.cuda.Event(enable_timing=True) for _ in range(3)])
@@ -176,7 +177,7 @@ def variant_leg(args, B, p, ws, nbytes, prob, ei64, ee64, stream, precision,
     out = {
         "precision": ("FP32-MFMA trailing updates, FP64 elsewhere" if precision
                       else "FP64"),
-        "refine": refine,
+        "refine": refine, "basis": "log(lambda/lam_ref)" if basis else "lambda/lam_ref",
         "interp_ms": t_int, "value": k * q / (t_int * 1e-3),
         "interp_ok": bool((info_i.cpu().numpy() == 0).all()
                           and (flags_i.cpu().numpy() == 0).all()),
@@ -291,6 +292,18 @@ def batching_leg(args, B, stream):
                for b in keep)
     gap = [float(np.max(np.abs(a.mean(0) - b.mean(0)) / b.mean(0))) for a, b in zip(ei, ee)]
     same_sel = sum(int(np.argmin(a.mean(0)) == np.argmin(b.mean(0))) for a, b in zip(ei, ee))
+    # the same batch with polynomials in log(lambda) (one untimed call)
+    ents_l = []
+    for e in ents_i:
+        pl = B.make_problem(e["p"].n, e["p"].d, e["p"].c, e["p"].k, e["p"].g, e["p"].r,
+                            e["p"].q, True, basis=1)
+        ents_l.append(dict(e, p=pl))
+    bat_l = B.Batch(ents_l)
+    B.pichol_cv_batch(bat_l, B.PICHOL_METHOD_INTERP, tune_i, ws, nbytes)
+    torch.cuda.synchronize()
+    el = [b[2]["err"].cpu().numpy().reshape(pb.k, pb.q) for b, pb in zip(keep, probs)]
+    gap_l = [float(np.max(np.abs(a.mean(0) - b.mean(0)) / b.mean(0))) for a, b in zip(el, ee)]
+    same_l = sum(int(np.argmin(a.mean(0)) == np.argmin(b.mean(0))) for a, b in zip(el, ee))
     out = {
         "workload": "48 power-law Gaussian problems, d in {256..2048}, n=8d, c in {1,10}, "
                     "k=5, g=5, r=2, q=32, lambda in [1e-4,1e1]*s",
@@ -304,6 +317,9 @@ def batching_leg(args, B, stream):
         "interp_ok": ok_i, "exact_ok": ok_e,
         "curve_gap_max_rel": max(gap), "curve_gap_median_rel": float(np.median(gap)),
         "same_selection": f"{same_sel}/{len(probs)}",
+        "log_basis_curve_gap_max_rel": max(gap_l),
+        "log_basis_curve_gap_median_rel": float(np.median(gap_l)),
+        "log_basis_same_selection": f"{same_l}/{len(probs)}",
         "note": "times include the Gram step of every problem",
     }
     log(f"many problems: graph {t_graph:.2f} ms ({out['value']:.0f} lambda-solves/s), "
@@ -614,6 +630,9 @@ def main():
             f"fp64_refine{args.refine}": variant_leg(
                 args, B, p, ws, nbytes, prob, ei, ee64, stream,
                 B.PICHOL_PREC_FP64, args.refine, W64),
+            "fp64_log_basis": variant_leg(
+                args, B, p, ws, nbytes, prob, ei, ee64, stream,
+                B.PICHOL_PREC_FP64, 0, W64, basis=1),
         }
         if not args.no_exact:
             for v in variants.values():
