@@ -229,10 +229,13 @@ pichol_status pichol_eval(int64_t d, int32_t nmat, int32_t r,
                           const double *lam, double lam_ref, double *Lhat,
                           void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* Scratch bytes for pichol_solve_interp: the q scaled lambdas and the
- * inverses of every diagonal 128 x 128 block of every interpolated factor,
- * in two layouts (2 * nmat * q * ceil(d/128) * 131072 bytes). */
-size_t pichol_solve_interp_workspace(int64_t d, int32_t nmat, int32_t q);
+/* Scratch bytes for pichol_solve_interp: the q scaled lambdas, the inverses
+ * of every diagonal 128 x 128 block of every interpolated factor in two
+ * layouts (2 * nmat * q * ceil(d/128) * 131072 bytes), and a second slab of
+ * the same shape as Z (the forward solves leave their blocks there).
+ * Returns 0 when an argument is below 1. */
+size_t pichol_solve_interp_workspace(int64_t d, int32_t nmat, int32_t q,
+                                     int32_t c);
 
 /* Interpolated solves for all q grid values of nmat folds (Sec. 3.2 applied
  * to the evaluated factor of Sec. 3.3), without materialising the factors:
@@ -245,7 +248,7 @@ size_t pichol_solve_interp_workspace(int64_t d, int32_t nmat, int32_t q);
  *      (device, padding rows 0); lam q values (host).
  * Out: Z nmat slabs of dp x pichol_slab_cols(q,c) (device): W for every
  *      (fold, lambda); flags nmat*q (device, int32), zeroed then set.
- * ws: pichol_solve_interp_workspace(d, nmat, q) bytes. */
+ * ws: pichol_solve_interp_workspace(d, nmat, q, c) bytes. */
 pichol_status pichol_solve_interp(int64_t d, int32_t nmat, int32_t c,
                                   int32_t r, const double *theta,
                                   const double *theta_t, const double *B,

@@ -96,7 +96,7 @@ _SIGNATURES = {
     "pichol_fit": (_i32, [_i64, _i32, _i32, _i32, _vp, _dbl, _vp, _vp, _vp,
                           _vp]),
     "pichol_lambda_workspace": (_sz, [_i32]),
-    "pichol_solve_interp_workspace": (_sz, [_i64, _i32, _i32]),
+    "pichol_solve_interp_workspace": (_sz, [_i64, _i32, _i32, _i32]),
     "pichol_eval": (_i32, [_i64, _i32, _i32, _vp, _i32, _vp, _dbl, _vp, _vp,
                            _sz, _vp]),
     "pichol_solve_interp": (_i32, [_i64, _i32, _i32, _i32, _vp, _vp, _vp,
@@ -286,8 +286,8 @@ def pichol_lambda_workspace(nlam: int) -> int:
     return int(load().pichol_lambda_workspace(nlam))
 
 
-def pichol_solve_interp_workspace(d: int, nmat: int, q: int) -> int:
-    return int(load().pichol_solve_interp_workspace(d, nmat, q))
+def pichol_solve_interp_workspace(d: int, nmat: int, q: int, c: int) -> int:
+    return int(load().pichol_solve_interp_workspace(d, nmat, q, c))
 
 
 def pichol_eval(d, nmat, r, theta, nlam, lam, lam_ref, Lhat, ws, ws_bytes,

@@ -39,7 +39,7 @@ struct Bucket {
   int stream = 0;
   size_t base = 0;         // byte offset of the bucket's workspace region
   // region offsets, relative to base
-  size_t G, C, yy, H, Bm, lam, tau, L, linv, th, tht, Z, part, dinv, dinvr,
+  size_t G, C, yy, H, Bm, lam, tau, L, linv, th, tht, Z, X, part, dinv, dinvr,
       info, flags, end;
 };
 
@@ -108,6 +108,7 @@ void layout_bucket(Bucket& b, int method) {
   b.th = o; o += interp ? align256(nmat * M * S * dbl) : 0;
   b.tht = o; o += interp ? align256(nmat * M * S * dbl) : 0;
   b.Z = o; o += align256(nmat * dp * ldz * dbl);
+  b.X = o; o += interp ? align256(nmat * dp * ldz * dbl) : 0;
   b.part = o; o += align256(nmat * nt * HOLDOUT_KSPLIT * ldz * dbl);
   b.dinv = o; o += interp ? align256(nmat * q * nt * NB2 * dbl) : 0;
   b.dinvr = o; o += interp ? align256(nmat * q * nt * NB2 * dbl) : 0;
@@ -222,7 +223,8 @@ hipError_t run_bucket(const Bucket& b, const pichol_batch_item* items,
       e = upload_tau(it0.lam_grid, q, it0.lam_ref, it0.p.basis, tau, st);
     if (e == hipSuccess) e = launch_fit(d, nmat, fc, L, th, tht, st);
     if (e == hipSuccess)
-      e = launch_solve_interp(d, nmat, c, M, th, tht, q, tau, ldz, Z, flags,
+      e = launch_solve_interp(d, nmat, c, M, th, tht, q, tau, ldz, Z,
+                              at<double>(base, b.X), flags,
                               at<double>(base, b.dinv),
                               at<double>(base, b.dinvr), 1, st);
   } else {

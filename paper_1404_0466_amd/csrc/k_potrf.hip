@@ -3,7 +3,7 @@
 //
 // Blocked right-looking algorithm on 128-wide panels over the tile-packed
 // layout.  For panel kk of every matrix in the batch:
-//   1. k_potrf_diag   factors the diagonal tile in LDS and writes the
+//   1. k_potrf_diag   factors the diagonal tile in registers and writes the
 //                     inverse of the factor to a scratch tile;
 //   2. k_potrf_panel  forms the tiles below it as A_{I,kk} L_kk^{-T}
 //                     (an FP64 MFMA product with the inverse);
@@ -61,145 +61,187 @@ __global__ void __launch_bounds__(256) k_shift_copy(int64_t d, int64_t S,
   if (blockIdx.x == 0 && threadIdx.x == 0) info[ms] = 0;
 }
 
-// Diagonal tile kk of factor f, in LDS (column-major, a[c*128 + r]):
-//  factorization in four 32-column blocks -- the 32 x 32 diagonal block by
-//  one wavefront with its rows in registers (readlane broadcasts, no
-//  barriers), the rows below it by forward substitution one row per thread,
-//  the trailing part by 4 x 4 register-blocked updates;
-//  then the inverse of the factor, recursively: the eight 16 x 16 diagonal
-//  blocks inverted by half-wavefronts, combined pairwise with
-//  [[A,0],[B,C]]^{-1} = [[A^{-1},0],[-C^{-1} B A^{-1}, C^{-1}]].
-// Writes the factor tile (zeros above the diagonal) and its inverse to linv.
+// Diagonal tile kk of factor f: its Cholesky factor and the inverse of that
+// factor, both held in registers.  Thread (ti, tk) = (tid % 16, tid / 16)
+// owns the entries (ti + 16a, tk + 16b), a >= b, of the tile (x) and of the
+// inverse (y): a two-dimensional cyclic layout, so every thread keeps work
+// until the last columns.  Column j is factored right-looking (pivot by a
+// refined reciprocal square root, column scaled, rank-1 update of the
+// trailing entries); the inverse is built alongside by forward substitution
+// on the identity, one column behind: row j-1 of the inverse is scaled by
+// 1/L(j-1,j-1) and the rows below it lose L(i, j-1) times that row.  Each
+// column is published in LDS with zeros at rows <= j (and the inverse's row
+// with zeros right of its diagonal), so every thread updates whole 16-entry
+// blocks without masks.  The step that consumes column j also produces
+// column j+1 (its block column is updated first, then its 16 owners factor
+// it), so one barrier per column suffices: column buffers rotate over
+// three slots, inverse rows and pivots over two.
+template <int JB, bool LAST>
+__device__ __forceinline__ void diag_step(int jj, double (&x)[8][8],
+                                          double (&y)[8][8], double (&prv)[8],
+                                          double* cbuf, double* rbuf,
+                                          double* pbuf, int* fail, int ti,
+                                          int tk) {
+  constexpr int NB1 = LAST ? JB + 1 : JB;  // block column of column j+1
+  constexpr bool NEXT = !(LAST && JB == 7);
+  const int j = 16 * JB + jj;
+  const double* cb = cbuf + (j % 3) * NB;
+  double cr[8], cc[8];  // column j at the thread's rows and columns
+#pragma unroll
+  for (int a = JB; a < 8; ++a) cr[a] = cb[ti + 16 * a];
+#pragma unroll
+  for (int b = JB; b < 8; ++b) cc[b] = cb[tk + 16 * b];
+  double v[8];
+  double inv = 0.0, piv = 0.0;
+  const int jn = j + 1, jn16 = jn & 15;
+  if (NEXT) {
+#pragma unroll
+    for (int a = NB1; a < 8; ++a) x[a][NB1] -= cr[a] * cc[NB1];
+    // pivot L(j+1, j+1)^2 sits with thread (jn16, jn16)
+    piv = bcast_lane(x[NB1][NB1], 16 * (jn16 & 3) + jn16);
+    double ljj;
+    sqrt_rsqrt(piv, ljj, inv);
+    const bool own = tk == jn16;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      v[a] = 0.0;
+      if (a >= NB1) {
+        const int i = ti + 16 * a;
+        const double sc = x[a][NB1] * inv;
+        if (i > jn) v[a] = sc;
+        const double nv = i > jn ? sc : (i == jn ? ljj : x[a][NB1]);
+        x[a][NB1] = own ? nv : x[a][NB1];
+      }
+    }
+  }
+  // the rest of the rank-1 update with column j (block column JB, when it
+  // is not NB1, only holds columns <= j: nothing to do)
+#pragma unroll
+  for (int b = NB1 + 1; b < 8; ++b)
+#pragma unroll
+    for (int a = b; a < 8; ++a) x[a][b] -= cr[a] * cc[b];
+  // inverse: rows below j-1 lose L(i, j-1) X(j-1, :)
+  if (j > 0) {
+    const double* rb = rbuf + ((j - 1) & 1) * NB;
+    double rr[8];
+#pragma unroll
+    for (int b = 0; b <= JB; ++b) rr[b] = rb[tk + 16 * b];
+#pragma unroll
+    for (int a = JB; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b <= JB; ++b) y[a][b] -= prv[a] * rr[b];
+  }
+  // inverse: row j is final once scaled by 1/L(j,j)
+  if (ti == jj) {
+    const double ij = pbuf[j & 1];
+    double* rb = rbuf + (j & 1) * NB;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      double o = 0.0;
+      if (b <= JB) {
+        y[JB][b] *= ij;
+        o = y[JB][b];
+      }
+      rb[tk + 16 * b] = o;
+    }
+  }
+#pragma unroll
+  for (int a = JB; a < 8; ++a) prv[a] = cr[a];
+  if (NEXT && tk == jn16) {
+    double* cn = cbuf + (jn % 3) * NB;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) cn[ti + 16 * a] = v[a];
+    if (ti == 0) {
+      pbuf[jn & 1] = inv;
+      if (!(piv > 0.0)) atomicMin(fail, jn);
+    }
+  }
+  __syncthreads();
+}
+
+template <int JB>
+__device__ __forceinline__ void diag_block(double (&x)[8][8], double (&y)[8][8],
+                                           double (&prv)[8], double* cbuf,
+                                           double* rbuf, double* pbuf, int* fail,
+                                           int ti, int tk) {
+#pragma unroll 1
+  for (int jj = 0; jj < 15; ++jj)
+    diag_step<JB, false>(jj, x, y, prv, cbuf, rbuf, pbuf, fail, ti, tk);
+  diag_step<JB, true>(15, x, y, prv, cbuf, rbuf, pbuf, fail, ti, tk);
+}
+
+// Writes the factor tile (zeros above the diagonal) in place and its inverse
+// (zeros above the diagonal) to linv; info[f] gets the global index + 1 of
+// the first non-positive pivot when it is the matrix's first failure.
 __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
                                                     int kk, double* L,
                                                     int* info, double* linv) {
-  __shared__ double a[NB2];
-  __shared__ double grp[32 * 4];  // one 4-column group of the 32 x 32 block
-  __shared__ double rdiag[NB];    // reciprocals of the factor's diagonal
+  __shared__ double cbuf[3 * NB];
+  __shared__ double rbuf[2 * NB];
+  __shared__ double pbuf[2];
+  __shared__ int fail;
   const int f = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, ti = tid & 15, tk = tid >> 4;
   double* tile = L + (int64_t)f * S + tile_off(kk, kk);
-  tile_to_lds(a, tile, tid);
-  __syncthreads();
-
-  for (int jb = 0; jb < 4; ++jb) {
-    const int j0 = 32 * jb;
-    // (1) diagonal 32 x 32 block, wave 0, lane = row j0 + lane.  Columns
-    // are factored in groups of four: inside a group by rank-1 updates with
-    // readlane broadcasts; then each lane publishes its row of the group in
-    // LDS and the trailing columns take the group's four contributions from
-    // there (one broadcast read per row instead of four readlane pairs).
-    // The subtractions keep the order of plain right-looking elimination.
-    if (w == 0) {
-      double r[32];
-      double myinv = 0.0;  // 1 / L(j0+lane, j0+lane)
+  double x[8][8], y[8][8], prv[8];
 #pragma unroll
-      for (int k = 0; k < 32; ++k)
-        r[k] = (lane < 32 && k <= lane) ? a[(j0 + k) * NB + j0 + lane] : 0.0;
+  for (int a = 0; a < 8; ++a) {
+    prv[a] = 0.0;
 #pragma unroll
-      for (int jg = 0; jg < 32; jg += 4) {
-#pragma unroll
-        for (int j = jg; j < jg + 4; ++j) {
-          const double piv = bcast_lane(r[j], j);
-          if (lane == 0 && !(piv > 0.0) && info[f] == 0 &&
-              (int64_t)kk * NB + j0 + j < d)
-            info[f] = kk * NB + j0 + j + 1;
-          double ljj, inv;
-          sqrt_rsqrt(piv, ljj, inv);
-          if (lane == j) {
-            r[j] = ljj;
-            myinv = inv;
-          } else if (lane > j) {
-            r[j] = r[j] * inv;
-          }
-#pragma unroll
-          for (int k = j + 1; k < jg + 4; ++k) {
-            const double lkj = bcast_lane(r[j], k);
-            if (lane >= k) r[k] -= r[j] * lkj;
-          }
-        }
-        if (jg + 4 < 32) {
-          if (lane < 32)
-            *(v4d*)(grp + 4 * lane) = v4d{r[jg], r[jg + 1], r[jg + 2], r[jg + 3]};
-          __builtin_amdgcn_wave_barrier();
-#pragma unroll
-          for (int k = jg + 4; k < 32; ++k) {
-            const v4d lk = *(const v4d*)(grp + 4 * k);
-            if (lane >= k) {
-              r[k] -= r[jg] * lk[0];
-              r[k] -= r[jg + 1] * lk[1];
-              r[k] -= r[jg + 2] * lk[2];
-              r[k] -= r[jg + 3] * lk[3];
-            }
-          }
-          __builtin_amdgcn_wave_barrier();
-        }
-      }
-      if (lane < 32) {
-#pragma unroll
-        for (int k = 0; k < 32; ++k)
-          if (k <= lane) a[(j0 + k) * NB + j0 + lane] = r[k];
-        rdiag[j0 + lane] = myinv;
-      }
+    for (int b = 0; b <= a; ++b) {
+      x[a][b] = tile[(tk + 16 * b) * NB + ti + 16 * a];
+      y[a][b] = (a == b && ti == tk) ? 1.0 : 0.0;
     }
-    __syncthreads();
-    if (jb == 3) break;
-    // (2) rows below: X = A L_d^{-T}, one row per thread
-    const int nrow = NB - j0 - 32;
-    if (tid < nrow) {
-      const int i = j0 + 32 + tid;
-      double x[32];
-#pragma unroll
-      for (int k = 0; k < 32; ++k) x[k] = a[(j0 + k) * NB + i];
-#pragma unroll
-      for (int j = 0; j < 32; ++j) {
-        x[j] = x[j] * rdiag[j0 + j];
-#pragma unroll
-        for (int p = j + 1; p < 32; ++p) x[p] -= x[j] * a[(j0 + j) * NB + j0 + p];
-      }
-#pragma unroll
-      for (int k = 0; k < 32; ++k) a[(j0 + k) * NB + i] = x[k];
-    }
-    __syncthreads();
-    // (3) trailing update of rows/columns [j0+32, 128), 4 x 4 blocks
-    const int nb4 = nrow / 4;
-    const int nblk = nb4 * (nb4 + 1) / 2;
-    for (int b = tid; b < nblk; b += blockDim.x) {
-      int bi = (int)((sqrtf(8.0f * (float)b + 1.0f) - 1.0f) * 0.5f);
-      while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
-      while (bi * (bi + 1) / 2 > b) --bi;
-      const int bj = b - bi * (bi + 1) / 2;
-      const int r0 = j0 + 32 + 4 * bi, c0 = j0 + 32 + 4 * bj;
-      double acc[4][4] = {};
-#pragma unroll 8
-      for (int p = 0; p < 32; ++p) {
-        const double* col = a + (j0 + p) * NB;
-        double xr[4], xc[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          xr[u] = col[r0 + u];
-          xc[u] = col[c0 + u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] += xr[u] * xc[v];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (r0 + u >= c0 + v) a[(c0 + v) * NB + r0 + u] -= acc[u][v];
-    }
-    __syncthreads();
   }
-
-  tile_lower_from_lds(tile, a, tid);
-
+  {  // column 0, by its owners (wave 0)
+    const double piv = bcast_lane(x[0][0], 0);
+    double ljj, inv;
+    sqrt_rsqrt(piv, ljj, inv);
+    if (tk == 0) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int i = ti + 16 * a;
+        double v = 0.0;
+        if (i > 0) {
+          x[a][0] *= inv;
+          v = x[a][0];
+        } else {
+          x[a][0] = ljj;
+        }
+        cbuf[i] = v;
+      }
+      if (ti == 0) {
+        pbuf[0] = inv;
+        fail = (piv > 0.0) ? NB : 0;
+      }
+    }
+  }
   __syncthreads();
-  invert_lower_lds(a, tid, rdiag);
+  diag_block<0>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
+  diag_block<1>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
+  diag_block<2>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
+  diag_block<3>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
+  diag_block<4>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
+  diag_block<5>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
+  diag_block<6>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
+  diag_block<7>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
   double* li = linv + (int64_t)f * NB2;
-  tile_lower_from_lds(li, a, tid);
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int i = ti + 16 * a, k = tk + 16 * b;
+      const bool low = a > b || (a == b && ti >= tk);
+      double xv = 0.0, yv = 0.0;
+      if (a >= b) {
+        xv = low ? x[a][b] : 0.0;
+        yv = low ? y[a][b] : 0.0;
+      }
+      tile[k * NB + i] = xv;
+      li[k * NB + i] = yv;
+    }
+  if (tid == 0 && fail < NB && (int64_t)kk * NB + fail < d && info[f] == 0)
+    info[f] = kk * NB + fail + 1;
 }
 
 // Panel tile (I, kk), I > kk: X = A L_kk^{-T}, in place.  The wave computes

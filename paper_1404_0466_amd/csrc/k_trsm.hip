@@ -180,25 +180,43 @@ __global__ void __launch_bounds__(256) k_diag_inv(int64_t d, FactorSrc src,
   }
 }
 
-// Apply the stored inverse of diagonal block i to the slab rows of tile i:
-// z <- M z for the c columns of lambda t = blockIdx.x of fold m =
-// blockIdx.y, where M(r,k) = mat[k*128 + r] (the inverse for forward steps,
-// its transpose for back steps).  One workgroup per (fold, lambda) owns the
-// whole block (the update is in place); its threads split the 128-long sums
-// into two halves of two 32-load rounds each, and the halves are added in
-// LDS.
+// Apply the stored inverse of diagonal block i to the slab rows of tile i,
+// out of place: dst rows of tile i = M (src rows of tile i), for the c
+// columns of lambda t of fold m, where M(r,k) = mat[k*128 + r] (the inverse
+// for forward steps, lower triangular; its transpose for back steps, upper
+// triangular).  Four workgroups per (fold, lambda) each own 32 rows of the
+// result; only the triangle's nonzero columns k of those rows are read
+// (k < r0 + 32 forward, k >= r0 backward).  The 32 rows of M and the
+// 128-row block of right-hand sides sit in LDS; thread (row, pair) sums two
+// columns over k in increasing order.  Grid x = 4 * lambda + quarter; nper
+// is the number of lambdas (the slab holds nper * c columns, then zero
+// padding up to ldz).
+template <bool FWD>
 __global__ void __launch_bounds__(256) k_diag_apply(int64_t d, int i, int nper,
                                                     int c, const double* mats,
-                                                    int64_t ldz, double* Z) {
-  __shared__ double zs[NB * 16];
-  __shared__ double part[NB * 17];
-  const int t = blockIdx.x;
+                                                    int64_t ldz,
+                                                    const double* src,
+                                                    double* dst) {
+  __shared__ v4d ms4[NB * 8];      // ms[k*32 + rr] = M(r0 + rr, k)
+  __shared__ double2 zs2[NB * 8];  // zs[k*16 + u] = src(k, cg + u)
+  double* ms = reinterpret_cast<double*>(ms4);
+  double* zs = reinterpret_cast<double*>(zs2);
+  const int qt = blockIdx.x & 3, t = blockIdx.x >> 2;
   const int64_t m = blockIdx.y;
   const int nt = (int)ntiles_of(d);
-  const int tid = threadIdx.x, row = tid & (NB - 1), kh = tid >> 7;
+  const int tid = threadIdx.x, rr = tid & 31, pr = tid >> 5;
+  const int r0 = 32 * qt;
+  const int klo = FWD ? 0 : r0, khi = FWD ? r0 + 32 : NB;
   const int64_t dp = (int64_t)nt * NB;
   const double* M = mats + ((m * nper + t) * nt + i) * (int64_t)NB2;
-  double* zb = Z + (m * dp + (int64_t)i * NB) * ldz + (int64_t)t * c;
+  const int64_t zoff = (m * dp + (int64_t)i * NB) * ldz + (int64_t)t * c;
+  const double* zs_src = src + zoff;
+  double* zd = dst + zoff;
+  // rows r0..r0+31 of M over the needed k: eight 32-byte pieces per k
+  for (int e = tid; e < (khi - klo) * 8; e += 256) {
+    const int k = klo + (e >> 3), part = e & 7;
+    *(v4d*)(ms + k * 32 + part * 4) = ld4(M + (int64_t)k * NB + r0 + part * 4);
+  }
   for (int cg = 0; cg < c; cg += 16) {
     const int cn = (c - cg) < 16 ? (c - cg) : 16;
     if (cg) __syncthreads();
@@ -206,33 +224,31 @@ __global__ void __launch_bounds__(256) k_diag_apply(int64_t d, int i, int nper,
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = tid + 256 * u, k = e >> 4, cc = e & 15;
-      zv[u] = cc < cn ? zb[(int64_t)k * ldz + cg + cc] : 0.0;
+      zv[u] = cc < cn ? zs_src[(int64_t)k * ldz + cg + cc] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) zs[tid + 256 * u] = zv[u];
     __syncthreads();
-    double acc[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-#pragma unroll 1
-    for (int k0 = 64 * kh; k0 < 64 * kh + 64; k0 += 32) {
-      double mv[32];
-#pragma unroll
-      for (int kk = 0; kk < 32; ++kk) mv[kk] = M[(k0 + kk) * NB + row];
-#pragma unroll
-      for (int kk = 0; kk < 32; ++kk)
-#pragma unroll
-        for (int u = 0; u < 16; ++u) acc[u] += mv[kk] * zs[(k0 + kk) * 16 + u];
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll 8
+    for (int k = klo; k < khi; ++k) {
+      const double mv = ms[k * 32 + rr];
+      const double2 zz = *(const double2*)(zs + k * 16 + 2 * pr);
+      a0 += mv * zz.x;
+      a1 += mv * zz.y;
     }
-    if (kh == 1) {
-#pragma unroll
-      for (int u = 0; u < 16; ++u) part[row * 17 + u] = acc[u];
-    }
-    __syncthreads();  // every read of the block's rows precedes the writes
-    if (kh == 0) {
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (u < cn) zb[(int64_t)row * ldz + cg + u] = acc[u] + part[row * 17 + u];
+    double* out = zd + (int64_t)(r0 + rr) * ldz + cg + 2 * pr;
+    if (2 * pr < cn) out[0] = a0;
+    if (2 * pr + 1 < cn) out[1] = a1;
+  }
+  // the last lambda's workgroups also keep the slab's padding columns
+  // (q*c .. ldz) of their rows at zero in the destination
+  if (t == nper - 1) {
+    const int64_t qc = (int64_t)nper * c;
+    double* pad = dst + (m * dp + (int64_t)i * NB + r0) * ldz;
+    for (int64_t e = tid; e < 32 * (ldz - qc); e += 256) {
+      const int64_t r = e / (ldz - qc);
+      pad[r * ldz + qc + e % (ldz - qc)] = 0.0;
     }
   }
 }
@@ -255,7 +271,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 k_update_interp(
     int64_t d, int i, const double* theta, const double* theta_t, int64_t S,
     int M, int q, int c, const double* tau, int64_t ldz, int ncb, int nrows,
-    double* Z) {
+    const double* X, double* Z) {
   __shared__ v4d xch[2][16][64];  // partial sums of the k-second-half waves
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int cb = id % ncb;
@@ -277,7 +293,7 @@ k_update_interp(
 
   const double* planes = FWD ? theta + m * M * S + tile_off(I, i)
                              : theta_t + m * M * S + tile_off(i, I);
-  const double* bsrc = Z + (m * dp + (int64_t)i * NB) * ldz + cb * NB + wj * 64;
+  const double* bsrc = X + (m * dp + (int64_t)i * NB) * ldz + cb * NB + wj * 64;
   double* zt = Z + (m * dp + (int64_t)I * NB + rh * 64) * ldz + col;
   Acc64 acc;
   if (kh == 0) {
@@ -399,10 +415,14 @@ hipError_t launch_slab_init(int64_t d, int nmat, int q, int c, int64_t ldz,
   return slab_init(d, nmat, q, c, ldz, B, Z, flags, s);
 }
 
+// Forward steps take the right-hand sides from Z and leave the solved
+// blocks in X; back steps take them from X and leave the solution in Z.
+// Each diagonal apply reads one slab and writes the other, so its four
+// workgroups per (fold, lambda) never overwrite rows another one reads.
 hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
                                const double* theta, const double* theta_t,
                                int q, const double* tau_dev, int64_t ldz,
-                               double* Z, int* flags, double* dinv,
+                               double* Z, double* X, int* flags, double* dinv,
                                double* dinv_r, int prepare, hipStream_t s) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
@@ -411,23 +431,24 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
   if (prepare)
     PICHOL_LAUNCH(k_diag_inv, dim3((unsigned)nt, (unsigned)q, (unsigned)nmat),
                   dim3(256), 0, s, d, src, dinv, dinv_r, flags);
+  const dim3 agrid((unsigned)(4 * q), (unsigned)nmat);
   for (int i = 0; i < nt; ++i) {
-    PICHOL_LAUNCH(k_diag_apply, dim3((unsigned)q, (unsigned)nmat), dim3(256), 0,
-                  s, d, i, q, c, dinv, ldz, Z);
+    PICHOL_LAUNCH(k_diag_apply<true>, agrid, dim3(256), 0, s, d, i, q, c, dinv,
+                  ldz, Z, X);
     if (i + 1 < nt) {
       const int nrows = nt - i - 1;
       PICHOL_LAUNCH(k_update_interp<true>, dim3(ncb * 2 * nrows * nmat),
                     dim3(256), 0, s, d, i, theta, theta_t, S, M, q, c, tau_dev,
-                    ldz, (int)ncb, nrows, Z);
+                    ldz, (int)ncb, nrows, X, Z);
     }
   }
   for (int i = nt - 1; i >= 0; --i) {
-    PICHOL_LAUNCH(k_diag_apply, dim3((unsigned)q, (unsigned)nmat), dim3(256), 0,
-                  s, d, i, q, c, dinv_r, ldz, Z);
+    PICHOL_LAUNCH(k_diag_apply<false>, agrid, dim3(256), 0, s, d, i, q, c,
+                  dinv_r, ldz, X, Z);
     if (i > 0)
       PICHOL_LAUNCH(k_update_interp<false>, dim3(ncb * 2 * i * nmat), dim3(256),
                     0, s, d, i, theta, theta_t, S, M, q, c, tau_dev, ldz,
-                    (int)ncb, i, Z);
+                    (int)ncb, i, Z, X);
   }
   return hipGetLastError();
 }

@@ -270,7 +270,7 @@ def test_solve_interp_matches_oracle(gu, d, c, g, r, q):
     ldz = gu.B.pichol_slab_cols(q, c)
     Z = gu.empty(dp * ldz)
     flags = gu.empty(q, torch.int32)
-    nb = gu.B.pichol_solve_interp_workspace(d, 1, q)
+    nb = gu.B.pichol_solve_interp_workspace(d, 1, q, c)
     gu.B.pichol_solve_interp(d, 1, c, r, th, tht, gu.dev(Bh), q, lam, lam_ref, Z,
                              flags, gu.ws(nb), nb)
     Wg = gu.slab_to_w(Z, d, 1, q, c)[0]
