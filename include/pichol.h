@@ -554,9 +554,10 @@ typedef enum {
    * first receives the group's earlier panels (a rank-128u update of that
    * column); after the group, one rank-(128 x group) update reaches the
    * rest of the trailing matrix, so larger groups read and write the
-   * trailing matrix fewer times.  The look-ahead schedule applies to groups
-   * of 2 only (other sizes run without it).  Results differ only by the
-   * rounding order of the trailing sums. */
+   * trailing matrix fewer times.  With the look-ahead option, the update
+   * of the next group's columns stays on the caller's stream and the rest
+   * of each group's trailing update runs on the side stream.  Results differ
+   * only by the rounding order of the trailing sums. */
   PICHOL_OPT_PANEL_GROUP = 2
 } pichol_option;
 

@@ -280,8 +280,8 @@ __device__ inline void mma_any(Acc64F& acc, const double* a, int64_t lda,
 }
 
 // Trailing tile (I,J): A_IJ -= sum_{c in [c0,c1)} L_Ic L_Jc^T, for the
-// tiles of the triangle j0 <= J <= I (mode 0), of the column J = j0
-// (mode 1), or of the two columns J = j0, j0+1 (mode 2).
+// tiles of the triangle j0 <= J <= I (mode 0) or of the `mode` whole
+// columns J = j0 .. j0+mode-1 (mode > 0).
 // The wave computes D'(n,m) = sum_p L_Jc(n,p) L_Ic(m,p) = update(m,n) and
 // subtracts it from the tile in its epilogue.  Two workgroups share a CU
 // (the register budget is capped for two waves per SIMD), so one's
@@ -389,14 +389,15 @@ static SideStream* side_stream() {
   return &ss;
 }
 
-// Panels are factored in pairs with a delayed update: after panel kk only
-// the next panel column is updated, panel kk+1 is factored, and the rest of
-// the trailing matrix receives both panels' contributions in one rank-256
-// update.  With the look-ahead option on, that update is split: the two
-// columns the next pair factors first stay on the caller's stream, the
-// remainder runs on a side stream, so the next pair's diagonal
-// factorizations and panel solves (short, latency-bound launches) overlap
-// the bulk of the update.
+// Panels in groups of G with a delayed update: before its diagonal
+// factorization, column kk+u receives the group's earlier panels (K = 128 u);
+// after the group, one update of rank 128 G reaches the rest of the trailing
+// matrix.  With the look-ahead option on, that update is split: the G
+// columns the next group factors stay on the caller's stream, the remainder
+// runs on a side stream, so the next group's diagonal factorizations, panel
+// solves and column updates (short, latency-bound launches) overlap the bulk
+// of the update.  The side update is joined before the next group's own
+// trailing update, the first launch that touches the same tiles.
 hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
                                 double* linv_ws, int mixed, int lookahead,
                                 int group, hipStream_t s) {
@@ -426,44 +427,30 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
                     0, st, S, nt, j0, m, c0, c1, ntile, L);
   };
   const int G = group > 0 ? group : option_panel_group();
-  if (!side || G != 2) {
-    // Panels in groups of G: before its diagonal factorization, column
-    // kk+u receives the group's earlier panels (K = 128 u); after the group,
-    // one update of rank 128 G reaches the rest of the trailing matrix.
-    for (int kk = 0; kk < nt; kk += G) {
-      for (int u = 0; u < G && kk + u < nt; ++u) {
-        if (u > 0) update(s, kk + u, 1, kk, kk + u);
-        diag_panel(kk + u);
-      }
-      if (kk + G < nt) update(s, kk + G, 0, kk, kk + G);
-    }
-    return hipGetLastError();
-  }
   int ring = 0;
   bool pending = false;  // a side-stream update not yet joined
   hipEvent_t joined = nullptr;
-  for (int kk = 0; kk < nt; kk += 2) {
-    diag_panel(kk);
-    if (kk + 1 >= nt) break;
-    update(s, kk + 1, 1, kk, kk + 1);  // next panel column only
-    diag_panel(kk + 1);
-    if (kk + 2 >= nt) break;
-    // columns kk+2, kk+3 also received the previous pair's remainder
+  for (int kk = 0; kk < nt; kk += G) {
+    for (int u = 0; u < G && kk + u < nt; ++u) {
+      if (u > 0) update(s, kk + u, 1, kk, kk + u);
+      diag_panel(kk + u);
+    }
+    if (kk + G >= nt) break;
     if (pending) {
       hipStreamWaitEvent(s, joined, 0);
       pending = false;
     }
-    if (side && kk + 4 < nt) {
+    if (side && kk + 2 * G < nt) {
       hipEvent_t ready = side->ev[ring++ & 7];
       hipEventRecord(ready, s);
-      update(s, kk + 2, 2, kk, kk + 2);
+      update(s, kk + G, G, kk, kk + G);  // the next group's columns
       hipStreamWaitEvent(side->stream, ready, 0);
-      update(side->stream, kk + 4, 0, kk, kk + 2);
+      update(side->stream, kk + 2 * G, 0, kk, kk + G);
       joined = side->ev[ring++ & 7];
       hipEventRecord(joined, side->stream);
       pending = true;
     } else {
-      update(s, kk + 2, 0, kk, kk + 2);
+      update(s, kk + G, 0, kk, kk + G);
     }
   }
   if (pending) hipStreamWaitEvent(s, joined, 0);
