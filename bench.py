@@ -664,7 +664,12 @@ def main():
         B.pichol_profile_reset()
         kernels = {name: {"launches": nl, "avg_ms": tot / nl, "total_ms_per_step": tot / args.steps}
                    for name, (nl, tot) in sorted(summ.items(), key=lambda kv: -kv[1][1])}
-        upd = summ.get("k_potrf_update")
+        # the trailing-update kernel has two instantiations (first touch of a
+        # tile reading the fold matrix, later touches reading the factor);
+        # the roofline covers both
+        parts = [v for nm, v in summ.items()
+                 if nm in ("k_potrf_update", "k_potrf_update<true>", "k_potrf_update<false>")]
+        upd = (sum(p[0] for p in parts), sum(p[1] for p in parts)) if parts else None
         if upd:
             flops = update_flops(d, k * g)
             if not args.no_exact:

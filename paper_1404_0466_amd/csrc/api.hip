@@ -445,9 +445,8 @@ pichol_status pichol_potrf_shifted_batched(int64_t d, int32_t nmat,
   double* linv = at<double>(ws, align256((size_t)nshift * sizeof(double)));
   hipError_t e = launch_store_doubles(lam, nshift, lam_dev, stream);
   if (e != hipSuccess) return hip_status(e);
-  e = launch_shift_copy(d, nmat, H, nshift, lam_dev, nmat, L, info, stream);
-  if (e != hipSuccess) return hip_status(e);
-  return hip_status(launch_potrf_blocked(d, nmat * nshift, L, info, linv,
+  const ShiftSrc src{H, nshift, lam_dev, nmat};
+  return hip_status(launch_potrf_blocked(d, nmat * nshift, src, L, info, linv,
                                          precision == PICHOL_PREC_MIXED,
                                          option_lookahead(), 0, stream));
 }
@@ -659,10 +658,9 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
   if (e == hipSuccess)
     e = upload_tau(lam_grid, q, lam_ref, p->basis, tau, stream);
   if (e == hipSuccess)
-    e = launch_shift_copy(p->d, k, at<double>(ws, L.H), g, lam_dev, k, Lf,
-                          info, stream);
-  if (e == hipSuccess)
-    e = launch_potrf_blocked(p->d, k * g, Lf, info, at<double>(ws, L.i_linv),
+    e = launch_potrf_blocked(p->d, k * g,
+                             ShiftSrc{at<double>(ws, L.H), g, lam_dev, k}, Lf,
+                             info, at<double>(ws, L.i_linv),
                              p->precision == PICHOL_PREC_MIXED,
                              option_lookahead(), 0, stream);
   if (e == hipSuccess) e = launch_fit(p->d, k, fc, Lf, th, tht, stream);
@@ -722,10 +720,9 @@ pichol_status pichol_cv_exact(const pichol_problem* p, const double* lam_grid,
   double* Z = at<double>(ws, L.e_Z);
   hipError_t e = launch_store_doubles(lam_grid, q, lam_dev, stream);
   if (e == hipSuccess)
-    e = launch_shift_copy(p->d, k, at<double>(ws, L.H), q, lam_dev, k, Lf,
-                          info, stream);
-  if (e == hipSuccess)
-    e = launch_potrf_blocked(p->d, k * q, Lf, info, at<double>(ws, L.e_linv),
+    e = launch_potrf_blocked(p->d, k * q,
+                             ShiftSrc{at<double>(ws, L.H), q, lam_dev, k}, Lf,
+                             info, at<double>(ws, L.e_linv),
                              p->precision == PICHOL_PREC_MIXED,
                              option_lookahead(), 0, stream);
   if (e == hipSuccess)

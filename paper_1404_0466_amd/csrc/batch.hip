@@ -207,9 +207,8 @@ hipError_t run_bucket(const Bucket& b, const pichol_batch_item* items,
   }
   if (e == hipSuccess) e = launch_store_doubles(lam_all.data(), nb * nf, lam, st);
   if (e == hipSuccess)
-    e = launch_shift_copy(d, nmat, H, nf, lam, k, L, info, st);
-  if (e == hipSuccess)
-    e = launch_potrf_blocked(d, nmat * nf, L, info, linv,
+    e = launch_potrf_blocked(d, nmat * nf, ShiftSrc{H, nf, lam, k}, L, info,
+                             linv,
                              b.precision == PICHOL_PREC_MIXED, 0, group, st);
   if (e == hipSuccess)
     e = launch_slab_init(d, nmat, q, c, ldz, Bm, Z, flags, st);

@@ -18,47 +18,14 @@
 
 namespace pichol {
 
-// L(m*nshift + s) = H(m) + lam_s I: lower part copied, shift on the first d
-// diagonal entries, identity padding, zeros above the diagonal of diagonal
-// tiles.  Also clears info.  Matrices m share their shift set in groups of
-// lam_group: matrix m uses lam[(m / lam_group) * nshift + s].
-__global__ void __launch_bounds__(256) k_shift_copy(int64_t d, int64_t S,
-                                                    const double* H,
-                                                    int nshift,
-                                                    const double* lam,
-                                                    int lam_group,
-                                                    double* L, int* info) {
-  const int64_t ms = blockIdx.y;
-  const int64_t m = ms / nshift;
-  const int s = (int)(ms % nshift);
-  const int I = tri_row(blockIdx.x), J = blockIdx.x - (int)tri(I);
-  const double shift = lam[(m / lam_group) * nshift + s];
-  const double* h = H + m * S + tile_off(I, J);
-  double* l = L + ms * S + tile_off(I, J);
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int it = 0; it < 16; it += 8) {
-    v4d v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = ld4(h + ((it + u) * 256 + tid) * 4);
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = ((it + u) * 256 + tid) * 4;
-      const int64_t j = (int64_t)J * NB + (e >> 7);
-#pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        const int64_t i = (int64_t)I * NB + ((e + x) & (NB - 1));
-        if (i >= d || j >= d)
-          v[u][x] = (i == j) ? 1.0 : 0.0;
-        else if (i < j)
-          v[u][x] = 0.0;
-        else if (i == j)
-          v[u][x] += shift;
-      }
-      st4(l + e, v[u]);
-    }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) info[ms] = 0;
+// Factor f's source tile at packed offset off, and its shift.
+__device__ inline const double* src_tile(const ShiftSrc& src, int64_t S,
+                                         int64_t f, int64_t off) {
+  return src.H + (f / src.nshift) * S + off;
+}
+__device__ inline double src_shift(const ShiftSrc& src, int64_t f) {
+  const int64_t m = f / src.nshift;
+  return src.lam[(m / src.lam_group) * src.nshift + f % src.nshift];
 }
 
 // Diagonal tile kk of factor f: its Cholesky factor and the inverse of that
@@ -172,10 +139,14 @@ __device__ __forceinline__ void diag_block(double (&x)[8][8], double (&y)[8][8],
 
 // Writes the factor tile (zeros above the diagonal) in place and its inverse
 // (zeros above the diagonal) to linv; info[f] gets the global index + 1 of
-// the first non-positive pivot when it is the matrix's first failure.
+// the first non-positive pivot when it is the matrix's first failure.  With
+// SRC (first panel only) the tile comes from the source matrix plus its
+// shift, and info is written either way (0 when no pivot failed).
+template <bool SRC>
 __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
                                                     int kk, double* L,
-                                                    int* info, double* linv) {
+                                                    int* info, double* linv,
+                                                    ShiftSrc src) {
   __shared__ double cbuf[3 * NB];
   __shared__ double rbuf[2 * NB];
   __shared__ double pbuf[2];
@@ -183,13 +154,18 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
   const int f = blockIdx.x;
   const int tid = threadIdx.x, ti = tid & 15, tk = tid >> 4;
   double* tile = L + (int64_t)f * S + tile_off(kk, kk);
+  const double* in = SRC ? src_tile(src, S, f, tile_off(kk, kk)) : tile;
+  const double shift = SRC ? src_shift(src, f) : 0.0;
   double x[8][8], y[8][8], prv[8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
     prv[a] = 0.0;
 #pragma unroll
     for (int b = 0; b <= a; ++b) {
-      x[a][b] = tile[(tk + 16 * b) * NB + ti + 16 * a];
+      // entries above the diagonal are never used: not read
+      x[a][b] = (a > b || ti >= tk) ? in[(tk + 16 * b) * NB + ti + 16 * a] : 0.0;
+      if (SRC && a == b && ti == tk && (int64_t)kk * NB + ti + 16 * a < d)
+        x[a][b] += shift;
       y[a][b] = (a == b && ti == tk) ? 1.0 : 0.0;
     }
   }
@@ -240,24 +216,31 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
       tile[k * NB + i] = xv;
       li[k * NB + i] = yv;
     }
-  if (tid == 0 && fail < NB && (int64_t)kk * NB + fail < d && info[f] == 0)
-    info[f] = kk * NB + fail + 1;
+  if (tid == 0) {
+    const bool bad = fail < NB && (int64_t)kk * NB + fail < d;
+    if (SRC)
+      info[f] = bad ? kk * NB + fail + 1 : 0;
+    else if (bad && info[f] == 0)
+      info[f] = kk * NB + fail + 1;
+  }
 }
 
-// Panel tile (I, kk), I > kk: X = A L_kk^{-T}, in place.  The wave computes
+// Panel tile (I, kk), I > kk: X = A L_kk^{-T}, in place (with SRC, A is
+// read from the source matrix).  The wave computes
 // D'(n,m) = sum_p Linv(n,p) A(m,p) = X(m,n), stored at n*128 + m.  Linv is
 // lower triangular, so the sum stops at the wave's last n.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_potrf_panel(int64_t S, int kk,
-                                                     double* L,
-                                                     const double* linv) {
+template <bool SRC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_potrf_panel(int64_t S, int kk, double* L, const double* linv, ShiftSrc src) {
   const int f = blockIdx.y;
   const int I = kk + 1 + blockIdx.x;
   const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
   double* tile = L + (int64_t)f * S + tile_off(I, kk);
+  const double* in = SRC ? src_tile(src, S, f, tile_off(I, kk)) : tile;
   const double* li = linv + (int64_t)f * NB2;
   Acc64 acc;
   acc.zero();
-  mma_panel(acc, li + wi * 64, NB, tile + wj * 64, NB, wi * 64 + 64);
+  mma_panel(acc, li + wi * 64, NB, in + wj * 64, NB, wi * 64 + 64);
   __syncthreads();  // the whole tile is read before any part is overwritten
   const LaneXY lx;
   const int m0 = wj * 64 + lx.col0();
@@ -288,9 +271,10 @@ __device__ inline void mma_any(Acc64F& acc, const double* a, int64_t lda,
 // read-modify-write epilogue overlaps the other's products.  Logical
 // workgroup ids are laid out matrix by matrix and spread over the XCDs in
 // contiguous ranges.
-template <typename ACC>
-__device__ inline void potrf_update_body(int64_t S, int nt, int j0, int mode, int c0, int c1, int ntile,
-               double* L) {
+template <typename ACC, bool SRC>
+__device__ inline void potrf_update_body(int64_t S, int nt, int j0, int mode,
+                                         int c0, int c1, int ntile, double* L,
+                                         int64_t d, const ShiftSrc& src) {
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int f = id / ntile;
   const int t = id - f * ntile;
@@ -313,6 +297,8 @@ __device__ inline void potrf_update_body(int64_t S, int nt, int j0, int mode, in
   if (I == J && wi > wj) return;  // block strictly above the diagonal
   double* Lf = L + (int64_t)f * S;
   double* ct = Lf + tile_off(I, J);
+  // the tile's current value: L itself, or (first touch) the source matrix
+  const double* cs = SRC ? src_tile(src, S, f, tile_off(I, J)) : ct;
   const LaneXY lx;
   const int m0 = wj * 64 + lx.col0();
   ACC acc;
@@ -320,48 +306,45 @@ __device__ inline void potrf_update_body(int64_t S, int nt, int j0, int mode, in
   for (int c = c0; c < c1; ++c)
     mma_any(acc, Lf + tile_off(J, c) + wi * 64, NB,
             Lf + tile_off(I, c) + wj * 64, NB, NB);
+  const double shift = (SRC && I == J) ? src_shift(src, f) : 0.0;
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi) {
       const int n = wi * 64 + ACC::row_of(lx.lq, v, bi);
       double* p = ct + n * NB + m0;
+      const double* q = cs + n * NB + m0;
       const v4d val = acc.row(v, bi);
       if (I != J || wi != wj) {
-        st4(p, ld4(p) - val);
+        st4(p, ld4(q) - val);
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          if (m0 + e >= n) p[e] -= val[e];
+          if (m0 + e >= n) {
+            double cv = q[e];
+            if (SRC && m0 + e == n && (int64_t)I * NB + n < d) cv += shift;
+            p[e] = cv - val[e];
+          }
       }
     }
 }
 
-hipError_t launch_shift_copy(int64_t d, int nmat, const double* H, int nshift,
-                             const double* lam_dev, int lam_group, double* L,
-                             int* info, hipStream_t s) {
-  const int64_t nt = ntiles_of(d);
-  PICHOL_LAUNCH(k_shift_copy,
-                     dim3((unsigned)tri(nt), (unsigned)(nmat * nshift)),
-                     dim3(256), 0, s, d, packed_elems_of(d), H, nshift,
-                     lam_dev, lam_group, L, info);
-  return hipGetLastError();
-}
-
+template <bool SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_potrf_update(int64_t S, int nt, int j0, int mode, int c0, int c1, int ntile,
-               double* L) {
-  potrf_update_body<Acc64>(S, nt, j0, mode, c0, c1, ntile, L);
+               double* L, int64_t d, ShiftSrc src) {
+  potrf_update_body<Acc64, SRC>(S, nt, j0, mode, c0, c1, ntile, L, d, src);
 }
 
 // Mixed precision: the same update with the products on FP32 MFMA (operands
 // rounded to FP32, FP32 accumulation over the 256-long sums); the tile
 // itself stays FP64.  FP32 accumulators take half the registers, so four
 // workgroups share a CU (measured faster than two at d = 4096).
+template <bool SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_potrf_update_f32(int64_t S, int nt, int j0, int mode, int c0, int c1,
-                   int ntile, double* L) {
-  potrf_update_body<Acc64F>(S, nt, j0, mode, c0, c1, ntile, L);
+                   int ntile, double* L, int64_t d, ShiftSrc src) {
+  potrf_update_body<Acc64F, SRC>(S, nt, j0, mode, c0, c1, ntile, L, d, src);
 }
 
 // Side stream for look-ahead: created once per device on first use, with
@@ -398,42 +381,63 @@ static SideStream* side_stream() {
 // solves and column updates (short, latency-bound launches) overlap the bulk
 // of the update.  The side update is joined before the next group's own
 // trailing update, the first launch that touches the same tiles.
-hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
-                                double* linv_ws, int mixed, int lookahead,
-                                int group, hipStream_t s) {
+hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
+                                double* L, int* info, double* linv_ws,
+                                int mixed, int lookahead, int group,
+                                hipStream_t s) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
+  const bool has_src = src.H != nullptr;
   std::unique_lock<std::mutex> lk(g_side_mu, std::defer_lock);
   if (lookahead) lk.lock();
   SideStream* side = lookahead ? side_stream() : nullptr;
-  auto diag_panel = [&](int kk) {
-    PICHOL_LAUNCH(k_potrf_diag, dim3((unsigned)nfac), dim3(256), 0, s, d, S,
-                  kk, L, info, linv_ws);
+  auto diag_panel = [&](int kk, bool first) {
+    if (first)
+      PICHOL_LAUNCH(k_potrf_diag<true>, dim3((unsigned)nfac), dim3(256), 0, s,
+                    d, S, kk, L, info, linv_ws, src);
+    else
+      PICHOL_LAUNCH(k_potrf_diag<false>, dim3((unsigned)nfac), dim3(256), 0, s,
+                    d, S, kk, L, info, linv_ws, src);
     const int rest = nt - kk - 1;
-    if (rest > 0)
-      PICHOL_LAUNCH(k_potrf_panel, dim3((unsigned)rest, (unsigned)nfac),
-                    dim3(256), 0, s, S, kk, L, linv_ws);
+    if (rest <= 0) return;
+    const dim3 grid((unsigned)rest, (unsigned)nfac);
+    if (first)
+      PICHOL_LAUNCH(k_potrf_panel<true>, grid, dim3(256), 0, s, S, kk, L,
+                    linv_ws, src);
+    else
+      PICHOL_LAUNCH(k_potrf_panel<false>, grid, dim3(256), 0, s, S, kk, L,
+                    linv_ws, src);
   };
-  auto update = [&](hipStream_t st, int j0, int mode, int c0, int c1) {
+  auto update = [&](hipStream_t st, int j0, int mode, int c0, int c1,
+                    bool first) {
     const int rest = nt - j0;
     if (rest <= 0) return;
     const int m = mode == 0 ? 0 : (mode < rest ? mode : rest);
     const int ntile = m == 0 ? (int)tri(rest) : m * rest - m * (m - 1) / 2;
-    if (mixed)
-      PICHOL_LAUNCH(k_potrf_update_f32, dim3((unsigned)(ntile * nfac)),
-                    dim3(256), 0, st, S, nt, j0, m, c0, c1, ntile, L);
+    const dim3 grid((unsigned)(ntile * nfac));
+    if (mixed && first)
+      PICHOL_LAUNCH(k_potrf_update_f32<true>, grid, dim3(256), 0, st, S, nt,
+                    j0, m, c0, c1, ntile, L, d, src);
+    else if (mixed)
+      PICHOL_LAUNCH(k_potrf_update_f32<false>, grid, dim3(256), 0, st, S, nt,
+                    j0, m, c0, c1, ntile, L, d, src);
+    else if (first)
+      PICHOL_LAUNCH(k_potrf_update<true>, grid, dim3(256), 0, st, S, nt, j0, m,
+                    c0, c1, ntile, L, d, src);
     else
-      PICHOL_LAUNCH(k_potrf_update, dim3((unsigned)(ntile * nfac)), dim3(256),
-                    0, st, S, nt, j0, m, c0, c1, ntile, L);
+      PICHOL_LAUNCH(k_potrf_update<false>, grid, dim3(256), 0, st, S, nt, j0,
+                    m, c0, c1, ntile, L, d, src);
   };
   const int G = group > 0 ? group : option_panel_group();
   int ring = 0;
   bool pending = false;  // a side-stream update not yet joined
   hipEvent_t joined = nullptr;
   for (int kk = 0; kk < nt; kk += G) {
+    // the first group's launches are the first to touch every tile
+    const bool first = has_src && kk == 0;
     for (int u = 0; u < G && kk + u < nt; ++u) {
-      if (u > 0) update(s, kk + u, 1, kk, kk + u);
-      diag_panel(kk + u);
+      if (u > 0) update(s, kk + u, 1, kk, kk + u, first);
+      diag_panel(kk + u, first && u == 0);
     }
     if (kk + G >= nt) break;
     if (pending) {
@@ -443,14 +447,14 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
     if (side && kk + 2 * G < nt) {
       hipEvent_t ready = side->ev[ring++ & 7];
       hipEventRecord(ready, s);
-      update(s, kk + G, G, kk, kk + G);  // the next group's columns
+      update(s, kk + G, G, kk, kk + G, first);  // the next group's columns
       hipStreamWaitEvent(side->stream, ready, 0);
-      update(side->stream, kk + 2 * G, 0, kk, kk + G);
+      update(side->stream, kk + 2 * G, 0, kk, kk + G, first);
       joined = side->ev[ring++ & 7];
       hipEventRecord(joined, side->stream);
       pending = true;
     } else {
-      update(s, kk + G, 0, kk, kk + G);
+      update(s, kk + G, 0, kk, kk + G, first);
     }
   }
   if (pending) hipStreamWaitEvent(s, joined, 0);

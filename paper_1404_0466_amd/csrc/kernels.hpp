@@ -63,15 +63,25 @@ hipError_t launch_gram(const double* X, int64_t ldx, const double* Y,
                        double* H, double* B, hipStream_t s);
 
 // ---- POTRF (k_potrf.hip)
-hipError_t launch_shift_copy(int64_t d, int nmat, const double* H, int nshift,
-                             const double* lam_dev, int lam_group, double* L,
-                             int* info, hipStream_t s);
+// Where the factorizations take their matrices: factor f is
+// H(f / nshift) + lam[((f / nshift) / lam_group) * nshift + f % nshift] I,
+// H tile-packed with identity padding.  The first launch that touches a
+// tile reads it from H (adding the shift on the diagonal) and writes L, so
+// no shifted copy of H is ever made.
+struct ShiftSrc {
+  const double* H;
+  int nshift;
+  const double* lam;  // device
+  int lam_group;
+};
 // lookahead: 1 runs the bulk of each trailing update on the library's side
 // stream (see k_potrf.hip), 0 keeps everything on s.  group: panels per
-// delayed trailing update (0: the library option).
-hipError_t launch_potrf_blocked(int64_t d, int nfac, double* L, int* info,
-                                double* linv_ws, int mixed, int lookahead,
-                                int group, hipStream_t s);
+// delayed trailing update (0: the library option).  info is written for
+// every factor (0, or the 1-based index of the first non-positive pivot).
+hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
+                                double* L, int* info, double* linv_ws,
+                                int mixed, int lookahead, int group,
+                                hipStream_t s);
 
 // ---- fit / evaluate (k_fit.hip)
 struct FitCoef {
