@@ -230,9 +230,9 @@ pichol_status pichol_eval(int64_t d, int32_t nmat, int32_t r,
                           void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Scratch bytes for pichol_solve_interp: the q scaled lambdas, the inverses
- * of every diagonal 128 x 128 block of every interpolated factor in two
- * layouts (2 * nmat * q * ceil(d/128) * 131072 bytes), and a second slab of
- * the same shape as Z (the forward solves leave their blocks there).
+ * of every diagonal 128 x 128 block of every interpolated factor
+ * (nmat * q * ceil(d/128) * 131072 bytes), and a second slab of the same
+ * shape as Z (the forward solves leave their blocks there).
  * Returns 0 when an argument is below 1. */
 size_t pichol_solve_interp_workspace(int64_t d, int32_t nmat, int32_t q,
                                      int32_t c);

@@ -194,7 +194,7 @@ struct Layout {
   size_t G, C, yy, H, B, region;  // byte offsets
   // interpolated region
   size_t i_lam, i_tau, i_L, i_linv, i_th, i_tht, i_Z, i_X, i_part, i_dinv,
-      i_dinvr, i_end;
+      i_end;
   // exact region
   size_t e_lam, e_L, e_linv, e_Z, e_part, e_end;
   // refinement scratch (full-tile H_f and the correction slab), appended to
@@ -234,7 +234,6 @@ static Layout layout_of(const pichol_problem* p) {
   L.i_X = a; a += align256(k * L.dp * L.ldz * dbl);
   L.i_part = a; a += align256(k * L.nt * HOLDOUT_KSPLIT * L.ldz * dbl);
   L.i_dinv = a; a += align256(k * q * L.nt * NB2 * dbl);
-  L.i_dinvr = a; a += align256(k * q * L.nt * NB2 * dbl);
   L.i_lamg = a; a += align256(q * dbl);
   const size_t rH = p->refine > 0 ? align256(k * L.dp * L.dp * dbl) : 0;
   const size_t rZ = p->refine > 0 ? align256(k * L.dp * L.ldz * dbl) : 0;
@@ -467,7 +466,7 @@ size_t pichol_lambda_workspace(int32_t nlam) {
   return nlam < 1 ? 0 : align256((size_t)nlam * sizeof(double));
 }
 
-// [scaled lambdas | inverses | transposed inverses | second slab]
+// [scaled lambdas | inverses | second slab]
 static size_t solve_inv_bytes(int64_t d, int32_t nmat, int32_t q) {
   return align256((size_t)nmat * q * ntiles_of(d) * NB2 * sizeof(double));
 }
@@ -475,7 +474,7 @@ static size_t solve_inv_bytes(int64_t d, int32_t nmat, int32_t q) {
 size_t pichol_solve_interp_workspace(int64_t d, int32_t nmat, int32_t q,
                                      int32_t c) {
   if (d < 1 || nmat < 1 || q < 1 || c < 1) return 0;
-  return pichol_lambda_workspace(q) + 2 * solve_inv_bytes(d, nmat, q) +
+  return pichol_lambda_workspace(q) + solve_inv_bytes(d, nmat, q) +
          align256((size_t)nmat * ntiles_of(d) * NB * pichol_slab_cols(q, c) *
                   sizeof(double));
 }
@@ -510,15 +509,13 @@ pichol_status pichol_solve_interp(int64_t d, int32_t nmat, int32_t c, int32_t r,
   const int64_t ldz = pichol_slab_cols(q, c);
   double* tau = at<double>(ws, 0);
   double* dinv = at<double>(ws, pichol_lambda_workspace(q));
-  double* dinv_r = at<double>(ws, pichol_lambda_workspace(q) +
-                                      solve_inv_bytes(d, nmat, q));
   double* X = at<double>(ws, pichol_lambda_workspace(q) +
-                                 2 * solve_inv_bytes(d, nmat, q));
+                                 solve_inv_bytes(d, nmat, q));
   hipError_t e = upload_tau(lam, q, lam_ref, 0, tau, stream);
   if (e == hipSuccess) e = launch_slab_init(d, nmat, q, c, ldz, B, Z, flags, stream);
   if (e == hipSuccess)
     e = launch_solve_interp(d, nmat, c, r + 1, theta, theta_t, q, tau, ldz, Z,
-                            X, flags, dinv, dinv_r, 1, stream);
+                            X, flags, dinv, 1, stream);
   return hip_status(e);
 }
 
@@ -670,8 +667,7 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
   if (e == hipSuccess)
     e = launch_solve_interp(p->d, k, c, M, th, tht, q, tau, L.ldz, Z,
                             at<double>(ws, L.i_X), flags,
-                            at<double>(ws, L.i_dinv), at<double>(ws, L.i_dinvr),
-                            1, stream);
+                            at<double>(ws, L.i_dinv), 1, stream);
   if (e == hipSuccess && p->refine > 0) {
     // Residual correction against H_f + lambda_t I; the correction solves
     // reuse the inverted diagonal blocks of the interpolated factors.
@@ -689,7 +685,7 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
         e = launch_solve_interp(p->d, k, c, M, th, tht, q, tau, L.ldz, D,
                                 at<double>(ws, L.i_X), flags,
                                 at<double>(ws, L.i_dinv),
-                                at<double>(ws, L.i_dinvr), 0, stream);
+                                0, stream);
       if (e == hipSuccess) e = launch_slab_add(p->d, k, L.ldz, D, Z, stream);
     }
   }
@@ -802,8 +798,7 @@ pichol_status pichol_cv_interp_grad(const pichol_problem* p,
     e = launch_solve_interp(p->d, k, c, M, at<double>(ws, L.i_th), th_t, q,
                             at<double>(ws, L.i_tau), L.ldz, Sg,
                             at<double>(ws, L.i_X), flags,
-                            at<double>(ws, L.i_dinv), at<double>(ws, L.i_dinvr),
-                            0, stream);
+                            at<double>(ws, L.i_dinv), 0, stream);
   double* a1 = at<double>(ws, L.i_ga1);
   double* b1 = at<double>(ws, L.i_gb1);
   double* a2 = at<double>(ws, L.i_ga2);

@@ -39,7 +39,7 @@ struct Bucket {
   int stream = 0;
   size_t base = 0;         // byte offset of the bucket's workspace region
   // region offsets, relative to base
-  size_t G, C, yy, H, Bm, lam, tau, L, linv, th, tht, Z, X, part, dinv, dinvr,
+  size_t G, C, yy, H, Bm, lam, tau, L, linv, th, tht, Z, X, part, dinv,
       info, flags, end;
 };
 
@@ -111,7 +111,6 @@ void layout_bucket(Bucket& b, int method) {
   b.X = o; o += interp ? align256(nmat * dp * ldz * dbl) : 0;
   b.part = o; o += align256(nmat * nt * HOLDOUT_KSPLIT * ldz * dbl);
   b.dinv = o; o += interp ? align256(nmat * q * nt * NB2 * dbl) : 0;
-  b.dinvr = o; o += interp ? align256(nmat * q * nt * NB2 * dbl) : 0;
   b.info = o; o += align256(nmat * nf * i32);
   b.flags = o; o += align256(nmat * q * i32);
   b.end = o;
@@ -224,8 +223,7 @@ hipError_t run_bucket(const Bucket& b, const pichol_batch_item* items,
     if (e == hipSuccess)
       e = launch_solve_interp(d, nmat, c, M, th, tht, q, tau, ldz, Z,
                               at<double>(base, b.X), flags,
-                              at<double>(base, b.dinv),
-                              at<double>(base, b.dinvr), 1, st);
+                              at<double>(base, b.dinv), 1, st);
   } else {
     if (e == hipSuccess)
       e = launch_solve_factors(d, nmat, q, c, L, ldz, Z, flags, st);

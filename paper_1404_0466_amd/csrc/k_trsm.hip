@@ -148,43 +148,144 @@ __global__ void __launch_bounds__(256) k_diag_solve(int64_t d, int i,
 }
 
 // Inverse of diagonal block i of the interpolated factor for lambda t of
-// fold m: the block is evaluated from the coefficient planes into LDS and
-// inverted there.  Written twice: column-major to dinv (forward solves) and
-// row-major to dinv_r (the transpose, for back solves).  A non-positive
-// diagonal entry sets flag bit1.
+// fold m, in registers.  Thread (ti, tk) = (tid % 16, tid / 16) evaluates
+// the entries (ti + 16a, tk + 16b), a >= b, of the block from the
+// coefficient planes (x) and builds the same entries of its inverse (y) by
+// forward substitution on the identity: row s of the inverse is final once
+// scaled by 1/L(s,s), and the rows below it then lose L(i,s) times it.
+// Columns of L go through LDS with zeros at rows <= s and rows of the
+// inverse with zeros right of the diagonal, so every thread updates whole
+// 16-entry blocks without masks; one barrier per row (column buffers rotate
+// over three slots, rows and reciprocals over two).
+template <int SB, bool LAST>
+__device__ __forceinline__ void inv_step(int ss, const double (&x)[8][8],
+                                         double (&y)[8][8], double* cbuf,
+                                         double* rbuf, double* pbuf, int ti,
+                                         int tk) {
+  constexpr int B1 = LAST ? SB + 1 : SB;  // block column of column s+1
+  constexpr bool NEXT = !(LAST && SB == 7);
+  const int s = 16 * SB + ss;
+  if (s > 0) {
+    // rows below s-1 lose L(i, s-1) X(s-1, :)
+    const double* cp = cbuf + ((s + 2) % 3) * NB;
+    const double* rp = rbuf + ((s + 1) & 1) * NB;
+    double pr[8], rr[8];
+#pragma unroll
+    for (int a = SB; a < 8; ++a) pr[a] = cp[ti + 16 * a];
+#pragma unroll
+    for (int b = 0; b <= SB; ++b) rr[b] = rp[tk + 16 * b];
+#pragma unroll
+    for (int a = SB; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b <= SB; ++b) y[a][b] -= pr[a] * rr[b];
+  }
+  if (ti == ss) {  // row s is final once scaled
+    const double is = pbuf[s & 1];
+    double* rb = rbuf + (s & 1) * NB;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      double o = 0.0;
+      if (b <= SB) {
+        y[SB][b] *= is;
+        o = y[SB][b];
+      }
+      rb[tk + 16 * b] = o;
+    }
+  }
+  const int sn = s + 1, sn16 = sn & 15;
+  if (NEXT && tk == sn16) {  // publish column s+1 and 1/L(s+1, s+1)
+    double* cn = cbuf + (sn % 3) * NB;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      double v = 0.0;
+      if (a > B1 || (a == B1 && ti > sn16)) v = x[a][B1];
+      cn[ti + 16 * a] = v;
+    }
+    if (ti == sn16) pbuf[sn & 1] = 1.0 / x[B1][B1];
+  }
+  __syncthreads();
+}
+
+template <int SB>
+__device__ __forceinline__ void inv_block(const double (&x)[8][8],
+                                          double (&y)[8][8], double* cbuf,
+                                          double* rbuf, double* pbuf, int ti,
+                                          int tk) {
+#pragma unroll 1
+  for (int ss = 0; ss < 15; ++ss)
+    inv_step<SB, false>(ss, x, y, cbuf, rbuf, pbuf, ti, tk);
+  inv_step<SB, true>(15, x, y, cbuf, rbuf, pbuf, ti, tk);
+}
+
+// Writes the inverse, column-major with zeros above the diagonal, to dinv.
+// A non-positive diagonal entry of the block sets flag bit1.
 __global__ void __launch_bounds__(256) k_diag_inv(int64_t d, FactorSrc src,
-                                                  double* dinv, double* dinv_r,
-                                                  int* flags) {
-  __shared__ double a[NB2];
-  __shared__ double rdiag[NB];
+                                                  double* dinv, int* flags) {
+  __shared__ double cbuf[3 * NB];
+  __shared__ double rbuf[2 * NB];
+  __shared__ double pbuf[2];
   const int i = blockIdx.x, t = blockIdx.y;
   const int64_t m = blockIdx.z;
   const int nt = gridDim.x;
-  const int tid = threadIdx.x;
-  tile_eval_to_lds(a, src.base + m * src.M * src.S + tile_off(i, i), src.S,
-                   src.M, src.tau[t], tid);
+  const int tid = threadIdx.x, ti = tid & 15, tk = tid >> 4;
+  const double* planes = src.base + m * src.M * src.S + tile_off(i, i);
+  const double tau = src.tau[t];
+  double x[8][8], y[8][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b <= a; ++b) {
+      x[a][b] = 0.0;
+      y[a][b] = (a == b && ti == tk) ? 1.0 : 0.0;
+    }
+  // sum_p tau^p Theta_p, p in increasing order (entries above the diagonal
+  // are never used: not read)
+  double pw = 1.0;
+  for (int p = 0; p < src.M; ++p) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b <= a; ++b)
+        if (a > b || ti >= tk)
+          x[a][b] += pw * planes[p * src.S + (tk + 16 * b) * NB + ti + 16 * a];
+    pw *= tau;
+  }
+  if (ti == tk) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if ((int64_t)i * NB + ti + 16 * a < d && !(x[a][a] > 0.0))
+        atomicOr(flags + m * src.nper + t, 2);
+  }
+  if (tk == 0) {  // column 0
+#pragma unroll
+    for (int a = 0; a < 8; ++a) cbuf[ti + 16 * a] = (a > 0 || ti > 0) ? x[a][0] : 0.0;
+    if (ti == 0) pbuf[0] = 1.0 / x[0][0];
+  }
   __syncthreads();
-  if (tid < NB) {
-    const double dg = a[tid * NB + tid];
-    if ((int64_t)i * NB + tid < d && !(dg > 0.0))
-      atomicOr(flags + m * src.nper + t, 2);
-    rdiag[tid] = 1.0 / dg;  // the leaves of the inverse multiply by these
-  }
-  invert_lower_lds(a, tid, rdiag);
-  const int64_t off = ((m * src.nper + t) * nt + i) * (int64_t)NB2;
-  tile_lower_from_lds(dinv + off, a, tid);
-#pragma unroll 8
-  for (int it = 0; it < 64; ++it) {
-    const int e = it * 256 + tid;
-    dinv_r[off + e] = a[(e & (NB - 1)) * NB + (e >> 7)];
-  }
+  inv_block<0>(x, y, cbuf, rbuf, pbuf, ti, tk);
+  inv_block<1>(x, y, cbuf, rbuf, pbuf, ti, tk);
+  inv_block<2>(x, y, cbuf, rbuf, pbuf, ti, tk);
+  inv_block<3>(x, y, cbuf, rbuf, pbuf, ti, tk);
+  inv_block<4>(x, y, cbuf, rbuf, pbuf, ti, tk);
+  inv_block<5>(x, y, cbuf, rbuf, pbuf, ti, tk);
+  inv_block<6>(x, y, cbuf, rbuf, pbuf, ti, tk);
+  inv_block<7>(x, y, cbuf, rbuf, pbuf, ti, tk);
+  double* out = dinv + ((m * src.nper + t) * nt + i) * (int64_t)NB2;
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      double v = 0.0;
+      if (a >= b) v = (a > b || ti >= tk) ? y[a][b] : 0.0;
+      out[(tk + 16 * b) * NB + ti + 16 * a] = v;
+    }
 }
 
 // Apply the stored inverse of diagonal block i to the slab rows of tile i,
 // out of place: dst rows of tile i = M (src rows of tile i), for the c
-// columns of lambda t of fold m, where M(r,k) = mat[k*128 + r] (the inverse
-// for forward steps, lower triangular; its transpose for back steps, upper
-// triangular).  Four workgroups per (fold, lambda) each own 32 rows of the
+// columns of lambda t of fold m.  The inverse is stored column-major
+// (entry (r,k) at k*128 + r); forward steps apply it (M lower triangular),
+// back steps its transpose (M(r,k) = mat[r*128 + k], upper triangular).  Four workgroups per (fold, lambda) each own 32 rows of the
 // result; only the triangle's nonzero columns k of those rows are read
 // (k < r0 + 32 forward, k >= r0 backward).  The 32 rows of M and the
 // 128-row block of right-hand sides sit in LDS; thread (row, pair) sums two
@@ -212,10 +313,21 @@ __global__ void __launch_bounds__(256) k_diag_apply(int64_t d, int i, int nper,
   const int64_t zoff = (m * dp + (int64_t)i * NB) * ldz + (int64_t)t * c;
   const double* zs_src = src + zoff;
   double* zd = dst + zoff;
-  // rows r0..r0+31 of M over the needed k: eight 32-byte pieces per k
-  for (int e = tid; e < (khi - klo) * 8; e += 256) {
-    const int k = klo + (e >> 3), part = e & 7;
-    *(v4d*)(ms + k * 32 + part * 4) = ld4(M + (int64_t)k * NB + r0 + part * 4);
+  if (FWD) {
+    // rows r0..r0+31 of M over the needed k: eight 32-byte pieces per k
+    for (int e = tid; e < (khi - klo) * 8; e += 256) {
+      const int k = klo + (e >> 3), part = e & 7;
+      *(v4d*)(ms + k * 32 + part * 4) = ld4(M + (int64_t)k * NB + r0 + part * 4);
+    }
+  } else {
+    // M(r0 + rr, k) = mat[(r0 + rr) * 128 + k]: 32-byte pieces along k,
+    // consecutive lanes on consecutive rows (conflict-free LDS stores)
+    for (int e = tid; e < (khi - klo) * 8; e += 256) {
+      const int rr = e & 31, k = klo + 4 * (e >> 5);
+      const v4d v = ld4(M + (int64_t)(r0 + rr) * NB + k);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ms[(k + u) * 32 + rr] = v[u];
+    }
   }
   for (int cg = 0; cg < c; cg += 16) {
     const int cn = (c - cg) < 16 ? (c - cg) : 16;
@@ -423,14 +535,14 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
                                const double* theta, const double* theta_t,
                                int q, const double* tau_dev, int64_t ldz,
                                double* Z, double* X, int* flags, double* dinv,
-                               double* dinv_r, int prepare, hipStream_t s) {
+                               int prepare, hipStream_t s) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
   const unsigned ncb = (unsigned)(ldz / NB);
   FactorSrc src{theta, S, M, 0, q, tau_dev};
   if (prepare)
     PICHOL_LAUNCH(k_diag_inv, dim3((unsigned)nt, (unsigned)q, (unsigned)nmat),
-                  dim3(256), 0, s, d, src, dinv, dinv_r, flags);
+                  dim3(256), 0, s, d, src, dinv, flags);
   const dim3 agrid((unsigned)(4 * q), (unsigned)nmat);
   for (int i = 0; i < nt; ++i) {
     PICHOL_LAUNCH(k_diag_apply<true>, agrid, dim3(256), 0, s, d, i, q, c, dinv,
@@ -444,7 +556,7 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
   }
   for (int i = nt - 1; i >= 0; --i) {
     PICHOL_LAUNCH(k_diag_apply<false>, agrid, dim3(256), 0, s, d, i, q, c,
-                  dinv_r, ldz, X, Z);
+                  dinv, ldz, X, Z);
     if (i > 0)
       PICHOL_LAUNCH(k_update_interp<false>, dim3(ncb * 2 * i * nmat), dim3(256),
                     0, s, d, i, theta, theta_t, S, M, q, c, tau_dev, ldz,

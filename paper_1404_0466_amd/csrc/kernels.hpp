@@ -110,7 +110,7 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int m,
                                const double* theta, const double* theta_t,
                                int q, const double* tau_dev, int64_t ldz,
                                double* Z, double* X, int* flags, double* dinv,
-                               double* dinv_r, int prepare, hipStream_t s);
+                               int prepare, hipStream_t s);
 hipError_t launch_solve_factors(int64_t d, int nmat, int nper, int c,
                                 const double* L, int64_t ldz, double* Z,
                                 int* flags, hipStream_t s);
