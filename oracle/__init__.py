@@ -81,6 +81,7 @@ def _load():
         "orc_holdout_sse": (_dbl, [_i64, _i64, _i64, _pd, _i64, _pd, _i64,
                                    _pd]),
         "orc_holdout_sst": (_dbl, [_i64, _i64, _pd, _i64]),
+        "orc_factor_nrmse": (_dbl, [_i64, _pd, _pd]),
         "orc_refine": (_i32, [_i64, _i64, _pd, _dbl, _pd, _pd, _pd, _i32]),
         "orc_eval_deriv": (None, [_i64, _i32, _pd, _dbl, _dbl, _pd, _i32]),
         "orc_cv_grad": (_i32, [_i64, _i64, _i64, _i32, _i32, _i32, _i32,
@@ -234,6 +235,31 @@ def holdout_sst(Yv) -> float:
         Yv = Yv[:, None].copy()
     nv, c = Yv.shape
     return float(_load().orc_holdout_sst(nv, c, _p(Yv), c))
+
+
+def factor_nrmse(Lhat, L) -> float:
+    """NRMSE of a fitted factor against the exact one (the paper's NRMSE
+    section): sqrt(sum (Lhat - L)^2) / sqrt(sum (L - mean L)^2) over the
+    entries i >= j of dense d x d lower factors."""
+    Lhat = _f64(Lhat)
+    L = _f64(L)
+    d = L.shape[0]
+    if Lhat.shape != (d, d) or L.shape != (d, d):
+        raise ValueError("factor_nrmse takes two d x d matrices")
+    return float(_load().orc_factor_nrmse(d, _p(Lhat), _p(L)))
+
+
+def cv_nrmse(Y, k: int, sse) -> np.ndarray:
+    """Hold-out NRMSE per (fold, lambda) from the summed squared residuals
+    sse (k x q): sqrt(sse / SST_f), SST_f the squared deviations of fold f's
+    labels from their column means.  Predicting every label by its fold's
+    column mean gives 1."""
+    Y = _f64(Y)
+    if Y.ndim == 1:
+        Y = Y[:, None].copy()
+    b = fold_bounds(Y.shape[0], k)
+    sst = np.array([holdout_sst(Y[b[f]:b[f + 1]]) for f in range(k)])
+    return np.sqrt(np.asarray(sse, dtype=np.float64) / sst[:, None])
 
 
 # ---------------------------------------------------------------- pipelines

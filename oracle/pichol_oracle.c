@@ -289,6 +289,32 @@ double orc_holdout_sst(int64_t nv, int64_t c, const double *Yv, int64_t ldy) {
   return sst;
 }
 
+/* Normalised root-mean-squared error of a fitted factor (the accuracy
+ * measure of the paper's NRMSE section): over the d(d+1)/2 entries with
+ * i >= j of dense row-major d x d lower factors,
+ *   sqrt(sum (Lhat - L)^2) / sqrt(sum (L - mean L)^2),
+ * the mean taken over those entries (two passes, rows then columns in
+ * increasing order).  Predicting every entry by the mean gives 1. */
+double orc_factor_nrmse(int64_t d, const double *Lhat, const double *L) {
+  double sum = 0.0;
+  int64_t cnt = 0;
+  for (int64_t i = 0; i < d; ++i)
+    for (int64_t j = 0; j <= i; ++j) {
+      sum += L[i * d + j];
+      ++cnt;
+    }
+  const double mean = sum / (double)cnt;
+  double sd = 0.0, ss = 0.0;
+  for (int64_t i = 0; i < d; ++i)
+    for (int64_t j = 0; j <= i; ++j) {
+      const double e = Lhat[i * d + j] - L[i * d + j];
+      const double v = L[i * d + j] - mean;
+      sd += e * e;
+      ss += v * v;
+    }
+  return sqrt(sd) / sqrt(ss);
+}
+
 /* One (fold, lambda) unit downstream of a factor: solve (then `refine`
  * steps of refinement against H + lam I), then hold-out. */
 static void unit_solve_holdout(int64_t d, int64_t c, const double *L,

@@ -99,6 +99,9 @@ double orc_holdout_sse(int64_t nv, int64_t d, int64_t c, const double *Xv,
 /* Sum over the c columns of the squared deviation of Y_v from its column
  * means (the denominator of the normalised RMSE). */
 double orc_holdout_sst(int64_t nv, int64_t c, const double *Yv, int64_t ldy);
+/* sqrt(sum (Lhat - L)^2) / sqrt(sum (L - mean L)^2) over the entries i >= j
+ * of dense row-major d x d lower factors (NRMSE section). */
+double orc_factor_nrmse(int64_t d, const double *Lhat, const double *L);
 
 /* Iterative refinement of the solution of (H + lam I) W = B (the classic
  * residual-correction method, e.g. Higham, "Accuracy and Stability of

@@ -277,6 +277,51 @@ def test_holdout_definition_and_gram_identity():
     np.testing.assert_allclose(sst, np.sum((Yv - Yv.mean(0)) ** 2), rtol=1e-13)
 
 
+def test_factor_nrmse_pins():
+    """NRMSE section: predicting every entry of the factor by its mean gives
+    exactly 1; an exact fit gives 0; the numerator is linear in the error
+    and entries above the diagonal are ignored."""
+    rng = np.random.default_rng(21)
+    d = 9
+    L = np.tril(rng.standard_normal((d, d)))
+    E = np.tril(rng.standard_normal((d, d)))
+    il = np.tril_indices(d)
+    assert oracle.factor_nrmse(L, L) == 0.0
+    mean = np.full((d, d), L[il].mean())
+    np.testing.assert_allclose(oracle.factor_nrmse(np.tril(mean), L), 1.0, rtol=1e-14)
+    base = oracle.factor_nrmse(L + E, L)
+    for delta in (0.5, -3.0, 1e-6):
+        np.testing.assert_allclose(oracle.factor_nrmse(L + delta * E, L),
+                                   abs(delta) * base, rtol=1e-9)
+    # a common affine map of the entries leaves the ratio unchanged
+    np.testing.assert_allclose(oracle.factor_nrmse(np.tril(2.5 * (L + E) - 7.0),
+                                                   np.tril(2.5 * L - 7.0)), base, rtol=1e-12)
+    junk = np.triu(rng.standard_normal((d, d)), 1)
+    assert oracle.factor_nrmse(L + E + junk, L - junk) == base
+
+
+def test_cv_nrmse_pins():
+    """Hold-out NRMSE: predicting each validation label by its fold's column
+    mean gives 1, an exact prediction gives 0."""
+    rng = np.random.default_rng(22)
+    n, d, c, k = 53, 4, 3, 5
+    X = rng.standard_normal((n, d))
+    X[:, 0] = 1.0
+    Y = np.sign(rng.standard_normal((n, c)))
+    b = oracle.fold_bounds(n, k)
+    sse = np.zeros((k, 2))
+    for f in range(k):
+        Xv, Yv = X[b[f]:b[f + 1]], Y[b[f]:b[f + 1]]
+        W = np.zeros((d, c))
+        W[0] = Yv.mean(0)              # the column means, through the ones column
+        sse[f, 0] = oracle.holdout_sse(Xv, Yv, W)
+        Wx = rng.standard_normal((d, c))
+        sse[f, 1] = oracle.holdout_sse(Xv, Xv @ Wx, Wx)   # labels fitted exactly
+    nr = oracle.cv_nrmse(Y, k, sse)
+    np.testing.assert_allclose(nr[:, 0], 1.0, rtol=1e-13)
+    np.testing.assert_allclose(nr[:, 1], 0.0, atol=1e-13)
+
+
 # ------------------------------------------------------------------ pipelines
 
 def _ridge_svd(Xt, Yt, lam, ntr):
