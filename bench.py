@@ -417,6 +417,63 @@ def differentiation_leg(args, B, stream):
     return out
 
 
+def accuracy_leg(args, B, prob, X, Y, stream):
+    """Interpolation accuracy on fold 0 of the headline workload (untimed):
+    the NRMSE of every interpolated factor at the q grid values against the
+    exact factor there (pichol_eval vs pichol_potrf_shifted_batched, then
+    pichol_factor_nrmse), the measure of the paper's NRMSE section."""
+    import torch
+    n, d, c, k, g, r, q = prob.n, prob.d, prob.c, prob.k, prob.g, prob.r, prob.q
+    dev = X.device
+    log("accuracy: fold-0 factors at every grid value")
+    f64 = dict(dtype=torch.float64, device=dev)
+    p = B.make_problem(n, d, c, k, g, r, q, True)
+    dp, S = B.pichol_padded_order(d), B.pichol_packed_elems(d)
+    G = torch.empty(k * dp * dp, **f64)
+    Cb, yy = torch.empty(k * dp * c, **f64), torch.empty(k, **f64)
+    H, Bf = torch.empty(k * S, **f64), torch.empty(k * dp * c, **f64)
+    B.pichol_gram(p, X, Y, G, Cb, yy, H, Bf)
+    del G, Cb, yy, Bf
+    H0 = H[:S]
+    Ls = torch.empty(g * S, **f64)
+    info = torch.empty(max(g, q), dtype=torch.int32, device=dev)
+    nb = B.pichol_potrf_workspace(1, max(g, q))
+    wsp = torch.empty(nb, dtype=torch.uint8, device=dev)
+    B.pichol_potrf_shifted_batched(d, 1, H0, g, prob.lam_s, Ls, info, wsp, nb)
+    th, tht = torch.empty((r + 1) * S, **f64), torch.empty((r + 1) * S, **f64)
+    B.pichol_fit(d, 1, g, r, prob.lam_s, prob.lam_ref, Ls, th, tht)
+    del Ls, tht
+    Lhat = torch.empty(q * S, **f64)
+    nbe = B.pichol_lambda_workspace(q)
+    B.pichol_eval(d, 1, r, th, q, prob.lam_grid, prob.lam_ref, Lhat,
+                  torch.empty(nbe, dtype=torch.uint8, device=dev), nbe)
+    Lex = torch.empty(q * S, **f64)
+    B.pichol_potrf_shifted_batched(d, 1, H0, q, prob.lam_grid, Lex, info, wsp, nb)
+    out = torch.empty(q, **f64)
+    nbn = B.pichol_factor_nrmse_workspace(d, q)
+    B.pichol_factor_nrmse(d, q, Lhat, Lex, out,
+                          torch.empty(nbn, dtype=torch.uint8, device=dev), nbn)
+    torch.cuda.synchronize()
+    nr = out.cpu().numpy()
+    ok = bool((info.cpu().numpy()[:q] == 0).all())
+    del Lhat, Lex, H, th
+    torch.cuda.empty_cache()
+    t = int(np.argmax(nr))
+    log(f"accuracy: factor NRMSE max {nr.max():.3e} at lambda/s={prob.lam_grid[t] / prob.scale:.3g}, "
+        f"median {np.median(nr):.3e}")
+    return {
+        "what": "NRMSE of the interpolated factor against the exact factor, "
+                "fold 0, every grid value (paper's NRMSE section)",
+        "factor_nrmse_max": float(nr.max()),
+        "factor_nrmse_median": float(np.median(nr)),
+        "factor_nrmse_at_samples_max": float(max(nr[int(np.argmin(np.abs(prob.lam_grid - ls)))]
+                                                 for ls in prob.lam_s)),
+        "lambda_over_s_at_max": float(prob.lam_grid[t] / prob.scale),
+        "exact_factors_ok": ok,
+        "paper_context": "max 0.0457 reported on MNIST (other data, other d)",
+    }
+
+
 def layout_leg(args, B, stream):
     """Table-1-style comparison of factor vectorisations (Sec. 5) on the GPU:
     for one fold with g = 4 sample factors, r = 2 and q = 31 grid values,
@@ -500,6 +557,8 @@ def main():
                          "refinement)")
     ap.add_argument("--no-layouts", action="store_true",
                     help="skip the vectorisation-layout comparison")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the fold-0 factor-accuracy diagnostic (NRMSE)")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the differentiation-form leg (d=2048 workload)")
     ap.add_argument("--no-batch", action="store_true",
@@ -606,6 +665,19 @@ def main():
             "speedup_vs_exact": t_ex / t_int, "exact_ok": ok_e,
             "err_gap": gaps(ei.mean(0), ee.mean(0), lam_grid),
         })
+        # the same curves as hold-out NRMSE (1 = predicting the fold's
+        # column means), computed on the GPU from the hold-out MSEs
+        nr_i = torch.empty(k * q, dtype=torch.float64, device=dev)
+        nr_e = torch.empty(k * q, dtype=torch.float64, device=dev)
+        B.pichol_holdout_nrmse(p, Y, err_i, nr_i)
+        B.pichol_holdout_nrmse(p, Y, err_e, nr_e)
+        torch.cuda.synchronize()
+        ni = nr_i.cpu().numpy().reshape(k, q).mean(0)
+        ne = nr_e.cpu().numpy().reshape(k, q).mean(0)
+        result_extra["holdout_nrmse"] = {
+            "min_interp": float(ni.min()), "min_exact": float(ne.min()),
+            "curve_gap_max_rel": float(np.max(np.abs(ni - ne) / ne)),
+        }
 
     variants = None
     if not args.no_variants:
@@ -642,6 +714,10 @@ def main():
     batching = None
     if not args.no_batch:
         batching = batching_leg(args, B, stream)
+
+    accuracy = None
+    if not args.no_accuracy:
+        accuracy = accuracy_leg(args, B, prob, X, Y, stream)
 
     layouts = None
     if not args.no_layouts:
@@ -718,6 +794,7 @@ def main():
         "batching_form": batching,
         "differentiation_form": differentiation,
         "layout_comparison": layouts,
+        "accuracy": accuracy,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

@@ -568,6 +568,35 @@ pichol_status pichol_set_option(int32_t option, int32_t value);
 /* Current value of an option, or -1 for an unknown option. */
 int32_t pichol_get_option(int32_t option);
 
+/* ---------------------------------------------------- accuracy diagnostics */
+
+/* Scratch bytes for pichol_factor_nrmse. */
+size_t pichol_factor_nrmse_workspace(int64_t d, int32_t nmat);
+
+/* Accuracy of fitted factors (the NRMSE section of Sec. 6): for each of
+ * nmat pairs of packed factors of order d,
+ *   out[m] = sqrt(sum (Lhat_m - L_m)^2) / sqrt(sum (L_m - mean L_m)^2)
+ * over the d(d+1)/2 entries with i >= j (padding excluded), mean over the
+ * same entries; predicting every entry by the mean gives 1.
+ * In:  Lhat, L nmat packed factors each (device), e.g. pichol_eval at some
+ *      lambdas and pichol_potrf_shifted_batched at the same lambdas.
+ * Out: out nmat doubles (device); inf/NaN when L is constant.
+ * ws: pichol_factor_nrmse_workspace(d, nmat) bytes.  Per-tile statistics
+ * are merged in a fixed order, so results are reproducible. */
+pichol_status pichol_factor_nrmse(int64_t d, int32_t nmat, const double *Lhat,
+                                  const double *L, double *out, void *ws,
+                                  size_t ws_bytes, hipStream_t stream);
+
+/* Hold-out NRMSE from the hold-out MSE of a cross-validation call:
+ *   nrmse[f*q + t] = sqrt(err[f*q + t] * n_v c / SST_f),
+ * SST_f the sum over fold f's rows and the c columns of (Y - the fold's
+ * column mean)^2, so predicting every label by that mean gives 1.
+ * In:  p (n, c, k, q, ldy are used), Y n x c (device, row-major, ldy);
+ *      err k x q (device).  Out: nrmse k x q (device). */
+pichol_status pichol_holdout_nrmse(const pichol_problem *p, const double *Y,
+                                   const double *err, double *nrmse,
+                                   hipStream_t stream);
+
 /* ------------------------------------------------------------- profiling */
 
 /* Per-kernel timing with HIP events, for benchmarks and tuning.  While

@@ -96,6 +96,9 @@ _SIGNATURES = {
     "pichol_fit": (_i32, [_i64, _i32, _i32, _i32, _vp, _dbl, _vp, _vp, _vp,
                           _vp]),
     "pichol_lambda_workspace": (_sz, [_i32]),
+    "pichol_factor_nrmse_workspace": (_sz, [_i64, _i32]),
+    "pichol_factor_nrmse": (_i32, [_i64, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "pichol_holdout_nrmse": (_i32, [_pprob, _vp, _vp, _vp, _vp]),
     "pichol_solve_interp_workspace": (_sz, [_i64, _i32, _i32, _i32]),
     "pichol_eval": (_i32, [_i64, _i32, _i32, _vp, _i32, _vp, _dbl, _vp, _vp,
                            _sz, _vp]),
@@ -288,6 +291,22 @@ def pichol_lambda_workspace(nlam: int) -> int:
 
 def pichol_solve_interp_workspace(d: int, nmat: int, q: int, c: int) -> int:
     return int(load().pichol_solve_interp_workspace(d, nmat, q, c))
+
+
+def pichol_factor_nrmse_workspace(d: int, nmat: int) -> int:
+    return int(load().pichol_factor_nrmse_workspace(d, nmat))
+
+
+def pichol_factor_nrmse(d, nmat, Lhat, L, out, ws, ws_bytes, stream=None):
+    _check("pichol_factor_nrmse", load().pichol_factor_nrmse(
+        d, nmat, _dev(Lhat, _f64()), _dev(L, _f64()), _dev(out, _f64()),
+        _dev(ws), ws_bytes, _stream(stream)))
+
+
+def pichol_holdout_nrmse(p: Problem, Y, err, nrmse, stream=None):
+    _check("pichol_holdout_nrmse", load().pichol_holdout_nrmse(
+        ctypes.byref(p), _dev(Y, _f64()), _dev(err, _f64()), _dev(nrmse, _f64()),
+        _stream(stream)))
 
 
 def pichol_eval(d, nmat, r, theta, nlam, lam, lam_ref, Lhat, ws, ws_bytes,

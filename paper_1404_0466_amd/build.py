@@ -21,7 +21,7 @@ ARCH = os.environ.get("PICHOL_ARCH", "gfx950")
 
 SOURCES = ["api.hip", "k_layout.hip", "k_gram.hip", "k_potrf.hip",
            "k_fit.hip", "k_trsm.hip", "k_holdout.hip", "k_refine.hip", "k_grad.hip",
-           "batch.hip"]
+           "k_nrmse.hip", "batch.hip"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -421,6 +421,31 @@ pichol_status pichol_gram(const pichol_problem* p, const double* X,
                                 H, B, stream));
 }
 
+size_t pichol_factor_nrmse_workspace(int64_t d, int32_t nmat) {
+  if (d < 1 || nmat < 1) return 0;
+  return align256((size_t)tri(ntiles_of(d)) * nmat * 4 * sizeof(double));
+}
+
+pichol_status pichol_factor_nrmse(int64_t d, int32_t nmat, const double* Lhat,
+                                  const double* L, double* out, void* ws,
+                                  size_t ws_bytes, hipStream_t stream) {
+  if (d < 1 || nmat < 1 || !Lhat || !L || !out) return PICHOL_ERR_ARG;
+  if (!ws || ws_bytes < pichol_factor_nrmse_workspace(d, nmat))
+    return PICHOL_ERR_WORKSPACE;
+  return hip_status(launch_factor_nrmse(d, nmat, Lhat, L, at<double>(ws, 0),
+                                        out, stream));
+}
+
+pichol_status pichol_holdout_nrmse(const pichol_problem* p, const double* Y,
+                                   const double* err, double* nrmse,
+                                   hipStream_t stream) {
+  if (!problem_ok(p) || !Y || !err || !nrmse) return PICHOL_ERR_ARG;
+  FoldSplit fs;
+  if (!fold_split(p->n, p->k, p->normalize, &fs)) return PICHOL_ERR_ARG;
+  return hip_status(launch_holdout_nrmse(fs, (int)p->c, p->q, Y, p->ldy, err,
+                                         nrmse, stream));
+}
+
 size_t pichol_potrf_workspace(int32_t nmat, int32_t nshift) {
   if (nmat < 1 || nshift < 1) return 0;
   return align256((size_t)nshift * sizeof(double)) +

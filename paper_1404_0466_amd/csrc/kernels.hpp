@@ -160,4 +160,14 @@ hipError_t launch_grad_dot(int64_t d, int nmat, int q, int c, int64_t ldz,
                            double* partial, double* dlog, int* flags,
                            hipStream_t s);
 
+// ---- accuracy diagnostics (k_nrmse.hip)
+// part: tri(ceil(d/128)) * nmat * 4 doubles.
+hipError_t launch_factor_nrmse(int64_t d, int nmat, const double* Lhat,
+                               const double* L, double* part, double* out,
+                               hipStream_t s);
+hipError_t launch_holdout_nrmse(const FoldSplit& fs, int c, int q,
+                                const double* Y, int64_t ldy,
+                                const double* err, double* nrmse,
+                                hipStream_t s);
+
 }  // namespace pichol
