@@ -445,68 +445,74 @@ k_update_interp(
 
 // Off-diagonal update for exact factors, one factor per lambda t:
 // forward rows of tile I > i lose L_t(I,i) U_i, backward rows of tile I < i
-// lose L_t(i,I)^T W_i.  One thread per row of tile I, all c columns; the
-// 128 x c right-hand-side rows sit in LDS.  Forward reads L(r,k) at
-// k*128 + r (coalesced across rows); backward reads column r of the tile,
-// contiguous per thread.  Small workgroups keep many tiles in flight: the
-// kernel streams every factor tile once per step.
+// lose L_t(i,I)^T W_i, on FP64 MFMA.  A workgroup of two waves takes one
+// (tile, lambda): each wave a 64-row half of the result and the lambda's c
+// columns in groups of 16 (v_mfma_f64_16x16x4 blocks; B lanes past c read
+// zeros).  Forward: one 32-byte load of four consecutive rows of L per lane
+// and k step feeds the four row blocks.  Backward: the transposed tile is
+// read along its columns, four consecutive k of one row per 32-byte load,
+// so a lane group supplies k = 4*lq + s in step s of each 16-long chunk and
+// the B lanes follow the same order.  The kernel streams every factor tile
+// once per step (HBM-bound).
 template <bool FWD>
 __global__ void __launch_bounds__(128) k_update_factors(int64_t d, int i,
                                                         const double* L,
                                                         int64_t S, int nper,
                                                         int c, int64_t ldz,
                                                         double* Z) {
-  __shared__ double zs[NB * 16];
   const int I = FWD ? i + 1 + (int)blockIdx.x : (int)blockIdx.x;
   const int t = blockIdx.y;
   const int64_t m = blockIdx.z;
-  const int row = threadIdx.x;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lq = l >> 4, lr = l & 15;
   const int64_t dp = ntiles_of(d) * NB;
   const double* tile = L + (m * nper + t) * S + (FWD ? tile_off(I, i) : tile_off(i, I));
   const double* zsrc = Z + (m * dp + (int64_t)i * NB) * ldz + (int64_t)t * c;
-  double* zdst = Z + (m * dp + (int64_t)I * NB + row) * ldz + (int64_t)t * c;
+  double* zdst = Z + (m * dp + (int64_t)I * NB + w * 64) * ldz + (int64_t)t * c;
   for (int cg = 0; cg < c; cg += 16) {
-    const int cn = (c - cg) < 16 ? (c - cg) : 16;
-    if (cg) __syncthreads();
-    {
-      double zv[16];
+    const bool cok = cg + lr < c;
+    v4d acc[4];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int e = row + NB * u, k = e >> 4, cc = e & 15;
-        zv[u] = cc < cn ? zsrc[(int64_t)k * ldz + cg + cc] : 0.0;
+    for (int bi = 0; bi < 4; ++bi) acc[bi] = v4d{0.0, 0.0, 0.0, 0.0};
+    if (FWD) {
+      // A(n, k) = L(I,i)(w*64 + n, k) at k*128 + w*64 + n
+      const double* pa = tile + (int64_t)lq * NB + w * 64 + 4 * lr;
+      const double* pb = zsrc + (int64_t)lq * ldz + cg + lr;
+#pragma unroll 4
+      for (int k0 = 0; k0 < NB; k0 += 4) {
+        const v4d av = ld4(pa + (int64_t)k0 * NB);
+        const double bv = cok ? pb[(int64_t)k0 * ldz] : 0.0;
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+          acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv, acc[bi], 0, 0, 0);
       }
+    } else {
+      // A(n, k) = L(i,I)(k, w*64 + n) at (w*64 + n)*128 + k
+#pragma unroll 2
+      for (int k0 = 0; k0 < NB; k0 += 16) {
+        v4d av[4];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) zs[row + NB * u] = zv[u];
-    }
-    __syncthreads();
-    double acc[16] = {};
-    // 32 entries of the lane's row of the tile are loaded together, so that
-    // many loads are in flight per thread (the kernel streams the tiles)
-#pragma unroll 1
-    for (int k0 = 0; k0 < NB; k0 += 32) {
-      double lv[32];
-      if (FWD) {
+        for (int bi = 0; bi < 4; ++bi)
+          av[bi] = ld4(tile + (int64_t)(w * 64 + 4 * lr + bi) * NB + k0 + 4 * lq);
+        double bv[4];
 #pragma unroll
-        for (int kk = 0; kk < 32; ++kk) lv[kk] = tile[(k0 + kk) * NB + row];
-      } else {
-        const double* colr = tile + row * NB + k0;
+        for (int sk = 0; sk < 4; ++sk)
+          bv[sk] = cok ? zsrc[(int64_t)(k0 + 4 * lq + sk) * ldz + cg + lr] : 0.0;
 #pragma unroll
-        for (int kk = 0; kk < 32; kk += 4) {
-          const v4d v = ld4(colr + kk);
-          lv[kk] = v[0];
-          lv[kk + 1] = v[1];
-          lv[kk + 2] = v[2];
-          lv[kk + 3] = v[3];
-        }
+        for (int sk = 0; sk < 4; ++sk)
+#pragma unroll
+          for (int bi = 0; bi < 4; ++bi)
+            acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi][sk], bv[sk], acc[bi], 0, 0, 0);
       }
-#pragma unroll
-      for (int kk = 0; kk < 32; ++kk)
-#pragma unroll
-        for (int u = 0; u < 16; ++u) acc[u] += lv[kk] * zs[(k0 + kk) * 16 + u];
     }
+    // element v of block bi: row 16v + 4lq + bi of the half, column lr
+    if (cok) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
-      if (u < cn) zdst[cg + u] -= acc[u];
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+          zdst[(int64_t)(16 * v + 4 * lq + bi) * ldz + cg + lr] -= acc[bi][v];
+    }
   }
 }
 
