@@ -24,7 +24,11 @@
  *                 matrix was not positive (LAPACK convention); the outputs
  *                 that depend on that factor are then NaN;
  *      flags[u] bit0 = a solution or hold-out error is not finite,
- *               bit1 = a diagonal entry of the (interpolated) factor is <= 0.
+ *               bit1 = a diagonal entry of an interpolated factor is <= 0
+ *                      (and, in pichol_solve_factors, of a given factor;
+ *                      the cross-validation calls report a failed exact
+ *                      factorization through info, and its NaN results
+ *                      through bit0).
  *  - Results are bitwise reproducible from run to run (no floating-point
  *    atomics; every reduction has a fixed order).
  *  - All arithmetic is IEEE FP64, except where a call is asked for

@@ -196,7 +196,7 @@ struct Layout {
   size_t i_lam, i_tau, i_L, i_linv, i_th, i_tht, i_Z, i_X, i_part, i_dinv,
       i_end;
   // exact region
-  size_t e_lam, e_L, e_linv, e_Z, e_part, e_end;
+  size_t e_lam, e_L, e_linv, e_Z, e_X, e_part, e_end;
   // refinement scratch (full-tile H_f and the correction slab), appended to
   // each method's region when refine > 0
   size_t i_rH, i_rZ, i_lamg, e_rH, e_rZ;
@@ -253,8 +253,9 @@ static Layout layout_of(const pichol_problem* p) {
   a = o;
   L.e_lam = a; a += align256(q * dbl);
   L.e_L = a; a += align256(k * q * L.S * dbl);
-  L.e_linv = a; a += align256(k * q * NB2 * dbl);
+  L.e_linv = a; a += align256(k * q * L.nt * NB2 * dbl);  // every diagonal tile
   L.e_Z = a; a += align256(k * L.dp * L.ldz * dbl);
+  L.e_X = a; a += align256(k * L.dp * L.ldz * dbl);
   L.e_part = a; a += align256(k * L.nt * HOLDOUT_KSPLIT * L.ldz * dbl);
   L.e_rH = a; a += rH;
   L.e_rZ = a; a += rZ;
@@ -471,7 +472,7 @@ pichol_status pichol_potrf_shifted_batched(int64_t d, int32_t nmat,
   if (e != hipSuccess) return hip_status(e);
   const ShiftSrc src{H, nshift, lam_dev, nmat};
   return hip_status(launch_potrf_blocked(d, nmat * nshift, src, L, info, linv,
-                                         precision == PICHOL_PREC_MIXED,
+                                         0, precision == PICHOL_PREC_MIXED,
                                          option_lookahead(), 0, stream));
 }
 
@@ -553,7 +554,8 @@ pichol_status pichol_solve_factors(int64_t d, int32_t nmat, int32_t nper,
   const int64_t ldz = pichol_slab_cols(nper, c);
   hipError_t e = launch_slab_init(d, nmat, nper, c, ldz, B, Z, flags, stream);
   if (e == hipSuccess)
-    e = launch_solve_factors(d, nmat, nper, c, L, ldz, Z, flags, stream);
+    e = launch_solve_factors(d, nmat, nper, c, L, ldz, Z, flags, nullptr,
+                             nullptr, stream);
   return hip_status(e);
 }
 
@@ -682,7 +684,7 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
   if (e == hipSuccess)
     e = launch_potrf_blocked(p->d, k * g,
                              ShiftSrc{at<double>(ws, L.H), g, lam_dev, k}, Lf,
-                             info, at<double>(ws, L.i_linv),
+                             info, at<double>(ws, L.i_linv), 0,
                              p->precision == PICHOL_PREC_MIXED,
                              option_lookahead(), 0, stream);
   if (e == hipSuccess) e = launch_fit(p->d, k, fc, Lf, th, tht, stream);
@@ -743,14 +745,16 @@ pichol_status pichol_cv_exact(const pichol_problem* p, const double* lam_grid,
   if (e == hipSuccess)
     e = launch_potrf_blocked(p->d, k * q,
                              ShiftSrc{at<double>(ws, L.H), q, lam_dev, k}, Lf,
-                             info, at<double>(ws, L.e_linv),
+                             info, at<double>(ws, L.e_linv), 1,
                              p->precision == PICHOL_PREC_MIXED,
                              option_lookahead(), 0, stream);
   if (e == hipSuccess)
     e = launch_slab_init(p->d, k, q, c, L.ldz, at<double>(ws, L.B), Z, flags,
                          stream);
   if (e == hipSuccess)
-    e = launch_solve_factors(p->d, k, q, c, Lf, L.ldz, Z, flags, stream);
+    e = launch_solve_factors(p->d, k, q, c, Lf, L.ldz, Z, flags,
+                             at<double>(ws, L.e_linv), at<double>(ws, L.e_X),
+                             stream);
   if (e == hipSuccess && p->refine > 0) {
     double* Hf = at<double>(ws, L.e_rH);
     double* D = at<double>(ws, L.e_rZ);
@@ -761,7 +765,9 @@ pichol_status pichol_cv_exact(const pichol_problem* p, const double* lam_grid,
       e = launch_residual(p->d, k, q, c, L.ldz, Hf, at<double>(ws, L.B),
                           lam_dev, Z, D, stream);
       if (e == hipSuccess)
-        e = launch_solve_factors(p->d, k, q, c, Lf, L.ldz, D, flags, stream);
+        e = launch_solve_factors(p->d, k, q, c, Lf, L.ldz, D, flags,
+                                 at<double>(ws, L.e_linv),
+                                 at<double>(ws, L.e_X), stream);
       if (e == hipSuccess) e = launch_slab_add(p->d, k, L.ldz, D, Z, stream);
     }
   }
@@ -870,7 +876,8 @@ pichol_status pichol_cv_exact_grad(const pichol_problem* p,
                         stream);
   if (e == hipSuccess)
     e = launch_solve_factors(p->d, k, q, c, at<double>(ws, L.e_L), L.ldz, Sg,
-                             flags, stream);
+                             flags, at<double>(ws, L.e_linv),
+                             at<double>(ws, L.e_X), stream);
   // dA/dlambda = I: <z, theta>
   if (e == hipSuccess)
     e = launch_grad_dot(p->d, k, q, c, L.ldz, Sg, Z, nullptr, nullptr,

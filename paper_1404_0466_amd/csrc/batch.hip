@@ -103,12 +103,14 @@ void layout_bucket(Bucket& b, int method) {
   b.lam = o; o += align256(nb * nf * dbl);
   b.tau = o; o += align256(q * dbl);
   b.L = o; o += align256(nmat * nf * S * dbl);
-  b.linv = o; o += align256(nmat * nf * NB2 * dbl);
+  // exact factors keep the inverse of every diagonal tile for the solves
+  b.linv = o;
+  o += align256(nmat * nf * (method == PICHOL_METHOD_INTERP ? 1 : nt) * NB2 * dbl);
   const bool interp = method == PICHOL_METHOD_INTERP;
   b.th = o; o += interp ? align256(nmat * M * S * dbl) : 0;
   b.tht = o; o += interp ? align256(nmat * M * S * dbl) : 0;
   b.Z = o; o += align256(nmat * dp * ldz * dbl);
-  b.X = o; o += interp ? align256(nmat * dp * ldz * dbl) : 0;
+  b.X = o; o += align256(nmat * dp * ldz * dbl);
   b.part = o; o += align256(nmat * nt * HOLDOUT_KSPLIT * ldz * dbl);
   b.dinv = o; o += interp ? align256(nmat * q * nt * NB2 * dbl) : 0;
   b.info = o; o += align256(nmat * nf * i32);
@@ -207,7 +209,7 @@ hipError_t run_bucket(const Bucket& b, const pichol_batch_item* items,
   if (e == hipSuccess) e = launch_store_doubles(lam_all.data(), nb * nf, lam, st);
   if (e == hipSuccess)
     e = launch_potrf_blocked(d, nmat * nf, ShiftSrc{H, nf, lam, k}, L, info,
-                             linv,
+                             linv, interp ? 0 : 1,
                              b.precision == PICHOL_PREC_MIXED, 0, group, st);
   if (e == hipSuccess)
     e = launch_slab_init(d, nmat, q, c, ldz, Bm, Z, flags, st);
@@ -226,7 +228,8 @@ hipError_t run_bucket(const Bucket& b, const pichol_batch_item* items,
                               at<double>(base, b.dinv), 1, st);
   } else {
     if (e == hipSuccess)
-      e = launch_solve_factors(d, nmat, q, c, L, ldz, Z, flags, st);
+      e = launch_solve_factors(d, nmat, q, c, L, ldz, Z, flags, linv,
+                               at<double>(base, b.X), st);
   }
   if (e == hipSuccess)
     e = launch_holdout_partial(d, nmat, c, q, ldz, Z, G, C, part, st);

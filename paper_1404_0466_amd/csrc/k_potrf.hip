@@ -138,7 +138,8 @@ __device__ __forceinline__ void diag_block(double (&x)[8][8], double (&y)[8][8],
 }
 
 // Writes the factor tile (zeros above the diagonal) in place and its inverse
-// (zeros above the diagonal) to linv; info[f] gets the global index + 1 of
+// (zeros above the diagonal) to linv + f * lstride + loff; info[f] gets the
+// global index + 1 of
 // the first non-positive pivot when it is the matrix's first failure.  With
 // SRC (first panel only) the tile comes from the source matrix plus its
 // shift, and info is written either way (0 when no pivot failed).
@@ -146,6 +147,8 @@ template <bool SRC>
 __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
                                                     int kk, double* L,
                                                     int* info, double* linv,
+                                                    int64_t lstride,
+                                                    int64_t loff,
                                                     ShiftSrc src) {
   __shared__ double cbuf[3 * NB];
   __shared__ double rbuf[2 * NB];
@@ -201,7 +204,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
   diag_block<5>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
   diag_block<6>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
   diag_block<7>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
-  double* li = linv + (int64_t)f * NB2;
+  double* li = linv + (int64_t)f * lstride + loff;
 #pragma unroll
   for (int a = 0; a < 8; ++a)
 #pragma unroll
@@ -231,13 +234,14 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
 // lower triangular, so the sum stops at the wave's last n.
 template <bool SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_potrf_panel(int64_t S, int kk, double* L, const double* linv, ShiftSrc src) {
+k_potrf_panel(int64_t S, int kk, double* L, const double* linv,
+              int64_t lstride, int64_t loff, ShiftSrc src) {
   const int f = blockIdx.y;
   const int I = kk + 1 + blockIdx.x;
   const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
   double* tile = L + (int64_t)f * S + tile_off(I, kk);
   const double* in = SRC ? src_tile(src, S, f, tile_off(I, kk)) : tile;
-  const double* li = linv + (int64_t)f * NB2;
+  const double* li = linv + (int64_t)f * lstride + loff;
   Acc64 acc;
   acc.zero();
   mma_panel(acc, li + wi * 64, NB, in + wj * 64, NB, wi * 64 + 64);
@@ -383,30 +387,34 @@ static SideStream* side_stream() {
 // trailing update, the first launch that touches the same tiles.
 hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
                                 double* L, int* info, double* linv_ws,
-                                int mixed, int lookahead, int group,
-                                hipStream_t s) {
+                                int keep_linv, int mixed, int lookahead,
+                                int group, hipStream_t s) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
+  // inverse of panel kk of factor f: at f * NB2 (scratch, overwritten by
+  // the next panel) or, kept for the solves, at (f * nt + kk) * NB2
+  const int64_t lstride = keep_linv ? (int64_t)nt * NB2 : NB2;
   const bool has_src = src.H != nullptr;
   std::unique_lock<std::mutex> lk(g_side_mu, std::defer_lock);
   if (lookahead) lk.lock();
   SideStream* side = lookahead ? side_stream() : nullptr;
   auto diag_panel = [&](int kk, bool first) {
+    const int64_t loff = keep_linv ? (int64_t)kk * NB2 : 0;
     if (first)
       PICHOL_LAUNCH(k_potrf_diag<true>, dim3((unsigned)nfac), dim3(256), 0, s,
-                    d, S, kk, L, info, linv_ws, src);
+                    d, S, kk, L, info, linv_ws, lstride, loff, src);
     else
       PICHOL_LAUNCH(k_potrf_diag<false>, dim3((unsigned)nfac), dim3(256), 0, s,
-                    d, S, kk, L, info, linv_ws, src);
+                    d, S, kk, L, info, linv_ws, lstride, loff, src);
     const int rest = nt - kk - 1;
     if (rest <= 0) return;
     const dim3 grid((unsigned)rest, (unsigned)nfac);
     if (first)
       PICHOL_LAUNCH(k_potrf_panel<true>, grid, dim3(256), 0, s, S, kk, L,
-                    linv_ws, src);
+                    linv_ws, lstride, loff, src);
     else
       PICHOL_LAUNCH(k_potrf_panel<false>, grid, dim3(256), 0, s, S, kk, L,
-                    linv_ws, src);
+                    linv_ws, lstride, loff, src);
   };
   auto update = [&](hipStream_t st, int j0, int mode, int c0, int c1,
                     bool first) {

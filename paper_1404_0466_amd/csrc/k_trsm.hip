@@ -459,6 +459,7 @@ __global__ void __launch_bounds__(128) k_update_factors(int64_t d, int i,
                                                         const double* L,
                                                         int64_t S, int nper,
                                                         int c, int64_t ldz,
+                                                        const double* Xs,
                                                         double* Z) {
   const int I = FWD ? i + 1 + (int)blockIdx.x : (int)blockIdx.x;
   const int t = blockIdx.y;
@@ -467,7 +468,8 @@ __global__ void __launch_bounds__(128) k_update_factors(int64_t d, int i,
   const int lq = l >> 4, lr = l & 15;
   const int64_t dp = ntiles_of(d) * NB;
   const double* tile = L + (m * nper + t) * S + (FWD ? tile_off(I, i) : tile_off(i, I));
-  const double* zsrc = Z + (m * dp + (int64_t)i * NB) * ldz + (int64_t)t * c;
+  // the solved block rows of tile i (in Xs) and the rows of tile I (in Z)
+  const double* zsrc = Xs + (m * dp + (int64_t)i * NB) * ldz + (int64_t)t * c;
   double* zdst = Z + (m * dp + (int64_t)I * NB + w * 64) * ldz + (int64_t)t * c;
   for (int cg = 0; cg < c; cg += 16) {
     const bool cok = cg + lr < c;
@@ -573,9 +575,32 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
 
 hipError_t launch_solve_factors(int64_t d, int nmat, int nper, int c,
                                 const double* L, int64_t ldz, double* Z,
-                                int* flags, hipStream_t s) {
+                                int* flags, const double* linv, double* X,
+                                hipStream_t s) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
+  if (linv && X) {
+    // as for interpolated factors: forward steps take the right-hand sides
+    // from Z and leave the solved blocks in X, back steps the reverse
+    const dim3 agrid((unsigned)(4 * nper), (unsigned)nmat);
+    for (int i = 0; i < nt; ++i) {
+      PICHOL_LAUNCH(k_diag_apply<true>, agrid, dim3(256), 0, s, d, i, nper, c,
+                    linv, ldz, Z, X);
+      if (i + 1 < nt)
+        PICHOL_LAUNCH(k_update_factors<true>,
+                      dim3((unsigned)(nt - i - 1), (unsigned)nper, (unsigned)nmat),
+                      dim3(128), 0, s, d, i, L, S, nper, c, ldz, X, Z);
+    }
+    for (int i = nt - 1; i >= 0; --i) {
+      PICHOL_LAUNCH(k_diag_apply<false>, agrid, dim3(256), 0, s, d, i, nper, c,
+                    linv, ldz, X, Z);
+      if (i > 0)
+        PICHOL_LAUNCH(k_update_factors<false>,
+                      dim3((unsigned)i, (unsigned)nper, (unsigned)nmat),
+                      dim3(128), 0, s, d, i, L, S, nper, c, ldz, Z, X);
+    }
+    return hipGetLastError();
+  }
   FactorSrc src{L, S, 1, 1, nper, nullptr};
   for (int i = 0; i < nt; ++i) {
     PICHOL_LAUNCH(k_diag_solve<true>, dim3((unsigned)nper, (unsigned)nmat),
@@ -583,7 +608,7 @@ hipError_t launch_solve_factors(int64_t d, int nmat, int nper, int c,
     if (i + 1 < nt)
       PICHOL_LAUNCH(k_update_factors<true>,
                     dim3((unsigned)(nt - i - 1), (unsigned)nper, (unsigned)nmat),
-                    dim3(128), 0, s, d, i, L, S, nper, c, ldz, Z);
+                    dim3(128), 0, s, d, i, L, S, nper, c, ldz, Z, Z);
   }
   for (int i = nt - 1; i >= 0; --i) {
     PICHOL_LAUNCH(k_diag_solve<false>, dim3((unsigned)nper, (unsigned)nmat),
@@ -591,7 +616,7 @@ hipError_t launch_solve_factors(int64_t d, int nmat, int nper, int c,
     if (i > 0)
       PICHOL_LAUNCH(k_update_factors<false>,
                     dim3((unsigned)i, (unsigned)nper, (unsigned)nmat),
-                    dim3(128), 0, s, d, i, L, S, nper, c, ldz, Z);
+                    dim3(128), 0, s, d, i, L, S, nper, c, ldz, Z, Z);
   }
   return hipGetLastError();
 }

@@ -78,10 +78,13 @@ struct ShiftSrc {
 // stream (see k_potrf.hip), 0 keeps everything on s.  group: panels per
 // delayed trailing update (0: the library option).  info is written for
 // every factor (0, or the 1-based index of the first non-positive pivot).
+// linv_ws: nfac * 16384 doubles of scratch, or with keep_linv
+// nfac * ceil(d/128) * 16384 doubles that keep the inverse of every
+// diagonal tile, (f * nt + I) * 16384 for tile I of factor f.
 hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
                                 double* L, int* info, double* linv_ws,
-                                int mixed, int lookahead, int group,
-                                hipStream_t s);
+                                int keep_linv, int mixed, int lookahead,
+                                int group, hipStream_t s);
 
 // ---- fit / evaluate (k_fit.hip)
 struct FitCoef {
@@ -111,9 +114,13 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int m,
                                int q, const double* tau_dev, int64_t ldz,
                                double* Z, double* X, int* flags, double* dinv,
                                int prepare, hipStream_t s);
+// With linv (the kept inverses of the factors' diagonal tiles, see
+// launch_potrf_blocked) and a second slab X, each diagonal step is a product
+// with a stored inverse; without them it is a substitution in place.
 hipError_t launch_solve_factors(int64_t d, int nmat, int nper, int c,
                                 const double* L, int64_t ldz, double* Z,
-                                int* flags, hipStream_t s);
+                                int* flags, const double* linv, double* X,
+                                hipStream_t s);
 
 // ---- hold-out (k_holdout.hip)
 struct HoldoutNorm {
