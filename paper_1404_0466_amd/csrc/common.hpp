@@ -241,143 +241,6 @@ __device__ inline double bcast_lane(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// One level of the recursive triangular inverse inside a 128 x 128 LDS
-// tile: for each pair of BS x BS diagonal blocks whose inverses are already
-// in place, replace the block below them, B, by -C^{-1} B A^{-1}.  All 256
-// threads take part; each computes a 4 x (BS/16) piece.
-template <int BS>
-__device__ inline void inv_combine(double* a, int tid) {
-  constexpr int CW = BS / 16, RB = BS / 4;
-  const int P = tid / (4 * BS), t = tid % (4 * BS);
-  const int i0 = 4 * (t % RB), j0 = CW * (t / RB);
-  const int o = 2 * BS * P;
-  double v[4][CW] = {};
-  // T = B A^{-1}: B at rows o+BS.., cols o..; A^{-1} lower at (o, o)
-  for (int p = j0; p < BS; ++p) {
-    const double* bc = a + (o + p) * NB + o + BS + i0;
-#pragma unroll
-    for (int c = 0; c < CW; ++c) {
-      const double ia = a[(o + j0 + c) * NB + o + p];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) v[u][c] += bc[u] * ia;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < CW; ++c)
-#pragma unroll
-    for (int u = 0; u < 4; ++u) a[(o + j0 + c) * NB + o + BS + i0 + u] = v[u][c];
-  __syncthreads();
-  // X = -C^{-1} T: C^{-1} lower at (o+BS, o+BS)
-  double x[4][CW] = {};
-  for (int p = 0; p <= i0 + 3; ++p) {
-    const double* cc = a + (o + BS + p) * NB + o + BS + i0;
-#pragma unroll
-    for (int c = 0; c < CW; ++c) {
-      const double tv = a[(o + j0 + c) * NB + o + BS + p];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (p <= i0 + u) x[u][c] -= cc[u] * tv;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < CW; ++c)
-#pragma unroll
-    for (int u = 0; u < 4; ++u) a[(o + j0 + c) * NB + o + BS + i0 + u] = x[u][c];
-  __syncthreads();
-}
-
-// In-place inverse of a lower-triangular 128 x 128 matrix held in LDS
-// (column-major, a[c*128 + r], strict upper part zero), by all 256 threads
-// of the workgroup: the eight 16 x 16 diagonal blocks are inverted by
-// half-wavefronts (lane = column, forward substitution in registers), then
-// pairs of blocks are combined at sizes 16, 32 and 64.  On return the lower
-// triangle holds the inverse and the strict upper part is still zero.
-// Ends with a barrier.
-__device__ inline void invert_lower_lds(double* a, int tid,
-                                        const double* rdiag = nullptr) {
-  __syncthreads();
-  {
-    const int lane = tid & 63, w = tid >> 6;
-    const int leaf = 2 * w + ((lane >> 4) & 1);
-    const int o = 16 * leaf, j = lane & 15;
-    double x[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) x[i] = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-    for (int p = 0; p < 16; ++p) {
-      const double* col = a + (o + p) * NB + o;
-      x[p] = rdiag ? x[p] * rdiag[o + p] : x[p] / col[p];
-#pragma unroll
-      for (int i = p + 1; i < 16; ++i) x[i] -= col[i] * x[p];
-    }
-    __syncthreads();
-    if (lane < 32) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) a[(o + j) * NB + o + i] = x[i];
-    }
-  }
-  __syncthreads();
-  inv_combine<16>(a, tid);
-  inv_combine<32>(a, tid);
-  inv_combine<64>(a, tid);
-}
-
-// Whole-tile transfers by a 256-thread workgroup.  A tile is 16384 doubles
-// (32-byte aligned); each thread moves sixteen 32-byte pieces, with eight
-// global loads in flight at a time so that their latencies overlap.
-__device__ inline void tile_to_lds(double* lds, const double* g, int tid) {
-#pragma unroll
-  for (int it = 0; it < 16; it += 8) {
-    v4d v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = ld4(g + ((it + u) * 256 + tid) * 4);
-#pragma unroll
-    for (int u = 0; u < 8; ++u) *(v4d*)(lds + ((it + u) * 256 + tid) * 4) = v[u];
-  }
-}
-
-// Writes the lower triangle of a column-major LDS tile (zeros above the
-// diagonal) to global memory.
-__device__ inline void tile_lower_from_lds(double* g, const double* lds,
-                                           int tid) {
-#pragma unroll
-  for (int it = 0; it < 16; ++it) {
-    const int e = (it * 256 + tid) * 4;
-    const int r = e & (NB - 1), c = e >> 7;
-    v4d v = *(const v4d*)(lds + e);
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (r + u < c) v[u] = 0.0;
-    st4(g + e, v);
-  }
-}
-
-// Evaluates sum_p w^p planes[p*S + e] for a whole tile into LDS (Horner-free
-// power sum in p order), eight 32-byte pieces per plane in flight.
-__device__ inline void tile_eval_to_lds(double* lds, const double* planes,
-                                        int64_t S, int M, double w, int tid) {
-#pragma unroll
-  for (int it = 0; it < 16; it += 8) {
-    v4d acc[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
-    double pw = 1.0;
-    for (int p = 0; p < M; ++p) {
-      v4d v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        v[u] = ld4(planes + p * S + ((it + u) * 256 + tid) * 4);
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] += pw * v[u];
-      pw *= w;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) *(v4d*)(lds + ((it + u) * 256 + tid) * 4) = acc[u];
-  }
-}
-
 // Lane coordinates inside a 64 x 64 wave block.
 struct LaneXY {
   int lq;  // l / 16
