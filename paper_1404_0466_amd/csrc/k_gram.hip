@@ -77,43 +77,86 @@ __global__ void __launch_bounds__(256) k_gram_tiles(const double* X,
     }
 }
 
-// C_b = X_b^T Y_b (dp x c, row-major, padding rows 0).  A workgroup takes
-// 64 rows i of C_b; its four wavefronts sum over interleaved quarters of the
-// block's rows (row r0 + 4u + w), then the quarters are added in a fixed
-// order.
+// C_b = X_b^T Y_b (dp x c, row-major, padding rows 0) on FP64 MFMA.  A
+// workgroup takes 64 rows i of C_b (64 columns of X) and 16 columns of Y at
+// a time; its four wavefronts sum over consecutive quarters of the block's
+// rows, then the quarters are added in a fixed order through LDS.  A lane
+// loads four consecutive columns of one row of X (32 bytes) per k step,
+// feeding the four 16-row blocks; B lanes past c read zeros.  Eight k steps
+// are issued together so that the stream of X keeps many loads in flight.
 __global__ void __launch_bounds__(256) k_gram_rhs(const double* X, int64_t ldx,
                                                   const double* Y, int64_t ldy,
                                                   int64_t d, int64_t c,
                                                   int64_t dp, FoldSplit fs,
-                                                  double* C) {
-  __shared__ double part[4][64][17];
+                                                  int vec_ok, double* C) {
+  __shared__ v4d part[3][4][64];
   const int b = blockIdx.y;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lq = l >> 4, lr = l & 15;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
   const int64_t r0 = fs.start[b], r1 = fs.start[b + 1];
-  double* crow = C + ((int64_t)b * dp + i) * c;
-  for (int64_t c0 = 0; c0 < c; c0 += 16) {
-    const int cn = (int)((c - c0) < 16 ? (c - c0) : 16);
-    double acc[16] = {};
-    if (i < d) {
-#pragma unroll 4
-      for (int64_t r = r0 + w; r < r1; r += 4) {
-        const double x = X[r * ldx + i];
-        const double* y = Y + r * ldy + c0;
+  const int64_t nq = ((r1 - r0 + 3) / 4 + 3) / 4 * 4;  // rows per quarter
+  const int64_t q0 = r0 + w * nq;
+  const int64_t q1 = (q0 + nq < r1) ? q0 + nq : r1;
+  const int64_t col = i0 + 4 * lr;
+  const bool fast = vec_ok && i0 + 64 <= d;
+  for (int64_t cg = 0; cg < c; cg += 16) {
+    const bool cok = cg + lr < c;
+    v4d acc[4];
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (j < cn) acc[j] += x * y[j];
+    for (int bi = 0; bi < 4; ++bi) acc[bi] = v4d{0.0, 0.0, 0.0, 0.0};
+    int64_t r = q0;
+    if (fast) {
+      for (; r + 32 <= q1; r += 32) {
+        v4d av[8];
+        double bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int64_t rr = r + 4 * u + lq;
+          av[u] = ld4(X + rr * ldx + col);
+          bv[u] = cok ? Y[rr * ldy + cg + lr] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int bi = 0; bi < 4; ++bi)
+            acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][bi], bv[u], acc[bi], 0, 0, 0);
       }
     }
+    // remaining rows of the quarter (all rows when not vectorizable)
+    for (; r < q1; r += 4) {
+      const int64_t rr = r + lq;
+      const bool ok = rr < q1;
+      v4d av = {0.0, 0.0, 0.0, 0.0};
+      if (ok) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) part[w][lane][j] = acc[j];
-    __syncthreads();
-    if (w == 0 && i < dp) {
-      for (int j = 0; j < cn; ++j)
-        crow[c0 + j] = ((part[0][lane][j] + part[1][lane][j]) + part[2][lane][j]) +
-                       part[3][lane][j];
+        for (int e = 0; e < 4; ++e)
+          if (col + e < d) av[e] = X[rr * ldx + col + e];
+      }
+      const double bv = (ok && cok) ? Y[rr * ldy + cg + lr] : 0.0;
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+        acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv, acc[bi], 0, 0, 0);
+    }
+    if (cg) __syncthreads();  // the previous group's partial sums were read
+    if (w > 0) {
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi) part[w - 1][bi][l] = acc[bi];
     }
     __syncthreads();
+    if (w == 0 && cok) {
+      // element v of block bi: row 16v + 4lq + bi of the 64, column lr
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi) {
+        const v4d s1 = part[0][bi][l], s2 = part[1][bi][l], s3 = part[2][bi][l];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t i = i0 + 16 * v + 4 * lq + bi;
+          C[((int64_t)b * dp + i) * c + cg + lr] =
+              ((acc[bi][v] + s1[v]) + s2[v]) + s3[v];
+        }
+      }
+    }
   }
 }
 
@@ -192,7 +235,7 @@ hipError_t launch_gram(const double* X, int64_t ldx, const double* Y,
   PICHOL_LAUNCH(k_gram_tiles, dim3((unsigned)tri(nt), (unsigned)fs.k),
                      dim3(256), 0, s, X, ldx, d, nt, fs, G, vec_ok);
   PICHOL_LAUNCH(k_gram_rhs, dim3((unsigned)(dp / 64), (unsigned)fs.k),
-                     dim3(256), 0, s, X, ldx, Y, ldy, d, c, dp, fs, C);
+                     dim3(256), 0, s, X, ldx, Y, ldy, d, c, dp, fs, vec_ok, C);
   PICHOL_LAUNCH(k_gram_yy, dim3((unsigned)fs.k), dim3(256), 0, s, Y, ldy,
                      c, fs, yy);
   PICHOL_LAUNCH(k_gram_combine_h, dim3((unsigned)tri(nt), (unsigned)fs.k),
