@@ -84,12 +84,18 @@ __global__ void __launch_bounds__(256) k_gram_tiles(const double* X,
 // loads four consecutive columns of one row of X (32 bytes) per k step,
 // feeding the four 16-row blocks; B lanes past c read zeros.  Eight k steps
 // are issued together so that the stream of X keeps many loads in flight.
+// The workgroups of the first 64 rows also return yy[b], the sum of squares
+// of Y over the block (each element of Y_b is loaded once by one lane; the
+// lanes' sums are added in a fixed tree).
 __global__ void __launch_bounds__(256) k_gram_rhs(const double* X, int64_t ldx,
                                                   const double* Y, int64_t ldy,
                                                   int64_t d, int64_t c,
                                                   int64_t dp, FoldSplit fs,
-                                                  int vec_ok, double* C) {
+                                                  int vec_ok, double* C,
+                                                  double* yy) {
   __shared__ v4d part[3][4][64];
+  __shared__ double red[256];
+  double ysq = 0.0;
   const int b = blockIdx.y;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int lq = l >> 4, lr = l & 15;
@@ -117,6 +123,8 @@ __global__ void __launch_bounds__(256) k_gram_rhs(const double* X, int64_t ldx,
           bv[u] = cok ? Y[rr * ldy + cg + lr] : 0.0;
         }
 #pragma unroll
+        for (int u = 0; u < 8; ++u) ysq += bv[u] * bv[u];
+#pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
           for (int bi = 0; bi < 4; ++bi)
@@ -134,6 +142,7 @@ __global__ void __launch_bounds__(256) k_gram_rhs(const double* X, int64_t ldx,
           if (col + e < d) av[e] = X[rr * ldx + col + e];
       }
       const double bv = (ok && cok) ? Y[rr * ldy + cg + lr] : 0.0;
+      ysq += bv * bv;
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi)
         acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv, acc[bi], 0, 0, 0);
@@ -158,32 +167,18 @@ __global__ void __launch_bounds__(256) k_gram_rhs(const double* X, int64_t ldx,
       }
     }
   }
-}
-
-// yy[b] = sum of squares of Y over block b; fixed-order tree reduction.
-__global__ void __launch_bounds__(256) k_gram_yy(const double* Y, int64_t ldy,
-                                                 int64_t c, FoldSplit fs,
-                                                 double* yy) {
-  __shared__ double red[256];
-  const int b = blockIdx.x;
-  const int64_t r0 = fs.start[b], r1 = fs.start[b + 1];
-  const int64_t n = (r1 - r0) * c;
-  double acc = 0.0;
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
-    const double y = Y[(r0 + e / c) * ldy + e % c];
-    acc += y * y;
-  }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+  if (blockIdx.x == 0) {
+    const int tid = threadIdx.x;
+    red[tid] = ysq;
     __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (tid < h) red[tid] += red[tid + h];
+      __syncthreads();
+    }
+    if (tid == 0) yy[b] = red[0];
   }
-  if (threadIdx.x == 0) yy[b] = red[0];
 }
 
-// H_f (packed) = scale_f * sum_{b != f} G_b over the lower tiles, identity
-// padding.
 __global__ void __launch_bounds__(256) k_gram_combine_h(int64_t d, int64_t nt,
                                                         FoldSplit fs,
                                                         const double* G,
@@ -235,9 +230,8 @@ hipError_t launch_gram(const double* X, int64_t ldx, const double* Y,
   PICHOL_LAUNCH(k_gram_tiles, dim3((unsigned)tri(nt), (unsigned)fs.k),
                      dim3(256), 0, s, X, ldx, d, nt, fs, G, vec_ok);
   PICHOL_LAUNCH(k_gram_rhs, dim3((unsigned)(dp / 64), (unsigned)fs.k),
-                     dim3(256), 0, s, X, ldx, Y, ldy, d, c, dp, fs, vec_ok, C);
-  PICHOL_LAUNCH(k_gram_yy, dim3((unsigned)fs.k), dim3(256), 0, s, Y, ldy,
-                     c, fs, yy);
+                     dim3(256), 0, s, X, ldx, Y, ldy, d, c, dp, fs, vec_ok, C,
+                     yy);
   PICHOL_LAUNCH(k_gram_combine_h, dim3((unsigned)tri(nt), (unsigned)fs.k),
                      dim3(256), 0, s, d, nt, fs, G, H, S);
   const int64_t nb = dp * c;
