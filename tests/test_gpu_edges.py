@@ -1,6 +1,7 @@
 """Edge cases of the pipeline calls against the oracle: unnormalised Gram
 matrices (the paper's X^T X), strided X rows (ldx > d), two folds and many
-folds, a single right-hand side and a single grid value, order-1 problems,
+folds, a single right-hand side and a single grid value, more than 16
+right-hand sides, order-1 problems,
 interpolation through every sample (r = g - 1) and the smallest batch."""
 import numpy as np
 import pytest
@@ -51,6 +52,21 @@ def test_single_rhs_single_lambda(gu):
         want = (oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r) if method == "interp"
                 else oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid))
         _check(got, want)
+
+
+@pytest.mark.parametrize("c", [17, 40])
+def test_many_right_hand_sides(gu, c):
+    """More than 16 label columns: the Gram right-hand sides, the diagonal
+    applies and the exact-factor updates loop over 16-column groups; the
+    interpolated update covers several 128-column slab blocks per lambda."""
+    p = workloads.gaussian_problem(700, 200, c, seed=50 + c, g=4, q=7)
+    for method in ["interp", "exact"]:
+        got = gu.cv(p, method)
+        want = (oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r, want_W=True)
+                if method == "interp" else
+                oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid, want_W=True))
+        _check(got, want)
+        np.testing.assert_allclose(got["W"], want["W"], rtol=1e-8, atol=1e-12)
 
 
 def test_order_one_problem(gu):
