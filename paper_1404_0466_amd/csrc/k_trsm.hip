@@ -4,17 +4,21 @@
 // The right-hand sides of one fold live in a row-major slab Z (dp x ldz);
 // columns t*c .. t*c+c-1 belong to lambda index t.  Forward substitution
 // walks the tile rows i = 0..nt-1: solve the diagonal block of every
-// lambda (k_diag_solve), then subtract the contribution of the solved rows
-// from every later tile row (update kernels).  Back substitution walks the
-// tile rows in reverse with the transposed blocks.
+// lambda, then subtract the contribution of the solved rows from every
+// later tile row (update kernels).  Back substitution walks the tile rows
+// in reverse with the transposed blocks.
 //
-// Interpolated factors (Sec. 3.3) are never materialised.  Their diagonal
-// blocks are evaluated and inverted once, up front, all in parallel
-// (k_diag_inv), so each sequential step applies a stored inverse; the
-// off-diagonal update of all lambdas is one FP64 MFMA product:
+// The diagonal steps multiply by stored inverses of the diagonal blocks
+// (k_diag_apply), out of place between Z and a second slab X, so several
+// workgroups can share one (fold, lambda).  Interpolated factors (Sec. 3.3)
+// are never materialised: their diagonal blocks are evaluated and inverted
+// once, up front, all in parallel (k_diag_inv), and the off-diagonal update
+// of all lambdas is one FP64 MFMA product
 // Lhat_t(I,i) U_t = sum_p Theta_p(I,i) (tau_t^p U_t), so each coefficient
-// tile is read once per step for all q values.
-// Exact factors (the per-lambda baseline) use one factor per lambda.
+// tile is read once per step for all q values.  Exact factors (the
+// per-lambda baseline) use one factor per lambda and the inverses their
+// factorization kept; factors given without inverses are solved in place by
+// substitution (k_diag_solve).
 #include "common.hpp"
 #include "kernels.hpp"
 
