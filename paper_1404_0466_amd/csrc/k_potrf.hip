@@ -61,7 +61,7 @@ __device__ __forceinline__ void diag_step(int jj, double (&x)[8][8],
   double v[8];
   double inv = 0.0, piv = 0.0;
   const int jn = j + 1, jn16 = jn & 15;
-  if (NEXT) {
+  if constexpr (NEXT) {
 #pragma unroll
     for (int a = NB1; a < 8; ++a) x[a][NB1] -= cr[a] * cc[NB1];
     // pivot L(j+1, j+1)^2 sits with thread (jn16, jn16)
@@ -449,23 +449,35 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
     }
     if (kk + G >= nt) break;
     if (pending) {
-      hipStreamWaitEvent(s, joined, 0);
       pending = false;
+      const hipError_t e = hipStreamWaitEvent(s, joined, 0);
+      if (e != hipSuccess) return e;
     }
     if (side && kk + 2 * G < nt) {
       hipEvent_t ready = side->ev[ring++ & 7];
-      hipEventRecord(ready, s);
+      hipError_t e = hipEventRecord(ready, s);
+      if (e != hipSuccess) return e;
       update(s, kk + G, G, kk, kk + G, first);  // the next group's columns
-      hipStreamWaitEvent(side->stream, ready, 0);
+      e = hipStreamWaitEvent(side->stream, ready, 0);
+      if (e != hipSuccess) return e;
       update(side->stream, kk + 2 * G, 0, kk, kk + G, first);
       joined = side->ev[ring++ & 7];
-      hipEventRecord(joined, side->stream);
+      e = hipEventRecord(joined, side->stream);
+      if (e != hipSuccess) {
+        // the side work is enqueued; make the caller's stream wait for all
+        // of the side stream's work before reporting
+        (void)hipStreamSynchronize(side->stream);
+        return e;
+      }
       pending = true;
     } else {
       update(s, kk + G, 0, kk, kk + G, first);
     }
   }
-  if (pending) hipStreamWaitEvent(s, joined, 0);
+  if (pending) {
+    const hipError_t e = hipStreamWaitEvent(s, joined, 0);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ hipError_t record_hip_error_code(hipError_t e);
 int option_lookahead();
 int option_panel_group();
 inline int record_hip_error(hipError_t e) {
-  record_hip_error_code(e);
+  (void)record_hip_error_code(e);
   return -3;  // PICHOL_ERR_HIP
 }
 
