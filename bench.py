@@ -417,6 +417,62 @@ def differentiation_leg(args, B, stream):
     return out
 
 
+def potrf_flops(d: int) -> float:
+    """Flops of one Cholesky factorization of order d, the usual count
+    d^3/3 + d^2/2 + d/6 (multiplies and adds; the d square roots are not
+    counted)."""
+    return d ** 3 / 3.0 + d ** 2 / 2.0 + d / 6.0
+
+
+def factorization_leg(args, B, prob, X, Y, stream):
+    """The whole blocked factorization stage alone (every kernel of it:
+    diagonal tiles, panels, column and trailing updates), timed with events
+    around pichol_potrf_shifted_batched at both of the workload's shapes:
+    k*g sample factorizations (the interpolated method) and k*q grid
+    factorizations (the exact method), against the FP64 MFMA peak."""
+    import torch
+    n, d, c, k, g, r, q = prob.n, prob.d, prob.c, prob.k, prob.g, prob.r, prob.q
+    dev = X.device
+    f64 = dict(dtype=torch.float64, device=dev)
+    p = B.make_problem(n, d, c, k, g, r, q, True)
+    dp, S = B.pichol_padded_order(d), B.pichol_packed_elems(d)
+    G = torch.empty(k * dp * dp, **f64)
+    Cb, yy = torch.empty(k * dp * c, **f64), torch.empty(k, **f64)
+    H, Bf = torch.empty(k * S, **f64), torch.empty(k * dp * c, **f64)
+    B.pichol_gram(p, X, Y, G, Cb, yy, H, Bf)
+    del G, Cb, yy, Bf
+    L = torch.empty(k * q * S, **f64)
+    info = torch.empty(k * q, dtype=torch.int32, device=dev)
+    nb = B.pichol_potrf_workspace(k, q)
+    wsp = torch.empty(nb, dtype=torch.uint8, device=dev)
+    out = {"what": "pichol_potrf_shifted_batched alone, all of its kernels, "
+                   "event-timed; flops d^3/3 + d^2/2 + d/6 per factor",
+           "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
+    for name, ns, lam in (("sample_factors", g, prob.lam_s),
+                          ("grid_factors", q, prob.lam_grid)):
+        def run():
+            B.pichol_potrf_shifted_batched(d, k, H, ns, lam, L, info, wsp, nb)
+        run()
+        torch.cuda.synchronize()
+        reps = 3
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        ok = bool((info.cpu().numpy()[:k * ns] == 0).all())
+        tf = k * ns * potrf_flops(d) / (ms * 1e-3) / 1e12
+        out[name] = {"factors": k * ns, "ms": ms, "achieved": tf,
+                     "frac": tf / PEAK_FP64_TFLOPS, "info_ok": ok}
+        log(f"factorization: {k * ns} factors of order {d} in {ms:.2f} ms, "
+            f"{tf:.2f} TFLOP/s ({100 * tf / PEAK_FP64_TFLOPS:.1f}% of FP64 peak)")
+    del L, H, wsp
+    torch.cuda.empty_cache()
+    return out
+
+
 def accuracy_leg(args, B, prob, X, Y, stream):
     """Interpolation accuracy on fold 0 of the headline workload (untimed):
     the NRMSE of every interpolated factor at the q grid values against the
@@ -557,6 +613,8 @@ def main():
                          "refinement)")
     ap.add_argument("--no-layouts", action="store_true",
                     help="skip the vectorisation-layout comparison")
+    ap.add_argument("--no-factorization", action="store_true",
+                    help="skip the stand-alone factorization timing")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the fold-0 factor-accuracy diagnostic (NRMSE)")
     ap.add_argument("--no-grad", action="store_true",
@@ -715,6 +773,10 @@ def main():
     if not args.no_batch:
         batching = batching_leg(args, B, stream)
 
+    factorization = None
+    if not args.no_factorization:
+        factorization = factorization_leg(args, B, prob, X, Y, stream)
+
     accuracy = None
     if not args.no_accuracy:
         accuracy = accuracy_leg(args, B, prob, X, Y, stream)
@@ -795,6 +857,7 @@ def main():
         "differentiation_form": differentiation,
         "layout_comparison": layouts,
         "accuracy": accuracy,
+        "factorization": factorization,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

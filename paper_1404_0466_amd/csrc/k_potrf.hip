@@ -3,15 +3,20 @@
 //
 // Blocked right-looking algorithm on 128-wide panels over the tile-packed
 // layout.  For panel kk of every matrix in the batch:
-//   1. k_potrf_diag   factors the diagonal tile in registers and writes the
-//                     inverse of the factor to a scratch tile;
+//   1. the diagonal tile is factored in registers and the inverse of its
+//      factor written to a scratch tile (diag_factor_tile);
 //   2. k_potrf_panel  forms the tiles below it as A_{I,kk} L_kk^{-T}
 //                     (an FP64 MFMA product with the inverse);
-//   3. k_potrf_update subtracts L_{I,kk} L_{J,kk}^T from every trailing tile
+//   3. k_potrf_update subtracts L_{I,kk} L_{J,kk}^T from the trailing tiles
 //                     (FP64 MFMA, the bulk of the flops).
+// Step 1 runs as its own launch (k_potrf_diag) for the first panel and on
+// the mixed-precision path; otherwise the update launch that gives the
+// diagonal tile its last update goes on to factor it, in the workgroups
+// that updated it.
 // One launch of each kernel covers the whole batch, so a batch of B
 // matrices of order d fills the GPU with B * (trailing tiles) workgroups.
 #include <mutex>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -137,28 +142,23 @@ __device__ __forceinline__ void diag_block(double (&x)[8][8], double (&y)[8][8],
   diag_step<JB, true>(15, x, y, prv, cbuf, rbuf, pbuf, fail, ti, tk);
 }
 
-// Writes the factor tile (zeros above the diagonal) in place and its inverse
-// (zeros above the diagonal) to linv + f * lstride + loff; info[f] gets the
-// global index + 1 of
-// the first non-positive pivot when it is the matrix's first failure.  With
-// SRC (first panel only) the tile comes from the source matrix plus its
-// shift, and info is written either way (0 when no pivot failed).
+// Factors one diagonal tile with the whole 256-thread workgroup.  Writes the
+// factor (zeros above the diagonal) to `tile` and its inverse (zeros above
+// the diagonal) to `li`; the tile's current lower triangle is read from `in`
+// (the tile itself, or with SRC the source matrix, plus `shift` on the
+// diagonal).  *info_f gets the global index + 1 of the first non-positive
+// pivot when it is the matrix's first failure; with SRC (the first panel) it
+// is written either way (0 when no pivot failed).
 template <bool SRC>
-__global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
-                                                    int kk, double* L,
-                                                    int* info, double* linv,
-                                                    int64_t lstride,
-                                                    int64_t loff,
-                                                    ShiftSrc src) {
+__device__ __forceinline__ void diag_factor_tile(int64_t d, int kk,
+                                                 double* tile, const double* in,
+                                                 double shift, int* info_f,
+                                                 double* li) {
   __shared__ double cbuf[3 * NB];
   __shared__ double rbuf[2 * NB];
   __shared__ double pbuf[2];
   __shared__ int fail;
-  const int f = blockIdx.x;
   const int tid = threadIdx.x, ti = tid & 15, tk = tid >> 4;
-  double* tile = L + (int64_t)f * S + tile_off(kk, kk);
-  const double* in = SRC ? src_tile(src, S, f, tile_off(kk, kk)) : tile;
-  const double shift = SRC ? src_shift(src, f) : 0.0;
   double x[8][8], y[8][8], prv[8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
@@ -204,7 +204,6 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
   diag_block<5>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
   diag_block<6>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
   diag_block<7>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
-  double* li = linv + (int64_t)f * lstride + loff;
 #pragma unroll
   for (int a = 0; a < 8; ++a)
 #pragma unroll
@@ -222,10 +221,28 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
   if (tid == 0) {
     const bool bad = fail < NB && (int64_t)kk * NB + fail < d;
     if (SRC)
-      info[f] = bad ? kk * NB + fail + 1 : 0;
-    else if (bad && info[f] == 0)
-      info[f] = kk * NB + fail + 1;
+      *info_f = bad ? kk * NB + fail + 1 : 0;
+    else if (bad && *info_f == 0)
+      *info_f = kk * NB + fail + 1;
   }
+}
+
+// Diagonal tile kk of every matrix of the batch (one workgroup each): the
+// factor in place, its inverse at linv + f * lstride + loff.  With SRC (first
+// panel only) the tile comes from the source matrix plus its shift.
+template <bool SRC>
+__global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
+                                                    int kk, double* L,
+                                                    int* info, double* linv,
+                                                    int64_t lstride,
+                                                    int64_t loff,
+                                                    ShiftSrc src) {
+  const int f = blockIdx.x;
+  double* tile = L + (int64_t)f * S + tile_off(kk, kk);
+  const double* in = SRC ? src_tile(src, S, f, tile_off(kk, kk)) : tile;
+  const double shift = SRC ? src_shift(src, f) : 0.0;
+  diag_factor_tile<SRC>(d, kk, tile, in, shift, info + f,
+                        linv + (int64_t)f * lstride + loff);
 }
 
 // Panel tile (I, kk), I > kk: X = A L_kk^{-T}, in place (with SRC, A is
@@ -266,6 +283,16 @@ __device__ inline void mma_any(Acc64F& acc, const double* a, int64_t lda,
   mma_panel_f32(acc, a, lda, b, ldb, K);
 }
 
+// Where a fused diagonal factorization writes: the inverse of tile j0 of
+// factor f goes to linv + f * lstride + loff, a failed pivot to info[f].
+struct DiagOut {
+  int* info;
+  double* linv;
+  int64_t lstride;
+  int64_t loff;
+  int fuse;  // 1: the launch also factors diagonal tile (j0, j0)
+};
+
 // Trailing tile (I,J): A_IJ -= sum_{c in [c0,c1)} L_Ic L_Jc^T, for the
 // tiles of the triangle j0 <= J <= I (mode 0) or of the `mode` whole
 // columns J = j0 .. j0+mode-1 (mode > 0).
@@ -275,13 +302,35 @@ __device__ inline void mma_any(Acc64F& acc, const double* a, int64_t lda,
 // read-modify-write epilogue overlaps the other's products.  Logical
 // workgroup ids are laid out matrix by matrix and spread over the XCDs in
 // contiguous ranges.
+// In both modes tile (j0, j0) receives its last update in this launch.  With
+// dout.fuse (FP64 only) the first nfac workgroups take those tiles, one per
+// matrix, and after the update go on to factor it (diag_factor_tile), so
+// the diagonal factorization runs while the rest of the launch is still
+// updating; the other workgroups take the remaining tiles.
 template <typename ACC, bool SRC>
 __device__ inline void potrf_update_body(int64_t S, int nt, int j0, int mode,
                                          int c0, int c1, int ntile, double* L,
-                                         int64_t d, const ShiftSrc& src) {
-  const int id = xcd_remap(blockIdx.x, gridDim.x);
-  const int f = id / ntile;
-  const int t = id - f * ntile;
+                                         int64_t d, const ShiftSrc& src,
+                                         const DiagOut& dout) {
+  constexpr bool kFusable = std::is_same<ACC, Acc64>::value;
+  const bool fuse = kFusable && dout.fuse;
+  int f, t;
+  if (fuse) {
+    const int nfac = (int)gridDim.x / ntile;
+    if ((int)blockIdx.x < nfac) {
+      f = blockIdx.x;
+      t = 0;
+    } else {
+      const int rest = ntile - 1;  // >= 1 here: the grid holds more tiles
+      const int id = xcd_remap((int)blockIdx.x - nfac, (int)gridDim.x - nfac);
+      f = id / rest;
+      t = 1 + (id - f * rest);
+    }
+  } else {
+    const int id = xcd_remap(blockIdx.x, gridDim.x);
+    f = id / ntile;
+    t = id - f * ntile;
+  }
   int I, J;
   if (mode == 0) {
     const int r = tri_row(t);
@@ -298,57 +347,71 @@ __device__ inline void potrf_update_body(int64_t S, int nt, int j0, int mode,
     J = J0;
   }
   const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
-  if (I == J && wi > wj) return;  // block strictly above the diagonal
   double* Lf = L + (int64_t)f * S;
   double* ct = Lf + tile_off(I, J);
-  // the tile's current value: L itself, or (first touch) the source matrix
-  const double* cs = SRC ? src_tile(src, S, f, tile_off(I, J)) : ct;
-  const LaneXY lx;
-  const int m0 = wj * 64 + lx.col0();
-  ACC acc;
-  acc.zero();
-  for (int c = c0; c < c1; ++c)
-    mma_any(acc, Lf + tile_off(J, c) + wi * 64, NB,
-            Lf + tile_off(I, c) + wj * 64, NB, NB);
-  const double shift = (SRC && I == J) ? src_shift(src, f) : 0.0;
+  if (!(I == J && wi > wj)) {  // that block lies strictly above the diagonal
+    // the tile's current value: L itself, or (first touch) the source matrix
+    const double* cs = SRC ? src_tile(src, S, f, tile_off(I, J)) : ct;
+    const LaneXY lx;
+    const int m0 = wj * 64 + lx.col0();
+    ACC acc;
+    acc.zero();
+    for (int c = c0; c < c1; ++c)
+      mma_any(acc, Lf + tile_off(J, c) + wi * 64, NB,
+              Lf + tile_off(I, c) + wj * 64, NB, NB);
+    const double shift = (SRC && I == J) ? src_shift(src, f) : 0.0;
 #pragma unroll
-  for (int v = 0; v < 4; ++v)
+    for (int v = 0; v < 4; ++v)
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
-      const int n = wi * 64 + ACC::row_of(lx.lq, v, bi);
-      double* p = ct + n * NB + m0;
-      const double* q = cs + n * NB + m0;
-      const v4d val = acc.row(v, bi);
-      if (I != J || wi != wj) {
-        st4(p, ld4(q) - val);
-      } else {
+      for (int bi = 0; bi < 4; ++bi) {
+        const int n = wi * 64 + ACC::row_of(lx.lq, v, bi);
+        double* p = ct + n * NB + m0;
+        const double* q = cs + n * NB + m0;
+        const v4d val = acc.row(v, bi);
+        if (I != J || wi != wj) {
+          st4(p, ld4(q) - val);
+        } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (m0 + e >= n) {
-            double cv = q[e];
-            if (SRC && m0 + e == n && (int64_t)I * NB + n < d) cv += shift;
-            p[e] = cv - val[e];
-          }
+          for (int e = 0; e < 4; ++e)
+            if (m0 + e >= n) {
+              double cv = q[e];
+              if (SRC && m0 + e == n && (int64_t)I * NB + n < d) cv += shift;
+              p[e] = cv - val[e];
+            }
+        }
       }
+  }
+  if constexpr (kFusable) {
+    if (fuse && t == 0) {
+      // the tile's lower triangle, just stored by three of the four waves,
+      // is read back by the whole workgroup once the barrier has passed
+      __syncthreads();
+      diag_factor_tile<false>(d, j0, ct, ct, 0.0, dout.info + f,
+                              dout.linv + (int64_t)f * dout.lstride + dout.loff);
     }
+  }
 }
 
 template <bool SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_potrf_update(int64_t S, int nt, int j0, int mode, int c0, int c1, int ntile,
-               double* L, int64_t d, ShiftSrc src) {
-  potrf_update_body<Acc64, SRC>(S, nt, j0, mode, c0, c1, ntile, L, d, src);
+               double* L, int64_t d, ShiftSrc src, DiagOut dout) {
+  potrf_update_body<Acc64, SRC>(S, nt, j0, mode, c0, c1, ntile, L, d, src,
+                                dout);
 }
 
 // Mixed precision: the same update with the products on FP32 MFMA (operands
 // rounded to FP32, FP32 accumulation over the 256-long sums); the tile
 // itself stays FP64.  FP32 accumulators take half the registers, so four
-// workgroups share a CU (measured faster than two at d = 4096).
+// workgroups share a CU (measured faster than two at d = 4096); that budget
+// leaves no room for the diagonal factorization, which runs in its own
+// launches on this path.
 template <bool SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_potrf_update_f32(int64_t S, int nt, int j0, int mode, int c0, int c1,
                    int ntile, double* L, int64_t d, ShiftSrc src) {
-  potrf_update_body<Acc64F, SRC>(S, nt, j0, mode, c0, c1, ntile, L, d, src);
+  potrf_update_body<Acc64F, SRC>(S, nt, j0, mode, c0, c1, ntile, L, d, src,
+                                 DiagOut{nullptr, nullptr, 0, 0, 0});
 }
 
 // Side stream for look-ahead: created once per device on first use, with
@@ -379,7 +442,8 @@ static SideStream* side_stream() {
 // Panels in groups of G with a delayed update: before its diagonal
 // factorization, column kk+u receives the group's earlier panels (K = 128 u);
 // after the group, one update of rank 128 G reaches the rest of the trailing
-// matrix.  With the look-ahead option on, that update is split: the G
+// matrix.  On the FP64 path each of these launches also factors the
+// diagonal tile it completes (tile kk+u, or the next group's first).  With the look-ahead option on, that update is split: the G
 // columns the next group factors stay on the caller's stream, the remainder
 // runs on a side stream, so the next group's diagonal factorizations, panel
 // solves and column updates (short, latency-bound launches) overlap the bulk
@@ -398,12 +462,16 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
   std::unique_lock<std::mutex> lk(g_side_mu, std::defer_lock);
   if (lookahead) lk.lock();
   SideStream* side = lookahead ? side_stream() : nullptr;
-  auto diag_panel = [&](int kk, bool first) {
+  // Every diagonal tile but the first is factored by the update launch that
+  // completes it (FP64 path): the column update inside a group, or the
+  // trailing update after it.  The mixed path launches k_potrf_diag itself.
+  const bool fuse = !mixed;
+  auto diag_panel = [&](int kk, bool first, bool factored) {
     const int64_t loff = keep_linv ? (int64_t)kk * NB2 : 0;
-    if (first)
+    if (!factored && first)
       PICHOL_LAUNCH(k_potrf_diag<true>, dim3((unsigned)nfac), dim3(256), 0, s,
                     d, S, kk, L, info, linv_ws, lstride, loff, src);
-    else
+    else if (!factored)
       PICHOL_LAUNCH(k_potrf_diag<false>, dim3((unsigned)nfac), dim3(256), 0, s,
                     d, S, kk, L, info, linv_ws, lstride, loff, src);
     const int rest = nt - kk - 1;
@@ -416,13 +484,16 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
       PICHOL_LAUNCH(k_potrf_panel<false>, grid, dim3(256), 0, s, S, kk, L,
                     linv_ws, lstride, loff, src);
   };
+  // fd: this launch also factors diagonal tile (j0, j0)
   auto update = [&](hipStream_t st, int j0, int mode, int c0, int c1,
-                    bool first) {
+                    bool first, bool fd) {
     const int rest = nt - j0;
     if (rest <= 0) return;
     const int m = mode == 0 ? 0 : (mode < rest ? mode : rest);
     const int ntile = m == 0 ? (int)tri(rest) : m * rest - m * (m - 1) / 2;
     const dim3 grid((unsigned)(ntile * nfac));
+    const DiagOut dout{info, linv_ws, lstride,
+                       keep_linv ? (int64_t)j0 * NB2 : 0, fd ? 1 : 0};
     if (mixed && first)
       PICHOL_LAUNCH(k_potrf_update_f32<true>, grid, dim3(256), 0, st, S, nt,
                     j0, m, c0, c1, ntile, L, d, src);
@@ -431,10 +502,10 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
                     j0, m, c0, c1, ntile, L, d, src);
     else if (first)
       PICHOL_LAUNCH(k_potrf_update<true>, grid, dim3(256), 0, st, S, nt, j0, m,
-                    c0, c1, ntile, L, d, src);
+                    c0, c1, ntile, L, d, src, dout);
     else
       PICHOL_LAUNCH(k_potrf_update<false>, grid, dim3(256), 0, st, S, nt, j0,
-                    m, c0, c1, ntile, L, d, src);
+                    m, c0, c1, ntile, L, d, src, dout);
   };
   const int G = group > 0 ? group : option_panel_group();
   int ring = 0;
@@ -444,8 +515,9 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
     // the first group's launches are the first to touch every tile
     const bool first = has_src && kk == 0;
     for (int u = 0; u < G && kk + u < nt; ++u) {
-      if (u > 0) update(s, kk + u, 1, kk, kk + u, first);
-      diag_panel(kk + u, first && u == 0);
+      if (u > 0) update(s, kk + u, 1, kk, kk + u, first, fuse);
+      // tile kk (u = 0) was factored by the previous group's trailing update
+      diag_panel(kk + u, first && u == 0, fuse && (u > 0 || kk > 0));
     }
     if (kk + G >= nt) break;
     if (pending) {
@@ -457,10 +529,10 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
       hipEvent_t ready = side->ev[ring++ & 7];
       hipError_t e = hipEventRecord(ready, s);
       if (e != hipSuccess) return e;
-      update(s, kk + G, G, kk, kk + G, first);  // the next group's columns
+      update(s, kk + G, G, kk, kk + G, first, fuse);  // the next group's columns
       e = hipStreamWaitEvent(side->stream, ready, 0);
       if (e != hipSuccess) return e;
-      update(side->stream, kk + 2 * G, 0, kk, kk + G, first);
+      update(side->stream, kk + 2 * G, 0, kk, kk + G, first, false);
       joined = side->ev[ring++ & 7];
       e = hipEventRecord(joined, side->stream);
       if (e != hipSuccess) {
@@ -471,7 +543,7 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
       }
       pending = true;
     } else {
-      update(s, kk + G, 0, kk, kk + G, first);
+      update(s, kk + G, 0, kk, kk + G, first, fuse);
     }
   }
   if (pending) {
