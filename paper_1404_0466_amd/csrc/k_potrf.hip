@@ -245,32 +245,90 @@ __global__ void __launch_bounds__(256) k_potrf_diag(int64_t d, int64_t S,
                         linv + (int64_t)f * lstride + loff);
 }
 
+// Products of the panel kernel for k in [kb, ke): the wave's 16-row blocks
+// j = J0..3 of Linv (rows no[j] .. no[j]+15), each against the wave's
+// 64 columns of A^T.  Lane l supplies Linv(no[j] + l%16, k + l/16) and
+// A^T(k + l/16, 4(l%16) + bj), so element v of c[j][bj] is
+// D'(no[j] + 4v + l/16, 4(l%16) + bj).
+template <int J0>
+__device__ __forceinline__ void panel_seg(v4d (&c)[4][4], const double* pa,
+                                          const int (&no)[4], const double* pb,
+                                          int kb, int ke) {
+  // operands of the next k step are loaded before this step's products
+  v4d bv = ld4(pb + (int64_t)kb * NB);
+  double av[4];
+#pragma unroll
+  for (int j = J0; j < 4; ++j) av[j] = pa[(int64_t)kb * NB + no[j]];
+  for (int k0 = kb + 4; k0 <= ke; k0 += 4) {
+    v4d bn = bv;
+    double an[4];
+    if (k0 < ke) {
+      bn = ld4(pb + (int64_t)k0 * NB);
+#pragma unroll
+      for (int j = J0; j < 4; ++j) an[j] = pa[(int64_t)k0 * NB + no[j]];
+    }
+#pragma unroll
+    for (int j = J0; j < 4; ++j)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj)
+        c[j][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[bj], c[j][bj],
+                                                        0, 0, 0);
+    bv = bn;
+#pragma unroll
+    for (int j = J0; j < 4; ++j) av[j] = an[j];
+  }
+}
+
 // Panel tile (I, kk), I > kk: X = A L_kk^{-T}, in place (with SRC, A is
-// read from the source matrix).  The wave computes
+// read from the source matrix).  The waves compute
 // D'(n,m) = sum_p Linv(n,p) A(m,p) = X(m,n), stored at n*128 + m.  Linv is
-// lower triangular, so the sum stops at the wave's last n.
+// lower triangular, so rows n of the 16-row block b need p < 16(b+1) only.
+// Wave w takes the columns m of half w & 1 and four row blocks chosen so
+// that both wave pairs do the same work: blocks 0, 1, 6, 7 or 2, 3, 4, 5
+// (288 of the 128 k values summed per block column either way, against 512
+// for the last 64 rows taken together).  Each block's sum runs only over
+// its nonzero k, in segments where the set of active blocks is fixed.
 template <bool SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_potrf_panel(int64_t S, int kk, double* L, const double* linv,
               int64_t lstride, int64_t loff, ShiftSrc src) {
   const int f = blockIdx.y;
   const int I = kk + 1 + blockIdx.x;
-  const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
+  const int w = threadIdx.x >> 6, wp = w >> 1, wj = w & 1;
+  const int l = threadIdx.x & 63, lq = l >> 4, lr = l & 15;
   double* tile = L + (int64_t)f * S + tile_off(I, kk);
   const double* in = SRC ? src_tile(src, S, f, tile_off(I, kk)) : tile;
   const double* li = linv + (int64_t)f * lstride + loff;
-  Acc64 acc;
-  acc.zero();
-  mma_panel(acc, li + wi * 64, NB, in + wj * 64, NB, wi * 64 + 64);
+  const double* pa = li + (int64_t)lq * NB + lr;
+  const double* pb = in + (int64_t)lq * NB + wj * 64 + 4 * lr;
+  v4d c[4][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) c[j][bj] = v4d{0.0, 0.0, 0.0, 0.0};
+  int no[4];
+  if (wp == 0) {
+    no[0] = 0; no[1] = 16; no[2] = 96; no[3] = 112;
+    panel_seg<0>(c, pa, no, pb, 0, 16);
+    panel_seg<1>(c, pa, no, pb, 16, 32);
+    panel_seg<2>(c, pa, no, pb, 32, 112);
+    panel_seg<3>(c, pa, no, pb, 112, 128);
+  } else {
+    no[0] = 32; no[1] = 48; no[2] = 64; no[3] = 80;
+    panel_seg<0>(c, pa, no, pb, 0, 48);
+    panel_seg<1>(c, pa, no, pb, 48, 64);
+    panel_seg<2>(c, pa, no, pb, 64, 80);
+    panel_seg<3>(c, pa, no, pb, 80, 96);
+  }
   __syncthreads();  // the whole tile is read before any part is overwritten
-  const LaneXY lx;
-  const int m0 = wj * 64 + lx.col0();
+  const int m0 = wj * 64 + 4 * lr;
 #pragma unroll
-  for (int v = 0; v < 4; ++v)
+  for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
-      const int n = wi * 64 + lx.row(v, bi);
-      st4(tile + n * NB + m0, acc.row(v, bi));
+    for (int v = 0; v < 4; ++v) {
+      const int n = no[j] + 4 * v + lq;
+      st4(tile + n * NB + m0,
+          v4d{c[j][0][v], c[j][1][v], c[j][2][v], c[j][3][v]});
     }
 }
 
