@@ -332,13 +332,43 @@ k_potrf_panel(int64_t S, int kk, double* L, const double* linv,
     }
 }
 
-__device__ inline void mma_any(Acc64& acc, const double* a, int64_t lda,
-                               const double* b, int64_t ldb, int K) {
-  mma_panel(acc, a, lda, b, ldb, K);
+// acc += sum over the panels c in [c0, c1) of L_Jc(wave rows, :) L_Ic(wave
+// columns, :)^T: one stream of 4-long k steps, whose operands are loaded
+// two steps ahead of the products, across the panel boundaries too.
+__device__ inline void mma_group(Acc64& acc, const double* Lf, int I, int J,
+                                 int c0, int c1, int wi, int wj) {
+  const int l = threadIdx.x & 63;
+  const int64_t lo = (int64_t)(l >> 4) * NB + 4 * (l & 15);
+  const int64_t st = 4 * NB;
+  const double* pa = Lf + tile_off(J, c0) + wi * 64 + lo;
+  const double* pb = Lf + tile_off(I, c0) + wj * 64 + lo;
+  v4d a0 = ld4(pa), b0 = ld4(pb), a1 = ld4(pa + st), b1 = ld4(pb + st);
+  for (int c = c0; c < c1; ++c) {
+    // the next panel's first two steps are loaded during this panel's last
+    // two (after the last panel, this panel's first two again, unused)
+    const bool more = c + 1 < c1;
+    const double* na = more ? Lf + tile_off(J, c + 1) + wi * 64 + lo : pa;
+    const double* nb = more ? Lf + tile_off(I, c + 1) + wj * 64 + lo : pb;
+#pragma unroll
+    for (int k = 2; k < 34; ++k) {
+      const double* qa = k < 32 ? pa + k * st : na + (k - 32) * st;
+      const double* qb = k < 32 ? pb + k * st : nb + (k - 32) * st;
+      const v4d a2 = ld4(qa), b2 = ld4(qb);
+      acc.mma(a0, b0);
+      a0 = a1;
+      b0 = b1;
+      a1 = a2;
+      b1 = b2;
+    }
+    pa = na;
+    pb = nb;
+  }
 }
-__device__ inline void mma_any(Acc64F& acc, const double* a, int64_t lda,
-                               const double* b, int64_t ldb, int K) {
-  mma_panel_f32(acc, a, lda, b, ldb, K);
+__device__ inline void mma_group(Acc64F& acc, const double* Lf, int I, int J,
+                                 int c0, int c1, int wi, int wj) {
+  for (int c = c0; c < c1; ++c)
+    mma_panel_f32(acc, Lf + tile_off(J, c) + wi * 64, NB,
+                  Lf + tile_off(I, c) + wj * 64, NB, NB);
 }
 
 // Where a fused diagonal factorization writes: the inverse of tile j0 of
@@ -414,9 +444,7 @@ __device__ inline void potrf_update_body(int64_t S, int nt, int j0, int mode,
     const int m0 = wj * 64 + lx.col0();
     ACC acc;
     acc.zero();
-    for (int c = c0; c < c1; ++c)
-      mma_any(acc, Lf + tile_off(J, c) + wi * 64, NB,
-              Lf + tile_off(I, c) + wj * 64, NB, NB);
+    mma_group(acc, Lf, I, J, c0, c1, wi, wj);
     const double shift = (SRC && I == J) ? src_shift(src, f) : 0.0;
 #pragma unroll
     for (int v = 0; v < 4; ++v)
