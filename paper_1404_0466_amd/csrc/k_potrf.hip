@@ -343,22 +343,23 @@ __device__ inline void mma_group(Acc64& acc, const double* Lf, int I, int J,
   const double* pa = Lf + tile_off(J, c0) + wi * 64 + lo;
   const double* pb = Lf + tile_off(I, c0) + wj * 64 + lo;
   v4d a0 = ld4(pa), b0 = ld4(pb), a1 = ld4(pa + st), b1 = ld4(pb + st);
+  v4d a2 = ld4(pa + 2 * st), b2 = ld4(pb + 2 * st);
   for (int c = c0; c < c1; ++c) {
-    // the next panel's first two steps are loaded during this panel's last
-    // two (after the last panel, this panel's first two again, unused)
     const bool more = c + 1 < c1;
     const double* na = more ? Lf + tile_off(J, c + 1) + wi * 64 + lo : pa;
     const double* nb = more ? Lf + tile_off(I, c + 1) + wj * 64 + lo : pb;
 #pragma unroll
-    for (int k = 2; k < 34; ++k) {
+    for (int k = 3; k < 35; ++k) {
       const double* qa = k < 32 ? pa + k * st : na + (k - 32) * st;
       const double* qb = k < 32 ? pb + k * st : nb + (k - 32) * st;
-      const v4d a2 = ld4(qa), b2 = ld4(qb);
+      const v4d a3 = ld4(qa), b3 = ld4(qb);
       acc.mma(a0, b0);
       a0 = a1;
       b0 = b1;
       a1 = a2;
       b1 = b2;
+      a2 = a3;
+      b2 = b3;
     }
     pa = na;
     pb = nb;
