@@ -280,7 +280,8 @@ size_t pichol_holdout_workspace(int64_t d, int32_t nmat, int32_t q,
  * sse = |R|_F^2 computed as |Y_v|^2 - 2<W, X_v^T Y_v> + <W, X_v^T X_v W>,
  * err = sse / (nv * c).
  * In:  Z nmat slabs (device, as produced by the solve calls);
- *      G, C, yy of the validation blocks (device, as from pichol_gram);
+ *      G, C, yy of the validation blocks (device, as from pichol_gram;
+ *      G is symmetric and only its tiles (I,J) with J <= I are read);
  *      nv nmat validation row counts (host).
  * Out: err nmat*q (device, FP64); flags nmat*q (device): bit0 is OR-ed in
  *      when err is not finite.

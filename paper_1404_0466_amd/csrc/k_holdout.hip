@@ -12,9 +12,12 @@ namespace pichol {
 
 // Partial sums over the rows of tile row I of
 //     W(r, col) * ((G W)_h(r, col) - [h == 0] 2 C(r, col mod c))
-// for the 128 slab columns of block cb, where (G W)_h sums over the h-th of
-// HOLDOUT_KSPLIT ranges of column blocks J (the expansion is linear in
-// G W); written to partial[m][I][h][col].
+// for the 128 slab columns of block cb, where (G W)_h sums over the column
+// blocks J <= I of the h-th of HOLDOUT_KSPLIT ranges, the blocks J < I
+// counted twice: G is symmetric, so <W, G W> = sum_I W_I^T (G_II W_I +
+// 2 sum_{J<I} G_IJ W_J), half the products of the full sum (the expansion
+// is linear in G W).  Written to partial[m][I][h][col]; a range that starts
+// past I writes zeros.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_holdout_partial(
     int64_t d, int q, int c, int64_t ldz, const double* Z, const double* G,
     const double* C, double* partial) {
@@ -28,17 +31,33 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
   const int J0 = (int)(nt * h / HOLDOUT_KSPLIT);
   const int J1 = (int)(nt * (h + 1) / HOLDOUT_KSPLIT);
   const LaneXY lx;
+  const int64_t col = (int64_t)cb * NB + wj * 64 + lx.col0();
+  const int64_t qc = (int64_t)q * c;
+  if (J0 > I) {  // the whole range lies above the diagonal
+    if (wi == 0 && lx.lq == 0) {
+      double* out = partial + ((m * nt + I) * HOLDOUT_KSPLIT + h) * ldz + col;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) out[e] = 0.0;
+    }
+    return;
+  }
   const double* gm = G + m * dp * dp + (int64_t)I * nt * NB2 + wi * 64;
   const double* zm = Z + m * dp * ldz + (int64_t)cb * NB + wj * 64;
   Acc64 acc;
   acc.zero();
-  for (int J = J0; J < J1; ++J)
+  const int Jl = J1 < I ? J1 : I;  // blocks strictly below the diagonal
+  for (int J = J0; J < Jl; ++J)
     mma_panel(acc, gm + (int64_t)J * NB2, NB, zm + (int64_t)J * NB * ldz, ldz,
+              NB);
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc.c[bi][bj] *= 2.0;
+  if (I < J1)
+    mma_panel(acc, gm + (int64_t)I * NB2, NB, zm + (int64_t)I * NB * ldz, ldz,
               NB);
   const double c2 = h == 0 ? 2.0 : 0.0;
 
-  const int64_t col = (int64_t)cb * NB + wj * 64 + lx.col0();
-  const int64_t qc = (int64_t)q * c;
   int cmod[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) cmod[e] = (int)((col + e) % c);
