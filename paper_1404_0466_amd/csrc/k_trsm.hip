@@ -151,138 +151,189 @@ __global__ void __launch_bounds__(256) k_diag_solve(int64_t d, int i,
   }
 }
 
-// Inverse of diagonal block i of the interpolated factor for lambda t of
-// fold m, in registers.  Thread (ti, tk) = (tid % 16, tid / 16) evaluates
-// the entries (ti + 16a, tk + 16b), a >= b, of the block from the
-// coefficient planes (x) and builds the same entries of its inverse (y) by
-// forward substitution on the identity: row s of the inverse is final once
-// scaled by 1/L(s,s), and the rows below it then lose L(i,s) times it.
-// Columns of L go through LDS with zeros at rows <= s and rows of the
-// inverse with zeros right of the diagonal, so every thread updates whole
-// 16-entry blocks without masks; one barrier per row (column buffers rotate
-// over three slots, rows and reciprocals over two).
-template <int SB, bool LAST>
-__device__ __forceinline__ void inv_step(int ss, const double (&x)[8][8],
-                                         double (&y)[8][8], double* cbuf,
-                                         double* rbuf, double* pbuf, int ti,
-                                         int tk) {
-  constexpr int B1 = LAST ? SB + 1 : SB;  // block column of column s+1
-  constexpr bool NEXT = !(LAST && SB == 7);
-  const int s = 16 * SB + ss;
-  if (s > 0) {
-    // rows below s-1 lose L(i, s-1) X(s-1, :)
-    const double* cp = cbuf + ((s + 2) % 3) * NB;
-    const double* rp = rbuf + ((s + 1) & 1) * NB;
-    double pr[8], rr[8];
+// A 128 x 128 lower-triangular matrix in LDS as its 36 blocks of 16 x 16:
+// block (I, J), I >= J, at blk_off(I, J), column-major with a column stride
+// of 17 doubles, so a wave reading a block along its columns (MFMA A
+// operands) or along its rows (B operands) meets no bank conflicts.  The
+// diagonal blocks hold zeros above their diagonal.
+constexpr int TLD = 17;
+constexpr int TBLK = 16 * TLD;
+__device__ inline int blk_off(int I, int J) { return (I * (I + 1) / 2 + J) * TBLK; }
+
+// acc (a 16 x 16 block in the accumulator layout: element v of lane l is
+// D(4v + l/16, l%16)) += A B for two LDS blocks; lane l supplies
+// A(l%16, 4s + l/16) and B(4s + l/16, l%16) in step s.
+__device__ inline void mfma_blk(v4d& acc, const double* A, const double* B,
+                                int lq, int lr) {
 #pragma unroll
-    for (int a = SB; a < 8; ++a) pr[a] = cp[ti + 16 * a];
-#pragma unroll
-    for (int b = 0; b <= SB; ++b) rr[b] = rp[tk + 16 * b];
-#pragma unroll
-    for (int a = SB; a < 8; ++a)
-#pragma unroll
-      for (int b = 0; b <= SB; ++b) y[a][b] -= pr[a] * rr[b];
+  for (int s = 0; s < 4; ++s) {
+    const int k = 4 * s + lq;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[k * TLD + lr], B[lr * TLD + k],
+                                               acc, 0, 0, 0);
   }
-  if (ti == ss) {  // row s is final once scaled
-    const double is = pbuf[s & 1];
-    double* rb = rbuf + (s & 1) * NB;
+}
+
+// One level of the blocked inverse: the matrix is split into diagonal
+// regions of 2n blocks, each [T11 0; T21 T22] with n x n blocks per part,
+// whose parts T11 and T22 already hold their inverses X11, X22.  Then
+// T^{-1} = [X11 0; X21 X22] with X21 = -X22 T21 X11, formed in two MFMA
+// products: P = T21 X11 overwrites T21, then X21 = -X22 P overwrites P.
+// Each output block of each region is one work unit, dealt to the four
+// waves in turn; a barrier separates every read of a part from its
+// overwrite.
+template <int N>
+__device__ __forceinline__ void inv_level(double* S, int w, int lq, int lr) {
+  constexpr int REG = 8 / (2 * N);         // regions
+  constexpr int UNITS = REG * N * N;       // output blocks per product
+  constexpr int PER = (UNITS + 3) / 4;     // units per wave
+  v4d acc[PER];
+  // P(r, c) = sum_{k >= c} T21(r, k) X11(k, c)   (X11 lower triangular)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      double o = 0.0;
-      if (b <= SB) {
-        y[SB][b] *= is;
-        o = y[SB][b];
-      }
-      rb[tk + 16 * b] = o;
+  for (int j = 0; j < PER; ++j) {
+    acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int u = w + 4 * j;
+    if (u < UNITS) {
+      const int g = u / (N * N), r = (u / N) % N, c = u % N;
+      const int a0 = 2 * N * g, c0 = a0 + N;
+      for (int k = c; k < N; ++k)
+        mfma_blk(acc[j], S + blk_off(c0 + r, a0 + k), S + blk_off(a0 + k, a0 + c),
+                 lq, lr);
     }
   }
-  const int sn = s + 1, sn16 = sn & 15;
-  if (NEXT && tk == sn16) {  // publish column s+1 and 1/L(s+1, s+1)
-    double* cn = cbuf + (sn % 3) * NB;
+  __syncthreads();
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      double v = 0.0;
-      if (a > B1 || (a == B1 && ti > sn16)) v = x[a][B1];
-      cn[ti + 16 * a] = v;
+  for (int j = 0; j < PER; ++j) {
+    const int u = w + 4 * j;
+    if (u < UNITS) {
+      const int g = u / (N * N), r = (u / N) % N, c = u % N;
+      const int a0 = 2 * N * g, c0 = a0 + N;
+      double* o = S + blk_off(c0 + r, a0 + c);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o[lr * TLD + 4 * v + lq] = acc[j][v];
     }
-    if (ti == sn16) pbuf[sn & 1] = 1.0 / x[B1][B1];
+  }
+  __syncthreads();
+  // X21(r, c) = -sum_{k <= r} X22(r, k) P(k, c)   (X22 lower triangular)
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int u = w + 4 * j;
+    if (u < UNITS) {
+      const int g = u / (N * N), r = (u / N) % N, c = u % N;
+      const int a0 = 2 * N * g, c0 = a0 + N;
+      for (int k = 0; k <= r; ++k)
+        mfma_blk(acc[j], S + blk_off(c0 + r, c0 + k), S + blk_off(c0 + k, a0 + c),
+                 lq, lr);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int u = w + 4 * j;
+    if (u < UNITS) {
+      const int g = u / (N * N), r = (u / N) % N, c = u % N;
+      const int a0 = 2 * N * g, c0 = a0 + N;
+      double* o = S + blk_off(c0 + r, a0 + c);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o[lr * TLD + 4 * v + lq] = -acc[j][v];
+    }
   }
   __syncthreads();
 }
 
-template <int SB>
-__device__ __forceinline__ void inv_block(const double (&x)[8][8],
-                                          double (&y)[8][8], double* cbuf,
-                                          double* rbuf, double* pbuf, int ti,
-                                          int tk) {
-#pragma unroll 1
-  for (int ss = 0; ss < 15; ++ss)
-    inv_step<SB, false>(ss, x, y, cbuf, rbuf, pbuf, ti, tk);
-  inv_step<SB, true>(15, x, y, cbuf, rbuf, pbuf, ti, tk);
-}
-
-// Writes the inverse, column-major with zeros above the diagonal, to dinv.
-// A non-positive diagonal entry of the block sets flag bit1.
-__global__ void __launch_bounds__(256) k_diag_inv(int64_t d, FactorSrc src,
+// Inverse of diagonal block i of the interpolated factor for lambda t of
+// fold m.  The block is evaluated from the coefficient planes into LDS
+// (sum_p tau^p Theta_p, p increasing; entries above the diagonal are not
+// read), then inverted in place, blocked:
+//   1. the eight 16 x 16 diagonal blocks by forward substitution, one
+//      column per lane (lanes 0-31 of each wave take two blocks);
+//   2. three levels that join inverses of 16, 32 and 64 rows into inverses
+//      of 32, 64 and 128 rows on FP64 MFMA (inv_level).
+// 77 KB of LDS, so two workgroups share a CU.  Writes the inverse,
+// column-major with zeros above the diagonal, to dinv.  A non-positive
+// diagonal entry of the block sets flag bit1.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_diag_inv(int64_t d, FactorSrc src,
                                                   double* dinv, int* flags) {
-  __shared__ double cbuf[3 * NB];
-  __shared__ double rbuf[2 * NB];
-  __shared__ double pbuf[2];
+  __shared__ double S[36 * TBLK];
   const int i = blockIdx.x, t = blockIdx.y;
   const int64_t m = blockIdx.z;
   const int nt = gridDim.x;
-  const int tid = threadIdx.x, ti = tid & 15, tk = tid >> 4;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int lq = l >> 4, lr = l & 15;
   const double* planes = src.base + m * src.M * src.S + tile_off(i, i);
   const double tau = src.tau[t];
-  double x[8][8], y[8][8];
+  // thread (r, h) = (tid % 128, tid / 128) evaluates row r at the columns
+  // c = 2k + h, k = 0..63.  Every load is unconditional (all inside the
+  // tile) and entries above the diagonal are dropped by a select, so all of
+  // a plane's loads are in flight at once.
+  const int r = tid & (NB - 1), h = tid >> 7;
+  double x[64];
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
-#pragma unroll
-    for (int b = 0; b <= a; ++b) {
-      x[a][b] = 0.0;
-      y[a][b] = (a == b && ti == tk) ? 1.0 : 0.0;
-    }
-  // sum_p tau^p Theta_p, p in increasing order (entries above the diagonal
-  // are never used: not read)
+  for (int k = 0; k < 64; ++k) x[k] = 0.0;
   double pw = 1.0;
   for (int p = 0; p < src.M; ++p) {
+    const double* pp = planes + p * src.S + r;
+    double v[64];
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+    for (int k = 0; k < 64; ++k) v[k] = pp[(2 * k + h) * NB];
 #pragma unroll
-      for (int b = 0; b <= a; ++b)
-        if (a > b || ti >= tk)
-          x[a][b] += pw * planes[p * src.S + (tk + 16 * b) * NB + ti + 16 * a];
+    for (int k = 0; k < 64; ++k) {
+      const double y = x[k] + pw * v[k];
+      x[k] = r >= 2 * k + h ? y : 0.0;
+    }
     pw *= tau;
   }
-  if (ti == tk) {
+  bool bad = false;
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
-      if ((int64_t)i * NB + ti + 16 * a < d && !(x[a][a] > 0.0))
-        atomicOr(flags + m * src.nper + t, 2);
+  for (int k = 0; k < 64; ++k) {
+    const int c = 2 * k + h;
+    if ((r >> 4) >= (c >> 4))
+      S[blk_off(r >> 4, c >> 4) + (c & 15) * TLD + (r & 15)] = x[k];
+    if (r == c && (int64_t)i * NB + r < d && !(x[k] > 0.0)) bad = true;
   }
-  if (tk == 0) {  // column 0
+  if (bad) atomicOr(flags + m * src.nper + t, 2);
+  __syncthreads();
+  // 1. diagonal blocks: lane j of the lower or upper 16 lanes of the first
+  // half of wave w solves column j of the inverse of block 2w or 2w + 1
+  // (entries above the diagonal come out zero; the second half repeats the
+  // work and does not store it)
+  double xc[16];
+  const int hb = 2 * w + ((l >> 4) & 1);
+  {
+    const double* T = S + blk_off(hb, hb);
+    const int j = lr;
 #pragma unroll
-    for (int a = 0; a < 8; ++a) cbuf[ti + 16 * a] = (a > 0 || ti > 0) ? x[a][0] : 0.0;
-    if (ti == 0) pbuf[0] = 1.0 / x[0][0];
+    for (int a = 0; a < 16; ++a) {
+      double s = a == j ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < a; ++k) s -= T[k * TLD + a] * xc[k];
+      xc[a] = s / T[a * TLD + a];
+      // keep the compiler from hoisting every row's loads at once: row a
+      // is complete before the next row's loads (an empty statement that
+      // emits no instruction)
+      asm volatile("" : "+v"(xc[a]) : : "memory");
+    }
   }
   __syncthreads();
-  inv_block<0>(x, y, cbuf, rbuf, pbuf, ti, tk);
-  inv_block<1>(x, y, cbuf, rbuf, pbuf, ti, tk);
-  inv_block<2>(x, y, cbuf, rbuf, pbuf, ti, tk);
-  inv_block<3>(x, y, cbuf, rbuf, pbuf, ti, tk);
-  inv_block<4>(x, y, cbuf, rbuf, pbuf, ti, tk);
-  inv_block<5>(x, y, cbuf, rbuf, pbuf, ti, tk);
-  inv_block<6>(x, y, cbuf, rbuf, pbuf, ti, tk);
-  inv_block<7>(x, y, cbuf, rbuf, pbuf, ti, tk);
+  if (l < 32) {
+    double* X = S + blk_off(hb, hb) + lr * TLD;
+#pragma unroll
+    for (int a = 0; a < 16; ++a) X[a] = xc[a];
+  }
+  __syncthreads();
+  // 2. join: 16 -> 32 -> 64 -> 128 rows
+  inv_level<1>(S, w, lq, lr);
+  inv_level<2>(S, w, lq, lr);
+  inv_level<4>(S, w, lq, lr);
   double* out = dinv + ((m * src.nper + t) * nt + i) * (int64_t)NB2;
-#pragma unroll
-  for (int a = 0; a < 8; ++a)
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      double v = 0.0;
-      if (a >= b) v = (a > b || ti >= tk) ? y[a][b] : 0.0;
-      out[(tk + 16 * b) * NB + ti + 16 * a] = v;
-    }
+#pragma unroll 8
+  for (int k = 0; k < 64; ++k) {
+    const int c = 2 * k + h;
+    out[c * NB + r] = (r >> 4) < (c >> 4)
+                          ? 0.0
+                          : S[blk_off(r >> 4, c >> 4) + (c & 15) * TLD + (r & 15)];
+  }
 }
 
 // Apply the stored inverse of diagonal block i to the slab rows of tile i,
