@@ -33,26 +33,19 @@ __device__ inline double src_shift(const ShiftSrc& src, int64_t f) {
   return src.lam[(m / src.lam_group) * src.nshift + f % src.nshift];
 }
 
-// Diagonal tile kk of factor f: its Cholesky factor and the inverse of that
-// factor, both held in registers.  Thread (ti, tk) = (tid % 16, tid / 16)
-// owns the entries (ti + 16a, tk + 16b), a >= b, of the tile (x) and of the
-// inverse (y): a two-dimensional cyclic layout, so every thread keeps work
-// until the last columns.  Column j is factored right-looking (pivot by a
-// refined reciprocal square root, column scaled, rank-1 update of the
-// trailing entries); the inverse is built alongside by forward substitution
-// on the identity, one column behind: row j-1 of the inverse is scaled by
-// 1/L(j-1,j-1) and the rows below it lose L(i, j-1) times that row.  Each
-// column is published in LDS with zeros at rows <= j (and the inverse's row
-// with zeros right of its diagonal), so every thread updates whole 16-entry
-// blocks without masks.  The step that consumes column j also produces
-// column j+1 (its block column is updated first, then its 16 owners factor
-// it), so one barrier per column suffices: column buffers rotate over
-// three slots, inverse rows and pivots over two.
+// Diagonal tile kk of factor f: its Cholesky factor, held in registers.
+// Thread (ti, tk) = (tid % 16, tid / 16) owns the entries (ti + 16a,
+// tk + 16b), a >= b, of the tile (x): a two-dimensional cyclic layout, so
+// every thread keeps work until the last columns.  Column j is factored
+// right-looking (pivot by a refined reciprocal square root, column scaled,
+// rank-1 update of the trailing entries).  Each column is published in LDS
+// with zeros at rows <= j, so every thread updates whole 16-entry blocks
+// without masks.  The step that consumes column j also produces column j+1
+// (its block column is updated first, then its 16 owners factor it), so
+// one barrier per column suffices; column buffers rotate over three slots.
 template <int JB, bool LAST>
 __device__ __forceinline__ void diag_step(int jj, double (&x)[8][8],
-                                          double (&y)[8][8], double (&prv)[8],
-                                          double* cbuf, double* rbuf,
-                                          double* pbuf, int* fail, int ti,
+                                          double* cbuf, int* fail, int ti,
                                           int tk) {
   constexpr int NB1 = LAST ? JB + 1 : JB;  // block column of column j+1
   constexpr bool NEXT = !(LAST && JB == 7);
@@ -64,14 +57,14 @@ __device__ __forceinline__ void diag_step(int jj, double (&x)[8][8],
 #pragma unroll
   for (int b = JB; b < 8; ++b) cc[b] = cb[tk + 16 * b];
   double v[8];
-  double inv = 0.0, piv = 0.0;
+  double piv = 0.0;
   const int jn = j + 1, jn16 = jn & 15;
   if constexpr (NEXT) {
 #pragma unroll
     for (int a = NB1; a < 8; ++a) x[a][NB1] -= cr[a] * cc[NB1];
     // pivot L(j+1, j+1)^2 sits with thread (jn16, jn16)
     piv = bcast_lane(x[NB1][NB1], 16 * (jn16 & 3) + jn16);
-    double ljj;
+    double ljj, inv;
     sqrt_rsqrt(piv, ljj, inv);
     const bool own = tk == jn16;
 #pragma unroll
@@ -92,84 +85,52 @@ __device__ __forceinline__ void diag_step(int jj, double (&x)[8][8],
   for (int b = NB1 + 1; b < 8; ++b)
 #pragma unroll
     for (int a = b; a < 8; ++a) x[a][b] -= cr[a] * cc[b];
-  // inverse: rows below j-1 lose L(i, j-1) X(j-1, :)
-  if (j > 0) {
-    const double* rb = rbuf + ((j - 1) & 1) * NB;
-    double rr[8];
-#pragma unroll
-    for (int b = 0; b <= JB; ++b) rr[b] = rb[tk + 16 * b];
-#pragma unroll
-    for (int a = JB; a < 8; ++a)
-#pragma unroll
-      for (int b = 0; b <= JB; ++b) y[a][b] -= prv[a] * rr[b];
-  }
-  // inverse: row j is final once scaled by 1/L(j,j)
-  if (ti == jj) {
-    const double ij = pbuf[j & 1];
-    double* rb = rbuf + (j & 1) * NB;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      double o = 0.0;
-      if (b <= JB) {
-        y[JB][b] *= ij;
-        o = y[JB][b];
-      }
-      rb[tk + 16 * b] = o;
-    }
-  }
-#pragma unroll
-  for (int a = JB; a < 8; ++a) prv[a] = cr[a];
   if (NEXT && tk == jn16) {
     double* cn = cbuf + (jn % 3) * NB;
 #pragma unroll
     for (int a = 0; a < 8; ++a) cn[ti + 16 * a] = v[a];
-    if (ti == 0) {
-      pbuf[jn & 1] = inv;
-      if (!(piv > 0.0)) atomicMin(fail, jn);
-    }
+    if (ti == 0 && !(piv > 0.0)) atomicMin(fail, jn);
   }
   __syncthreads();
 }
 
 template <int JB>
-__device__ __forceinline__ void diag_block(double (&x)[8][8], double (&y)[8][8],
-                                           double (&prv)[8], double* cbuf,
-                                           double* rbuf, double* pbuf, int* fail,
-                                           int ti, int tk) {
+__device__ __forceinline__ void diag_block(double (&x)[8][8], double* cbuf,
+                                           int* fail, int ti, int tk) {
 #pragma unroll 1
   for (int jj = 0; jj < 15; ++jj)
-    diag_step<JB, false>(jj, x, y, prv, cbuf, rbuf, pbuf, fail, ti, tk);
-  diag_step<JB, true>(15, x, y, prv, cbuf, rbuf, pbuf, fail, ti, tk);
+    diag_step<JB, false>(jj, x, cbuf, fail, ti, tk);
+  diag_step<JB, true>(15, x, cbuf, fail, ti, tk);
 }
 
 // Factors one diagonal tile with the whole 256-thread workgroup.  Writes the
 // factor (zeros above the diagonal) to `tile` and its inverse (zeros above
 // the diagonal) to `li`; the tile's current lower triangle is read from `in`
 // (the tile itself, or with SRC the source matrix, plus `shift` on the
-// diagonal).  *info_f gets the global index + 1 of the first non-positive
-// pivot when it is the matrix's first failure; with SRC (the first panel) it
-// is written either way (0 when no pivot failed).
+// diagonal).  The factor is formed in registers (diag_step), then staged in
+// LDS and inverted there by tri_inv_lds (16 x 16 diagonal blocks by forward
+// substitution, joined on FP64 MFMA); the column buffers of the first part
+// share that LDS.  *info_f gets the global index + 1 of the first
+// non-positive pivot when it is the matrix's first failure; with SRC (the
+// first panel) it is written either way (0 when no pivot failed).
 template <bool SRC>
 __device__ __forceinline__ void diag_factor_tile(int64_t d, int kk,
                                                  double* tile, const double* in,
                                                  double shift, int* info_f,
                                                  double* li) {
-  __shared__ double cbuf[3 * NB];
-  __shared__ double rbuf[2 * NB];
-  __shared__ double pbuf[2];
+  __shared__ double S[TRI_LDS];
   __shared__ int fail;
+  double* cbuf = S;  // 3 * 128 doubles, free again once the factor is done
   const int tid = threadIdx.x, ti = tid & 15, tk = tid >> 4;
-  double x[8][8], y[8][8], prv[8];
+  double x[8][8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
-    prv[a] = 0.0;
 #pragma unroll
     for (int b = 0; b <= a; ++b) {
       // entries above the diagonal are never used: not read
       x[a][b] = (a > b || ti >= tk) ? in[(tk + 16 * b) * NB + ti + 16 * a] : 0.0;
       if (SRC && a == b && ti == tk && (int64_t)kk * NB + ti + 16 * a < d)
         x[a][b] += shift;
-      y[a][b] = (a == b && ti == tk) ? 1.0 : 0.0;
     }
   }
   {  // column 0, by its owners (wave 0)
@@ -189,35 +150,40 @@ __device__ __forceinline__ void diag_factor_tile(int64_t d, int kk,
         }
         cbuf[i] = v;
       }
-      if (ti == 0) {
-        pbuf[0] = inv;
-        fail = (piv > 0.0) ? NB : 0;
-      }
+      if (ti == 0) fail = (piv > 0.0) ? NB : 0;
     }
   }
   __syncthreads();
-  diag_block<0>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
-  diag_block<1>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
-  diag_block<2>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
-  diag_block<3>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
-  diag_block<4>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
-  diag_block<5>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
-  diag_block<6>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
-  diag_block<7>(x, y, prv, cbuf, rbuf, pbuf, &fail, ti, tk);
+  diag_block<0>(x, cbuf, &fail, ti, tk);
+  diag_block<1>(x, cbuf, &fail, ti, tk);
+  diag_block<2>(x, cbuf, &fail, ti, tk);
+  diag_block<3>(x, cbuf, &fail, ti, tk);
+  diag_block<4>(x, cbuf, &fail, ti, tk);
+  diag_block<5>(x, cbuf, &fail, ti, tk);
+  diag_block<6>(x, cbuf, &fail, ti, tk);
+  diag_block<7>(x, cbuf, &fail, ti, tk);
+  // the last step ended with a barrier: the column buffers are free
 #pragma unroll
   for (int a = 0; a < 8; ++a)
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
       const int i = ti + 16 * a, k = tk + 16 * b;
       const bool low = a > b || (a == b && ti >= tk);
-      double xv = 0.0, yv = 0.0;
-      if (a >= b) {
-        xv = low ? x[a][b] : 0.0;
-        yv = low ? y[a][b] : 0.0;
-      }
+      const double xv = (a >= b && low) ? x[a][b] : 0.0;
       tile[k * NB + i] = xv;
-      li[k * NB + i] = yv;
+      if (a >= b) S[blk_off(a, b) + tk * TLD + ti] = xv;
     }
+  __syncthreads();
+  tri_inv_lds(S);
+  // thread (r, h) writes row r of the inverse at the columns 2k + h
+  const int r = tid & (NB - 1), h = tid >> 7;
+#pragma unroll 8
+  for (int k = 0; k < 64; ++k) {
+    const int c = 2 * k + h;
+    li[c * NB + r] = (r >> 4) < (c >> 4)
+                         ? 0.0
+                         : S[blk_off(r >> 4, c >> 4) + (c & 15) * TLD + (r & 15)];
+  }
   if (tid == 0) {
     const bool bad = fail < NB && (int64_t)kk * NB + fail < d;
     if (SRC)

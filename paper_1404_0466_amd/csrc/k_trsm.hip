@@ -151,116 +151,22 @@ __global__ void __launch_bounds__(256) k_diag_solve(int64_t d, int i,
   }
 }
 
-// A 128 x 128 lower-triangular matrix in LDS as its 36 blocks of 16 x 16:
-// block (I, J), I >= J, at blk_off(I, J), column-major with a column stride
-// of 17 doubles, so a wave reading a block along its columns (MFMA A
-// operands) or along its rows (B operands) meets no bank conflicts.  The
-// diagonal blocks hold zeros above their diagonal.
-constexpr int TLD = 17;
-constexpr int TBLK = 16 * TLD;
-__device__ inline int blk_off(int I, int J) { return (I * (I + 1) / 2 + J) * TBLK; }
-
-// acc (a 16 x 16 block in the accumulator layout: element v of lane l is
-// D(4v + l/16, l%16)) += A B for two LDS blocks; lane l supplies
-// A(l%16, 4s + l/16) and B(4s + l/16, l%16) in step s.
-__device__ inline void mfma_blk(v4d& acc, const double* A, const double* B,
-                                int lq, int lr) {
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int k = 4 * s + lq;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[k * TLD + lr], B[lr * TLD + k],
-                                               acc, 0, 0, 0);
-  }
-}
-
-// One level of the blocked inverse: the matrix is split into diagonal
-// regions of 2n blocks, each [T11 0; T21 T22] with n x n blocks per part,
-// whose parts T11 and T22 already hold their inverses X11, X22.  Then
-// T^{-1} = [X11 0; X21 X22] with X21 = -X22 T21 X11, formed in two MFMA
-// products: P = T21 X11 overwrites T21, then X21 = -X22 P overwrites P.
-// Each output block of each region is one work unit, dealt to the four
-// waves in turn; a barrier separates every read of a part from its
-// overwrite.
-template <int N>
-__device__ __forceinline__ void inv_level(double* S, int w, int lq, int lr) {
-  constexpr int REG = 8 / (2 * N);         // regions
-  constexpr int UNITS = REG * N * N;       // output blocks per product
-  constexpr int PER = (UNITS + 3) / 4;     // units per wave
-  v4d acc[PER];
-  // P(r, c) = sum_{k >= c} T21(r, k) X11(k, c)   (X11 lower triangular)
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
-    const int u = w + 4 * j;
-    if (u < UNITS) {
-      const int g = u / (N * N), r = (u / N) % N, c = u % N;
-      const int a0 = 2 * N * g, c0 = a0 + N;
-      for (int k = c; k < N; ++k)
-        mfma_blk(acc[j], S + blk_off(c0 + r, a0 + k), S + blk_off(a0 + k, a0 + c),
-                 lq, lr);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int u = w + 4 * j;
-    if (u < UNITS) {
-      const int g = u / (N * N), r = (u / N) % N, c = u % N;
-      const int a0 = 2 * N * g, c0 = a0 + N;
-      double* o = S + blk_off(c0 + r, a0 + c);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) o[lr * TLD + 4 * v + lq] = acc[j][v];
-    }
-  }
-  __syncthreads();
-  // X21(r, c) = -sum_{k <= r} X22(r, k) P(k, c)   (X22 lower triangular)
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
-    const int u = w + 4 * j;
-    if (u < UNITS) {
-      const int g = u / (N * N), r = (u / N) % N, c = u % N;
-      const int a0 = 2 * N * g, c0 = a0 + N;
-      for (int k = 0; k <= r; ++k)
-        mfma_blk(acc[j], S + blk_off(c0 + r, c0 + k), S + blk_off(c0 + k, a0 + c),
-                 lq, lr);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int u = w + 4 * j;
-    if (u < UNITS) {
-      const int g = u / (N * N), r = (u / N) % N, c = u % N;
-      const int a0 = 2 * N * g, c0 = a0 + N;
-      double* o = S + blk_off(c0 + r, a0 + c);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) o[lr * TLD + 4 * v + lq] = -acc[j][v];
-    }
-  }
-  __syncthreads();
-}
-
 // Inverse of diagonal block i of the interpolated factor for lambda t of
 // fold m.  The block is evaluated from the coefficient planes into LDS
 // (sum_p tau^p Theta_p, p increasing; entries above the diagonal are not
-// read), then inverted in place, blocked:
-//   1. the eight 16 x 16 diagonal blocks by forward substitution, one
-//      column per lane (lanes 0-31 of each wave take two blocks);
-//   2. three levels that join inverses of 16, 32 and 64 rows into inverses
-//      of 32, 64 and 128 rows on FP64 MFMA (inv_level).
-// 77 KB of LDS, so two workgroups share a CU.  Writes the inverse,
-// column-major with zeros above the diagonal, to dinv.  A non-positive
-// diagonal entry of the block sets flag bit1.
+// read), then inverted in place by tri_inv_lds (16 x 16 diagonal blocks by
+// forward substitution, joined on FP64 MFMA).  77 KB of LDS, so two
+// workgroups share a CU.  Writes the inverse, column-major with zeros above
+// the diagonal, to dinv.  A non-positive diagonal entry of the block sets
+// flag bit1.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_diag_inv(int64_t d, FactorSrc src,
                                                   double* dinv, int* flags) {
-  __shared__ double S[36 * TBLK];
+  __shared__ double S[TRI_LDS];
   const int i = blockIdx.x, t = blockIdx.y;
   const int64_t m = blockIdx.z;
   const int nt = gridDim.x;
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const int lq = l >> 4, lr = l & 15;
+  const int tid = threadIdx.x;
   const double* planes = src.base + m * src.M * src.S + tile_off(i, i);
   const double tau = src.tau[t];
   // thread (r, h) = (tid % 128, tid / 128) evaluates row r at the columns
@@ -294,38 +200,7 @@ k_diag_inv(int64_t d, FactorSrc src,
   }
   if (bad) atomicOr(flags + m * src.nper + t, 2);
   __syncthreads();
-  // 1. diagonal blocks: lane j of the lower or upper 16 lanes of the first
-  // half of wave w solves column j of the inverse of block 2w or 2w + 1
-  // (entries above the diagonal come out zero; the second half repeats the
-  // work and does not store it)
-  double xc[16];
-  const int hb = 2 * w + ((l >> 4) & 1);
-  {
-    const double* T = S + blk_off(hb, hb);
-    const int j = lr;
-#pragma unroll
-    for (int a = 0; a < 16; ++a) {
-      double s = a == j ? 1.0 : 0.0;
-#pragma unroll
-      for (int k = 0; k < a; ++k) s -= T[k * TLD + a] * xc[k];
-      xc[a] = s / T[a * TLD + a];
-      // keep the compiler from hoisting every row's loads at once: row a
-      // is complete before the next row's loads (an empty statement that
-      // emits no instruction)
-      asm volatile("" : "+v"(xc[a]) : : "memory");
-    }
-  }
-  __syncthreads();
-  if (l < 32) {
-    double* X = S + blk_off(hb, hb) + lr * TLD;
-#pragma unroll
-    for (int a = 0; a < 16; ++a) X[a] = xc[a];
-  }
-  __syncthreads();
-  // 2. join: 16 -> 32 -> 64 -> 128 rows
-  inv_level<1>(S, w, lq, lr);
-  inv_level<2>(S, w, lq, lr);
-  inv_level<4>(S, w, lq, lr);
+  tri_inv_lds(S);
   double* out = dinv + ((m * src.nper + t) * nt + i) * (int64_t)NB2;
 #pragma unroll 8
   for (int k = 0; k < 64; ++k) {
