@@ -215,8 +215,8 @@ pichol_status pichol_potrf_shifted_batched(int64_t d, int32_t nmat,
  * Out: theta nmat*(r+1) packed coefficient planes (device), plane (m,j) at
  *      (m*(r+1) + j)*S;
  *      theta_t (optional, may be NULL) the same planes with every tile
- *      stored row-major instead of column-major (for callers that want
- *      the transposed tiles; no call of this library needs them). */
+ *      stored row-major instead of column-major (used by the backward
+ *      solve of pichol_solve_interp). */
 pichol_status pichol_fit(int64_t d, int32_t nmat, int32_t g, int32_t r,
                          const double *lam_s, double lam_ref, const double *L,
                          double *theta, double *theta_t, hipStream_t stream);
@@ -248,10 +248,8 @@ size_t pichol_solve_interp_workspace(int64_t d, int32_t nmat, int32_t q,
  * evaluated and inverted once; each step multiplies by the stored inverses,
  * and the off-diagonal updates of all q values are one FP64 MFMA product
  * with the r+1 coefficient planes.
- * In:  theta from pichol_fit (device); theta_t is not read and may be
- *      NULL (the backward steps read theta's tiles along their columns);
- *      B nmat x dp x c row-major (device, padding rows 0); lam q values
- *      (host).
+ * In:  theta, theta_t from pichol_fit (device); B nmat x dp x c row-major
+ *      (device, padding rows 0); lam q values (host).
  * Out: Z nmat slabs of dp x pichol_slab_cols(q,c) (device): W for every
  *      (fold, lambda); flags nmat*q (device, int32), zeroed then set.
  * ws: pichol_solve_interp_workspace(d, nmat, q, c) bytes. */

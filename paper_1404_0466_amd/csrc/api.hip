@@ -193,7 +193,7 @@ struct Layout {
   int64_t d, nt, dp, S, ldz;
   size_t G, C, yy, H, B, region;  // byte offsets
   // interpolated region
-  size_t i_lam, i_tau, i_L, i_linv, i_th, i_Z, i_X, i_part, i_dinv,
+  size_t i_lam, i_tau, i_L, i_linv, i_th, i_tht, i_Z, i_X, i_part, i_dinv,
       i_end;
   // exact region
   size_t e_lam, e_L, e_linv, e_Z, e_X, e_part, e_end;
@@ -229,6 +229,7 @@ static Layout layout_of(const pichol_problem* p) {
   L.i_L = a; a += align256(k * g * L.S * dbl);
   L.i_linv = a; a += align256(k * g * NB2 * dbl);
   L.i_th = a; a += align256(k * M * L.S * dbl);
+  L.i_tht = a; a += align256(k * M * L.S * dbl);
   L.i_Z = a; a += align256(k * L.dp * L.ldz * dbl);
   L.i_X = a; a += align256(k * L.dp * L.ldz * dbl);
   L.i_part = a; a += align256(k * L.nt * HOLDOUT_KSPLIT * L.ldz * dbl);
@@ -525,9 +526,8 @@ pichol_status pichol_solve_interp(int64_t d, int32_t nmat, int32_t c, int32_t r,
                                   double lam_ref, double* Z, int32_t* flags,
                                   void* ws, size_t ws_bytes,
                                   hipStream_t stream) {
-  (void)theta_t;  // not read: the backward steps read theta's tiles transposed
   if (d < 1 || nmat < 1 || c < 1 || r < 0 || r > 7 || q < 1 || !theta ||
-      !B || !lam || !Z || !flags || !(lam_ref > 0.0) ||
+      !theta_t || !B || !lam || !Z || !flags || !(lam_ref > 0.0) ||
       !isfinite(lam_ref))
     return PICHOL_ERR_ARG;
   if (!ws || ws_bytes < pichol_solve_interp_workspace(d, nmat, q, c))
@@ -540,7 +540,7 @@ pichol_status pichol_solve_interp(int64_t d, int32_t nmat, int32_t c, int32_t r,
   hipError_t e = upload_tau(lam, q, lam_ref, 0, tau, stream);
   if (e == hipSuccess) e = launch_slab_init(d, nmat, q, c, ldz, B, Z, flags, stream);
   if (e == hipSuccess)
-    e = launch_solve_interp(d, nmat, c, r + 1, theta, q, tau, ldz, Z,
+    e = launch_solve_interp(d, nmat, c, r + 1, theta, theta_t, q, tau, ldz, Z,
                             X, flags, dinv, 1, stream);
   return hip_status(e);
 }
@@ -676,6 +676,7 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
   double* tau = at<double>(ws, L.i_tau);
   double* Lf = at<double>(ws, L.i_L);
   double* th = at<double>(ws, L.i_th);
+  double* tht = at<double>(ws, L.i_tht);
   double* Z = at<double>(ws, L.i_Z);
   hipError_t e = launch_store_doubles(lam_s, g, lam_dev, stream);
   if (e == hipSuccess)
@@ -686,12 +687,12 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
                              info, at<double>(ws, L.i_linv), 0,
                              p->precision == PICHOL_PREC_MIXED,
                              option_lookahead(), 0, stream);
-  if (e == hipSuccess) e = launch_fit(p->d, k, fc, Lf, th, nullptr, stream);
+  if (e == hipSuccess) e = launch_fit(p->d, k, fc, Lf, th, tht, stream);
   if (e == hipSuccess)
     e = launch_slab_init(p->d, k, q, c, L.ldz, at<double>(ws, L.B), Z, flags,
                          stream);
   if (e == hipSuccess)
-    e = launch_solve_interp(p->d, k, c, M, th, q, tau, L.ldz, Z,
+    e = launch_solve_interp(p->d, k, c, M, th, tht, q, tau, L.ldz, Z,
                             at<double>(ws, L.i_X), flags,
                             at<double>(ws, L.i_dinv), 1, stream);
   if (e == hipSuccess && p->refine > 0) {
@@ -708,7 +709,7 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
       e = launch_residual(p->d, k, q, c, L.ldz, Hf, at<double>(ws, L.B), lamg,
                           Z, D, stream);
       if (e == hipSuccess)
-        e = launch_solve_interp(p->d, k, c, M, th, q, tau, L.ldz, D,
+        e = launch_solve_interp(p->d, k, c, M, th, tht, q, tau, L.ldz, D,
                                 at<double>(ws, L.i_X), flags,
                                 at<double>(ws, L.i_dinv),
                                 0, stream);
@@ -795,7 +796,7 @@ pichol_status pichol_cv_interp_grad(const pichol_problem* p,
   const int k = p->k, q = p->q, c = (int)p->c, M = p->r + 1;
   double* Z = at<double>(ws, L.i_Z);
   double* Sg = at<double>(ws, L.i_gS);
-  const double* th = at<double>(ws, L.i_th);
+  double* th_t = at<double>(ws, L.i_tht);
   double* wts = at<double>(ws, L.i_gw);
   // plane weights per lambda: tau^p (value) and p tau^(p-1) / lam_ref
   std::vector<double> w(2 * 8 * (size_t)q, 0.0), zero(q, 0.0);
@@ -825,7 +826,7 @@ pichol_status pichol_cv_interp_grad(const pichol_problem* p,
                         stream);
   // z = A^{-1} X_v^T R with the stored diagonal-block inverses
   if (e == hipSuccess)
-    e = launch_solve_interp(p->d, k, c, M, th, q,
+    e = launch_solve_interp(p->d, k, c, M, at<double>(ws, L.i_th), th_t, q,
                             at<double>(ws, L.i_tau), L.ldz, Sg,
                             at<double>(ws, L.i_X), flags,
                             at<double>(ws, L.i_dinv), 0, stream);
@@ -834,14 +835,14 @@ pichol_status pichol_cv_interp_grad(const pichol_problem* p,
   double* a2 = at<double>(ws, L.i_ga2);
   double* b2 = at<double>(ws, L.i_gb2);
   if (e == hipSuccess)
-    e = launch_trmv_interp(p->d, k, M, q, c, L.ldz, th, wts, Z, a1, stream);
+    e = launch_trmv_interp(p->d, k, M, q, c, L.ldz, th_t, wts, Z, a1, stream);
   if (e == hipSuccess)
-    e = launch_trmv_interp(p->d, k, M, q, c, L.ldz, th, wts + 8 * q, Z, b1,
+    e = launch_trmv_interp(p->d, k, M, q, c, L.ldz, th_t, wts + 8 * q, Z, b1,
                            stream);
   if (e == hipSuccess)
-    e = launch_trmv_interp(p->d, k, M, q, c, L.ldz, th, wts, Sg, a2, stream);
+    e = launch_trmv_interp(p->d, k, M, q, c, L.ldz, th_t, wts, Sg, a2, stream);
   if (e == hipSuccess)
-    e = launch_trmv_interp(p->d, k, M, q, c, L.ldz, th, wts + 8 * q, Sg, b2,
+    e = launch_trmv_interp(p->d, k, M, q, c, L.ldz, th_t, wts + 8 * q, Sg, b2,
                            stream);
   // <dLhat^T z, Lhat^T theta> + <Lhat^T z, dLhat^T theta>
   if (e == hipSuccess)

@@ -39,7 +39,7 @@ struct Bucket {
   int stream = 0;
   size_t base = 0;         // byte offset of the bucket's workspace region
   // region offsets, relative to base
-  size_t G, C, yy, H, Bm, lam, tau, L, linv, th, Z, X, part, dinv,
+  size_t G, C, yy, H, Bm, lam, tau, L, linv, th, tht, Z, X, part, dinv,
       info, flags, end;
 };
 
@@ -108,6 +108,7 @@ void layout_bucket(Bucket& b, int method) {
   o += align256(nmat * nf * (method == PICHOL_METHOD_INTERP ? 1 : nt) * NB2 * dbl);
   const bool interp = method == PICHOL_METHOD_INTERP;
   b.th = o; o += interp ? align256(nmat * M * S * dbl) : 0;
+  b.tht = o; o += interp ? align256(nmat * M * S * dbl) : 0;
   b.Z = o; o += align256(nmat * dp * ldz * dbl);
   b.X = o; o += align256(nmat * dp * ldz * dbl);
   b.part = o; o += align256(nmat * nt * HOLDOUT_KSPLIT * ldz * dbl);
@@ -217,11 +218,12 @@ hipError_t run_bucket(const Bucket& b, const pichol_batch_item* items,
     FitCoef fc;
     fit_coef(b.g, b.r, it0.lam_s, it0.lam_ref, it0.p.basis, &fc);
     double* th = at<double>(base, b.th);
+    double* tht = at<double>(base, b.tht);
     if (e == hipSuccess)
       e = upload_tau(it0.lam_grid, q, it0.lam_ref, it0.p.basis, tau, st);
-    if (e == hipSuccess) e = launch_fit(d, nmat, fc, L, th, nullptr, st);
+    if (e == hipSuccess) e = launch_fit(d, nmat, fc, L, th, tht, st);
     if (e == hipSuccess)
-      e = launch_solve_interp(d, nmat, c, M, th, q, tau, ldz, Z,
+      e = launch_solve_interp(d, nmat, c, M, th, tht, q, tau, ldz, Z,
                               at<double>(base, b.X), flags,
                               at<double>(base, b.dinv), 1, st);
   } else {

@@ -187,32 +187,6 @@ __device__ inline void mma_panel_scaled(Acc64& acc, const double* a,
   acc.mma(av, bv * scale);
 }
 
-// The same product with A' stored transposed: A'(i,k) at a[i*lda + k] (the
-// column-major tile of A'^T, read without a transposed copy).  Each lane
-// reads four consecutive k of one row with a 32-byte load, so within a
-// 16-long chunk of k the lane group l/16 supplies k = 4(l/16) + s in step s,
-// and the B operands follow the same order.  K is a multiple of 16.
-__device__ inline void mma_panel_scaled_t(Acc64& acc, const double* a,
-                                          int64_t lda, const double* b,
-                                          int64_t ldb, int K, v4d scale) {
-  const int l = threadIdx.x & 63, lq = l >> 4, lr = l & 15;
-  // A'(4lr + bi, k0 + 4lq + s) at pa[bi*lda + k0 + s];
-  // B'(k0 + 4lq + s, 4lr + bj) at pb[(k0 + s)*ldb + bj]
-  const double* pa = a + (int64_t)(4 * lr) * lda + 4 * lq;
-  const double* pb = b + (int64_t)(4 * lq) * ldb + 4 * lr;
-#pragma unroll 1
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    v4d ar[4], br[4];
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi) ar[bi] = ld4(pa + bi * lda + k0);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) br[s] = ld4(pb + (int64_t)(k0 + s) * ldb);
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-      acc.mma(v4d{ar[0][s], ar[1][s], ar[2][s], ar[3][s]}, br[s] * scale);
-  }
-}
-
 // acc -= sum over k in [0,K) of A'(i,k) B'(k,j) (the A operand negated).
 __device__ inline void mma_panel_sub(Acc64& acc, const double* a, int64_t lda,
                                      const double* b, int64_t ldb, int K) {

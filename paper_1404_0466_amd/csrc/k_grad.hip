@@ -19,11 +19,11 @@ namespace pichol {
 // Out rows of tile I, slab columns of block cb:
 //   Out_I = sum_{J >= I} sum_p Theta_p(J,I)^T (w_p(col) .* X_J),
 // i.e. (sum_p w_p Theta_p)^T X per lambda, with w[p*q + t] the weight of
-// plane p for lambda t (columns t*c .. t*c+c-1).  The tiles are read along
-// their columns (mma_panel_scaled_t), so no transposed copy is needed.
-// Four waves own 64 x 64 quarters of the 128 x 128 output block.
+// plane p for lambda t (columns t*c .. t*c+c-1).  The transposed tiles are
+// read from the row-major copy of the planes.  Four waves own 64 x 64
+// quarters of the 128 x 128 output block.
 __global__ void __launch_bounds__(256) k_trmv_interp(
-    int64_t dp, int nt, const double* theta, int64_t S, int M, int q, int c,
+    int64_t dp, int nt, const double* theta_t, int64_t S, int M, int q, int c,
     int64_t ldz, int ncb, const double* w, const double* X, double* Out) {
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int cb = id % ncb;
@@ -42,15 +42,14 @@ __global__ void __launch_bounds__(256) k_trmv_interp(
       wp[p][e] = (p < M && (col + e) < qc) ? w[p * q + (col + e) / c] : 0.0;
   Acc64 acc;
   acc.zero();
-  const double* planes = theta + m * M * S;
+  const double* planes = theta_t + m * M * S;
   const double* xb = X + m * dp * ldz + (int64_t)cb * NB + wj * 64;
   for (int J = I; J < nt; ++J) {
-    // A'(n, k) = Theta_p(J,I)(k, wi*64 + n), at n*128 + k
-    const double* tile = planes + tile_off(J, I) + (int64_t)wi * 64 * NB;
+    const double* tile = planes + tile_off(J, I) + wi * 64;
     const double* xj = xb + (int64_t)J * NB * ldz;
 #pragma unroll
     for (int p = 0; p < 8; ++p)
-      if (p < M) mma_panel_scaled_t(acc, tile + p * S, NB, xj, ldz, NB, wp[p]);
+      if (p < M) mma_panel_scaled(acc, tile + p * S, NB, xj, ldz, NB, wp[p]);
   }
   const int64_t row0 = m * dp + (int64_t)I * NB + wi * 64;
 #pragma unroll
@@ -100,14 +99,14 @@ __global__ void __launch_bounds__(64) k_grad_final(int nt, int q,
 }
 
 hipError_t launch_trmv_interp(int64_t d, int nmat, int M, int q, int c,
-                              int64_t ldz, const double* theta,
+                              int64_t ldz, const double* theta_t,
                               const double* w_dev, const double* X, double* Out,
                               hipStream_t s) {
   const int nt = (int)ntiles_of(d);
   const int64_t dp = (int64_t)nt * NB;
   const int ncb = (int)(ldz / NB);
   PICHOL_LAUNCH(k_trmv_interp, dim3((unsigned)(ncb * nt * nmat)), dim3(256), 0,
-                s, dp, nt, theta, packed_elems_of(d), M, q, c, ldz, ncb,
+                s, dp, nt, theta_t, packed_elems_of(d), M, q, c, ldz, ncb,
                 w_dev, X, Out);
   return hipGetLastError();
 }

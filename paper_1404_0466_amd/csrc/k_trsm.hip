@@ -297,8 +297,8 @@ __global__ void __launch_bounds__(256) k_diag_apply(int64_t d, int i, int nper,
 
 // Off-diagonal update for interpolated factors.  Forward step i: rows of
 // tile I > i lose sum_p Theta_p(I,i) (tau^p .* U_i); backward step i: rows
-// of tile I < i lose sum_p Theta_p(i,I)^T (tau^p .* W_i), the tile read
-// along its columns (mma_panel_scaled_t).  A workgroup owns a 64 x 128 block (half of
+// of tile I < i lose sum_p Theta_p(i,I)^T (tau^p .* W_i), read from the
+// row-major copy of the planes.  A workgroup owns a 64 x 128 block (half of
 // the tile's rows, one 128-column block of the slab); its four waves split
 // it into two 64-column halves and the 128-long sums of every plane into two
 // 64-long halves, so a launch has twice as many, twice as short workgroups
@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(256) k_diag_apply(int64_t d, int i, int nper,
 template <bool FWD>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_update_interp(
-    int64_t d, int i, const double* theta, int64_t S,
+    int64_t d, int i, const double* theta, const double* theta_t, int64_t S,
     int M, int q, int c, const double* tau, int64_t ldz, int ncb, int nrows,
     const double* X, double* Z) {
   __shared__ v4d xch[2][16][64];  // partial sums of the k-second-half waves
@@ -333,7 +333,8 @@ k_update_interp(
   for (int e = 0; e < 4; ++e)
     tau4[e] = (col + e) < qc ? tau[(col + e) / c] : 0.0;
 
-  const double* planes = theta + m * M * S + (FWD ? tile_off(I, i) : tile_off(i, I));
+  const double* planes = FWD ? theta + m * M * S + tile_off(I, i)
+                             : theta_t + m * M * S + tile_off(i, I);
   const double* bsrc = X + (m * dp + (int64_t)i * NB) * ldz + cb * NB + wj * 64;
   double* zt = Z + (m * dp + (int64_t)I * NB + rh * 64) * ldz + col;
   Acc64 acc;
@@ -348,12 +349,8 @@ k_update_interp(
   }
   v4d scale = {-1.0, -1.0, -1.0, -1.0};
   for (int p = 0; p < M; ++p) {
-    if constexpr (FWD)
-      mma_panel_scaled(acc, planes + p * S + rh * 64 + (int64_t)kh * 64 * NB, NB,
-                       bsrc + (int64_t)kh * 64 * ldz, ldz, 64, scale);
-    else  // Theta_p(i, I)^T: the tile read along its columns
-      mma_panel_scaled_t(acc, planes + p * S + (int64_t)rh * 64 * NB + kh * 64,
-                         NB, bsrc + (int64_t)kh * 64 * ldz, ldz, 64, scale);
+    mma_panel_scaled(acc, planes + p * S + rh * 64 + (int64_t)kh * 64 * NB, NB,
+                     bsrc + (int64_t)kh * 64 * ldz, ldz, 64, scale);
     scale *= tau4;
   }
   if (kh == 1) {
@@ -473,7 +470,7 @@ hipError_t launch_slab_init(int64_t d, int nmat, int q, int c, int64_t ldz,
 // Each diagonal apply reads one slab and writes the other, so its four
 // workgroups per (fold, lambda) never overwrite rows another one reads.
 hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
-                               const double* theta,
+                               const double* theta, const double* theta_t,
                                int q, const double* tau_dev, int64_t ldz,
                                double* Z, double* X, int* flags, double* dinv,
                                int prepare, hipStream_t s) {
@@ -491,7 +488,7 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
     if (i + 1 < nt) {
       const int nrows = nt - i - 1;
       PICHOL_LAUNCH(k_update_interp<true>, dim3(ncb * 2 * nrows * nmat),
-                    dim3(256), 0, s, d, i, theta, S, M, q, c, tau_dev,
+                    dim3(256), 0, s, d, i, theta, theta_t, S, M, q, c, tau_dev,
                     ldz, (int)ncb, nrows, X, Z);
     }
   }
@@ -500,7 +497,7 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
                   dinv, ldz, X, Z);
     if (i > 0)
       PICHOL_LAUNCH(k_update_interp<false>, dim3(ncb * 2 * i * nmat), dim3(256),
-                    0, s, d, i, theta, S, M, q, c, tau_dev, ldz,
+                    0, s, d, i, theta, theta_t, S, M, q, c, tau_dev, ldz,
                     (int)ncb, i, Z, X);
   }
   return hipGetLastError();

@@ -110,7 +110,7 @@ hipError_t launch_slab_init(int64_t d, int nmat, int q, int c, int64_t ldz,
                             const double* B, double* Z, int* flags,
                             hipStream_t s);
 hipError_t launch_solve_interp(int64_t d, int nmat, int c, int m,
-                               const double* theta,
+                               const double* theta, const double* theta_t,
                                int q, const double* tau_dev, int64_t ldz,
                                double* Z, double* X, int* flags, double* dinv,
                                int prepare, hipStream_t s);
@@ -157,7 +157,7 @@ hipError_t launch_slab_add(int64_t d, int nmat, int64_t ldz, const double* D,
 
 // ---- derivative of the hold-out error (k_grad.hip)
 hipError_t launch_trmv_interp(int64_t d, int nmat, int M, int q, int c,
-                              int64_t ldz, const double* theta,
+                              int64_t ldz, const double* theta_t,
                               const double* w_dev, const double* X, double* Out,
                               hipStream_t s);
 hipError_t launch_grad_dot(int64_t d, int nmat, int q, int c, int64_t ldz,

@@ -271,9 +271,8 @@ def test_solve_interp_matches_oracle(gu, d, c, g, r, q):
     Z = gu.empty(dp * ldz)
     flags = gu.empty(q, torch.int32)
     nb = gu.B.pichol_solve_interp_workspace(d, 1, q, c)
-    # theta_t is optional and not read by the solve: pass it for odd d only
-    gu.B.pichol_solve_interp(d, 1, c, r, th, tht if d % 2 else None, gu.dev(Bh), q,
-                             lam, lam_ref, Z, flags, gu.ws(nb), nb)
+    gu.B.pichol_solve_interp(d, 1, c, r, th, tht, gu.dev(Bh), q, lam, lam_ref, Z,
+                             flags, gu.ws(nb), nb)
     Wg = gu.slab_to_w(Z, d, 1, q, c)[0]
     T = np.stack([oracle.pack_lower(oracle.cholesky(H, l)[0]) for l in lam_s])
     Tho = oracle.fit(T, lam_s, r, lam_ref)
