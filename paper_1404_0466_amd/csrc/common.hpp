@@ -241,7 +241,6 @@ __device__ inline double bcast_lane(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Lane coordinates inside a 64 x 64 wave block.
 // A 128 x 128 lower-triangular matrix in LDS as its 36 blocks of 16 x 16:
 // block (I, J), I >= J, at blk_off(I, J), column-major with a column stride
 // of 17 doubles, so a wave reading a block along its columns (MFMA A
@@ -378,6 +377,7 @@ __device__ __forceinline__ void tri_inv_lds(double* S) {
   inv_level<4>(S, w, lq, lr);
 }
 
+// Lane coordinates inside a 64 x 64 wave block.
 struct LaneXY {
   int lq;  // l / 16
   int lr;  // l % 16
