@@ -9,14 +9,14 @@
 //                     (an FP64 MFMA product with the inverse);
 //   3. k_potrf_update subtracts L_{I,kk} L_{J,kk}^T from the trailing tiles
 //                     (FP64 MFMA, the bulk of the flops).
-// Step 1 runs as its own launch (k_potrf_diag) for the first panel and on
-// the mixed-precision path; otherwise the update launch that gives the
+// Step 1 runs as its own launch (k_potrf_diag) for the first panel (and on
+// the mixed-precision path for the first panel of each group, or for all
+// panels of a large batch); otherwise the update launch that gives the
 // diagonal tile its last update goes on to factor it, in the workgroups
 // that updated it.
 // One launch of each kernel covers the whole batch, so a batch of B
 // matrices of order d fills the GPU with B * (trailing tiles) workgroups.
 #include <mutex>
-#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -358,17 +358,17 @@ struct DiagOut {
 // workgroup ids are laid out matrix by matrix and spread over the XCDs in
 // contiguous ranges.
 // In both modes tile (j0, j0) receives its last update in this launch.  With
-// dout.fuse (FP64 only) the first nfac workgroups take those tiles, one per
-// matrix, and after the update go on to factor it (diag_factor_tile), so
+// dout.fuse (FUSABLE instantiations, whose register budget leaves room for
+// it) the first nfac workgroups take those tiles, one per matrix, and after
+// the update go on to factor it (diag_factor_tile), so
 // the diagonal factorization runs while the rest of the launch is still
 // updating; the other workgroups take the remaining tiles.
-template <typename ACC, bool SRC>
+template <typename ACC, bool SRC, bool FUSABLE>
 __device__ inline void potrf_update_body(int64_t S, int nt, int j0, int mode,
                                          int c0, int c1, int ntile, double* L,
                                          int64_t d, const ShiftSrc& src,
                                          const DiagOut& dout) {
-  constexpr bool kFusable = std::is_same<ACC, Acc64>::value;
-  const bool fuse = kFusable && dout.fuse;
+  const bool fuse = FUSABLE && dout.fuse;
   int f, t;
   if (fuse) {
     const int nfac = (int)gridDim.x / ntile;
@@ -434,7 +434,7 @@ __device__ inline void potrf_update_body(int64_t S, int nt, int j0, int mode,
         }
       }
   }
-  if constexpr (kFusable) {
+  if constexpr (FUSABLE) {
     if (fuse && t == 0) {
       // the tile's lower triangle, just stored by three of the four waves,
       // is read back by the whole workgroup once the barrier has passed
@@ -449,22 +449,34 @@ template <bool SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_potrf_update(int64_t S, int nt, int j0, int mode, int c0, int c1, int ntile,
                double* L, int64_t d, ShiftSrc src, DiagOut dout) {
-  potrf_update_body<Acc64, SRC>(S, nt, j0, mode, c0, c1, ntile, L, d, src,
-                                dout);
+  potrf_update_body<Acc64, SRC, true>(S, nt, j0, mode, c0, c1, ntile, L, d,
+                                      src, dout);
 }
 
 // Mixed precision: the same update with the products on FP32 MFMA (operands
 // rounded to FP32, FP32 accumulation over the 256-long sums); the tile
 // itself stays FP64.  FP32 accumulators take half the registers, so four
 // workgroups share a CU (measured faster than two at d = 4096); that budget
-// leaves no room for the diagonal factorization, which runs in its own
-// launches on this path.
+// leaves no room for the diagonal factorization.  The trailing updates use
+// this form, and the first panel of each group has its own diagonal launch.
 template <bool SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_potrf_update_f32(int64_t S, int nt, int j0, int mode, int c0, int c1,
                    int ntile, double* L, int64_t d, ShiftSrc src) {
-  potrf_update_body<Acc64F, SRC>(S, nt, j0, mode, c0, c1, ntile, L, d, src,
-                                 DiagOut{nullptr, nullptr, 0, 0, 0});
+  potrf_update_body<Acc64F, SRC, false>(S, nt, j0, mode, c0, c1, ntile, L, d,
+                                        src, DiagOut{nullptr, nullptr, 0, 0, 0});
+}
+
+// The mixed-precision column updates inside a group (short launches, with
+// the diagonal factorization on the critical path) at two workgroups per CU,
+// which leaves room for factoring the diagonal tile the launch completes.
+template <bool SRC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_potrf_update_f32_diag(int64_t S, int nt, int j0, int mode, int c0, int c1,
+                        int ntile, double* L, int64_t d, ShiftSrc src,
+                        DiagOut dout) {
+  potrf_update_body<Acc64F, SRC, true>(S, nt, j0, mode, c0, c1, ntile, L, d,
+                                       src, dout);
 }
 
 // Side stream for look-ahead: created once per device on first use, with
@@ -516,9 +528,15 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
   if (lookahead) lk.lock();
   SideStream* side = lookahead ? side_stream() : nullptr;
   // Every diagonal tile but the first is factored by the update launch that
-  // completes it (FP64 path): the column update inside a group, or the
-  // trailing update after it.  The mixed path launches k_potrf_diag itself.
-  const bool fuse = !mixed;
+  // completes it: the column update inside a group, or (FP64 path) the
+  // trailing update after it.  The mixed path launches k_potrf_diag itself
+  // for the first panel of each group, and for every panel when the batch
+  // is large: its fused column updates run two workgroups per CU instead of
+  // four, which costs more than the fusion saves once the launches fill the
+  // GPU (measured at d = 4096: 30 matrices 0.35 ms faster, 320 matrices
+  // 0.5 ms slower).
+  const bool fuse_cols = !mixed || nfac < 128;
+  const bool fuse_trail = !mixed;
   auto diag_panel = [&](int kk, bool first, bool factored) {
     const int64_t loff = keep_linv ? (int64_t)kk * NB2 : 0;
     if (!factored && first)
@@ -547,7 +565,13 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
     const dim3 grid((unsigned)(ntile * nfac));
     const DiagOut dout{info, linv_ws, lstride,
                        keep_linv ? (int64_t)j0 * NB2 : 0, fd ? 1 : 0};
-    if (mixed && first)
+    if (mixed && fd && first)
+      PICHOL_LAUNCH(k_potrf_update_f32_diag<true>, grid, dim3(256), 0, st, S,
+                    nt, j0, m, c0, c1, ntile, L, d, src, dout);
+    else if (mixed && fd)
+      PICHOL_LAUNCH(k_potrf_update_f32_diag<false>, grid, dim3(256), 0, st, S,
+                    nt, j0, m, c0, c1, ntile, L, d, src, dout);
+    else if (mixed && first)
       PICHOL_LAUNCH(k_potrf_update_f32<true>, grid, dim3(256), 0, st, S, nt,
                     j0, m, c0, c1, ntile, L, d, src);
     else if (mixed)
@@ -568,9 +592,11 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
     // the first group's launches are the first to touch every tile
     const bool first = has_src && kk == 0;
     for (int u = 0; u < G && kk + u < nt; ++u) {
-      if (u > 0) update(s, kk + u, 1, kk, kk + u, first, fuse);
+      if (u > 0) update(s, kk + u, 1, kk, kk + u, first, fuse_cols);
       // tile kk (u = 0) was factored by the previous group's trailing update
-      diag_panel(kk + u, first && u == 0, fuse && (u > 0 || kk > 0));
+      // on the FP64 path
+      diag_panel(kk + u, first && u == 0,
+                 u > 0 ? fuse_cols : (fuse_trail && kk > 0));
     }
     if (kk + G >= nt) break;
     if (pending) {
@@ -582,7 +608,7 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
       hipEvent_t ready = side->ev[ring++ & 7];
       hipError_t e = hipEventRecord(ready, s);
       if (e != hipSuccess) return e;
-      update(s, kk + G, G, kk, kk + G, first, fuse);  // the next group's columns
+      update(s, kk + G, G, kk, kk + G, first, fuse_trail);  // the next group's columns
       e = hipStreamWaitEvent(side->stream, ready, 0);
       if (e != hipSuccess) return e;
       update(side->stream, kk + 2 * G, 0, kk, kk + G, first, false);
@@ -596,7 +622,7 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
       }
       pending = true;
     } else {
-      update(s, kk + G, 0, kk, kk + G, first, fuse);
+      update(s, kk + G, 0, kk, kk + G, first, fuse_trail);
     }
   }
   if (pending) {
