@@ -243,20 +243,41 @@ __global__ void __launch_bounds__(256) k_diag_apply(int64_t d, int i, int nper,
   const int64_t zoff = (m * dp + (int64_t)i * NB) * ldz + (int64_t)t * c;
   const double* zs_src = src + zoff;
   double* zd = dst + zoff;
+  // The needed part of M in at most four 32-byte pieces per thread, all
+  // loaded before any is stored (pieces past the end re-read the last one,
+  // inside the tile, and are not stored).
+  const int npc = (khi - klo) * 8;  // pieces
   if (FWD) {
     // rows r0..r0+31 of M over the needed k: eight 32-byte pieces per k
-    for (int e = tid; e < (khi - klo) * 8; e += 256) {
+    v4d v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = min(tid + 256 * u, npc - 1);
       const int k = klo + (e >> 3), part = e & 7;
-      *(v4d*)(ms + k * 32 + part * 4) = ld4(M + (int64_t)k * NB + r0 + part * 4);
+      v[u] = ld4(M + (int64_t)k * NB + r0 + part * 4);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u;
+      if (e < npc) *(v4d*)(ms + (klo + (e >> 3)) * 32 + (e & 7) * 4) = v[u];
     }
   } else {
     // M(r0 + rr, k) = mat[(r0 + rr) * 128 + k]: 32-byte pieces along k,
     // consecutive lanes on consecutive rows (conflict-free LDS stores)
-    for (int e = tid; e < (khi - klo) * 8; e += 256) {
-      const int rr = e & 31, k = klo + 4 * (e >> 5);
-      const v4d v = ld4(M + (int64_t)(r0 + rr) * NB + k);
+    v4d v[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) ms[(k + u) * 32 + rr] = v[u];
+    for (int u = 0; u < 4; ++u) {
+      const int e = min(tid + 256 * u, npc - 1);
+      v[u] = ld4(M + (int64_t)(r0 + (e & 31)) * NB + klo + 4 * (e >> 5));
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u;
+      if (e < npc) {
+        const int rr = e & 31, k = klo + 4 * (e >> 5);
+#pragma unroll
+        for (int x = 0; x < 4; ++x) ms[(k + x) * 32 + rr] = v[u][x];
+      }
     }
   }
   for (int cg = 0; cg < c; cg += 16) {
