@@ -458,13 +458,21 @@ __global__ void __launch_bounds__(128) k_update_factors(int64_t d, int i,
             acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi][sk], bv[sk], acc[bi], 0, 0, 0);
       }
     }
-    // element v of block bi: row 16v + 4lq + bi of the half, column lr
+    // element v of block bi: row 16v + 4lq + bi of the half, column lr;
+    // the sixteen slab values are all loaded before any is stored
     if (cok) {
+      double cur[4][4];
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi)
-          zdst[(int64_t)(16 * v + 4 * lq + bi) * ldz + cg + lr] -= acc[bi][v];
+          cur[v][bi] = zdst[(int64_t)(16 * v + 4 * lq + bi) * ldz + cg + lr];
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+          zdst[(int64_t)(16 * v + 4 * lq + bi) * ldz + cg + lr] =
+              cur[v][bi] - acc[bi][v];
     }
   }
 }
