@@ -87,6 +87,21 @@ def test_mixed_factor_backward_error(gu, d):
         assert np.max(np.abs(Lg - L6)) > 0.0
 
 
+def test_mixed_large_batch_matches_small_batch(gu):
+    """Batches of 128 or more matrices take the mixed schedule with the
+    diagonal tiles in their own launches; smaller ones factor them inside
+    the column updates.  The arithmetic is the same, so each matrix's factor
+    must be the same bit for bit."""
+    d = 300
+    H = spd(d, 5 * d, cond=1e3)[None]
+    lam = np.logspace(-3, 0, 128)
+    Lbig, info_big = factor(gu, H, lam, gu.B.PICHOL_PREC_MIXED)
+    Lsmall, info_small = factor(gu, H, lam[:8], gu.B.PICHOL_PREC_MIXED)
+    assert np.all(info_big == 0) and np.all(info_small == 0)
+    S = gu.B.pichol_packed_elems(d)
+    np.testing.assert_array_equal(Lbig[:8 * S].cpu().numpy(), Lsmall.cpu().numpy())
+
+
 def test_mixed_factor_padding_is_exact(gu):
     d = 300
     Lm, info = factor(gu, spd(d, 9, 1e2)[None], np.array([0.1]), gu.B.PICHOL_PREC_MIXED)
