@@ -652,6 +652,67 @@ pichol_status pichol_cv_gram(const pichol_problem* p, const double* X,
                      at<double>(ws, L.B), stream);
 }
 
+// Second stream of the interpolated pipeline (default priority, created
+// once per device with two events).  While the last kLateColumns columns of
+// the sample factors are factored (short, latency-bound launches that leave
+// most of the GPU idle), it fits the columns already finished and inverts
+// their interpolated diagonal blocks.
+namespace {
+constexpr int kLateColumns = 8;
+struct OverlapStream {
+  bool ready = false;
+  hipStream_t stream = nullptr;
+  hipEvent_t start = nullptr, done = nullptr;
+};
+std::mutex g_overlap_mu;
+OverlapStream g_overlap[64];
+
+OverlapStream* overlap_stream() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  OverlapStream& os = g_overlap[dev];
+  if (!os.ready) {
+    if (hipStreamCreateWithFlags(&os.stream, hipStreamNonBlocking) != hipSuccess)
+      return nullptr;
+    if (hipEventCreateWithFlags(&os.start, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&os.done, hipEventDisableTiming) != hipSuccess)
+      return nullptr;
+    os.ready = true;
+  }
+  return &os;
+}
+
+// The early part of the fit and of the diagonal-block inverses, forked off
+// the caller's stream once column cols-1 of every sample factor is final.
+struct EarlyFit {
+  OverlapStream* os;
+  hipStream_t main;
+  int64_t d;
+  int k, q, M, cols;
+  const FitCoef* fc;
+  const double* Lf;
+  double *th, *tht, *dinv;
+  const double* tau;
+  int* flags;
+};
+
+hipError_t early_fit(void* ctx) {
+  const EarlyFit& c = *static_cast<const EarlyFit*>(ctx);
+  hipError_t e = hipEventRecord(c.os->start, c.main);
+  if (e == hipSuccess) e = hipStreamWaitEvent(c.os->stream, c.os->start, 0);
+  if (e != hipSuccess) return e;
+  e = launch_fit_cols(c.d, c.k, *c.fc, c.Lf, c.th, c.tht, 0, c.cols,
+                      c.os->stream);
+  if (e == hipSuccess)
+    e = launch_diag_inv(c.d, c.k, c.M, c.th, c.q, c.tau, c.dinv, c.flags, 0,
+                        c.cols, c.os->stream);
+  // the caller's stream waits for this event before it needs the results,
+  // so it is recorded even after a failed launch
+  const hipError_t r = hipEventRecord(c.os->done, c.os->stream);
+  return e != hipSuccess ? e : r;
+}
+}  // namespace
+
 pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
                                const double* lam_grid, double lam_ref, void* ws,
                                size_t ws_bytes, double* err, double* W,
@@ -678,23 +739,47 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
   double* th = at<double>(ws, L.i_th);
   double* tht = at<double>(ws, L.i_tht);
   double* Z = at<double>(ws, L.i_Z);
+  double* dinv = at<double>(ws, L.i_dinv);
   hipError_t e = launch_store_doubles(lam_s, g, lam_dev, stream);
   if (e == hipSuccess)
     e = upload_tau(lam_grid, q, lam_ref, p->basis, tau, stream);
+  // the flags are cleared here, before any diagonal-block inverse can set
+  // one of their bits
+  if (e == hipSuccess)
+    e = launch_slab_init(p->d, k, q, c, L.ldz, at<double>(ws, L.B), Z, flags,
+                         stream);
+  // columns 0 .. cols-1 are fitted and their diagonal blocks inverted on the
+  // second stream while the last columns are still being factored
+  const int nt = (int)L.nt;
+  std::unique_lock<std::mutex> lk(g_overlap_mu, std::defer_lock);
+  OverlapStream* os = nullptr;
+  if (nt > kLateColumns) {
+    lk.lock();
+    os = overlap_stream();
+  }
+  const int cols = os ? nt - kLateColumns : 0;
+  EarlyFit ef{os, stream, p->d, k, q, M, cols, &fc, Lf, th, tht, dinv, tau,
+              flags};
+  const PanelHook hook{cols - 1, early_fit, &ef};
   if (e == hipSuccess)
     e = launch_potrf_blocked(p->d, k * g,
                              ShiftSrc{at<double>(ws, L.H), g, lam_dev, k}, Lf,
                              info, at<double>(ws, L.i_linv), 0,
                              p->precision == PICHOL_PREC_MIXED,
-                             option_lookahead(), 0, stream);
-  if (e == hipSuccess) e = launch_fit(p->d, k, fc, Lf, th, tht, stream);
+                             option_lookahead(), 0, stream, os ? &hook : nullptr);
   if (e == hipSuccess)
-    e = launch_slab_init(p->d, k, q, c, L.ldz, at<double>(ws, L.B), Z, flags,
-                         stream);
+    e = launch_fit_cols(p->d, k, fc, Lf, th, tht, cols, nt, stream);
+  if (os) {
+    // join the second stream (its work was forked by the hook, which ran
+    // unless an earlier launch failed)
+    const hipError_t j = hipStreamWaitEvent(stream, os->done, 0);
+    if (e == hipSuccess) e = j;
+  }
+  if (e == hipSuccess)
+    e = launch_diag_inv(p->d, k, M, th, q, tau, dinv, flags, cols, nt, stream);
   if (e == hipSuccess)
     e = launch_solve_interp(p->d, k, c, M, th, tht, q, tau, L.ldz, Z,
-                            at<double>(ws, L.i_X), flags,
-                            at<double>(ws, L.i_dinv), 1, stream);
+                            at<double>(ws, L.i_X), flags, dinv, 0, stream);
   if (e == hipSuccess && p->refine > 0) {
     // Residual correction against H_f + lambda_t I; the correction solves
     // reuse the inverted diagonal blocks of the interpolated factors.

@@ -13,14 +13,21 @@
 namespace pichol {
 
 // Theta(m, p) tile (I,J) = sum_s P[p][s] L(m, s) tile (I,J); also written
-// with the tile stored row-major into theta_t (when non-null).
+// with the tile stored row-major into theta_t (when non-null).  The grid
+// covers the tiles of columns J0, J0+1, ... column by column (each column J
+// holds the tiles I = J .. nt-1).
 template <int M>
 __global__ void __launch_bounds__(256) k_fit(int64_t S, FitCoef fc,
                                              const double* L, double* theta,
-                                             double* theta_t) {
+                                             double* theta_t, int nt, int J0) {
   __shared__ double lds[16 * LDS_LD];
   const int64_t m = blockIdx.y;
-  const int I = tri_row(blockIdx.x), J = blockIdx.x - (int)tri(I);
+  int J = J0, I = blockIdx.x;
+  while (I >= nt - J) {
+    I -= nt - J;
+    ++J;
+  }
+  I += J;
   const int64_t toff = tile_off(I, J);
   const int g = fc.g;
   const int tid = threadIdx.x;
@@ -91,15 +98,21 @@ __global__ void __launch_bounds__(256) k_eval(int64_t S, int M,
   }
 }
 
-hipError_t launch_fit(int64_t d, int nmat, const FitCoef& fc, const double* L,
-                      double* theta, double* theta_t, hipStream_t s) {
-  const int64_t nt = ntiles_of(d), S = packed_elems_of(d);
-  dim3 grid((unsigned)tri(nt), (unsigned)nmat);
+hipError_t launch_fit_cols(int64_t d, int nmat, const FitCoef& fc,
+                           const double* L, double* theta, double* theta_t,
+                           int J0, int J1, hipStream_t s) {
+  const int nt = (int)ntiles_of(d);
+  const int64_t S = packed_elems_of(d);
+  if (J0 < 0 || J1 > nt || J0 > J1) return hipErrorInvalidValue;
+  // tiles of columns J0 .. J1-1
+  const int64_t ntile = tri(nt - J0) - tri(nt - J1);
+  if (ntile == 0) return hipSuccess;
+  dim3 grid((unsigned)ntile, (unsigned)nmat);
   switch (fc.m) {
 #define PICHOL_FIT_CASE(MM)                                                   \
   case MM:                                                                    \
-    PICHOL_LAUNCH(k_fit<MM>, grid, dim3(256), 0, s, S, fc, L, theta,     \
-                       theta_t);                                              \
+    PICHOL_LAUNCH(k_fit<MM>, grid, dim3(256), 0, s, S, fc, L, theta,          \
+                  theta_t, nt, J0);                                           \
     break;
     PICHOL_FIT_CASE(1)
     PICHOL_FIT_CASE(2)
@@ -114,6 +127,12 @@ hipError_t launch_fit(int64_t d, int nmat, const FitCoef& fc, const double* L,
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_fit(int64_t d, int nmat, const FitCoef& fc, const double* L,
+                      double* theta, double* theta_t, hipStream_t s) {
+  return launch_fit_cols(d, nmat, fc, L, theta, theta_t, 0,
+                         (int)ntiles_of(d), s);
 }
 
 hipError_t launch_eval(int64_t d, int nmat, int m, const double* theta,

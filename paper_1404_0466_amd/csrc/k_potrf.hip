@@ -508,8 +508,9 @@ static SideStream* side_stream() {
 // factorization, column kk+u receives the group's earlier panels (K = 128 u);
 // after the group, one update of rank 128 G reaches the rest of the trailing
 // matrix.  On the FP64 path each of these launches also factors the
-// diagonal tile it completes (tile kk+u, or the next group's first).  With the look-ahead option on, that update is split: the G
-// columns the next group factors stay on the caller's stream, the remainder
+// diagonal tile it completes (tile kk+u, or the next group's first).  With
+// the look-ahead option on, that update is split: the G columns the next
+// group factors stay on the caller's stream, the remainder
 // runs on a side stream, so the next group's diagonal factorizations, panel
 // solves and column updates (short, latency-bound launches) overlap the bulk
 // of the update.  The side update is joined before the next group's own
@@ -517,7 +518,8 @@ static SideStream* side_stream() {
 hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
                                 double* L, int* info, double* linv_ws,
                                 int keep_linv, int mixed, int lookahead,
-                                int group, hipStream_t s) {
+                                int group, hipStream_t s,
+                                const PanelHook* hook) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
   // inverse of panel kk of factor f: at f * NB2 (scratch, overwritten by
@@ -597,6 +599,10 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
       // on the FP64 path
       diag_panel(kk + u, first && u == 0,
                  u > 0 ? fuse_cols : (fuse_trail && kk > 0));
+      if (hook && kk + u == hook->col) {
+        const hipError_t e = hook->fn(hook->ctx);
+        if (e != hipSuccess) return e;
+      }
     }
     if (kk + G >= nt) break;
     if (pending) {

@@ -158,14 +158,13 @@ __global__ void __launch_bounds__(256) k_diag_solve(int64_t d, int i,
 // forward substitution, joined on FP64 MFMA).  77 KB of LDS, so two
 // workgroups share a CU.  Writes the inverse, column-major with zeros above
 // the diagonal, to dinv.  A non-positive diagonal entry of the block sets
-// flag bit1.
+// flag bit1.  The grid covers the tile rows i0, i0+1, ...
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_diag_inv(int64_t d, FactorSrc src,
-                                                  double* dinv, int* flags) {
+k_diag_inv(int64_t d, FactorSrc src, double* dinv, int* flags, int i0) {
   __shared__ double S[TRI_LDS];
-  const int i = blockIdx.x, t = blockIdx.y;
+  const int i = i0 + (int)blockIdx.x, t = blockIdx.y;
   const int64_t m = blockIdx.z;
-  const int nt = gridDim.x;
+  const int nt = (int)ntiles_of(d);
   const int tid = threadIdx.x;
   const double* planes = src.base + m * src.M * src.S + tile_off(i, i);
   const double tau = src.tau[t];
@@ -498,6 +497,21 @@ hipError_t launch_slab_init(int64_t d, int nmat, int q, int c, int64_t ldz,
 // blocks in X; back steps take them from X and leave the solution in Z.
 // Each diagonal apply reads one slab and writes the other, so its four
 // workgroups per (fold, lambda) never overwrite rows another one reads.
+// The inverted diagonal blocks of tile rows i0 .. i1-1 of every
+// interpolated factor (k_diag_inv).
+hipError_t launch_diag_inv(int64_t d, int nmat, int M, const double* theta,
+                           int q, const double* tau_dev, double* dinv,
+                           int* flags, int i0, int i1, hipStream_t s) {
+  const int nt = (int)ntiles_of(d);
+  if (i0 < 0 || i1 > nt || i0 > i1) return hipErrorInvalidValue;
+  if (i0 == i1) return hipSuccess;
+  FactorSrc src{theta, packed_elems_of(d), M, 0, q, tau_dev};
+  PICHOL_LAUNCH(k_diag_inv,
+                dim3((unsigned)(i1 - i0), (unsigned)q, (unsigned)nmat),
+                dim3(256), 0, s, d, src, dinv, flags, i0);
+  return hipGetLastError();
+}
+
 hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
                                const double* theta, const double* theta_t,
                                int q, const double* tau_dev, int64_t ldz,
@@ -506,10 +520,11 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
   const unsigned ncb = (unsigned)(ldz / NB);
-  FactorSrc src{theta, S, M, 0, q, tau_dev};
-  if (prepare)
-    PICHOL_LAUNCH(k_diag_inv, dim3((unsigned)nt, (unsigned)q, (unsigned)nmat),
-                  dim3(256), 0, s, d, src, dinv, flags);
+  if (prepare) {
+    const hipError_t e =
+        launch_diag_inv(d, nmat, M, theta, q, tau_dev, dinv, flags, 0, nt, s);
+    if (e != hipSuccess) return e;
+  }
   const dim3 agrid((unsigned)(4 * q), (unsigned)nmat);
   for (int i = 0; i < nt; ++i) {
     PICHOL_LAUNCH(k_diag_apply<true>, agrid, dim3(256), 0, s, d, i, q, c, dinv,

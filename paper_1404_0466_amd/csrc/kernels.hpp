@@ -81,10 +81,19 @@ struct ShiftSrc {
 // linv_ws: nfac * 16384 doubles of scratch, or with keep_linv
 // nfac * ceil(d/128) * 16384 doubles that keep the inverse of every
 // diagonal tile, (f * nt + I) * 16384 for tile I of factor f.
+// Called by launch_potrf_blocked once the launches that finish column `col`
+// (its diagonal tile and panel) are enqueued on the stream: every tile of
+// columns 0 .. col is then final once the stream reaches that point.
+struct PanelHook {
+  int col;
+  hipError_t (*fn)(void* ctx);
+  void* ctx;
+};
 hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
                                 double* L, int* info, double* linv_ws,
                                 int keep_linv, int mixed, int lookahead,
-                                int group, hipStream_t s);
+                                int group, hipStream_t s,
+                                const PanelHook* hook = nullptr);
 
 // ---- fit / evaluate (k_fit.hip)
 struct FitCoef {
@@ -93,6 +102,10 @@ struct FitCoef {
 };
 hipError_t launch_fit(int64_t d, int nmat, const FitCoef& fc, const double* L,
                       double* theta, double* theta_t, hipStream_t s);
+// The fit of the tiles of columns J0 .. J1-1 only.
+hipError_t launch_fit_cols(int64_t d, int nmat, const FitCoef& fc,
+                           const double* L, double* theta, double* theta_t,
+                           int J0, int J1, hipStream_t s);
 hipError_t launch_fit_flat(int64_t N, int nmat, const FitCoef& fc,
                            const double* T, double* theta, hipStream_t s);
 hipError_t launch_eval_flat(int64_t N, int nmat, int m, const double* theta,
@@ -109,6 +122,11 @@ hipError_t launch_eval(int64_t d, int nmat, int m, const double* theta,
 hipError_t launch_slab_init(int64_t d, int nmat, int q, int c, int64_t ldz,
                             const double* B, double* Z, int* flags,
                             hipStream_t s);
+// The inverted diagonal blocks of tile rows i0 .. i1-1 of every
+// interpolated factor, as pichol_solve_interp prepares them.
+hipError_t launch_diag_inv(int64_t d, int nmat, int M, const double* theta,
+                           int q, const double* tau_dev, double* dinv,
+                           int* flags, int i0, int i1, hipStream_t s);
 hipError_t launch_solve_interp(int64_t d, int nmat, int c, int m,
                                const double* theta, const double* theta_t,
                                int q, const double* tau_dev, int64_t ldz,
