@@ -318,7 +318,14 @@ pichol_status pichol_cv_gram(const pichol_problem *p, const double *X,
  *   err  k*q (device) hold-out mean squared error
  *   W    k*q*d*c (device) weights, or NULL
  *   info k*g (device) status of the sample factorizations
- *   flags k*q (device) */
+ *   flags k*q (device)
+ * When d spans more than 8 tiles of 128, the fit and the diagonal-block
+ * inverses of the finished columns run on a second stream that the library
+ * creates once per device (default priority); it is forked from and joined
+ * back into `stream` by events inside the call, so the call stays ordered
+ * on `stream` and may be captured into a graph.  Calls from several host
+ * threads take a library mutex for their host part and are serialised
+ * there. */
 pichol_status pichol_cv_interp(const pichol_problem *p, const double *lam_s,
                                const double *lam_grid, double lam_ref,
                                void *ws, size_t ws_bytes, double *err,

@@ -672,11 +672,23 @@ OverlapStream* overlap_stream() {
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
   OverlapStream& os = g_overlap[dev];
   if (!os.ready) {
-    if (hipStreamCreateWithFlags(&os.stream, hipStreamNonBlocking) != hipSuccess)
+    // each handle is created once: a call that failed part-way keeps what it
+    // made and the next call creates only the rest
+    if (!os.stream &&
+        hipStreamCreateWithFlags(&os.stream, hipStreamNonBlocking) != hipSuccess) {
+      os.stream = nullptr;
       return nullptr;
-    if (hipEventCreateWithFlags(&os.start, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&os.done, hipEventDisableTiming) != hipSuccess)
+    }
+    if (!os.start &&
+        hipEventCreateWithFlags(&os.start, hipEventDisableTiming) != hipSuccess) {
+      os.start = nullptr;
       return nullptr;
+    }
+    if (!os.done &&
+        hipEventCreateWithFlags(&os.done, hipEventDisableTiming) != hipSuccess) {
+      os.done = nullptr;
+      return nullptr;
+    }
     os.ready = true;
   }
   return &os;
