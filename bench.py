@@ -339,7 +339,7 @@ def differentiation_leg(args, B, stream):
     import workloads
 
     t0 = time.perf_counter()
-    pb = workloads.config(2)
+    pb = workloads.named("rff_n20000_d2048")
     log(f"differentiation workload {pb.name} ({time.perf_counter() - t0:.1f} s)")
     dev = torch.device("cuda:0")
     n, d, c, k, g, r, q = pb.n, pb.d, pb.c, pb.k, pb.g, pb.r, pb.q
@@ -594,12 +594,15 @@ def layout_leg(args, B, stream):
 
 
 def main():
+    import workloads
+
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=3,
-                    help="workload: 1 (d=256), 2 (d=2048), 3 (d=4096, default)")
+    ap.add_argument("--workload", default="rff_n60000_d4096",
+                    choices=workloads.WORKLOADS,
+                    help="named workload (default: the d=4096 one)")
     ap.add_argument("--no-exact", action="store_true",
                     help="skip the exact baseline stage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -635,7 +638,6 @@ def main():
         sys.exit(2)
 
     import torch
-    import workloads
     from paper_1404_0466_amd import binding as B
 
     if not torch.cuda.is_available():
@@ -645,9 +647,9 @@ def main():
     B.pichol_set_option(B.PICHOL_OPT_LOOKAHEAD, args.lookahead)
     dev = torch.device("cuda:0")
 
-    log(f"generating workload {args.config}")
+    log(f"generating workload {args.workload}")
     t0 = time.perf_counter()
-    prob = workloads.config(args.config)
+    prob = workloads.named(args.workload)
     log(f"workload {prob.name}: n={prob.n} d={prob.d} c={prob.c} k={prob.k} "
         f"g={prob.g} r={prob.r} q={prob.q} ({time.perf_counter() - t0:.1f} s)")
     n, d, c, k, g, r, q = prob.n, prob.d, prob.c, prob.k, prob.g, prob.r, prob.q

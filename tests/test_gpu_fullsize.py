@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def big(gpu):
     import gpu_util
-    prob = workloads.config(3)
+    prob = workloads.named("rff_n60000_d4096")
     return gpu_util, prob
 
 
@@ -114,7 +114,7 @@ def test_batch_fullsize_matches_oracle_and_single(manyprob):
 @pytest.fixture(scope="module")
 def c5(gpu):
     import gpu_util
-    return gpu_util, workloads.config(2)
+    return gpu_util, workloads.named("rff_n20000_d2048")
 
 
 def _grad(gu, prob, lam_grid, method="interp"):

@@ -294,15 +294,15 @@ def _check_cv(got, want, rel_err=1e-10, rel_w=1e-9):
         close(got["W"], want["W"], rel_w, "W")
 
 
-def test_cv_interp_config1(gu):
-    p = workloads.config(1)
+def test_cv_interp_gauss_n2000_d256(gu):
+    p = workloads.named("gauss_n2000_d256")
     got = gu.cv(p, "interp")
     want = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r, want_W=True)
     _check_cv(got, want)
 
 
-def test_cv_exact_config1(gu):
-    p = workloads.config(1)
+def test_cv_exact_gauss_n2000_d256(gu):
+    p = workloads.named("gauss_n2000_d256")
     got = gu.cv(p, "exact")
     want = oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid, want_W=True)
     _check_cv(got, want)
@@ -333,6 +333,18 @@ def test_cv_rff_midsize(gu):
     gote = gu.cv(p, "exact", want_W=False)
     wante = oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid)
     _check_cv(gote, wante)
+
+
+@pytest.mark.parametrize("d", [1024, 1025, 1300])
+def test_cv_interp_around_overlap_threshold(gu, d):
+    """Above eight tile columns the fit and the diagonal-block inverses of
+    the finished columns run on a second stream while the last eight columns
+    are factored: at d=1024 (eight columns) nothing is forked, at 1025 one
+    column is (the ninth column is a one-row ragged tile), at 1300 three."""
+    p = workloads.gaussian_problem(2 * d + 7, d, 3, seed=21, g=4, q=8)
+    got = gu.cv(p, "interp")
+    want = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r, want_W=True)
+    _check_cv(got, want)
 
 
 def test_cv_interp_is_exact_when_samples_are_the_grid(gu):

@@ -410,10 +410,10 @@ def test_selection_helpers():
     np.testing.assert_allclose(g["curve_gap"], 4.0)
 
 
-def test_config1_matches_known_behaviour():
-    """Config 1 (Gaussian, n=2000, d=256): piCholesky selects the same grid
+def test_gauss_n2000_d256_matches_known_behaviour():
+    """Gaussian workload n=2000, d=256: piCholesky selects the same grid
     value as exact CV and its curve stays within 1% of it."""
-    p = workloads.config(1)
+    p = workloads.named("gauss_n2000_d256")
     ex = oracle.cv_exact(p.X, p.Y, p.k, p.lam_grid)
     pi = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r)
     g = oracle.gaps(oracle.cv_curve(pi["mse"]), oracle.cv_curve(ex["mse"]), p.lam_grid)

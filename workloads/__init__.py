@@ -176,22 +176,24 @@ def batch_problems(count: int = 48, seed0: int = 1000, ds=BATCH_DS,
     return out
 
 
-def config(i: int) -> Problem:
-    """The workloads of the parity tests and the benchmark.
+WORKLOADS = ("gauss_n2000_d256", "rff_n20000_d2048", "rff_n60000_d4096")
 
-    1: Gaussian, n=2000, d=256, c=10, k=5, g=4, r=2, q=31, range [1e-4, 1e1]
-    2: random Fourier features, n=20000, d=2048, c=10, k=5, g=6, r=2, q=64,
-       range [1e-6, 1]
-    3: random Fourier features, n=60000, d=4096, c=10, k=5, g=6, r=2, q=64,
-       range [1e-6, 1] (the benchmark workload)
+
+def named(name: str) -> Problem:
+    """The named workloads of the parity tests and the benchmark.
+
+    gauss_n2000_d256: Gaussian, n=2000, d=256, c=10, k=5, g=4, r=2, q=31,
+        range [1e-4, 1e1]
+    rff_n20000_d2048: random Fourier features, n=20000, d=2048, c=10, k=5,
+        g=6, r=2, q=64, range [1e-6, 1]
+    rff_n60000_d4096: random Fourier features, n=60000, d=4096, c=10, k=5,
+        g=6, r=2, q=64, range [1e-6, 1] (the benchmark workload)
     """
-    if i == 1:
+    if name == "gauss_n2000_d256":
         return gaussian_problem(2000, 256, 10, seed=0, g=4, r=2, q=31,
-                                lam_range=(1e-4, 1e1), name="gauss_n2000_d256")
-    if i == 2:
-        return rff_problem(20000, 2048, 10, seed=0, g=6, r=2, q=64,
-                           name="rff_n20000_d2048")
-    if i == 3:
-        return rff_problem(60000, 4096, 10, seed=0, g=6, r=2, q=64,
-                           name="rff_n60000_d4096")
-    raise ValueError(f"unknown workload {i}")
+                                lam_range=(1e-4, 1e1), name=name)
+    if name == "rff_n20000_d2048":
+        return rff_problem(20000, 2048, 10, seed=0, g=6, r=2, q=64, name=name)
+    if name == "rff_n60000_d4096":
+        return rff_problem(60000, 4096, 10, seed=0, g=6, r=2, q=64, name=name)
+    raise ValueError(f"unknown workload {name!r}; known: {', '.join(WORKLOADS)}")
