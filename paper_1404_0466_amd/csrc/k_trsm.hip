@@ -246,6 +246,20 @@ __global__ void __launch_bounds__(256) k_diag_apply(int64_t d, int i, int nper,
   // loaded before any is stored (pieces past the end re-read the last one,
   // inside the tile, and are not stored).
   const int npc = (khi - klo) * 8;  // pieces
+  // Right-hand sides of columns cg .. cg+15 (zero past the lambda's c
+  // columns): every load unconditional, at most column c-1, so the loads of
+  // the first block are in flight together with those of M.
+  auto load_z = [&](int cg, double (&zv)[8]) {
+    const int cn = (c - cg) < 16 ? (c - cg) : 16;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + 256 * u, k = e >> 4, cc = e & 15;
+      const double x = zs_src[(int64_t)k * ldz + cg + min(cc, cn - 1)];
+      zv[u] = cc < cn ? x : 0.0;
+    }
+  };
+  double zv[8];
+  load_z(0, zv);
   if (FWD) {
     // rows r0..r0+31 of M over the needed k: eight 32-byte pieces per k
     v4d v[4];
@@ -281,12 +295,9 @@ __global__ void __launch_bounds__(256) k_diag_apply(int64_t d, int i, int nper,
   }
   for (int cg = 0; cg < c; cg += 16) {
     const int cn = (c - cg) < 16 ? (c - cg) : 16;
-    if (cg) __syncthreads();
-    double zv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = tid + 256 * u, k = e >> 4, cc = e & 15;
-      zv[u] = cc < cn ? zs_src[(int64_t)k * ldz + cg + cc] : 0.0;
+    if (cg) {
+      __syncthreads();
+      load_z(cg, zv);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) zs[tid + 256 * u] = zv[u];
