@@ -148,7 +148,7 @@ struct HoldoutNorm {
 // The hold-out products split their 128-row-block sums over this many
 // ranges of column blocks (more, shorter workgroups); partial sums hold
 // nmat * nt * HOLDOUT_KSPLIT * ldz doubles.
-constexpr int HOLDOUT_KSPLIT = 4;
+constexpr int HOLDOUT_KSPLIT = 8;
 hipError_t launch_holdout_partial(int64_t d, int nmat, int c, int q,
                                   int64_t ldz, const double* Z,
                                   const double* G, const double* C,
