@@ -18,9 +18,11 @@ C-contiguous float64 copies, outputs are freshly allocated.
 Parity status: every entry point is pinned by the CPU tests in
 ``tests/test_oracle_*.py`` (closed forms, LAPACK, SVD ridge form, polynomial
 reproduction, interpolation of the samples, the error bound of Thm. 4.7 at
-tiny sizes).  The off-sample interpolated hold-out curve at large d has no pin
-beyond these building blocks: its parity there is "parity unpinned" beyond the
-oracle itself.
+tiny sizes).  The whole interpolated pipeline off the samples is pinned at
+small d against the same steps composed from library routines (LAPACK
+Cholesky, numpy polyfit/polyval, LAPACK triangular solves, the validation
+residual).  At large d the curve has no pin beyond these: its parity there is
+"parity unpinned" beyond the oracle itself.
 """
 from __future__ import annotations
 

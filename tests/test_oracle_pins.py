@@ -363,6 +363,42 @@ def test_interp_equals_exact_when_samples_are_the_grid():
     np.testing.assert_allclose(pi["W"], ex["W"], rtol=0, atol=1e-8 * np.abs(ex["W"]).max())
 
 
+@pytest.mark.parametrize("g,r", [(4, 3), (6, 2)])
+def test_interp_cv_off_sample_matches_library_composition(g, r):
+    """piCholesky CV (sec. 4: exact factors at the samples, an entry-wise
+    polynomial of degree r in lambda fitted by least squares, evaluated off
+    the samples, then the two triangular solves and the hold-out error) at
+    grid values between and beyond the samples, against the same steps done
+    with independent library routines: LAPACK Cholesky of the normalised
+    training Gram, numpy's polyfit/polyval on every entry, LAPACK triangular
+    solves and the residual of the validation rows."""
+    from numpy.polynomial import polynomial as P
+    p = workloads.gaussian_problem(180, 12, 3, seed=31, k=3, g=g, q=9,
+                                   lam_range=(1e-2, 2.0))
+    lam_s = np.geomspace(0.03, 1.5, g)
+    lam_grid = np.concatenate([np.geomspace(0.012, 1.9, 8), [2.5]])
+    out = oracle.cv_interp(p.X, p.Y, p.k, lam_s, lam_grid, r, want_W=True)
+    b = oracle.fold_bounds(p.n, p.k)
+    x = lam_s / lam_s.max()
+    for f in range(p.k):
+        mask = np.ones(p.n, bool)
+        mask[b[f]:b[f + 1]] = False
+        Xt, Yt, Xv, Yv = p.X[mask], p.Y[mask], p.X[~mask], p.Y[~mask]
+        ntr = mask.sum()
+        H, B = Xt.T @ Xt / ntr, Xt.T @ Yt / ntr
+        Ls = np.stack([np.linalg.cholesky(H + lam * np.eye(p.d)) for lam in lam_s])
+        coef = P.polyfit(x, Ls.reshape(g, -1), r)  # (r+1) x d^2
+        for t, lam in enumerate(lam_grid):
+            L = P.polyval(lam / lam_s.max(), coef).reshape(p.d, p.d)
+            L = np.tril(L)
+            z = scipy.linalg.solve_triangular(L, B, lower=True)
+            w = scipy.linalg.solve_triangular(L.T, z, lower=False)
+            np.testing.assert_allclose(out["W"][f, t], w, rtol=0,
+                                       atol=1e-9 * np.abs(w).max())
+            mse = np.sum((Yv - Xv @ w) ** 2) / Yv.size
+            np.testing.assert_allclose(out["mse"][f, t], mse, rtol=1e-9)
+
+
 def test_interp_cv_reproduces_sample_points():
     """At grid values that coincide with samples, r = g - 1 reproduces the
     exact hold-out errors even when the rest of the grid is interpolated."""
