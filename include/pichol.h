@@ -28,7 +28,15 @@
  *                      (and, in pichol_solve_factors, of a given factor;
  *                      the cross-validation calls report a failed exact
  *                      factorization through info, and its NaN results
- *                      through bit0).
+ *                      through bit0),
+ *               bit2 = advisory: the hold-out error came from the Gram
+ *                      expansion of |Y_v - X_v W|^2 (pichol_holdout) and
+ *                      cancellation there may cost it more than 1e-11 of
+ *                      its relative accuracy (a well-fitted target: |R|^2
+ *                      far below |Y_v|^2).  The calls that hold X and Y
+ *                      (pichol_cv, pichol_exact_cv, pichol_cv_batch)
+ *                      recompute such units from the residual itself
+ *                      (pichol_holdout_direct) and clear the bit.
  *  - Results are bitwise reproducible from run to run (no floating-point
  *    atomics; every reduction has a fixed order).
  *  - All arithmetic is IEEE FP64, except where a call is asked for
@@ -276,9 +284,14 @@ pichol_status pichol_solve_factors(int64_t d, int32_t nmat, int32_t nper,
 size_t pichol_holdout_workspace(int64_t d, int32_t nmat, int32_t q,
                                 int32_t c);
 
-/* Hold-out error of every (fold, lambda): with R = Y_v - X_v W,
+/* Hold-out error of every (fold, lambda), the quantity whose mean over the
+ * folds k-fold cross-validation minimises over lambda (Sec. 3.1; its mean
+ * squared form, the hold-out errors of Sec. 6.5): with R = Y_v - X_v W,
  * sse = |R|_F^2 computed as |Y_v|^2 - 2<W, X_v^T Y_v> + <W, X_v^T X_v W>,
- * err = sse / (nv * c).
+ * err = sse / (nv * c).  The expansion reads the validation Gram matrices
+ * of the Gram step instead of X_v; where its terms cancel (estimated
+ * rounding 4 eps |Y_v|^2 (sqrt(nv) + sqrt(dp)) above 1e-11 sse, or
+ * sse <= 0) flags bit2 is set (see pichol_holdout_direct).
  * In:  Z nmat slabs (device, as produced by the solve calls);
  *      G, C, yy of the validation blocks (device, as from pichol_gram;
  *      G is symmetric and only its tiles (I,J) with J <= I are read);
@@ -291,6 +304,26 @@ pichol_status pichol_holdout(int64_t d, int32_t nmat, int32_t c, int32_t q,
                              const double *C, const double *yy,
                              const int64_t *nv, double *err, int32_t *flags,
                              void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Scratch bytes for pichol_holdout_direct (0 on invalid arguments). */
+size_t pichol_holdout_direct_workspace(const pichol_problem *p);
+
+/* Hold-out error of every (fold, lambda) from its definition (Sec. 3.1):
+ * R = Y_v - X_v W, err = |R|_F^2 / (nv * c), the product X_v W on FP64
+ * MFMA (2 nv d q c flops per fold; the squares summed per 128-row block,
+ * then over the blocks in order).  This is the form the oracle takes; the
+ * pipeline calls with X at hand use it for the units flagged bit2 by the
+ * Gram expansion.
+ * In:  p (n, d, c, k, q, normalize, ldx, ldy are used), X, Y (device, as
+ *      for pichol_gram); Z k slabs of dp x pichol_slab_cols(q, c) (device,
+ *      as produced by the solve calls, rows >= d zero).
+ * Out: err k*q (device); flags k*q (device, read and updated): bit2
+ *      cleared, bit0 OR-ed in when err is not finite.
+ * ws: pichol_holdout_direct_workspace(p) bytes. */
+pichol_status pichol_holdout_direct(const pichol_problem *p, const double *X,
+                                    const double *Y, const double *Z,
+                                    double *err, int32_t *flags, void *ws,
+                                    size_t ws_bytes, hipStream_t stream);
 
 /* Copy slabs to the k x q x d x c weight layout: W[m][t][i][j] =
  * Z[m][i][t*c + j]. */
@@ -311,9 +344,12 @@ pichol_status pichol_cv_gram(const pichol_problem *p, const double *X,
                              const double *Y, void *ws, size_t ws_bytes,
                              hipStream_t stream);
 
-/* Stage 2 (piCholesky): from the Grams in ws, the g sample factorizations
- * per fold, the fit, the solves at the q grid values and the hold-out
- * errors.
+/* Stage 2 (piCholesky, Algorithm 1 and the evaluation of Sec. 3.3): from
+ * the Grams in ws, the g sample factorizations per fold (Algorithm 1 step
+ * 1), the least-squares fit of every factor entry (steps 2-6; the
+ * tile-packed factor is the row of T), the evaluation at the q grid values
+ * fused into the forward and back substitutions of Sec. 3.2, and the
+ * hold-out errors of Sec. 3.1 (Gram expansion, see pichol_holdout).
  *   lam_s (host, g distinct values), lam_grid (host, q), lam_ref > 0
  *   err  k*q (device) hold-out mean squared error
  *   W    k*q*d*c (device) weights, or NULL
@@ -332,8 +368,11 @@ pichol_status pichol_cv_interp(const pichol_problem *p, const double *lam_s,
                                double *W, int32_t *info, int32_t *flags,
                                hipStream_t stream);
 
-/* Stage 2 (exact baseline): one exact factorization per (fold, grid
- * value), the solves and the hold-out errors.  info is k*q. */
+/* Stage 2 (exact baseline, the "Chol" method of the comparison in
+ * Sec. 6.2): one exact Cholesky factorization per (fold, grid value) of
+ * H_f + lambda_t I (Sec. 3.2), the forward and back substitutions, and the
+ * hold-out errors of Sec. 3.1 (Gram expansion, see pichol_holdout).
+ * info is k*q. */
 pichol_status pichol_cv_exact(const pichol_problem *p, const double *lam_grid,
                               void *ws, size_t ws_bytes, double *err,
                               double *W, int32_t *info, int32_t *flags,
@@ -386,14 +425,22 @@ pichol_status pichol_cv_pinrmse(const pichol_problem *p, const double *lam_s,
                                 double *err_s, int32_t *info, int32_t *flags,
                                 hipStream_t stream);
 
-/* pichol_cv_gram followed by pichol_cv_interp. */
+/* piCholesky k-fold cross-validation of ridge regression from X and Y
+ * (Sec. 3.1 problem, Sec. 3.3 method): pichol_cv_gram followed by
+ * pichol_cv_interp, then the units flagged bit2 recomputed from the
+ * residual Y_v - X_v W (pichol_holdout_direct), so that every hold-out
+ * error is accurate to the FP64 level whatever the fit's quality.  X and Y
+ * are read again by that last step. */
 pichol_status pichol_cv(const pichol_problem *p, const double *X,
                         const double *Y, const double *lam_s,
                         const double *lam_grid, double lam_ref, void *ws,
                         size_t ws_bytes, double *err, double *W,
                         int32_t *info, int32_t *flags, hipStream_t stream);
 
-/* pichol_cv_gram followed by pichol_cv_exact. */
+/* Exact k-fold cross-validation of ridge regression from X and Y
+ * (Sec. 3.1 problem, Sec. 3.2 solves; the "Chol" baseline of Sec. 6.2):
+ * pichol_cv_gram followed by pichol_cv_exact, then the units flagged bit2
+ * recomputed from the residual as in pichol_cv. */
 pichol_status pichol_exact_cv(const pichol_problem *p, const double *X,
                               const double *Y, const double *lam_grid,
                               void *ws, size_t ws_bytes, double *err,
@@ -541,7 +588,8 @@ pichol_status pichol_graph_end(hipStream_t stream, pichol_graph *graph);
 
 /* Synchronise the stream and inspect info/flags (device arrays, either may
  * be NULL): PICHOL_ERR_NOT_PD when some info is non-zero, PICHOL_ERR_DATA
- * when some flag is set, PICHOL_ERR_HIP on a runtime failure. */
+ * when some flag has bit0 or bit1 set (bit2 is advisory),
+ * PICHOL_ERR_HIP on a runtime failure. */
 pichol_status pichol_check(const int32_t *info, int64_t n_info,
                            const int32_t *flags, int64_t n_flags,
                            hipStream_t stream);

@@ -109,6 +109,9 @@ _SIGNATURES = {
     "pichol_holdout_workspace": (_sz, [_i64, _i32, _i32, _i32]),
     "pichol_holdout": (_i32, [_i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
                               _vp, _vp, _vp, _sz, _vp]),
+    "pichol_holdout_direct_workspace": (_sz, [_pprob]),
+    "pichol_holdout_direct": (_i32, [_pprob, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
+                                     _vp]),
     "pichol_slab_to_weights": (_i32, [_i64, _i32, _i32, _i32, _vp, _vp, _vp]),
     "pichol_workspace_size": (_i32, [_pprob, _i32, ctypes.POINTER(_sz)]),
     "pichol_cv_gram": (_i32, [_pprob, _vp, _vp, _vp, _sz, _vp]),
@@ -343,6 +346,18 @@ def pichol_holdout(d, nmat, c, q, Z, G, C, yy, nv, err, flags, ws, ws_bytes,
         d, nmat, c, q, _dev(Z, _f64()), _dev(G, _f64()), _dev(C, _f64()),
         _dev(yy, _f64()), nv_h.ptr, _dev(err, _f64()), _dev(flags, _i32t()),
         _dev(ws), ws_bytes, _stream(stream)))
+
+
+def pichol_holdout_direct_workspace(p: Problem) -> int:
+    return int(load().pichol_holdout_direct_workspace(ctypes.byref(p)))
+
+
+def pichol_holdout_direct(p: Problem, X, Y, Z, err, flags, ws, ws_bytes,
+                          stream=None):
+    _check("pichol_holdout_direct", load().pichol_holdout_direct(
+        ctypes.byref(p), _dev(X, _f64()), _dev(Y, _f64()), _dev(Z, _f64()),
+        _dev(err, _f64()), _dev(flags, _i32t()), _dev(ws), ws_bytes,
+        _stream(stream)))
 
 
 def pichol_slab_to_weights(d, nmat, q, c, Z, W, stream=None):

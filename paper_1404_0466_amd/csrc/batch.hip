@@ -36,11 +36,12 @@ struct Bucket {
   int64_t d = 0, c = 0;
   int k = 0, g = 0, r = 0, q = 0, precision = 0;
   double cost = 0.0;       // estimated work, for the stream assignment
+  int64_t nrb = 0;         // row blocks of the largest validation fold
   int stream = 0;
   size_t base = 0;         // byte offset of the bucket's workspace region
   // region offsets, relative to base
   size_t G, C, yy, H, Bm, lam, tau, L, linv, th, tht, Z, X, part, dinv,
-      info, flags, end;
+      dpart, info, flags, end;
 };
 
 // Scaled values lambda/lam_ref of two problems agree to a few ulps (they are
@@ -113,6 +114,8 @@ void layout_bucket(Bucket& b, int method) {
   b.X = o; o += align256(nmat * dp * ldz * dbl);
   b.part = o; o += align256(nmat * nt * HOLDOUT_KSPLIT * ldz * dbl);
   b.dinv = o; o += interp ? align256(nmat * q * nt * NB2 * dbl) : 0;
+  // direct hold-out partial sums, shared by the bucket's problems in turn
+  b.dpart = o; o += align256((size_t)b.k * b.nrb * ldz * dbl);
   b.info = o; o += align256(nmat * nf * i32);
   b.flags = o; o += align256(nmat * q * i32);
   b.end = o;
@@ -148,6 +151,9 @@ bool make_buckets(int nprob, const pichol_batch_item* items, int method,
       hit->precision = p.precision;
     }
     hit->items.push_back(i);
+    FoldSplit fs;
+    fold_split(items[i].p.n, items[i].p.k, items[i].p.normalize, &fs);
+    hit->nrb = std::max(hit->nrb, holdout_direct_rowblocks(fs));
   }
   size_t base = 0;
   for (Bucket& b : bs) {
@@ -243,6 +249,15 @@ hipError_t run_bucket(const Bucket& b, const pichol_batch_item* items,
     e = launch_holdout_final(d, k, c, q, ldz,
                              part + m0 * nt * HOLDOUT_KSPLIT * ldz, yy + m0, hn,
                              it.err, flags + m0 * q, st);
+    // units where the Gram form cancels: the residual from X and Y
+    if (e == hipSuccess) {
+      FoldSplit fs;
+      fold_split(it.p.n, k, it.p.normalize, &fs);
+      e = launch_holdout_direct(d, k, c, q, ldz, Z + m0 * dp * ldz, it.X,
+                                it.p.ldx, it.Y, it.p.ldy, fs, hn,
+                                at<double>(base, b.dpart), it.err,
+                                flags + m0 * q, 1, st);
+    }
     if (e == hipSuccess)
       e = launch_copy_i32((int64_t)k * nf, info + m0 * nf, it.info, st);
     if (e == hipSuccess)

@@ -162,6 +162,22 @@ hipError_t launch_holdout(int64_t d, int nmat, int c, int q, int64_t ldz,
                           const double* yy, const HoldoutNorm& hn,
                           double* partial, double* err, int* flags,
                           hipStream_t s);
+// Flag bit 2: the Gram-form hold-out error of the unit lost accuracy to
+// cancellation (its estimated rounding exceeds 1e-11 of the result).
+constexpr int FLAG_CANCEL = 4;
+// Row blocks of 128 of the largest fold: the direct hold-out partial sums
+// hold nmat * holdout_direct_rowblocks(fs) * ldz doubles.
+int64_t holdout_direct_rowblocks(const FoldSplit& fs);
+// Hold-out errors from the residual R = Y_v - X_v W itself (fold m's
+// validation rows fs.start[m] .. fs.start[m+1]-1 of X and Y, its solutions
+// in slab m of Z): every unit, or (only_flagged) those marked FLAG_CANCEL.
+// The recomputed units' FLAG_CANCEL bit is cleared.
+hipError_t launch_holdout_direct(int64_t d, int nmat, int c, int q,
+                                 int64_t ldz, const double* Z, const double* X,
+                                 int64_t ldx, const double* Y, int64_t ldy,
+                                 const FoldSplit& fs, const HoldoutNorm& hn,
+                                 double* partial, double* err, int* flags,
+                                 int only_flagged, hipStream_t s);
 
 // ---- iterative refinement (k_refine.hip)
 hipError_t launch_full_h(int64_t d, const FoldSplit& fs, const double* G,

@@ -97,6 +97,30 @@ def gaussian_problem(n: int, d: int, c: int = 10, seed: int = 0, k: int = 5,
                    {"kind": "gaussian", "seed": seed, "lam_range": lam_range})
 
 
+def lowres_problem(n: int = 3000, d: int = 384, c: int = 10, seed: int = 7,
+                   k: int = 5, g: int = 6, r: int = 2, q: int = 31,
+                   noise: float = 1e-3, lam_range=(1e-6, 1e1),
+                   name: str | None = None) -> Problem:
+    """A well-fitted regression target (the hold-out residual far below the
+    labels): X ~ N(0,1)^{n x d} with column j scaled by 1/sqrt(1 + j/16);
+    teacher W0 ~ N(0,1)^{d x c}, each column rescaled so that the column of
+    X W0 has unit standard deviation; Y = X W0 + noise * N(0,1)^{n x c}.
+    At the small lambdas of the range, |Y_v - X_v W|^2 / |Y_v|^2 is about
+    noise^2.  Draw order: X, W0, the noise."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, d))
+    X *= 1.0 / np.sqrt(1.0 + np.arange(d) / 16.0)
+    W0 = rng.standard_normal((d, c))
+    W0 /= (X @ W0).std(axis=0)
+    Y = X @ W0 + noise * rng.standard_normal((n, c))
+    s = lam_scale(X)
+    return Problem(name or f"lowres_n{n}_d{d}_c{c}", np.ascontiguousarray(X),
+                   np.ascontiguousarray(Y), k, g, r,
+                   log_grid(s, *lam_range, g), log_grid(s, *lam_range, q), s,
+                   {"kind": "lowres", "seed": seed, "noise": noise,
+                    "lam_range": lam_range})
+
+
 def rff_problem(n: int, d: int, c: int = 10, seed: int = 0, k: int = 5,
                 g: int = 6, r: int = 2, q: int = 64, p: int = 784,
                 sigma: float = 5.0, lam_range=(1e-6, 1e0),
