@@ -161,14 +161,17 @@ int64_t pichol_padded_order(int64_t d);
 /* Column count of a right-hand-side slab holding q*c columns. */
 int64_t pichol_slab_cols(int64_t q, int64_t c);
 
-/* Dense -> packed.  A: nmat row-major d x d matrices (device, leading
+/* Dense -> packed (the vectorisation of a factor, Sec. 5: the tile-packed
+ * triangle is this library's layout of a row of T in Algorithm 1).
+ * A: nmat row-major d x d matrices (device, leading
  * dimension lda >= d, consecutive matrices lda*d apart); only entries with
  * i >= j are read.  P: nmat packed triangles (device), padding written as
  * above; the strict upper part of diagonal tiles is written as 0. */
 pichol_status pichol_pack(int64_t d, int32_t nmat, const double *A,
                           int64_t lda, double *P, hipStream_t stream);
 
-/* Packed -> dense lower triangle.  A receives nmat row-major d x d
+/* Packed -> dense lower triangle (inverse of the Sec. 5 vectorisation
+ * above; for tests).  A receives nmat row-major d x d
  * matrices (device, leading dimension lda >= d) with zeros above the
  * diagonal. */
 pichol_status pichol_unpack(int64_t d, int32_t nmat, const double *P,
@@ -325,8 +328,8 @@ pichol_status pichol_holdout_direct(const pichol_problem *p, const double *X,
                                     double *err, int32_t *flags, void *ws,
                                     size_t ws_bytes, hipStream_t stream);
 
-/* Copy slabs to the k x q x d x c weight layout: W[m][t][i][j] =
- * Z[m][i][t*c + j]. */
+/* Copy slabs to the k x q x d x c weight layout of the ridge solutions
+ * theta(lambda) of Sec. 3.1: W[m][t][i][j] = Z[m][i][t*c + j]. */
 pichol_status pichol_slab_to_weights(int64_t d, int32_t nmat, int32_t q,
                                      int32_t c, const double *Z, double *W,
                                      hipStream_t stream);
@@ -339,7 +342,9 @@ pichol_status pichol_slab_to_weights(int64_t d, int32_t nmat, int32_t q,
 pichol_status pichol_workspace_size(const pichol_problem *p, int32_t methods,
                                     size_t *bytes);
 
-/* Stage 1: the fold Gram matrices of X, Y into the workspace. */
+/* Stage 1: the fold Gram matrices H_f = X_tr^T X_tr, B_f = X_tr^T Y_tr of
+ * Sec. 3.1 (and the validation blocks' G, C, |Y_v|^2) into the workspace,
+ * as pichol_gram computes them. */
 pichol_status pichol_cv_gram(const pichol_problem *p, const double *X,
                              const double *Y, void *ws, size_t ws_bytes,
                              hipStream_t stream);
@@ -399,7 +404,7 @@ pichol_status pichol_cv_interp_grad(const pichol_problem *p,
                                     double *dlog, double *W, int32_t *info,
                                     int32_t *flags, hipStream_t stream);
 
-/* The same derivative for the exact method (dA/dlambda = I):
+/* The same derivative for the exact method of Sec. 3.2 (dA/dlambda = I):
  * d err / d lambda = 2/(n_v c) <z, theta>, z = (H_f + lambda I)^{-1} X_v^T R,
  * i.e. the exact gradient the interpolated one approximates.
  * ws: pichol_workspace_size with PICHOL_METHOD_EXACT | PICHOL_METHOD_GRAD. */
@@ -473,13 +478,15 @@ typedef enum {
 int64_t pichol_vector_length(int64_t d, int32_t layout);
 
 /* Tile-packed factors (device, nmat of them) -> their vectors in `layout`
- * (ROWWISE, FULL or RECURSIVE with threshold h0 >= 1), T nmat x
+ * (Sec. 5 and Table 1: ROWWISE, FULL or RECURSIVE block vectorisation with
+ * threshold h0 >= 1), T nmat x
  * pichol_vector_length(d, layout) (device). */
 pichol_status pichol_vectorize(int64_t d, int32_t nmat, const double *L,
                                int32_t layout, int32_t h0, double *T,
                                hipStream_t stream);
 
-/* The fit of pichol_fit on flat vectors of length N (a multiple of 4):
+/* The fit of pichol_fit (Algorithm 1 steps 2-6) on flat vectors of length
+ * N (a multiple of 4), as in the layout comparison of Table 1:
  * theta(m, j) = sum_s P[j][s] T(m, s), T nmat*g x N, theta nmat*(r+1) x N
  * (device). */
 pichol_status pichol_fit_vec(int64_t N, int32_t nmat, int32_t g, int32_t r,
@@ -487,7 +494,8 @@ pichol_status pichol_fit_vec(int64_t N, int32_t nmat, int32_t g, int32_t r,
                              const double *T, double *theta,
                              hipStream_t stream);
 
-/* The evaluation of pichol_eval on flat vectors: out(m, t) =
+/* The evaluation of pichol_eval (Sec. 3.3) on flat vectors, as in the
+ * layout comparison of Table 1: out(m, t) =
  * sum_j (lam_t/lam_ref)^j theta(m, j), out nmat*nlam x N (device).
  * ws: pichol_lambda_workspace(nlam) bytes. */
 pichol_status pichol_eval_vec(int64_t N, int32_t nmat, int32_t r,
@@ -647,7 +655,8 @@ pichol_status pichol_factor_nrmse(int64_t d, int32_t nmat, const double *Lhat,
                                   const double *L, double *out, void *ws,
                                   size_t ws_bytes, hipStream_t stream);
 
-/* Hold-out NRMSE from the hold-out MSE of a cross-validation call:
+/* Hold-out NRMSE (the normalised error of the Sec. 6.5 hold-out tables)
+ * from the hold-out MSE of a cross-validation call:
  *   nrmse[f*q + t] = sqrt(err[f*q + t] * n_v c / SST_f),
  * SST_f the sum over fold f's rows and the c columns of (Y - the fold's
  * column mean)^2, so predicting every label by that mean gives 1.

@@ -36,6 +36,56 @@ def test_header_declares_the_expected_calls():
         assert must in names
 
 
+# The calls that compute a step of the method, and the passage that defines
+# each: every one must cite a section, algorithm, table or theorem of the
+# paper in its comment block.
+COMPUTE_CALLS = [
+    "pichol_pack", "pichol_unpack", "pichol_gram",
+    "pichol_potrf_shifted_batched", "pichol_fit", "pichol_eval",
+    "pichol_solve_interp", "pichol_solve_factors", "pichol_holdout",
+    "pichol_holdout_direct", "pichol_slab_to_weights", "pichol_cv_gram",
+    "pichol_cv_interp", "pichol_cv_exact", "pichol_cv_interp_grad",
+    "pichol_cv_exact_grad", "pichol_cv_pinrmse", "pichol_cv", "pichol_exact_cv",
+    "pichol_vectorize", "pichol_fit_vec", "pichol_eval_vec", "pichol_cv_batch",
+    "pichol_factor_nrmse", "pichol_holdout_nrmse",
+]
+CITATION = re.compile(r"(Sec\.\s*\d|Algorithm\s*\d|Table\s*\d|Thm\.\s*\d)")
+
+
+def comment_blocks():
+    """name -> the comment block documenting it: the block right above its
+    declaration, or above the run of declarations it belongs to."""
+    text = open(HEADER).read()
+    out = {}
+    last = ""
+    tok = re.compile(r"/\*.*?\*/|\b(pichol_[a-z_0-9]+)\s*\(|;|\{|\}", re.S)
+    pending = ""
+    for m in tok.finditer(text):
+        t = m.group(0)
+        if t.startswith("/*"):
+            pending = t
+        elif m.group(1):
+            name = m.group(1)
+            if pending:
+                last = pending
+                pending = ""
+            out.setdefault(name, last)
+    return out
+
+
+def test_compute_calls_cite_the_paper():
+    blocks = comment_blocks()
+    missing = [n for n in COMPUTE_CALLS
+               if n not in blocks or not CITATION.search(blocks[n])]
+    assert not missing, "no passage of the paper cited for: %s" % missing
+
+
+def test_citation_check_would_catch_a_missing_citation():
+    assert not CITATION.search("/* Copy slabs to the weight layout. */")
+    assert CITATION.search("/* Algorithm 1 steps 2-6 */")
+    assert CITATION.search("/* (Sec. 3.1) */")
+
+
 def test_every_declared_symbol_is_exported(lib):
     raw = ctypes.CDLL(B.LIB_PATH)
     for name in declared_functions():

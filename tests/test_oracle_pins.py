@@ -229,6 +229,40 @@ def test_interpolated_factor_tracks_exact_factor():
         assert err <= 0.05 * spread
 
 
+@pytest.mark.parametrize("g", [4, 6])
+def test_interpolation_error_is_cubic_in_the_sample_width(g):
+    """Sec. 4 main result: with the g samples within w of lambda_c and the
+    evaluation point within gamma <= w of it, the RMS error of the degree-2
+    piCholesky factor is bounded by a multiple of w^3 (gamma^3 and
+    w^3 (1 + gamma^2) terms, R and |V^+| bounded as w shrinks).  Halving w
+    (and gamma = w/2 with it) must divide the error by about 8; a fit of too
+    low a degree, a dropped coefficient or a wrong sample abscissa would
+    divide it by 4 or less."""
+    A = spd(4, 41, cond=20.0)
+    lam_c = 0.5
+    D = 4 * 5 // 2
+    errs = []
+    for w in [0.16, 0.08, 0.04, 0.02]:
+        lam_s = lam_c + w * np.linspace(-1.0, 1.0, g)
+        T = np.stack([oracle.pack_lower(oracle.cholesky(A, l)[0]) for l in lam_s])
+        Theta = oracle.fit(T, lam_s, 2, lam_s.max())
+        lam = lam_c + 0.5 * w
+        exact = oracle.pack_lower(oracle.cholesky(A, lam)[0])
+        errs.append(np.linalg.norm(oracle.evaluate(Theta, lam, lam_s.max())
+                                   - exact) / np.sqrt(D))
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all(ratios > 6.5) and np.all(ratios < 9.5), ratios
+    # the degree-1 fit of the same samples only reaches second order
+    w = 0.02
+    lam_s = lam_c + w * np.linspace(-1.0, 1.0, g)
+    T = np.stack([oracle.pack_lower(oracle.cholesky(A, l)[0]) for l in lam_s])
+    lin = oracle.fit(T, lam_s, 1, lam_s.max())
+    exact = oracle.pack_lower(oracle.cholesky(A, lam_c + 0.5 * w)[0])
+    e1 = np.linalg.norm(oracle.evaluate(lin, lam_c + 0.5 * w, lam_s.max())
+                        - exact) / np.sqrt(D)
+    assert e1 > 20 * errs[-1]
+
+
 # ------------------------------------------------------------------ solves / hold-out
 
 def test_solve_diagonal_closed_form():
@@ -444,6 +478,8 @@ def test_selection_helpers():
     np.testing.assert_allclose(g["regret"], 0.2)
     np.testing.assert_allclose(g["sel_err_log10"], 1.0)
     np.testing.assert_allclose(g["curve_gap"], 4.0)
+    # smallest interpolated minus smallest exact, relative to the latter
+    np.testing.assert_allclose(g["min_gap"], (0.5 - 0.4) / 0.4)
 
 
 def test_gauss_n2000_d256_matches_known_behaviour():
