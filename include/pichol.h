@@ -308,6 +308,27 @@ pichol_status pichol_holdout(int64_t d, int32_t nmat, int32_t c, int32_t q,
                              const int64_t *nv, double *err, int32_t *flags,
                              void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* pichol_holdout for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, results and kernels, with no workspace argument.  The
+ * partial sums live in a static device array of the library of
+ * PICHOL_HOLDOUT_SCRATCH_BYTES (16 MiB), one per GPU, held until the process
+ * ends; the call allocates nothing.  Calls whose partial sums need more
+ * (pichol_holdout_workspace(d, nmat, q, c) above the limit; at d = 4096,
+ * q = 64, c = 10 that is nmat > 12) return PICHOL_ERR_WORKSPACE before
+ * anything is enqueued, with a message in pichol_last_error.  Every call on
+ * a GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams, or from different threads) race and give wrong
+ * results; calls in stream order are safe.  The array keeps the last call's
+ * partial sums; each call writes every entry it later reads. */
+#define PICHOL_HOLDOUT_SCRATCH_BYTES (16u << 20)
+pichol_status pichol_holdout_noalloc(int64_t d, int32_t nmat, int32_t c,
+                                     int32_t q, const double *Z,
+                                     const double *G, const double *C,
+                                     const double *yy, const int64_t *nv,
+                                     double *err, int32_t *flags,
+                                     hipStream_t stream);
+
 /* Scratch bytes for pichol_holdout_direct (0 on invalid arguments). */
 size_t pichol_holdout_direct_workspace(const pichol_problem *p);
 
@@ -605,7 +626,8 @@ pichol_status pichol_check(const int32_t *info, int64_t n_info,
 /* Static description of a status code. */
 const char *pichol_status_string(pichol_status s);
 
-/* Text of the last HIP error the library saw on this thread ("" if none). */
+/* Text of the last HIP error the library saw on this thread, or of the
+ * last argument error that carries a message ("" if none). */
 const char *pichol_last_error(void);
 
 /* ---------------------------------------------------------------- options */

@@ -109,6 +109,8 @@ _SIGNATURES = {
     "pichol_holdout_workspace": (_sz, [_i64, _i32, _i32, _i32]),
     "pichol_holdout": (_i32, [_i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
                               _vp, _vp, _vp, _sz, _vp]),
+    "pichol_holdout_noalloc": (_i32, [_i64, _i32, _i32, _i32, _vp, _vp, _vp,
+                                      _vp, _vp, _vp, _vp, _vp]),
     "pichol_holdout_direct_workspace": (_sz, [_pprob]),
     "pichol_holdout_direct": (_i32, [_pprob, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                                      _vp]),
@@ -346,6 +348,18 @@ def pichol_holdout(d, nmat, c, q, Z, G, C, yy, nv, err, flags, ws, ws_bytes,
         d, nmat, c, q, _dev(Z, _f64()), _dev(G, _f64()), _dev(C, _f64()),
         _dev(yy, _f64()), nv_h.ptr, _dev(err, _f64()), _dev(flags, _i32t()),
         _dev(ws), ws_bytes, _stream(stream)))
+
+
+PICHOL_HOLDOUT_SCRATCH_BYTES = 16 << 20
+
+
+def pichol_holdout_noalloc(d, nmat, c, q, Z, G, C, yy, nv, err, flags,
+                           stream=None):
+    nv_h = _Host(nv, np.int64)
+    _check("pichol_holdout_noalloc", load().pichol_holdout_noalloc(
+        d, nmat, c, q, _dev(Z, _f64()), _dev(G, _f64()), _dev(C, _f64()),
+        _dev(yy, _f64()), nv_h.ptr, _dev(err, _f64()), _dev(flags, _i32t()),
+        _stream(stream)))
 
 
 def pichol_holdout_direct_workspace(p: Problem) -> int:

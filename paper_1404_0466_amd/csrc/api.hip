@@ -300,6 +300,41 @@ hipError_t upload_tau(const double* lam, int nlam, double lam_ref, int basis,
 
 using namespace pichol;
 
+// Scratch of pichol_holdout_noalloc: the partial sums of the hold-out
+// product, in a file-scope device array instead of a caller's workspace.
+// Each device holds its own copy; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[PICHOL_HOLDOUT_SCRATCH_BYTES /
+                                                sizeof(double)];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices];
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+static hipError_t scratch_address(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// An argument error with a message for pichol_last_error.
+static pichol_status arg_error(pichol_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
 extern "C" {
 
 int64_t pichol_packed_elems(int64_t d) { return packed_elems_of(d); }
@@ -593,6 +628,40 @@ pichol_status pichol_holdout(int64_t d, int32_t nmat, int32_t c, int32_t q,
   return hip_status(launch_holdout(d, nmat, c, q, pichol_slab_cols(q, c), Z, G,
                                    C, yy, hn, static_cast<double*>(ws), err,
                                    flags, stream));
+}
+
+pichol_status pichol_holdout_noalloc(int64_t d, int32_t nmat, int32_t c,
+                                     int32_t q, const double* Z,
+                                     const double* G, const double* C,
+                                     const double* yy, const int64_t* nv,
+                                     double* err, int32_t* flags,
+                                     hipStream_t stream) {
+  if (d < 1 || nmat < 1 || nmat > 64 || c < 1 || q < 1 || !Z || !G || !C ||
+      !yy || !nv || !err || !flags)
+    return arg_error(PICHOL_ERR_ARG, "pichol_holdout_noalloc: invalid argument");
+  const size_t need = pichol_holdout_workspace(d, nmat, q, c);
+  if (need > PICHOL_HOLDOUT_SCRATCH_BYTES)
+    return arg_error(PICHOL_ERR_WORKSPACE,
+                "pichol_holdout_noalloc: the partial sums need " +
+                    std::to_string(need) + " bytes, more than the " +
+                    std::to_string((size_t)PICHOL_HOLDOUT_SCRATCH_BYTES) +
+                    " bytes of the static scratch (use pichol_holdout)");
+  HoldoutNorm hn;
+  memset(&hn, 0, sizeof(hn));
+  hn.nmat = nmat;
+  for (int m = 0; m < nmat; ++m) {
+    if (nv[m] < 1)
+      return arg_error(PICHOL_ERR_ARG, "pichol_holdout_noalloc: nv[m] < 1");
+    hn.count[m] = (double)nv[m] * (double)c;
+  }
+  double* part = nullptr;
+  hipError_t e = scratch_address(&part);
+  if (e != hipSuccess) return hip_status(e);
+  // every partial sum the final reduction reads is written by the partial
+  // kernel (ranges above the diagonal and padding columns as zeros), so the
+  // scratch needs no clearing between calls
+  return hip_status(launch_holdout(d, nmat, c, q, pichol_slab_cols(q, c), Z, G,
+                                   C, yy, hn, part, err, flags, stream));
 }
 
 size_t pichol_holdout_direct_workspace(const pichol_problem* p) {

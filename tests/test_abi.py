@@ -174,3 +174,20 @@ def test_options(lib):
     for bad in [0, 9]:
         with pytest.raises(B.PicholError):
             B.pichol_set_option(B.PICHOL_OPT_PANEL_GROUP, bad)
+
+
+def test_noalloc_holdout_rejects_oversize_before_touching_the_device(lib):
+    """The allocation-free hold-out call checks its scratch limit on the host
+    first: at d = 4096, q = 64, c = 10 the partial sums of 13 folds exceed
+    16 MiB.  (Nothing is enqueued, so no GPU is needed.)"""
+    assert B.pichol_holdout_workspace(4096, 13, 64, 10) > B.PICHOL_HOLDOUT_SCRATCH_BYTES
+    assert B.pichol_holdout_workspace(4096, 12, 64, 10) <= B.PICHOL_HOLDOUT_SCRATCH_BYTES
+    fake = ctypes.c_void_p(256)  # never dereferenced: the call returns first
+    nv = (ctypes.c_int64 * 13)(*([12000] * 13))
+    st = lib.pichol_holdout_noalloc(4096, 13, 10, 64, fake, fake, fake, fake,
+                                    ctypes.cast(nv, ctypes.c_void_p), fake, fake,
+                                    None)
+    assert st == B.PICHOL_ERR_WORKSPACE
+    assert b"static scratch" in lib.pichol_last_error()
+    assert "#define PICHOL_HOLDOUT_SCRATCH_BYTES (16u << 20)" in open(HEADER).read()
+    assert B.PICHOL_HOLDOUT_SCRATCH_BYTES == 16 << 20
