@@ -54,25 +54,26 @@ def update_flops(d: int, nfac: int) -> float:
     return tot
 
 
-def measured_traffic(exact: bool, lookahead: int, group: int):
-    """HBM bytes per launch of k_potrf_update from the committed rocprofv3
-    counter record (profiles/k_potrf_update_traffic.json), or None when the
-    kernel's sources changed since the counters were taken or this run's
-    launch mix (methods, look-ahead, panel group) differs from the profiled
-    one."""
+def measured_traffic(stage: str, lookahead: int, group: int):
+    """HBM bytes per launch of k_potrf_update in one stage ("interp" or
+    "exact") from the committed rocprofv3 counter record
+    (profiles/k_potrf_update_traffic.json), or None when the kernel's sources
+    changed since the counters were taken or this run's launch mix
+    (look-ahead, panel group) differs from the profiled one."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_potrf_update_traffic.json")
-    if not os.path.exists(path) or not exact or lookahead != 0:
+    if not os.path.exists(path) or lookahead != 0:
         return None
     rec = json.load(open(path))
-    if rec.get("panel_group") != group:
+    st = rec.get("stages", {}).get(stage)
+    if st is None or rec.get("panel_group") != group:
         return None
     h = hashlib.sha256()
     for f in rec["source_files"]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if h.hexdigest() != rec["source_sha256"]:
         return None
-    return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return st["read_bytes_per_launch"] + st["write_bytes_per_launch"]
 
 
 def gaps(cp, ce, lam):
@@ -88,10 +89,28 @@ def gaps(cp, ce, lam):
     }
 
 
-def cpu_baseline(prob, gpu_err_fold0):
-    """The oracle on a bounded sample: fold 0 of the workload from its Gram
-    matrices (formed with numpy outside the timed region), i.e. the g sample
-    factorizations, the fit, and q evaluations + solves + hold-out errors."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prob, gpu_err_fold0, gpu_err_exact_fold0=None):
+    """CPU baselines on bounded samples of the workload's fold 0, from its
+    Gram matrices (formed with numpy outside the timed regions):
+      value      the oracle's interpolated fold (g sample factorizations,
+                 fit, q evaluations + solves + hold-out errors) on all the
+                 oracle's threads;
+      one_thread the same fold's rate on one thread, extrapolated from parts
+                 timed on one thread (one factorization, one fit, two units);
+      exact      the oracle's exact method at 8 of the q grid values, on all
+                 threads, extrapolated to the whole job;
+      lapack     numpy/LAPACK (multi-threaded BLAS) running both methods on
+                 fold 0, the analogue of a multi-threaded CPU library setting."""
     import oracle
     nv = len(np.array_split(np.arange(prob.n), prob.k)[0])
     Xv, Yv = prob.X[:nv], prob.Y[:nv]
@@ -100,21 +119,125 @@ def cpu_baseline(prob, gpu_err_fold0):
     H = Xt.T @ Xt / Xt.shape[0]
     Bm = Xt.T @ Yt / Xt.shape[0]
     oracle.build()
-    log(f"cpu baseline: oracle fold 0 on {oracle.num_threads()} threads")
+    nthr = oracle.num_threads()
+    k, q, g, r, d = prob.k, prob.q, prob.g, prob.r, prob.d
+    log(f"cpu baseline: oracle fold 0 on {nthr} threads")
     t0 = time.perf_counter()
-    out = oracle.fold_interp(H, Bm, Xv, Yv, prob.lam_s, prob.lam_grid, prob.r)
+    out = oracle.fold_interp(H, Bm, Xv, Yv, prob.lam_s, prob.lam_grid, r)
     dt = time.perf_counter() - t0
     rel = np.abs(np.asarray(gpu_err_fold0) - out["mse"]) / np.abs(out["mse"])
     log(f"cpu baseline: {dt:.1f} s, max rel diff vs GPU fold-0 errors {rel.max():.2e}")
+
+    # one thread: the fold's parts, each timed once
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        L0, _ = oracle.cholesky(H, float(prob.lam_s[-1]))
+        t_chol = time.perf_counter() - t0
+        T = np.tile(oracle.pack_lower(L0), (g, 1))
+        t0 = time.perf_counter()
+        Th = oracle.fit(T, prob.lam_s, r, prob.lam_ref)
+        t_fit = time.perf_counter() - t0
+        del T
+        t0 = time.perf_counter()
+        for lam in prob.lam_grid[[0, q - 1]]:
+            Lh = oracle.unpack_lower(oracle.evaluate(Th, float(lam), prob.lam_ref), d)
+            W, _ = oracle.solve(Lh, Bm)
+            oracle.holdout_sse(Xv, Yv, W)
+        t_unit = (time.perf_counter() - t0) / 2
+    finally:
+        oracle.set_num_threads(nthr)
+    t_one = g * t_chol + t_fit + q * t_unit
+    log(f"cpu baseline, 1 thread: factorization {t_chol:.1f} s, fit {t_fit:.1f} s, "
+        f"unit {t_unit:.2f} s -> fold {t_one:.0f} s (extrapolated)")
+
+    # the exact method at 8 grid values
+    idx = np.linspace(0, q - 1, 8).round().astype(int)
+    t0 = time.perf_counter()
+    ex = oracle.fold_exact(H, Bm, Xv, Yv, prob.lam_grid[idx])
+    t_ex = time.perf_counter() - t0
+    exact = {"value": len(idx) / t_ex, "unit": "λ-solves/s", "cores": nthr,
+             "kind": "oracle", "seconds": t_ex,
+             "sample": f"fold 0, exact factorization + solves + hold-out at {len(idx)} "
+                       f"of the {q} grid values (indices {idx.tolist()})",
+             "whole_job_seconds_extrapolated": k * q * t_ex / len(idx)}
+    if gpu_err_exact_fold0 is not None:
+        exact["max_rel_diff_vs_gpu"] = float(np.max(
+            np.abs(np.asarray(gpu_err_exact_fold0)[idx] - ex["mse"]) / ex["mse"]))
+    log(f"cpu baseline, exact oracle: {len(idx)} grid values in {t_ex:.1f} s")
+
     return {
-        "value": prob.q / dt, "unit": "λ-solves/s",
-        "cores": oracle.num_threads(), "kind": "oracle",
-        "sample": (f"fold 0 of {prob.k} at n={prob.n}, d={prob.d}, c={prob.c}: "
-                   f"g={prob.g} sample factorizations, fit, q={prob.q} "
+        "value": q / dt, "unit": "λ-solves/s",
+        "cores": nthr, "kind": "oracle",
+        "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+        "sample": (f"fold 0 of {k} at n={prob.n}, d={d}, c={prob.c}: "
+                   f"g={g} sample factorizations, fit, q={q} "
                    "evaluations + solves + hold-out errors, from numpy-formed "
                    "Gram matrices"),
         "seconds": dt,
+        "whole_job_seconds_extrapolated": k * dt,
         "fold0_err_max_rel_diff_vs_gpu": float(rel.max()),
+        "one_thread": {
+            "value": q / t_one, "unit": "λ-solves/s", "cores": 1, "kind": "oracle",
+            "extrapolated": True,
+            "sample": "fold 0 on one thread from parts timed once: one sample "
+                      "factorization, one fit of g packed factors, two "
+                      "evaluate + solve + hold-out units; g*fact + fit + q*unit",
+            "factorization_s": t_chol, "fit_s": t_fit, "unit_s": t_unit,
+        },
+        "exact": exact,
+        "lapack": lapack_baseline(prob, H, Bm, Xv, Yv),
+    }
+
+
+def lapack_baseline(prob, H, Bm, Xv, Yv):
+    """Both methods on fold 0 with numpy/scipy LAPACK and the host's
+    multi-threaded BLAS (not the oracle): exact Cholesky at 8 grid values,
+    and piCholesky (6 factorizations, least-squares fit by one product with
+    the pseudo-inverse, evaluation, solves and residuals at all q values)."""
+    import scipy.linalg
+    k, q, g, r, d = prob.k, prob.q, prob.g, prob.r, prob.d
+    I = np.eye(d)
+
+    def unit(L):
+        z = scipy.linalg.solve_triangular(L, Bm, lower=True, check_finite=False)
+        w = scipy.linalg.solve_triangular(L, z, lower=True, trans="T",
+                                          check_finite=False)
+        res = Yv - Xv @ w
+        return float(np.sum(res * res)) / Yv.size
+
+    idx = np.linspace(0, q - 1, 8).round().astype(int)
+    t0 = time.perf_counter()
+    for lam in prob.lam_grid[idx]:
+        unit(np.linalg.cholesky(H + lam * I))
+    t_ex = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tri = np.tril_indices(d)
+    T = np.stack([np.linalg.cholesky(H + lam * I)[tri] for lam in prob.lam_s])
+    V = np.vander(prob.lam_s / prob.lam_ref, r + 1, increasing=True)
+    Th = np.linalg.pinv(V) @ T
+    del T
+    mse = []
+    L = np.zeros((d, d))
+    for lam in prob.lam_grid:
+        L[tri] = np.vander([lam / prob.lam_ref], r + 1, increasing=True)[0] @ Th
+        mse.append(unit(L))
+    t_int = time.perf_counter() - t0
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        blas = ", ".join(sorted({f"{i.get('internal_api')} {i.get('num_threads')} threads"
+                                 for i in info if i.get("user_api") == "blas"}))
+    except Exception:
+        blas = "unknown"
+    log(f"lapack baseline: exact {len(idx)} values {t_ex:.1f} s, "
+        f"interpolated fold {t_int:.1f} s ({blas})")
+    return {
+        "kind": "numpy/LAPACK", "blas": blas,
+        "interp": {"value": q / t_int, "unit": "λ-solves/s", "seconds": t_int,
+                   "sample": f"fold 0, all {q} grid values"},
+        "exact": {"value": len(idx) / t_ex, "unit": "λ-solves/s", "seconds": t_ex,
+                  "sample": f"fold 0, {len(idx)} of the {q} grid values"},
     }
 
 
@@ -593,6 +716,87 @@ def layout_leg(args, B, stream):
     return {"setting": "one fold, g=4, r=2, q=31, recursive threshold 128", "rows": rows}
 
 
+def merged(summ, base):
+    """(launches, total ms) of every instantiation of a kernel."""
+    parts = [v for nm, v in summ.items() if nm == base or nm.startswith(base + "<")]
+    if not parts:
+        return None
+    return sum(x[0] for x in parts), sum(x[1] for x in parts)
+
+
+def solve_tiles(d: int) -> int:
+    """Off-diagonal tile products of one blocked forward (or back)
+    substitution: sum over the steps of the tile rows left to update."""
+    nt = (d + NB - 1) // NB
+    return nt * (nt - 1) // 2
+
+
+def stage_rooflines(summ, prob, steps, stage, lookahead, B):
+    """Roofline entries of one stage's main kernels, from the event pass:
+    algorithmic work per launch (formulas of DESIGN section 5) over the mean
+    launch duration."""
+    d, k, g, q, c, r = prob.d, prob.k, prob.g, prob.q, prob.c, prob.r
+    nfac = k * (g if stage == "interp" else q)
+    out = {}
+    upd = merged(summ, "k_potrf_update")
+    if upd:
+        nl, tot = upd
+        flops = update_flops(d, nfac) * steps / nl
+        ms = tot / nl
+        tf = flops / (ms * 1e-3) / 1e12
+        out["k_potrf_update"] = {
+            "kernel": "k_potrf_update", "bound": "mfma", "achieved": tf,
+            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": tf / PEAK_FP64_TFLOPS,
+            "traffic": measured_traffic(stage, lookahead,
+                                        B.pichol_get_option(B.PICHOL_OPT_PANEL_GROUP)),
+            "flops_per_launch": flops, "avg_launch_ms": ms,
+            "launches_per_step": nl / steps, "factorizations": nfac,
+        }
+    ldz = ((q * c + NB - 1) // NB) * NB
+    dp = ((d + NB - 1) // NB) * NB
+    ui = merged(summ, "k_update_interp")
+    if ui and stage == "interp":
+        nl, tot = ui
+        stacked = 2 * k * solve_tiles(d) * 2.0 * NB * NB * (r + 1) * ldz * steps / nl
+        method = k * q * 2.0 * c * d * d * steps / nl
+        ms = tot / nl
+        tf = stacked / (ms * 1e-3) / 1e12
+        out["k_update_interp"] = {
+            "kernel": "k_update_interp", "bound": "mfma", "achieved": tf,
+            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": tf / PEAK_FP64_TFLOPS,
+            "flops_per_launch": stacked, "avg_launch_ms": ms,
+            "method_flops_per_launch": method,
+            "method_frac": method / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "launches_per_step": nl / steps,
+        }
+    uf = merged(summ, "k_update_factors")
+    if uf and stage == "exact":
+        nl, tot = uf
+        # every off-diagonal factor tile read once per (fold, lambda) and
+        # direction, and the c-column slab rows it updates read and written
+        byts = 2 * k * q * solve_tiles(d) * (NB * NB * 8 + 2 * NB * c * 8) * steps / nl
+        ms = tot / nl
+        gbs = byts / (ms * 1e-3) / 1e9
+        out["k_update_factors"] = {
+            "kernel": "k_update_factors", "bound": "hbm", "achieved": gbs,
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+            "bytes_per_launch": byts, "avg_launch_ms": ms, "launches_per_step": nl / steps,
+        }
+    hp = merged(summ, "k_holdout_partial")
+    if hp:
+        nl, tot = hp
+        nt = dp // NB
+        flops = k * nt * (nt + 1) / 2 * 2.0 * NB * NB * ldz * steps / nl
+        ms = tot / nl
+        tf = flops / (ms * 1e-3) / 1e12
+        out["k_holdout_partial"] = {
+            "kernel": "k_holdout_partial", "bound": "mfma", "achieved": tf,
+            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": tf / PEAK_FP64_TFLOPS,
+            "flops_per_launch": flops, "avg_launch_ms": ms, "launches_per_step": nl / steps,
+        }
+    return out
+
+
 def main():
     import workloads
 
@@ -792,44 +996,46 @@ def main():
         differentiation = differentiation_leg(args, B, stream)
 
     roofline = None
+    rooflines = None
     kernels = None
     if not args.no_profile:
-        log("per-kernel event pass")
-        B.pichol_profile_start(4000 * max(1, args.steps))
-        for i in range(args.steps):
-            step(new_events())
-        torch.cuda.synchronize()
-        B.pichol_profile_stop()
-        summ = B.pichol_profile_summary()
-        B.pichol_profile_reset()
-        kernels = {name: {"launches": nl, "avg_ms": tot / nl, "total_ms_per_step": tot / args.steps}
-                   for name, (nl, tot) in sorted(summ.items(), key=lambda kv: -kv[1][1])}
-        # the trailing-update kernel has two instantiations (first touch of a
-        # tile reading the fold matrix, later touches reading the factor);
-        # the roofline covers both
-        parts = [v for nm, v in summ.items()
-                 if nm in ("k_potrf_update", "k_potrf_update<true>", "k_potrf_update<false>")]
-        upd = (sum(p[0] for p in parts), sum(p[1] for p in parts)) if parts else None
-        if upd:
-            flops = update_flops(d, k * g)
-            if not args.no_exact:
-                flops += update_flops(d, k * q)
-            nl, tot = upd
-            per_step_launches = nl / args.steps
-            avg_flops = flops / per_step_launches
-            avg_ms = tot / nl
-            achieved = avg_flops / (avg_ms * 1e-3) / 1e12
-            roofline = {
-                "kernel": "k_potrf_update", "bound": "mfma",
-                "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": measured_traffic(not args.no_exact, args.lookahead,
-                                            B.pichol_get_option(B.PICHOL_OPT_PANEL_GROUP)),
-                "flops_per_launch": avg_flops, "avg_launch_ms": avg_ms,
-                "launches_per_step": per_step_launches,
-            }
-            log(f"k_potrf_update: {achieved:.2f} TFLOP/s "
-                f"({100 * achieved / PEAK_FP64_TFLOPS:.1f}% of FP64 peak)")
+        def profile(fn, what):
+            log(f"per-kernel event pass: {what}")
+            B.pichol_profile_start(4000 * max(1, args.steps))
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            B.pichol_profile_stop()
+            summ = B.pichol_profile_summary()
+            B.pichol_profile_reset()
+            return summ
+
+        summ_i = profile(lambda: B.pichol_cv_interp(p, lam_s, lam_grid, lam_ref, ws, nbytes,
+                                                    err_i, None, info_i, flags_i),
+                         "interpolated stage")
+        summ_e = None
+        if not args.no_exact:
+            summ_e = profile(lambda: B.pichol_cv_exact(p, lam_grid, ws, nbytes, err_e, None,
+                                                       info_e, flags_e), "exact stage")
+
+        def table(summ):
+            return {name: {"launches_per_step": nl / args.steps, "avg_ms": tot / nl,
+                           "total_ms_per_step": tot / args.steps}
+                    for name, (nl, tot) in sorted(summ.items(), key=lambda kv: -kv[1][1])}
+
+        kernels = {"interp": table(summ_i), "exact": table(summ_e) if summ_e else None}
+        mix = "interp" if args.no_exact else "both"
+        rooflines = {"interp": stage_rooflines(summ_i, prob, args.steps, "interp",
+                                               args.lookahead, B),
+                     "exact": (stage_rooflines(summ_e, prob, args.steps, "exact",
+                                               args.lookahead, B) if summ_e else None)}
+        roofline = rooflines["interp"].get("k_potrf_update")
+        if roofline is not None:
+            roofline = dict(roofline)
+            roofline["stage"] = "pichol_cv_interp (the headline stage)"
+        log("interpolated stage: " + ", ".join(
+            f"{nm} {v['total_ms_per_step']:.2f} ms" for nm, v in list(kernels["interp"].items())[:6]))
+        del mix
 
     if args.calibrate_copy_mib > 0:
         nel = args.calibrate_copy_mib * (1 << 20) // 8
@@ -843,7 +1049,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(prob, ei[0])
+        cpu = cpu_baseline(prob, ei[0], None if args.no_exact else ee[0])
 
     out = {
         "metric": METRIC, "value": value, "unit": "λ-solves/s", "n_gpus": 1,
@@ -861,6 +1067,7 @@ def main():
         "accuracy": accuracy,
         "factorization": factorization,
         "roofline": roofline,
+        "rooflines": rooflines,
         "cpu_baseline": cpu,
         "kernels": kernels,
     }

@@ -103,6 +103,7 @@ def _load():
                                    _i64, _pd, _i64, _pd, _i64, _pd, _pd, _dbl,
                                    _pd, _pd, _pi32, _pi32, _i32, _i32]),
         "orc_num_threads": (_i32, []),
+        "orc_set_num_threads": (None, [_i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -130,6 +131,11 @@ def _p(a):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (n >= 1)."""
+    _load().orc_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------- building blocks
@@ -422,6 +428,54 @@ def fold_interp(H, B, Xv, Yv, lam_s, lam_grid, r: int,
                                  _p(flags), int(refine), int(basis))
     if rc != 0:
         raise ValueError("oracle fold_interp rejected its arguments")
+    return {"mse": mse, "W": W, "info": info, "flags": flags}
+
+
+def fold_exact(H, B, Xv, Yv, lam_grid, want_W: bool = False) -> dict:
+    """The exact method on one fold from its H_f (both triangles) and B_f:
+    at each grid value the Cholesky factor of H_f + lambda I, the forward and
+    back substitutions (Sec. 3.2) and the hold-out error of the validation
+    rows, composed from cholesky, solve and holdout_sse above.  The grid
+    values run on a thread pool (the C calls release the interpreter lock).
+    A failed factorization gives info = j+1, NaN results and flags bit0."""
+    import concurrent.futures
+    H = _f64(H)
+    B = _f64(B)
+    Xv = _f64(Xv)
+    Yv = _f64(Yv)
+    if B.ndim == 1:
+        B = B[:, None].copy()
+    if Yv.ndim == 1:
+        Yv = Yv[:, None].copy()
+    lam_grid = _f64(lam_grid)
+    d, c = B.shape
+    q = lam_grid.shape[0]
+    nv = Xv.shape[0]
+    mse = np.zeros(q)
+    W = np.zeros((q, d, c)) if want_W else None
+    info = np.zeros(q, dtype=np.int32)
+    flags = np.zeros(q, dtype=np.int32)
+
+    def unit(t):
+        L, inf = cholesky(H, float(lam_grid[t]))
+        info[t] = inf
+        if inf != 0:
+            mse[t] = np.nan
+            flags[t] = 1
+            if want_W:
+                W[t] = np.nan
+            return
+        Wt, fl = solve(L, B)
+        sse = holdout_sse(Xv, Yv, Wt)
+        if not np.isfinite(sse):
+            fl |= 1
+        flags[t] = fl
+        mse[t] = sse / (nv * c)
+        if want_W:
+            W[t] = Wt
+
+    with concurrent.futures.ThreadPoolExecutor(max(1, min(q, num_threads()))) as ex:
+        list(ex.map(unit, range(q)))
     return {"mse": mse, "W": W, "info": info, "flags": flags}
 
 

@@ -27,6 +27,14 @@ int32_t orc_num_threads(void) {
 #endif
 }
 
+void orc_set_num_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads((int)n);
+#else
+  (void)n;
+#endif
+}
+
 /* numpy.array_split sizes: the first n % k folds get one extra row. */
 void orc_fold_bounds(int64_t n, int32_t k, int64_t *start) {
   int64_t base = n / k, extra = n % k;

@@ -181,6 +181,8 @@ int32_t orc_cv_grad(int64_t n, int64_t d, int64_t c, int32_t k, int32_t g,
 
 /* Number of OpenMP threads the oracle runs with. */
 int32_t orc_num_threads(void);
+/* Threads of the OpenMP regions that follow (n >= 1; no arithmetic). */
+void orc_set_num_threads(int32_t n);
 
 #ifdef __cplusplus
 }

@@ -5,8 +5,11 @@ times (the pipeline calls through the C-ABI).
 The oracle cannot redo the whole job in a test's time, so the checks are
 (1) fold 0 of the interpolated cross-validation, which the oracle computes
 in full from that fold's Gram matrices (about 20 s on 16 cores), and
-(2) properties checked entry by entry on samples: Gram entries against
-their definition, and L L^T = H + lambda I for exact factors.
+(2) the exact baseline at four grid values of fold 0, which the oracle
+factors and solves in full, and (3) properties checked entry by entry on
+samples: Gram entries against their definition, and L L^T = H + lambda I for
+exact factors.  The d = 2048 random-feature workload is compared with the
+oracle at every grid value.
 """
 import numpy as np
 import pytest
@@ -36,6 +39,30 @@ def test_fullsize_fold0_matches_oracle(big):
     want = oracle.fold_interp(H, Bm, p.X[:nv], p.Y[:nv], p.lam_s, p.lam_grid, p.r)
     assert np.all(want["info"] == 0) and np.all(want["flags"] == 0)
     np.testing.assert_allclose(got["mse"][0], want["mse"], rtol=1e-10, atol=0)
+
+
+def _fold_grams(p, f):
+    """H_f, B_f (numpy, from the training rows) and the validation rows."""
+    b = oracle.fold_bounds(p.n, p.k)
+    mask = np.ones(p.n, bool)
+    mask[b[f]:b[f + 1]] = False
+    Xt, Yt = p.X[mask], p.Y[mask]
+    ntr = mask.sum()
+    return Xt.T @ Xt / ntr, Xt.T @ Yt / ntr, p.X[~mask], p.Y[~mask]
+
+
+def test_fullsize_exact_sampled_against_oracle(big):
+    """The exact baseline at full size: the GPU's exact CV (all 320
+    factorizations, as bench.py times it) at four grid values of fold 0
+    against the oracle's factorization, solves and direct residual there."""
+    gu, p = big
+    got = gu.cv(p, "exact", want_W=False)
+    assert np.all(got["info"] == 0) and np.all(got["flags"] == 0)
+    idx = [0, 21, 42, 63]
+    H, Bm, Xv, Yv = _fold_grams(p, 0)
+    want = oracle.fold_exact(H, Bm, Xv, Yv, p.lam_grid[idx])
+    assert np.all(want["info"] == 0) and np.all(want["flags"] == 0)
+    np.testing.assert_allclose(got["mse"][0, idx], want["mse"], rtol=1e-10, atol=0)
 
 
 def test_fullsize_gram_and_factor_properties(big):
@@ -107,6 +134,43 @@ def test_batch_fullsize_matches_oracle_and_single(manyprob):
         seen.add(probs[i].d)
         one = gu.cv(probs[i], "interp", want_W=False)
         np.testing.assert_allclose(got[i]["mse"], one["mse"], rtol=1e-13, atol=0)
+
+
+# ---------------------------------------------------------------- d=2048 random features
+
+@pytest.fixture(scope="module")
+def c2(gpu):
+    import gpu_util
+    return gpu_util, workloads.named("rff_n20000_d2048")
+
+
+def test_rff_d2048_interp_all_grid_values_match_oracle(c2):
+    """The d = 2048 random-feature workload (n = 20000, k = 5, g = 6, r = 2,
+    q = 64) end to end: every fold at all 64 grid values against the
+    oracle's piCholesky path, weights included."""
+    gu, p = c2
+    got = gu.cv(p, "interp")
+    assert np.all(got["info"] == 0) and np.all(got["flags"] == 0)
+    for f in range(p.k):
+        H, Bm, Xv, Yv = _fold_grams(p, f)
+        want = oracle.fold_interp(H, Bm, Xv, Yv, p.lam_s, p.lam_grid, p.r, want_W=True)
+        assert np.all(want["info"] == 0) and np.all(want["flags"] == 0)
+        np.testing.assert_allclose(got["mse"][f], want["mse"], rtol=1e-10, atol=0)
+        scale = np.abs(want["W"]).max()
+        assert np.abs(got["W"][f] - want["W"]).max() <= 1e-9 * scale, f
+
+
+def test_rff_d2048_exact_all_grid_values_match_oracle(c2):
+    """The same workload's exact CV at all 64 grid values of folds 0 and 4
+    against the oracle's exact path."""
+    gu, p = c2
+    got = gu.cv(p, "exact", want_W=False)
+    assert np.all(got["info"] == 0) and np.all(got["flags"] == 0)
+    for f in [0, 4]:
+        H, Bm, Xv, Yv = _fold_grams(p, f)
+        want = oracle.fold_exact(H, Bm, Xv, Yv, p.lam_grid)
+        assert np.all(want["info"] == 0) and np.all(want["flags"] == 0)
+        np.testing.assert_allclose(got["mse"][f], want["mse"], rtol=1e-10, atol=0)
 
 
 # ---------------------------------------------------------------- derivative at d=2048

@@ -284,6 +284,85 @@ def test_solve_interp_matches_oracle(gu, d, c, g, r, q):
         close(Wg[t], Wo, rel, f"W t={t}")
 
 
+def _library_fit_solve(H, lam_s, lam_ref, r, lam, Bd):
+    """The interpolated solve composed from library routines: LAPACK
+    Cholesky at the samples, a least-squares fit of every entry in
+    tau = lambda/lam_ref by LAPACK (SVD based, accurate to cond(V) eps, not
+    cond(V)^2 eps as the normal equations), evaluation, and LAPACK
+    triangular solves."""
+    import scipy.linalg
+    d = H.shape[0]
+    g = len(lam_s)
+    Ls = np.stack([np.linalg.cholesky(H + l * np.eye(d)) for l in lam_s])
+    V = np.vander(np.asarray(lam_s) / lam_ref, r + 1, increasing=True)
+    coef, *_ = np.linalg.lstsq(V, Ls.reshape(g, -1), rcond=None)
+    out = []
+    for l in lam:
+        L = np.tril((np.vander([l / lam_ref], r + 1, increasing=True)[0] @ coef)
+                    .reshape(d, d))
+        z = scipy.linalg.solve_triangular(L, Bd, lower=True)
+        out.append(scipy.linalg.solve_triangular(L.T, z, lower=False))
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("d,c,g,r,q", [(140, 5, 5, 4, 9), (140, 5, 6, 4, 9),
+                                       (200, 3, 6, 3, 12), (257, 10, 6, 4, 17)])
+def test_solve_interp_high_degree_wide_range(gu, d, c, g, r, q):
+    """Degrees 3 and 4 over three decades (tau in [1e-3, 1], cond(V) up to
+    2.6e5): the oracle's normal equations are good only to cond(V)^2 eps
+    there, so the HIP path (whose fit multiplies by a pseudo-inverse from a
+    Householder QR) is held at 1e-10 to the same steps composed from LAPACK
+    routines, which two backward-stable fits meet to about 3e-12."""
+    rng = np.random.default_rng(7 * d + q)
+    H = spd(d, d + 3, cond=1e2)
+    lam_s = np.logspace(-3, 0, g)
+    lam_ref = lam_s.max()
+    lam = np.logspace(-3, 0, q)
+    L = _factors(gu, H, lam_s, d)
+    S = gu.B.pichol_packed_elems(d)
+    th = gu.empty((r + 1) * S)
+    tht = gu.empty((r + 1) * S)
+    gu.B.pichol_fit(d, 1, g, r, lam_s, lam_ref, L, th, tht)
+    dp = gu.B.pichol_padded_order(d)
+    Bh = np.zeros((dp, c))
+    Bh[:d] = rng.standard_normal((d, c))
+    ldz = gu.B.pichol_slab_cols(q, c)
+    Z = gu.empty(dp * ldz)
+    flags = gu.empty(q, torch.int32)
+    nb = gu.B.pichol_solve_interp_workspace(d, 1, q, c)
+    gu.B.pichol_solve_interp(d, 1, c, r, th, tht, gu.dev(Bh), q, lam, lam_ref, Z,
+                             flags, gu.ws(nb), nb)
+    Wg = gu.slab_to_w(Z, d, 1, q, c)[0]
+    assert np.all(flags.cpu().numpy() == 0)
+    want = _library_fit_solve(H, lam_s, lam_ref, r, lam, Bh[:d])
+    for t in range(q):
+        close(Wg[t], want[t], 1e-10, f"W t={t}")
+
+
+def test_cv_interp_quartic_wide_range_matches_library_composition(gu):
+    """The whole interpolated pipeline at degree 4 (g = 6) over four decades
+    of lambda, hold-out errors at 1e-10 against the library composition of
+    the same steps (validation residual formed directly)."""
+    p = workloads.gaussian_problem(1200, 160, 4, seed=17, k=3, g=6, q=13,
+                                   lam_range=(1e-4, 1.0))
+    lam_s = p.lam_grid[[0, 3, 5, 7, 9, 12]]
+    got = gu.cv(p, "interp", lam_s=lam_s, r=4)
+    assert np.all(got["info"] == 0) and np.all(got["flags"] == 0)
+    b = oracle.fold_bounds(p.n, p.k)
+    lam_ref = lam_s.max()
+    for f in range(p.k):
+        mask = np.ones(p.n, bool)
+        mask[b[f]:b[f + 1]] = False
+        Xt, Yt, Xv, Yv = p.X[mask], p.Y[mask], p.X[~mask], p.Y[~mask]
+        ntr = mask.sum()
+        H, Bm = Xt.T @ Xt / ntr, Xt.T @ Yt / ntr
+        W = _library_fit_solve(H, lam_s, lam_ref, 4, p.lam_grid, Bm)
+        for t in range(len(p.lam_grid)):
+            close(got["W"][f, t], W[t], 1e-10, f"W f={f} t={t}")
+            mse = np.sum((Yv - Xv @ W[t]) ** 2) / Yv.size
+            assert abs(got["mse"][f, t] - mse) <= 1e-10 * mse, (f, t)
+
+
 # ------------------------------------------------------------------ pipelines
 
 def _check_cv(got, want, rel_err=1e-10, rel_w=1e-9):

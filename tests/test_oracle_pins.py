@@ -387,6 +387,34 @@ def test_exact_cv_matches_svd_ridge_form(n, d, c, k):
             np.testing.assert_allclose(out["mse"][f, t], mse, rtol=1e-9)
 
 
+def test_fold_exact_matches_svd_ridge_form_and_cv_exact():
+    """The one-fold exact path (from numpy-formed H_f, B_f) against the SVD
+    ridge form and the whole-CV oracle on the same fold; a non-PD shift gives
+    the same info, NaN and flag pattern as cv_exact."""
+    n, d, c, k = 203, 17, 4, 5
+    p = workloads.gaussian_problem(n, d, c, seed=n, k=k, q=7)
+    b = oracle.fold_bounds(n, k)
+    lam = np.concatenate([p.lam_grid, [-1e3]])
+    full = oracle.cv_exact(p.X, p.Y, k, lam, want_W=True)
+    for f in [0, 3]:
+        mask = np.ones(n, bool)
+        mask[b[f]:b[f + 1]] = False
+        Xt, Yt, Xv, Yv = p.X[mask], p.Y[mask], p.X[~mask], p.Y[~mask]
+        H, Bm = Xt.T @ Xt / mask.sum(), Xt.T @ Yt / mask.sum()
+        out = oracle.fold_exact(H, Bm, Xv, Yv, lam, want_W=True)
+        np.testing.assert_array_equal(out["info"], full["info"][f])
+        np.testing.assert_array_equal(out["flags"], full["flags"][f])
+        assert out["info"][-1] == 1 and np.isnan(out["mse"][-1])
+        assert np.all(np.isnan(out["W"][-1]))
+        np.testing.assert_allclose(out["mse"][:-1], full["mse"][f, :-1], rtol=1e-12)
+        for t, l in enumerate(p.lam_grid):
+            th = _ridge_svd(Xt, Yt, l, mask.sum())
+            np.testing.assert_allclose(out["W"][t], th, rtol=0,
+                                       atol=1e-9 * np.abs(th).max())
+            mse = np.sum((Yv - Xv @ th) ** 2) / Yv.size
+            np.testing.assert_allclose(out["mse"][t], mse, rtol=1e-9)
+
+
 def test_interp_equals_exact_when_samples_are_the_grid():
     """With g = q, the samples equal to the grid and r = g - 1 the fit
     interpolates every exact factor, so piCholesky CV is exact CV."""
