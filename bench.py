@@ -814,6 +814,9 @@ def main():
                     help="skip the per-kernel event pass (no roofline)")
     ap.add_argument("--lookahead", type=int, default=0, choices=[0, 1],
                     help="side-stream look-ahead in the factorizations")
+    ap.add_argument("--solve-form", type=int, default=0, choices=[0, 1],
+                    help="interpolated solves per lambda with fused diagonal "
+                         "blocks (0) or stacked over the planes (1)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the precision-form legs timed after the FP64 "
                          "headline (FP32-MFMA trailing updates, iterative "
@@ -849,6 +852,7 @@ def main():
         sys.exit(2)
     B.load()
     B.pichol_set_option(B.PICHOL_OPT_LOOKAHEAD, args.lookahead)
+    B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, args.solve_form)
     dev = torch.device("cuda:0")
 
     log(f"generating workload {args.workload}")
@@ -1058,7 +1062,8 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": prob.name, "n": n, "d": d, "c": c, "k": k, "g": g,
                    "r": r, "q": q, "lam_range": list(prob.meta.get("lam_range", [])),
-                   "kind": prob.meta.get("kind"), "lookahead": args.lookahead},
+                   "kind": prob.meta.get("kind"), "lookahead": args.lookahead,
+                   "solve_form": args.solve_form},
         **result_extra,
         "precision_forms": variants,
         "batching_form": batching,

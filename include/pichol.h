@@ -648,7 +648,15 @@ typedef enum {
    * of the next group's columns stays on the caller's stream and the rest
    * of each group's trailing update runs on the side stream.  Results differ
    * only by the rounding order of the trailing sums. */
-  PICHOL_OPT_PANEL_GROUP = 2
+  PICHOL_OPT_PANEL_GROUP = 2,
+  /* 0 (default) or 1: the form of the interpolated solves (Sec. 3.2 with
+   * the factors of Sec. 3.3).  0: per lambda, each step evaluating every
+   * lambda's coefficient tile in registers and multiplying it with that
+   * lambda's columns only, with the next diagonal block solved inside the
+   * same launch; 1: stacked, each step one product of the r+1 coefficient
+   * tiles with every column scaled by the powers of tau, and a launch of
+   * its own for each diagonal block.  Results differ only by rounding. */
+  PICHOL_OPT_SOLVE_FORM = 3
 } pichol_option;
 
 /* Set a process-wide option; PICHOL_ERR_ARG for an unknown option or

@@ -35,6 +35,7 @@ PICHOL_LAYOUT_RECURSIVE = 3
 PICHOL_LAYOUT_TILE = 4
 PICHOL_OPT_LOOKAHEAD = 1
 PICHOL_OPT_PANEL_GROUP = 2
+PICHOL_OPT_SOLVE_FORM = 3
 PICHOL_PREC_FP64 = 0
 PICHOL_PREC_MIXED = 1
 PICHOL_MAX_REFINE = 16

@@ -36,6 +36,8 @@ static std::atomic<int> g_opt_lookahead{0};
 int option_lookahead() { return g_opt_lookahead.load(); }
 static std::atomic<int> g_opt_group{4};
 int option_panel_group() { return g_opt_group.load(); }
+static std::atomic<int> g_opt_solve{0};
+int option_solve_form() { return g_opt_solve.load(); }
 
 // ---------------------------------------------------------------- profiling
 struct ProfState {
@@ -367,6 +369,10 @@ pichol_status pichol_set_option(int32_t option, int32_t value) {
       if (value < 1 || value > 8) return PICHOL_ERR_ARG;
       g_opt_group.store(value);
       return PICHOL_OK;
+    case PICHOL_OPT_SOLVE_FORM:
+      if (value != 0 && value != 1) return PICHOL_ERR_ARG;
+      g_opt_solve.store(value);
+      return PICHOL_OK;
   }
   return PICHOL_ERR_ARG;
 }
@@ -375,6 +381,7 @@ int32_t pichol_get_option(int32_t option) {
   switch (option) {
     case PICHOL_OPT_LOOKAHEAD: return g_opt_lookahead.load();
     case PICHOL_OPT_PANEL_GROUP: return g_opt_group.load();
+    case PICHOL_OPT_SOLVE_FORM: return g_opt_solve.load();
   }
   return -1;
 }

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace pichol {
 
 constexpr int NB = 128;          // tile edge
@@ -41,6 +43,15 @@ __device__ inline int tri_row(int t) {
 }
 
 __device__ inline v4d ld4(const double* p) { return *(const v4d*)p; }
+
+// base + e elements, with the offset formed as a 32-bit byte count: a
+// wave-uniform base plus a per-lane offset below 4 GiB, the form of the
+// scalar-base, 32-bit-offset global addressing mode.
+template <typename T>
+__device__ inline T* at_elem(T* base, unsigned e) {
+  typedef typename std::conditional<std::is_const<T>::value, const char, char>::type B;
+  return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + e * (unsigned)sizeof(T));
+}
 __device__ inline void st4(double* p, v4d v) { *(v4d*)p = v; }
 
 // ---------------------------------------------------------------------------

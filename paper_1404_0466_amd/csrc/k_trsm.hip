@@ -404,6 +404,321 @@ k_update_interp(
   }
 }
 
+// Per-lambda form of one interpolated solve step, with the next diagonal
+// solve fused in.  The right-hand sides are taken in units of one lambda
+// and up to 16 of its columns (unit u = t * ncu + h, ncu = ceil(c / 16),
+// columns t*c + 16h ...).  A workgroup owns the 128 rows of one tile row I
+// and STEP_UNITS consecutive units; wave w takes the 64 rows of half
+// rh = w & 1 and the half kh = w >> 1 of the 128-long sums, for all of the
+// workgroup's units.  For every k step it loads the r+1 coefficient tiles'
+// values once, evaluates each unit's Lhat_t(I, i) = sum_p tau_t^p
+// Theta_p(I, i) from them in registers (Horner's rule), and multiplies that
+// with the unit's 16 columns on FP64 MFMA.  Against the stacked product
+// (every column scaled by each of the r+1 powers, K = (r+1) * 128) this
+// takes (r+1) * c / 16 times fewer products per column when c <= 16, at 2r
+// fused multiply-adds per operand value on the vector unit.  The second
+// half of the sums is handed to the first through LDS (a fixed order).
+// The workgroups of tile row i+1 (forward; i-1 backward) come first in the
+// grid.  After their update they stage the updated rows in LDS and multiply
+// them by the stored inverse of that diagonal block (backward: by its
+// transpose), writing the block the next step reads, so the steps need no
+// diagonal launches of their own.  Their updated rows themselves are not
+// stored: no later step reads them.
+//   forward : dst rows of I > i  -=  Lhat(I, i) src(i);
+//             out(i+1) = Linv(i+1) dst(i+1)
+//   backward: dst rows of I < i  -=  Lhat(i, I)^T src(i);
+//             out(i-1) = Linv(i-1)^T dst(i-1)
+// theta is the column-major planes (forward) or their row-major copy
+// (backward), so that A(row, k) sits at k * 128 + row either way.  MT is
+// the number of planes r+1 (0: any, read inside the k loop).
+constexpr int STEP_UNITS = 4;
+
+template <bool FWD, int MT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_step_interp(int64_t d, int i, int nmat, const double* theta, int64_t S,
+              int M, int q, int c, const double* tau, int64_t ldz, int nrows,
+              int ngrp, const double* dinv, const double* src, double* dst,
+              double* out) {
+  constexpr int U = STEP_UNITS;
+  __shared__ double zl[U * NB * 16];  // [unit][row][column]
+  const int nt = (int)ntiles_of(d);
+  const int64_t dp = (int64_t)nt * NB;
+  // the fused tile row's workgroups take the first ids, one per XCD in
+  // turn; the others are spread over the XCDs in contiguous ranges, the
+  // units of one coefficient tile together
+  const int nf = nmat * ngrp;
+  int id = blockIdx.x;
+  if (id >= nf) id = nf + xcd_remap(id - nf, (int)gridDim.x - nf);
+  const int g = id % ngrp;
+  const int64_t m = (id / ngrp) % nmat;
+  const int ro = id / (ngrp * nmat);
+  const int I = FWD ? i + 1 + ro : i - 1 - ro;
+  // wave-uniform indices (kept in scalar registers), so that every address
+  // below is a uniform base plus a 32-bit lane offset
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int rh = w & 1, kh = w >> 1;
+  const int l = threadIdx.x & 63, lq = l >> 4, lr = l & 15;
+  const int ncu = (c + 15) >> 4;
+  const int nunits = q * ncu;
+  const int ldzi = (int)ldz;
+  int tt[U];
+  unsigned cofs[U];  // slab column of the lane's entry of each unit
+  bool ok[U];   // the lane's column belongs to a valid unit
+  double tv[U];
+#pragma unroll
+  for (int j = 0; j < U; ++j) {
+    const int u = g * U + j;
+    const int uc = u < nunits ? u : nunits - 1;
+    const int t = uc / ncu, h = uc - t * ncu;
+    const int ncol = (c - 16 * h) < 16 ? (c - 16 * h) : 16;
+    tt[j] = t;
+    ok[j] = u < nunits && lr < ncol;
+    cofs[j] = (unsigned)(t * c + 16 * h + (lr < ncol ? lr : ncol - 1));
+    tv[j] = tau[t];
+  }
+  const int kb = 64 * kh;  // the wave's k range [kb, kb + 64)
+  const double* pl = theta + m * M * S + (FWD ? tile_off(I, i) : tile_off(i, I)) +
+                     rh * 64 + (int64_t)kb * NB;
+  const unsigned plo = (unsigned)(lq * NB + 4 * lr);
+  double* drow = dst + (m * dp + (int64_t)I * NB + rh * 64) * ldz;
+  unsigned dro[U];
+#pragma unroll
+  for (int j = 0; j < U; ++j) dro[j] = (unsigned)(4 * lq * ldzi) + cofs[j];
+  // the first k half starts from the rows being updated; element v of
+  // block bi is row 16v + 4lq + bi of the half, column lr of the unit
+  v4d acc[U][4];
+  if (kh == 0) {
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double x = *at_elem(drow + (int64_t)(16 * v + bi) * ldz, dro[j]);
+          acc[j][bi][v] = ok[j] ? x : 0.0;
+        }
+  } else {
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi) acc[j][bi] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  // (MT > 0) the coefficient values of the first k step, loaded before the
+  // staging below so that both round trips to memory overlap
+  v4d th[3][MT > 0 ? MT : 1];
+  if constexpr (MT > 0) {
+#pragma unroll
+    for (int p = 0; p < MT; ++p) th[0][p] = ld4(at_elem(pl + p * S, plo));
+  }
+  // The solved rows of tile i for the workgroup's units, staged in LDS
+  // (zl[unit][k][column], zeros past each unit's columns, negated: the
+  // products are subtracted), all loads in flight together.  Thread
+  // (row r0 = tid / 16, column cc = tid % 16) takes rows r0 + 16 n of every
+  // unit.
+  {
+    const int cc = threadIdx.x & 15, r0 = threadIdx.x >> 4;
+    const double* srow = src + (m * dp + (int64_t)i * NB) * ldz;
+    unsigned so[U];
+    bool sok[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int u = g * U + j;
+      const int uc = u < nunits ? u : nunits - 1;
+      const int t = uc / ncu, h = uc - t * ncu;
+      const int ncol = (c - 16 * h) < 16 ? (c - 16 * h) : 16;
+      sok[j] = u < nunits && cc < ncol;
+      so[j] = (unsigned)(r0 * ldzi + t * c + 16 * h + (cc < ncol ? cc : ncol - 1));
+    }
+    double v[U][8];
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+#pragma unroll
+      for (int n = 0; n < 8; ++n) v[j][n] = *at_elem(srow + (int64_t)16 * n * ldz, so[j]);
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+#pragma unroll
+      for (int n = 0; n < 8; ++n)
+        zl[((j * NB + r0 + 16 * n) << 4) + cc] = sok[j] ? -v[j][n] : 0.0;
+  }
+  __syncthreads();
+  const double* zb = zl + ((kb + lq) << 4) + lr;  // B(k, lane column) of unit 0
+  if constexpr (MT > 0) {
+    // the coefficient values of each k step are loaded two steps before
+    // its products (three register sets; the 16 steps are unrolled, and
+    // scheduling barriers keep the compiler from moving products ahead of
+    // loads issued after them, which would make them wait for those loads)
+    auto load = [&](int k0, v4d (&t)[MT]) {
+      const double* pk = pl + (int64_t)k0 * NB;
+#pragma unroll
+      for (int p = 0; p < MT; ++p) t[p] = ld4(at_elem(pk + p * S, plo));
+    };
+    auto step = [&](int k0, const v4d (&t)[MT]) {
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        v4d a = t[MT - 1];
+#pragma unroll
+        for (int p = MT - 2; p >= 0; --p) a = a * tv[j] + t[p];
+        const double b = zb[(j * NB + k0) << 4];
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+          acc[j][bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b, acc[j][bi], 0, 0, 0);
+      }
+    };
+    load(4, th[1]);
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+      if (st + 2 < 16) load(4 * (st + 2), th[(st + 2) % 3]);
+      __builtin_amdgcn_sched_barrier(0);
+      step(4 * st, th[st % 3]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else {
+#pragma unroll 1
+    for (int k0 = 0; k0 < 64; k0 += 4) {
+      const double* pk = pl + (int64_t)k0 * NB;
+      v4d a[U];
+      v4d th = ld4(at_elem(pk + (int64_t)(M - 1) * S, plo));
+#pragma unroll
+      for (int j = 0; j < U; ++j) a[j] = th;
+      for (int p = M - 2; p >= 0; --p) {
+        th = ld4(at_elem(pk + (int64_t)p * S, plo));
+#pragma unroll
+        for (int j = 0; j < U; ++j) a[j] = a[j] * tv[j] + th;
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const double b = zb[(j * NB + k0) << 4];
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+          acc[j][bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j][bi], b, acc[j][bi],
+                                                            0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();  // every wave is done with the staged rows
+  // the second k half's partial sums to the first (LDS, fixed order)
+  auto zidx = [&](int j, int v, int bi) {
+    return ((j * NB + rh * 64 + 16 * v + 4 * lq + bi) << 4) + lr;
+  };
+  if (kh == 1) {
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) zl[zidx(j, v, bi)] = acc[j][bi][v];
+  }
+  __syncthreads();
+  if (kh == 0) {
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[j][bi][v] += zl[zidx(j, v, bi)];
+    if (ro != 0) {
+#pragma unroll
+      for (int j = 0; j < U; ++j)
+        if (ok[j])
+#pragma unroll
+          for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              *at_elem(drow + (int64_t)(16 * v + bi) * ldz, dro[j]) = acc[j][bi][v];
+    } else {
+      // the updated block, whole, for the diagonal solve below (each lane
+      // overwrites only the entries it has just read)
+#pragma unroll
+      for (int j = 0; j < U; ++j)
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) zl[zidx(j, v, bi)] = acc[j][bi][v];
+    }
+  }
+  if (ro != 0) return;
+  __syncthreads();
+  // fused diagonal solve of tile row I: wave (rh, kh) forms the rows of
+  // half rh for the units 2kh, 2kh + 1
+  constexpr int UH = U / 2;
+  v4d ac2[UH][4];
+#pragma unroll
+  for (int j = 0; j < UH; ++j)
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) ac2[j][bi] = v4d{0.0, 0.0, 0.0, 0.0};
+  const double* lbase = dinv + ((m * q) * nt + I) * (int64_t)NB2;
+  unsigned lvo[UH];  // offset of the unit's inverse from lbase
+#pragma unroll
+  for (int j = 0; j < UH; ++j) lvo[j] = (unsigned)(tt[kh * UH + j] * nt * NB2);
+  // The inverse is read in chunks of 32 k, all of a chunk's loads issued
+  // before its products (the accumulators of the update are free by now).
+  if (FWD) {
+    // row r of the inverse is zero beyond column r: half rh needs k < 64(rh+1)
+    const int kend = 64 * (rh + 1);
+    const unsigned ao = (unsigned)(rh * 64 + 4 * lr + lq * NB);
+#pragma unroll 1
+    for (int kc = 0; kc < kend; kc += 32) {
+      v4d a[8][UH];
+#pragma unroll
+      for (int st = 0; st < 8; ++st)
+#pragma unroll
+        for (int j = 0; j < UH; ++j)
+          a[st][j] = ld4(at_elem(lbase + (kc + 4 * st) * NB, lvo[j] + ao));
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int st = 0; st < 8; ++st)
+#pragma unroll
+        for (int j = 0; j < UH; ++j) {
+          const double b = zl[(((kh * UH + j) * NB + kc + 4 * st + lq) << 4) + lr];
+#pragma unroll
+          for (int bi = 0; bi < 4; ++bi)
+            ac2[j][bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][j][bi], b, ac2[j][bi],
+                                                              0, 0, 0);
+        }
+    }
+  } else {
+    // the transpose: A(row, k) = Linv(k, row) at row * 128 + k, nonzero for
+    // k >= row, so half rh needs k >= 64 rh.  Four consecutive k of a row per
+    // 32-byte load: in step s of a 16-long block lane group lq supplies
+    // k = k0 + 4 lq + s, and the B operand follows that order.
+    const unsigned ao = (unsigned)((rh * 64 + 4 * lr) * NB + 4 * lq);
+#pragma unroll 1
+    for (int kc = 64 * rh; kc < NB; kc += 32) {
+      v4d a[2][UH][4];
+#pragma unroll
+      for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+        for (int j = 0; j < UH; ++j)
+#pragma unroll
+          for (int bi = 0; bi < 4; ++bi)
+            a[hb][j][bi] = ld4(at_elem(lbase + bi * NB + kc + 16 * hb, lvo[j] + ao));
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+        for (int j = 0; j < UH; ++j)
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const double b =
+                zl[(((kh * UH + j) * NB + kc + 16 * hb + 4 * lq + s4) << 4) + lr];
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+              ac2[j][bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[hb][j][bi][s4], b,
+                                                                ac2[j][bi], 0, 0, 0);
+          }
+    }
+  }
+  double* orow = out + (m * dp + (int64_t)I * NB + rh * 64) * ldz;
+#pragma unroll
+  for (int j = 0; j < UH; ++j)
+    if (ok[kh * UH + j])
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          *at_elem(orow + (int64_t)(16 * v + bi) * ldz, dro[kh * UH + j]) = ac2[j][bi][v];
+}
+
 // Off-diagonal update for exact factors, one factor per lambda t:
 // forward rows of tile I > i lose L_t(I,i) U_i, backward rows of tile I < i
 // lose L_t(i,I)^T W_i, on FP64 MFMA.  A workgroup of two waves takes one
@@ -523,6 +838,27 @@ hipError_t launch_diag_inv(int64_t d, int nmat, int M, const double* theta,
   return hipGetLastError();
 }
 
+
+template <bool FWD>
+static hipError_t step_interp(int M, dim3 grid, hipStream_t s, int64_t d, int i,
+                              int nmat, const double* theta, int64_t S, int q,
+                              int c, const double* tau, int64_t ldz, int nrows,
+                              int ngrp, const double* dinv, const double* src,
+                              double* dst, double* out) {
+#define PICHOL_STEP(MT)                                                          \
+  PICHOL_LAUNCH((k_step_interp<FWD, MT>), grid, dim3(256), 0, s, d, i,          \
+                nmat, theta, S, M, q, c, tau, ldz, nrows, ngrp, dinv, src, dst,  \
+                out)
+  switch (M) {
+    case 1: PICHOL_STEP(1); break;
+    case 2: PICHOL_STEP(2); break;
+    case 3: PICHOL_STEP(3); break;
+    default: PICHOL_STEP(0); break;
+  }
+#undef PICHOL_STEP
+  return hipGetLastError();
+}
+
 hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
                                const double* theta, const double* theta_t,
                                int q, const double* tau_dev, int64_t ldz,
@@ -537,23 +873,48 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
     if (e != hipSuccess) return e;
   }
   const dim3 agrid((unsigned)(4 * q), (unsigned)nmat);
-  for (int i = 0; i < nt; ++i) {
-    PICHOL_LAUNCH(k_diag_apply<true>, agrid, dim3(256), 0, s, d, i, q, c, dinv,
-                  ldz, Z, X);
-    if (i + 1 < nt) {
-      const int nrows = nt - i - 1;
-      PICHOL_LAUNCH(k_update_interp<true>, dim3(ncb * 2 * nrows * nmat),
-                    dim3(256), 0, s, d, i, theta, theta_t, S, M, q, c, tau_dev,
-                    ldz, (int)ncb, nrows, X, Z);
+  if (option_solve_form() == 1) {
+    // stacked form: a diagonal launch and an update launch per step
+    for (int i = 0; i < nt; ++i) {
+      PICHOL_LAUNCH(k_diag_apply<true>, agrid, dim3(256), 0, s, d, i, q, c, dinv,
+                    ldz, Z, X);
+      if (i + 1 < nt) {
+        const int nrows = nt - i - 1;
+        PICHOL_LAUNCH(k_update_interp<true>, dim3(ncb * 2 * nrows * nmat),
+                      dim3(256), 0, s, d, i, theta, theta_t, S, M, q, c, tau_dev,
+                      ldz, (int)ncb, nrows, X, Z);
+      }
     }
+    for (int i = nt - 1; i >= 0; --i) {
+      PICHOL_LAUNCH(k_diag_apply<false>, agrid, dim3(256), 0, s, d, i, q, c,
+                    dinv, ldz, X, Z);
+      if (i > 0)
+        PICHOL_LAUNCH(k_update_interp<false>, dim3(ncb * 2 * i * nmat), dim3(256),
+                      0, s, d, i, theta, theta_t, S, M, q, c, tau_dev, ldz,
+                      (int)ncb, i, Z, X);
+    }
+    return hipGetLastError();
   }
-  for (int i = nt - 1; i >= 0; --i) {
-    PICHOL_LAUNCH(k_diag_apply<false>, agrid, dim3(256), 0, s, d, i, q, c,
-                  dinv, ldz, X, Z);
-    if (i > 0)
-      PICHOL_LAUNCH(k_update_interp<false>, dim3(ncb * 2 * i * nmat), dim3(256),
-                    0, s, d, i, theta, theta_t, S, M, q, c, tau_dev, ldz,
-                    (int)ncb, i, Z, X);
+  // per-lambda form: the first diagonal block of each sweep on its own,
+  // every other one inside the step that completes it
+  const int ncu = (c + 15) / 16;
+  const int ngrp = (q * ncu + STEP_UNITS - 1) / STEP_UNITS;
+  PICHOL_LAUNCH(k_diag_apply<true>, agrid, dim3(256), 0, s, d, 0, q, c, dinv,
+                ldz, Z, X);
+  for (int i = 0; i + 1 < nt; ++i) {
+    const int nrows = nt - i - 1;
+    const hipError_t e = step_interp<true>(M, dim3((unsigned)(nmat * nrows * ngrp)),
+                                           s, d, i, nmat, theta, S, q, c, tau_dev,
+                                           ldz, nrows, ngrp, dinv, X, Z, X);
+    if (e != hipSuccess) return e;
+  }
+  PICHOL_LAUNCH(k_diag_apply<false>, agrid, dim3(256), 0, s, d, nt - 1, q, c,
+                dinv, ldz, X, Z);
+  for (int i = nt - 1; i > 0; --i) {
+    const hipError_t e = step_interp<false>(M, dim3((unsigned)(nmat * i * ngrp)), s,
+                                            d, i, nmat, theta_t, S, q, c, tau_dev,
+                                            ldz, i, ngrp, dinv, Z, X, Z);
+    if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }

@@ -30,6 +30,7 @@ hipError_t record_hip_error_code(hipError_t e);
 // Library options (pichol_set_option).
 int option_lookahead();
 int option_panel_group();
+int option_solve_form();
 inline int record_hip_error(hipError_t e) {
   (void)record_hip_error_code(e);
   return -3;  // PICHOL_ERR_HIP

@@ -174,6 +174,12 @@ def test_options(lib):
     for bad in [0, 9]:
         with pytest.raises(B.PicholError):
             B.pichol_set_option(B.PICHOL_OPT_PANEL_GROUP, bad)
+    assert B.pichol_get_option(B.PICHOL_OPT_SOLVE_FORM) == 0
+    B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, 1)
+    assert B.pichol_get_option(B.PICHOL_OPT_SOLVE_FORM) == 1
+    B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, 0)
+    with pytest.raises(B.PicholError):
+        B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, 2)
 
 
 def test_noalloc_holdout_rejects_oversize_before_touching_the_device(lib):

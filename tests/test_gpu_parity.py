@@ -363,6 +363,64 @@ def test_cv_interp_quartic_wide_range_matches_library_composition(gu):
             assert abs(got["mse"][f, t] - mse) <= 1e-10 * mse, (f, t)
 
 
+@pytest.mark.parametrize("d,c,g,r,q", [(1, 2, 3, 2, 4), (129, 17, 4, 2, 7),
+                                       (300, 10, 6, 2, 31), (257, 1, 5, 4, 9),
+                                       (384, 33, 3, 0, 5), (200, 16, 7, 6, 3)])
+def test_solve_forms_agree(gu, d, c, g, r, q):
+    """The two forms of the interpolated solves (per lambda with the
+    diagonal blocks fused into the steps, and stacked over the planes) on
+    ragged shapes: c above and at 16, one tile, degrees 0 to 6 (the generic
+    plane count), q*c not a multiple of the units per workgroup."""
+    B = gu.B
+    rng = np.random.default_rng(3 * d + c)
+    H = spd(d, d + 7, cond=1e2)
+    lam_s = np.logspace(-2, 0, g)
+    lam_ref = lam_s.max()
+    lam = np.logspace(-2, 0, q)
+    L = _factors(gu, H, lam_s, d)
+    S = B.pichol_packed_elems(d)
+    th = gu.empty((r + 1) * S)
+    tht = gu.empty((r + 1) * S)
+    B.pichol_fit(d, 1, g, r, lam_s, lam_ref, L, th, tht)
+    dp = B.pichol_padded_order(d)
+    Bh = np.zeros((dp, c))
+    Bh[:d] = rng.standard_normal((d, c))
+    ldz = B.pichol_slab_cols(q, c)
+    nb = B.pichol_solve_interp_workspace(d, 1, q, c)
+    out = {}
+    try:
+        for form in (0, 1):
+            B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, form)
+            Z = gu.empty(dp * ldz)
+            flags = gu.empty(q, torch.int32)
+            B.pichol_solve_interp(d, 1, c, r, th, tht, gu.dev(Bh), q, lam, lam_ref, Z,
+                                  flags, gu.ws(nb), nb)
+            torch.cuda.synchronize()
+            out[form] = (Z.cpu().numpy().reshape(dp, ldz), flags.cpu().numpy())
+    finally:
+        B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, 0)
+    Z0, f0 = out[0]
+    Z1, f1 = out[1]
+    np.testing.assert_array_equal(f0, f1)
+    assert np.all(Z0[d:] == 0.0) and np.all(Z0[:, q * c:] == 0.0)
+    close(Z0[:d, :q * c], Z1[:d, :q * c], 1e-12, "forms")
+
+
+@pytest.mark.parametrize("method", ["interp"])
+def test_cv_stacked_solve_form_matches_oracle(gu, method):
+    """The stacked form of the solves, selected by option, against the
+    oracle on the Gaussian workload."""
+    B = gu.B
+    p = workloads.named("gauss_n2000_d256")
+    B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, 1)
+    try:
+        got = gu.cv(p, method)
+    finally:
+        B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, 0)
+    want = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r, want_W=True)
+    _check_cv(got, want)
+
+
 # ------------------------------------------------------------------ pipelines
 
 def _check_cv(got, want, rel_err=1e-10, rel_w=1e-9):
