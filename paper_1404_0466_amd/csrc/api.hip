@@ -765,10 +765,11 @@ pichol_status pichol_cv_gram(const pichol_problem* p, const double* X,
 // Second stream of the interpolated pipeline (default priority, created
 // once per device with two events).  While the last kLateColumns columns of
 // the sample factors are factored (short, latency-bound launches that leave
-// most of the GPU idle), it fits the columns already finished and inverts
-// their interpolated diagonal blocks.
+// most of the GPU idle), it fits the columns already finished, inverts
+// their interpolated diagonal blocks and runs the forward solve steps that
+// need only those columns.
 namespace {
-constexpr int kLateColumns = 8;
+constexpr int kLateColumns = 12;
 struct OverlapStream {
   bool ready = false;
   hipStream_t stream = nullptr;
@@ -805,17 +806,22 @@ OverlapStream* overlap_stream() {
 }
 
 // The early part of the fit and of the diagonal-block inverses, forked off
-// the caller's stream once column cols-1 of every sample factor is final.
+// the caller's stream once column cols-1 of every sample factor is final,
+// and (fwd > 0, the per-lambda solve form) the forward solve steps
+// 0 .. fwd-1, which read only those columns' coefficients and inverses.
 struct EarlyFit {
   OverlapStream* os;
   hipStream_t main;
   int64_t d;
-  int k, q, M, cols;
+  int k, q, M, cols, c;
   const FitCoef* fc;
   const double* Lf;
   double *th, *tht, *dinv;
   const double* tau;
   int* flags;
+  int fwd;
+  int64_t ldz;
+  double *Z, *X;
 };
 
 hipError_t early_fit(void* ctx) {
@@ -828,6 +834,9 @@ hipError_t early_fit(void* ctx) {
   if (e == hipSuccess)
     e = launch_diag_inv(c.d, c.k, c.M, c.th, c.q, c.tau, c.dinv, c.flags, 0,
                         c.cols, c.os->stream);
+  if (e == hipSuccess && c.fwd > 0)
+    e = launch_solve_fwd(c.d, c.k, c.c, c.M, c.th, c.q, c.tau, c.ldz, c.Z, c.X,
+                         c.dinv, 0, c.fwd, c.os->stream);
   // the caller's stream waits for this event before it needs the results,
   // so it is recorded even after a failed launch
   const hipError_t r = hipEventRecord(c.os->done, c.os->stream);
@@ -880,8 +889,11 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
     os = overlap_stream();
   }
   const int cols = os ? nt - kLateColumns : 0;
-  EarlyFit ef{os, stream, p->d, k, q, M, cols, &fc, Lf, th, tht, dinv, tau,
-              flags};
+  // forward steps 0 .. cols-2 need only the early columns (step i reads
+  // column i and the inverse of block i+1)
+  const int fwd = (os && option_solve_form() == 0) ? cols - 1 : 0;
+  EarlyFit ef{os, stream, p->d, k, q, M, cols, c, &fc, Lf, th, tht, dinv, tau,
+              flags, fwd, L.ldz, Z, at<double>(ws, L.i_X)};
   const PanelHook hook{cols - 1, early_fit, &ef};
   if (e == hipSuccess)
     e = launch_potrf_blocked(p->d, k * g,
@@ -901,7 +913,7 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
     e = launch_diag_inv(p->d, k, M, th, q, tau, dinv, flags, cols, nt, stream);
   if (e == hipSuccess)
     e = launch_solve_interp(p->d, k, c, M, th, tht, q, tau, L.ldz, Z,
-                            at<double>(ws, L.i_X), flags, dinv, 0, stream);
+                            at<double>(ws, L.i_X), flags, dinv, 0, stream, fwd);
   if (e == hipSuccess && p->refine > 0) {
     // Residual correction against H_f + lambda_t I; the correction solves
     // reuse the inverted diagonal blocks of the interpolated factors.

@@ -859,11 +859,37 @@ static hipError_t step_interp(int M, dim3 grid, hipStream_t s, int64_t d, int i,
   return hipGetLastError();
 }
 
+// Forward steps i0 .. i1-1 of the per-lambda form (i0 = 0 starts with the
+// first diagonal block): afterwards the solved blocks 0 .. i1 are in X and
+// the rows below block i1 have received blocks 0 .. i1-1.  Step i reads the
+// coefficient tiles of column i and the inverted diagonal block i+1 only.
+hipError_t launch_solve_fwd(int64_t d, int nmat, int c, int M,
+                            const double* theta, int q, const double* tau_dev,
+                            int64_t ldz, double* Z, double* X,
+                            const double* dinv, int i0, int i1, hipStream_t s) {
+  const int nt = (int)ntiles_of(d);
+  const int64_t S = packed_elems_of(d);
+  if (i0 < 0 || i1 > nt - 1 || i0 > i1) return hipErrorInvalidValue;
+  const int ncu = (c + 15) / 16;
+  const int ngrp = (q * ncu + STEP_UNITS - 1) / STEP_UNITS;
+  if (i0 == 0)
+    PICHOL_LAUNCH(k_diag_apply<true>, dim3((unsigned)(4 * q), (unsigned)nmat),
+                  dim3(256), 0, s, d, 0, q, c, dinv, ldz, Z, X);
+  for (int i = i0; i < i1; ++i) {
+    const int nrows = nt - i - 1;
+    const hipError_t e = step_interp<true>(M, dim3((unsigned)(nmat * nrows * ngrp)),
+                                           s, d, i, nmat, theta, S, q, c, tau_dev,
+                                           ldz, nrows, ngrp, dinv, X, Z, X);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
                                const double* theta, const double* theta_t,
                                int q, const double* tau_dev, int64_t ldz,
                                double* Z, double* X, int* flags, double* dinv,
-                               int prepare, hipStream_t s) {
+                               int prepare, hipStream_t s, int fwd_from) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
   const unsigned ncb = (unsigned)(ldz / NB);
@@ -899,15 +925,9 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
   // every other one inside the step that completes it
   const int ncu = (c + 15) / 16;
   const int ngrp = (q * ncu + STEP_UNITS - 1) / STEP_UNITS;
-  PICHOL_LAUNCH(k_diag_apply<true>, agrid, dim3(256), 0, s, d, 0, q, c, dinv,
-                ldz, Z, X);
-  for (int i = 0; i + 1 < nt; ++i) {
-    const int nrows = nt - i - 1;
-    const hipError_t e = step_interp<true>(M, dim3((unsigned)(nmat * nrows * ngrp)),
-                                           s, d, i, nmat, theta, S, q, c, tau_dev,
-                                           ldz, nrows, ngrp, dinv, X, Z, X);
-    if (e != hipSuccess) return e;
-  }
+  const hipError_t ef = launch_solve_fwd(d, nmat, c, M, theta, q, tau_dev, ldz,
+                                         Z, X, dinv, fwd_from, nt - 1, s);
+  if (ef != hipSuccess) return ef;
   PICHOL_LAUNCH(k_diag_apply<false>, agrid, dim3(256), 0, s, d, nt - 1, q, c,
                 dinv, ldz, X, Z);
   for (int i = nt - 1; i > 0; --i) {

@@ -128,11 +128,18 @@ hipError_t launch_slab_init(int64_t d, int nmat, int q, int c, int64_t ldz,
 hipError_t launch_diag_inv(int64_t d, int nmat, int M, const double* theta,
                            int q, const double* tau_dev, double* dinv,
                            int* flags, int i0, int i1, hipStream_t s);
+// The interpolated solves of every fold at the q values (Z: right-hand
+// sides in, solutions out; X: second slab).  With the per-lambda form,
+// fwd_from > 0 skips the forward steps launch_solve_fwd has already run.
 hipError_t launch_solve_interp(int64_t d, int nmat, int c, int m,
                                const double* theta, const double* theta_t,
                                int q, const double* tau_dev, int64_t ldz,
                                double* Z, double* X, int* flags, double* dinv,
-                               int prepare, hipStream_t s);
+                               int prepare, hipStream_t s, int fwd_from = 0);
+hipError_t launch_solve_fwd(int64_t d, int nmat, int c, int M,
+                            const double* theta, int q, const double* tau_dev,
+                            int64_t ldz, double* Z, double* X,
+                            const double* dinv, int i0, int i1, hipStream_t s);
 // With linv (the kept inverses of the factors' diagonal tiles, see
 // launch_potrf_blocked) and a second slab X, each diagonal step is a product
 // with a stored inverse; without them it is a substitution in place.

@@ -472,12 +472,14 @@ def test_cv_rff_midsize(gu):
     _check_cv(gote, wante)
 
 
-@pytest.mark.parametrize("d", [1024, 1025, 1300])
+@pytest.mark.parametrize("d", [1536, 1537, 1700, 1800])
 def test_cv_interp_around_overlap_threshold(gu, d):
-    """Above eight tile columns the fit and the diagonal-block inverses of
-    the finished columns run on a second stream while the last eight columns
-    are factored: at d=1024 (eight columns) nothing is forked, at 1025 one
-    column is (the ninth column is a one-row ragged tile), at 1300 three."""
+    """Above twelve tile columns the fit and the diagonal-block inverses of
+    the finished columns, and the forward solve steps that need only them,
+    run on a second stream while the last twelve columns are factored: at
+    d=1536 (twelve columns) nothing is forked, at 1537 one column is (the
+    thirteenth is a one-row ragged tile; no forward step can start early),
+    at 1700 two (one early forward step), at 1800 three (two)."""
     p = workloads.gaussian_problem(2 * d + 7, d, 3, seed=21, g=4, q=8)
     got = gu.cv(p, "interp")
     want = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r, want_W=True)
