@@ -609,7 +609,10 @@ pichol_status pichol_graph_destroy(pichol_graph graph);
  * sequence then replays with one pichol_graph_launch.  Host arrays
  * (lambda values) are read during the capture and recorded in the graph.
  * The look-ahead side stream and per-kernel profiling must be off during a
- * capture; other threads' work is not captured (thread-local capture). */
+ * capture; other threads' work is not captured (thread-local capture).
+ * pichol_cv_interp (and pichol_cv) called on a capturing stream runs all of
+ * its work on that stream: it does not fork the second stream it uses
+ * above twelve tile columns (same results). */
 pichol_status pichol_graph_begin(hipStream_t stream);
 pichol_status pichol_graph_end(hipStream_t stream, pichol_graph *graph);
 

@@ -882,9 +882,15 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
   // columns 0 .. cols-1 are fitted and their diagonal blocks inverted on the
   // second stream while the last columns are still being factored
   const int nt = (int)L.nt;
+  // (not under stream capture: the shared second stream would join the
+  // caller's capture, and any other call using it meanwhile would land in
+  // or break that capture; the results are the same either way)
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (stream && hipStreamIsCapturing(stream, &cap) != hipSuccess)
+    cap = hipStreamCaptureStatusActive;  // unknown: do not fork
   std::unique_lock<std::mutex> lk(g_overlap_mu, std::defer_lock);
   OverlapStream* os = nullptr;
-  if (nt > kLateColumns) {
+  if (nt > kLateColumns && cap == hipStreamCaptureStatusNone) {
     lk.lock();
     os = overlap_stream();
   }

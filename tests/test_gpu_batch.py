@@ -143,11 +143,14 @@ def test_batch_rejects_bad_items(gu):
         gu.B.pichol_cv_batch(run.batch, run.method, dict(streams=5), run.ws, run.nbytes)
 
 
-def test_captured_single_problem_stage_replays_match_eager(gu):
+@pytest.mark.parametrize("n,d", [(900, 300), (3700, 1800)])
+def test_captured_single_problem_stage_replays_match_eager(gu, n, d):
     """pichol_graph_begin/end around the piCholesky stage of one problem:
-    replays equal the eager call bit for bit, with eager work between."""
+    replays equal the eager call bit for bit, with eager work between.  At
+    d = 1800 (15 tile columns) the eager call forks its second stream and
+    the captured one does not."""
     B = gu.B
-    p = workloads.gaussian_problem(900, 300, 3, seed=31, g=5, r=2, q=11)
+    p = workloads.gaussian_problem(n, d, 3, seed=31, g=5, r=2, q=11)
     prob = B.make_problem(p.n, p.d, p.c, p.k, p.g, p.r, p.q, True)
     nb = B.pichol_workspace_size(prob, B.PICHOL_METHOD_INTERP)
     w = gu.ws(nb)
