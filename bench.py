@@ -386,12 +386,24 @@ def batching_leg(args, B, stream):
         + ", ".join(f"{k_}={v:.2f} ms" for k_, v in times_i["schedule"].items())
         + "; panel groups per nt "
         + "; ".join(f"{nt}: " + ", ".join(f"{g_}={v:.2f}" for g_, v in tv.items())
-                    for nt, tv in times_i["panel_group"].items()))
+                    for nt, tv in times_i["panel_group"].items())
+        + "; solve forms per nt "
+        + "; ".join(f"{nt}: " + ", ".join(f"{f_}={v:.2f}" for f_, v in tv.items())
+                    for nt, tv in times_i["solve_form"].items()))
     t_eager = timed(lambda: B.pichol_cv_batch(bat_i, B.PICHOL_METHOD_INTERP, tune_i,
                                               ws, nbytes), reps)
     gi = B.pichol_cv_batch_graph(bat_i, B.PICHOL_METHOD_INTERP, tune_i, ws, nbytes)
     t_graph = timed(lambda: B.pichol_graph_launch(gi), reps)
     B.pichol_graph_destroy(gi)
+    # the same batch without its problems of d <= 768 (the buckets whose
+    # factorizations and solves have at most six tile columns): how much of
+    # the batch's time those buckets account for at all
+    big = [e for e in ents_i if e["p"].d > 768]
+    bat_big = B.Batch(big)
+    gb = B.pichol_cv_batch_graph(bat_big, B.PICHOL_METHOD_INTERP, tune_i, ws, nbytes)
+    t_big = timed(lambda: B.pichol_graph_launch(gb), reps)
+    B.pichol_graph_destroy(gb)
+    del bat_big
     ei = [b[2]["err"].cpu().numpy().reshape(pb.k, pb.q) for b, pb in zip(keep, probs)]
     ok_i = all(bool((b[2]["info"] == 0).all()) and bool((b[2]["flags"] == 0).all())
                for b in keep)
@@ -433,6 +445,8 @@ def batching_leg(args, B, stream):
         "lambda_solves": nsolves, "buckets": B.pichol_batch_buckets(bat_i, B.PICHOL_METHOD_INTERP),
         "tuning": tune_i, "tuning_times_ms": times_i,
         "graph_ms": t_graph, "value": nsolves / (t_graph * 1e-3),
+        "graph_ms_without_d_le_768": t_big,
+        "problems_d_le_768": len(ents_i) - len(big),
         "eager_ms": t_eager, "sequential_single_ms": t_seq,
         "speedup_vs_sequential": t_seq / t_graph,
         "exact_graph_ms": t_exact, "exact_value": nsolves / (t_exact * 1e-3),
@@ -445,6 +459,8 @@ def batching_leg(args, B, stream):
         "log_basis_same_selection": f"{same_l}/{len(probs)}",
         "note": "times include the Gram step of every problem",
     }
+    log(f"many problems: without the {len(ents_i) - len(big)} problems of d <= 768 "
+        f"the graph takes {t_big:.2f} ms")
     log(f"many problems: graph {t_graph:.2f} ms ({out['value']:.0f} lambda-solves/s), "
         f"eager {t_eager:.2f} ms, one by one {t_seq:.2f} ms, exact {t_exact:.2f} ms; "
         f"gap max {max(gap):.2e}, same selection {same_sel}/{len(probs)}")
@@ -814,9 +830,9 @@ def main():
                     help="skip the per-kernel event pass (no roofline)")
     ap.add_argument("--lookahead", type=int, default=0, choices=[0, 1],
                     help="side-stream look-ahead in the factorizations")
-    ap.add_argument("--solve-form", type=int, default=0, choices=[0, 1],
-                    help="interpolated solves per lambda with fused diagonal "
-                         "blocks (0) or stacked over the planes (1)")
+    ap.add_argument("--solve-form", type=int, default=0, choices=[0, 1, 2],
+                    help="interpolated solves: automatic (0), stacked over the "
+                         "planes (1) or per lambda with fused diagonal blocks (2)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the precision-form legs timed after the FP64 "
                          "headline (FP32-MFMA trailing updates, iterative "

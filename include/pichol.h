@@ -552,11 +552,15 @@ typedef struct {
  *                1: input order, round-robin over the streams
  *   panel_group  per d bucket: panel_group[nt-1] (nt = ceil(d/128) <= 32)
  *                panels per delayed trailing update in that bucket's
- *                factorizations, 1..8, or 0 for PICHOL_OPT_PANEL_GROUP */
+ *                factorizations, 1..8, or 0 for PICHOL_OPT_PANEL_GROUP
+ *   solve_form   per d bucket: the form of its interpolated solves, 1
+ *                (stacked) or 2 (per lambda), or 0 for
+ *                PICHOL_OPT_SOLVE_FORM */
 typedef struct {
   int32_t streams;
   int32_t order;
   int32_t panel_group[32];
+  int32_t solve_form[32];
 } pichol_batch_tuning;
 
 /* Many independent problems of uneven size in one call (Sec. 3.3's method
@@ -652,13 +656,16 @@ typedef enum {
    * of each group's trailing update runs on the side stream.  Results differ
    * only by the rounding order of the trailing sums. */
   PICHOL_OPT_PANEL_GROUP = 2,
-  /* 0 (default) or 1: the form of the interpolated solves (Sec. 3.2 with
-   * the factors of Sec. 3.3).  0: per lambda, each step evaluating every
-   * lambda's coefficient tile in registers and multiplying it with that
-   * lambda's columns only, with the next diagonal block solved inside the
-   * same launch; 1: stacked, each step one product of the r+1 coefficient
-   * tiles with every column scaled by the powers of tau, and a launch of
-   * its own for each diagonal block.  Results differ only by rounding. */
+  /* 0 (default), 1 or 2: the form of the interpolated solves (Sec. 3.2
+   * with the factors of Sec. 3.3).  2: per lambda, each step evaluating
+   * every lambda's coefficient tile in registers and multiplying it with
+   * that lambda's columns only (padded to 16 per lambda), with the next
+   * diagonal block solved inside the same launch; 1: stacked, each step one
+   * product of the r+1 coefficient tiles with every column scaled by the
+   * powers of tau (q*c columns rounded up to 128), and a launch of its own
+   * for each diagonal block; 0: per call, by their product counts (per
+   * lambda when (r+1) * slab columns >= 24 q ceil(c/16), e.g. c = 10;
+   * stacked for c = 1).  Results differ only by rounding. */
   PICHOL_OPT_SOLVE_FORM = 3
 } pichol_option;
 

@@ -1,13 +1,17 @@
 """Autotuner for batched cross-validation (pichol_cv_batch).
 
 The kernels' tile edge is fixed at 128 by the tile-packed layout; what is
-tuned is how the tiles are scheduled:
+tuned is which kernels run on the tiles and how they are scheduled:
   1. per d bucket, the number of 128-wide panels taken per delayed
      trailing update of the factorizations (the panel group: a larger group
      reads and writes the trailing tiles fewer times but lengthens the
      per-column updates inside the group) -- each bucket's problems are
      timed alone for every candidate group size;
-  2. for the whole batch, how many library streams run the independent
+  2. per d bucket (interpolated method), the form of the solves: the
+     stacked product over the r+1 coefficient planes, or the per-lambda
+     kernel that evaluates each lambda's tile in registers and pads its c
+     columns to 16 (the better one depends on c and q);
+  3. for the whole batch, how many library streams run the independent
      buckets concurrently and whether buckets are dealt out by decreasing
      work or in input order.
 Every candidate is timed as a few replays of a captured HIP graph on the
@@ -108,26 +112,56 @@ def tune_groups(batch, method, ws, nbytes, reps=3, groups=GROUPS):
     return best, times
 
 
+FORMS = (1, 2)
+
+
+def tune_forms(batch, method, ws, nbytes, groups, reps=3, forms=FORMS):
+    """Best solve form per d bucket for the interpolated method: {nt: form},
+    and the timings {nt: {form: ms}} (each bucket alone, with its chosen
+    panel group)."""
+    if method != B.PICHOL_METHOD_INTERP:
+        return {}, {}
+    by_nt = {}
+    for i in range(batch.n):
+        nt = (batch.items[i].p.d + 127) // 128
+        by_nt.setdefault(nt, []).append(i)
+    best, times = {}, {}
+    for nt, idx in sorted(by_nt.items()):
+        if nt > 32:
+            continue
+        sub = _Subset(batch, idx)
+        times[nt] = {}
+        for form in forms:
+            tune_ = {"streams": 1, "order": 0, "panel_group": {nt: groups.get(nt, 0)},
+                     "solve_form": {nt: form}}
+            times[nt][form] = time_schedule(sub, method, tune_, ws, nbytes, reps)
+        best[nt] = min(times[nt], key=times[nt].get)
+    return best, times
+
+
 def tune(batch: B.Batch, method: int, ws, nbytes, cache: str | None = DEFAULT_CACHE,
          reps: int = 3, force: bool = False, groups=GROUPS):
     """Returns (best tuning dict, timings or None when the cached choice was
-    used).  The tuning dict has streams, order and panel_group
-    ({nt: group})."""
+    used).  The tuning dict has streams, order, panel_group ({nt: group})
+    and solve_form ({nt: form})."""
     key = signature(batch, method)
     table = _load(cache) if cache else {}
     if not force and key in table:
         choice = table[key]["tune"]
-        choice["panel_group"] = {int(k): v for k, v in choice.get("panel_group", {}).items()}
+        for field in ("panel_group", "solve_form"):
+            choice[field] = {int(k): v for k, v in choice.get(field, {}).items()}
         return choice, None
     best_groups, group_times = tune_groups(batch, method, ws, nbytes, reps, groups)
+    best_forms, form_times = tune_forms(batch, method, ws, nbytes, best_groups, reps)
     times = {}
     for cand in CANDIDATES:
-        c = dict(cand, panel_group=best_groups)
+        c = dict(cand, panel_group=best_groups, solve_form=best_forms)
         times[json.dumps(cand, sort_keys=True)] = time_schedule(batch, method, c, ws,
                                                                nbytes, reps)
     best = min(times, key=times.get)
-    choice = dict(json.loads(best), panel_group=best_groups)
+    choice = dict(json.loads(best), panel_group=best_groups, solve_form=best_forms)
     if cache:
         table[key] = {"tune": choice, "ms": times[best]}
         _store(cache, table)
-    return choice, {"schedule": times, "panel_group": group_times}
+    return choice, {"schedule": times, "panel_group": group_times,
+                    "solve_form": form_times}

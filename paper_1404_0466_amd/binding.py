@@ -78,7 +78,8 @@ class BatchItem(ctypes.Structure):
 
 class BatchTuning(ctypes.Structure):
     """pichol_batch_tuning."""
-    _fields_ = [("streams", _i32), ("order", _i32), ("panel_group", _i32 * 32)]
+    _fields_ = [("streams", _i32), ("order", _i32), ("panel_group", _i32 * 32),
+                ("solve_form", _i32 * 32)]
 
 
 _pitem = ctypes.POINTER(BatchItem)
@@ -580,6 +581,8 @@ def _tune(tune):
     t = BatchTuning(int(tune.get("streams", 0)), int(tune.get("order", 0)))
     for nt, gsz in (tune.get("panel_group") or {}).items():
         t.panel_group[int(nt) - 1] = int(gsz)
+    for nt, form in (tune.get("solve_form") or {}).items():
+        t.solve_form[int(nt) - 1] = int(form)
     return ctypes.byref(t)
 
 

@@ -370,7 +370,7 @@ pichol_status pichol_set_option(int32_t option, int32_t value) {
       g_opt_group.store(value);
       return PICHOL_OK;
     case PICHOL_OPT_SOLVE_FORM:
-      if (value != 0 && value != 1) return PICHOL_ERR_ARG;
+      if (value < 0 || value > 2) return PICHOL_ERR_ARG;
       g_opt_solve.store(value);
       return PICHOL_OK;
   }
@@ -897,7 +897,7 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
   const int cols = os ? nt - kLateColumns : 0;
   // forward steps 0 .. cols-2 need only the early columns (step i reads
   // column i and the inverse of block i+1)
-  const int fwd = (os && option_solve_form() == 0) ? cols - 1 : 0;
+  const int fwd = (os && solve_form_for(M, q, c, L.ldz, 0) == 2) ? cols - 1 : 0;
   EarlyFit ef{os, stream, p->d, k, q, M, cols, c, &fc, Lf, th, tht, dinv, tau,
               flags, fwd, L.ldz, Z, at<double>(ws, L.i_X)};
   const PanelHook hook{cols - 1, early_fit, &ef};

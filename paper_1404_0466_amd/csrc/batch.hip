@@ -177,7 +177,7 @@ T* at(void* ws, size_t off) {
 
 // One bucket's pipeline on stream st.
 hipError_t run_bucket(const Bucket& b, const pichol_batch_item* items,
-                      int method, int group, void* ws, hipStream_t st) {
+                      int method, int group, int form, void* ws, hipStream_t st) {
   const bool interp = method == PICHOL_METHOD_INTERP;
   const int64_t d = b.d, nt = ntiles_of(d), dp = nt * NB;
   const int64_t S = packed_elems_of(d);
@@ -231,7 +231,7 @@ hipError_t run_bucket(const Bucket& b, const pichol_batch_item* items,
     if (e == hipSuccess)
       e = launch_solve_interp(d, nmat, c, M, th, tht, q, tau, ldz, Z,
                               at<double>(base, b.X), flags,
-                              at<double>(base, b.dinv), 1, st);
+                              at<double>(base, b.dinv), 1, st, 0, form);
   } else {
     if (e == hipSuccess)
       e = launch_solve_factors(d, nmat, q, c, L, ldz, Z, flags, linv,
@@ -357,7 +357,8 @@ pichol_status pichol_cv_batch(int32_t nprob, const pichol_batch_item* items,
         tune->order > 1)
       return PICHOL_ERR_ARG;
     for (int i = 0; i < 32; ++i)
-      if (tune->panel_group[i] < 0 || tune->panel_group[i] > 8)
+      if (tune->panel_group[i] < 0 || tune->panel_group[i] > 8 ||
+          tune->solve_form[i] < 0 || tune->solve_form[i] > 2)
         return PICHOL_ERR_ARG;
     if (tune->streams > 0) nstreams = tune->streams;
     order = tune->order;
@@ -367,6 +368,11 @@ pichol_status pichol_cv_batch(int32_t nprob, const pichol_batch_item* items,
     const int64_t nt = ntiles_of(b.d);
     return (tune && nt >= 1 && nt <= 32) ? tune->panel_group[nt - 1] : 0;
   };
+  // form of the interpolated solves for the bucket (0: option / automatic)
+  auto form_of = [&](const Bucket& b) {
+    const int64_t nt = ntiles_of(b.d);
+    return (tune && nt >= 1 && nt <= 32) ? tune->solve_form[nt - 1] : 0;
+  };
   if (!ws || ws_bytes < total) return PICHOL_ERR_WORKSPACE;
   if (nstreams > (int)bs.size()) nstreams = (int)bs.size();
   std::vector<int> run_order;
@@ -374,7 +380,8 @@ pichol_status pichol_cv_batch(int32_t nprob, const pichol_batch_item* items,
   if (nstreams == 1) {
     hipError_t e = hipSuccess;
     for (int j : run_order) {
-      e = run_bucket(bs[j], items, method, group_of(bs[j]), ws, stream);
+      e = run_bucket(bs[j], items, method, group_of(bs[j]), form_of(bs[j]), ws,
+                     stream);
       if (e != hipSuccess) break;
     }
     return hip_status(e);
@@ -388,7 +395,7 @@ pichol_status pichol_cv_batch(int32_t nprob, const pichol_batch_item* items,
     e = hipStreamWaitEvent(S->st[i], S->fork, 0);
   for (int j : run_order) {
     if (e != hipSuccess) break;
-    e = run_bucket(bs[j], items, method, group_of(bs[j]), ws,
+    e = run_bucket(bs[j], items, method, group_of(bs[j]), form_of(bs[j]), ws,
                    S->st[bs[j].stream]);
   }
   // join every forked stream back, also after a failure, so that no stream

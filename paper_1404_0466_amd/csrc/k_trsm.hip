@@ -885,11 +885,23 @@ hipError_t launch_solve_fwd(int64_t d, int nmat, int c, int M,
   return hipGetLastError();
 }
 
+int solve_form_for(int M, int q, int c, int64_t ldz, int requested) {
+  if (requested == 0) requested = option_solve_form();
+  if (requested == 1 || requested == 2) return requested;
+  // automatic: per step and tile, the stacked product runs over M * ldz
+  // columns (K = 128 per plane), the per-lambda one over 16 * q * ncu (each
+  // lambda's columns padded to 16); the per-lambda kernel also evaluates
+  // its operands and reaches about two thirds of the stacked one's rate
+  const int64_t ncu = (c + 15) / 16;
+  return (int64_t)M * ldz >= 24 * (int64_t)q * ncu ? 2 : 1;
+}
+
 hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
                                const double* theta, const double* theta_t,
                                int q, const double* tau_dev, int64_t ldz,
                                double* Z, double* X, int* flags, double* dinv,
-                               int prepare, hipStream_t s, int fwd_from) {
+                               int prepare, hipStream_t s, int fwd_from,
+                               int form) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
   const unsigned ncb = (unsigned)(ldz / NB);
@@ -899,7 +911,7 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
     if (e != hipSuccess) return e;
   }
   const dim3 agrid((unsigned)(4 * q), (unsigned)nmat);
-  if (option_solve_form() == 1) {
+  if (solve_form_for(M, q, c, ldz, form) == 1) {
     // stacked form: a diagonal launch and an update launch per step
     for (int i = 0; i < nt; ++i) {
       PICHOL_LAUNCH(k_diag_apply<true>, agrid, dim3(256), 0, s, d, i, q, c, dinv,

@@ -128,14 +128,20 @@ hipError_t launch_slab_init(int64_t d, int nmat, int q, int c, int64_t ldz,
 hipError_t launch_diag_inv(int64_t d, int nmat, int M, const double* theta,
                            int q, const double* tau_dev, double* dinv,
                            int* flags, int i0, int i1, hipStream_t s);
+// The form of the interpolated solves for M planes, q values, c columns
+// and slab width ldz: requested 1 (stacked) or 2 (per lambda) as given,
+// 0 the PICHOL_OPT_SOLVE_FORM option, whose 0 is the automatic choice.
+int solve_form_for(int M, int q, int c, int64_t ldz, int requested);
 // The interpolated solves of every fold at the q values (Z: right-hand
-// sides in, solutions out; X: second slab).  With the per-lambda form,
-// fwd_from > 0 skips the forward steps launch_solve_fwd has already run.
+// sides in, solutions out; X: second slab) in the form solve_form_for
+// gives.  With the per-lambda form, fwd_from > 0 skips the forward steps
+// launch_solve_fwd has already run.
 hipError_t launch_solve_interp(int64_t d, int nmat, int c, int m,
                                const double* theta, const double* theta_t,
                                int q, const double* tau_dev, int64_t ldz,
                                double* Z, double* X, int* flags, double* dinv,
-                               int prepare, hipStream_t s, int fwd_from = 0);
+                               int prepare, hipStream_t s, int fwd_from = 0,
+                               int form = 0);
 hipError_t launch_solve_fwd(int64_t d, int nmat, int c, int M,
                             const double* theta, int q, const double* tau_dev,
                             int64_t ldz, double* Z, double* X,

@@ -175,11 +175,20 @@ def test_options(lib):
         with pytest.raises(B.PicholError):
             B.pichol_set_option(B.PICHOL_OPT_PANEL_GROUP, bad)
     assert B.pichol_get_option(B.PICHOL_OPT_SOLVE_FORM) == 0
-    B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, 1)
-    assert B.pichol_get_option(B.PICHOL_OPT_SOLVE_FORM) == 1
-    B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, 0)
-    with pytest.raises(B.PicholError):
-        B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, 2)
+    for form in [1, 2, 0]:
+        B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, form)
+        assert B.pichol_get_option(B.PICHOL_OPT_SOLVE_FORM) == form
+    for bad in [-1, 3]:
+        with pytest.raises(B.PicholError):
+            B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, bad)
+
+
+def test_batch_tuning_struct_layout():
+    t = B.BatchTuning()
+    assert ctypes.sizeof(t) == 4 * (2 + 32 + 32)
+    assert B.BatchTuning.solve_form.offset == 4 * (2 + 32)
+    text = open(HEADER).read()
+    assert "int32_t solve_form[32];" in text
 
 
 def test_noalloc_holdout_rejects_oversize_before_touching_the_device(lib):

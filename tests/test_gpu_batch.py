@@ -99,6 +99,22 @@ def test_batch_schedule_does_not_change_results(gu, interp_run, tune):
         np.testing.assert_array_equal(a["flags"], b["flags"])
 
 
+@pytest.mark.parametrize("form", [1, 2])
+def test_batch_solve_form_per_bucket(gu, interp_run, form):
+    """A solve form chosen per d bucket through the tuning record: results
+    within rounding of the default run, and against the oracle."""
+    probs, run, ref = interp_run
+    run.clear()
+    nts = sorted({(p.d + 127) // 128 for p in probs})
+    got = run.run(dict(streams=2, order=0, solve_form={nt: form for nt in nts}))
+    for a, b in zip(got, ref):
+        np.testing.assert_allclose(a["mse"], b["mse"], rtol=1e-12, atol=0)
+        np.testing.assert_array_equal(a["flags"], b["flags"])
+    p = probs[0]
+    want = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r)
+    np.testing.assert_allclose(got[0]["mse"], want["mse"], rtol=1e-10, atol=0)
+
+
 def test_batch_mixed_precision_equals_single_mixed(gu):
     probs = small_batch()[2:4]
     run = gu.BatchRun(probs, "interp", precision=gu.B.PICHOL_PREC_MIXED)

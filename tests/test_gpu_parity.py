@@ -389,7 +389,7 @@ def test_solve_forms_agree(gu, d, c, g, r, q):
     nb = B.pichol_solve_interp_workspace(d, 1, q, c)
     out = {}
     try:
-        for form in (0, 1):
+        for form in (2, 1):
             B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, form)
             Z = gu.empty(dp * ldz)
             flags = gu.empty(q, torch.int32)
@@ -399,22 +399,22 @@ def test_solve_forms_agree(gu, d, c, g, r, q):
             out[form] = (Z.cpu().numpy().reshape(dp, ldz), flags.cpu().numpy())
     finally:
         B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, 0)
-    Z0, f0 = out[0]
+    Z0, f0 = out[2]
     Z1, f1 = out[1]
     np.testing.assert_array_equal(f0, f1)
     assert np.all(Z0[d:] == 0.0) and np.all(Z0[:, q * c:] == 0.0)
     close(Z0[:d, :q * c], Z1[:d, :q * c], 1e-12, "forms")
 
 
-@pytest.mark.parametrize("method", ["interp"])
-def test_cv_stacked_solve_form_matches_oracle(gu, method):
-    """The stacked form of the solves, selected by option, against the
-    oracle on the Gaussian workload."""
+@pytest.mark.parametrize("form,c", [(1, 10), (2, 10), (1, 1), (2, 1), (0, 1)])
+def test_cv_solve_forms_match_oracle(gu, form, c):
+    """Each form of the solves, selected by option (0: the automatic choice,
+    stacked for c = 1), against the oracle on the Gaussian workload."""
     B = gu.B
-    p = workloads.named("gauss_n2000_d256")
-    B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, 1)
+    p = workloads.gaussian_problem(2000, 256, c, seed=0, g=4, r=2, q=31)
+    B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, form)
     try:
-        got = gu.cv(p, method)
+        got = gu.cv(p, "interp")
     finally:
         B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, 0)
     want = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r, want_W=True)
