@@ -408,7 +408,7 @@ k_update_interp(
 // solve fused in.  The right-hand sides are taken in units of one lambda
 // and up to 16 of its columns (unit u = t * ncu + h, ncu = ceil(c / 16),
 // columns t*c + 16h ...).  A workgroup owns the 128 rows of one tile row I
-// and STEP_UNITS consecutive units; wave w takes the 64 rows of half
+// and U consecutive units; wave w takes the 64 rows of half
 // rh = w & 1 and the half kh = w >> 1 of the 128-long sums, for all of the
 // workgroup's units.  For every k step it loads the r+1 coefficient tiles'
 // values once, evaluates each unit's Lhat_t(I, i) = sum_p tau_t^p
@@ -431,15 +431,14 @@ k_update_interp(
 // theta is the column-major planes (forward) or their row-major copy
 // (backward), so that A(row, k) sits at k * 128 + row either way.  MT is
 // the number of planes r+1 (0: any, read inside the k loop).
-constexpr int STEP_UNITS = 4;
-
-template <bool FWD, int MT>
+// U units per workgroup: 4, or 2 for launches too small to fill the GPU
+// (half the serial work per workgroup, twice the workgroups).
+template <bool FWD, int MT, int U>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_step_interp(int64_t d, int i, int nmat, const double* theta, int64_t S,
               int M, int q, int c, const double* tau, int64_t ldz, int nrows,
               int ngrp, const double* dinv, const double* src, double* dst,
               double* out) {
-  constexpr int U = STEP_UNITS;
   __shared__ double zl[U * NB * 16];  // [unit][row][column]
   const int nt = (int)ntiles_of(d);
   const int64_t dp = (int64_t)nt * NB;
@@ -839,21 +838,38 @@ hipError_t launch_diag_inv(int64_t d, int nmat, int M, const double* theta,
 }
 
 
+// Launches of the per-lambda step with fewer workgroups than this at four
+// units each take two units per workgroup.
+constexpr int STEP_SMALL_LAUNCH = 512;
+
 template <bool FWD>
-static hipError_t step_interp(int M, dim3 grid, hipStream_t s, int64_t d, int i,
+static hipError_t step_interp(int M, int nrows, hipStream_t s, int64_t d, int i,
                               int nmat, const double* theta, int64_t S, int q,
-                              int c, const double* tau, int64_t ldz, int nrows,
-                              int ngrp, const double* dinv, const double* src,
+                              int c, const double* tau, int64_t ldz,
+                              const double* dinv, const double* src,
                               double* dst, double* out) {
-#define PICHOL_STEP(MT)                                                          \
-  PICHOL_LAUNCH((k_step_interp<FWD, MT>), grid, dim3(256), 0, s, d, i,          \
-                nmat, theta, S, M, q, c, tau, ldz, nrows, ngrp, dinv, src, dst,  \
-                out)
-  switch (M) {
-    case 1: PICHOL_STEP(1); break;
-    case 2: PICHOL_STEP(2); break;
-    case 3: PICHOL_STEP(3); break;
-    default: PICHOL_STEP(0); break;
+  const int nunits = q * ((c + 15) / 16);
+  const int g4 = (nunits + 3) / 4;
+  const bool small = (int64_t)nmat * nrows * g4 < STEP_SMALL_LAUNCH;
+  const int ngrp = small ? (nunits + 1) / 2 : g4;
+  const dim3 grid((unsigned)(nmat * nrows * ngrp));
+#define PICHOL_STEP(MT, U)                                                      \
+  PICHOL_LAUNCH((k_step_interp<FWD, MT, U>), grid, dim3(256), 0, s, d, i, nmat, \
+                theta, S, M, q, c, tau, ldz, nrows, ngrp, dinv, src, dst, out)
+  if (small) {
+    switch (M) {
+      case 1: PICHOL_STEP(1, 2); break;
+      case 2: PICHOL_STEP(2, 2); break;
+      case 3: PICHOL_STEP(3, 2); break;
+      default: PICHOL_STEP(0, 2); break;
+    }
+  } else {
+    switch (M) {
+      case 1: PICHOL_STEP(1, 4); break;
+      case 2: PICHOL_STEP(2, 4); break;
+      case 3: PICHOL_STEP(3, 4); break;
+      default: PICHOL_STEP(0, 4); break;
+    }
   }
 #undef PICHOL_STEP
   return hipGetLastError();
@@ -870,16 +886,12 @@ hipError_t launch_solve_fwd(int64_t d, int nmat, int c, int M,
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
   if (i0 < 0 || i1 > nt - 1 || i0 > i1) return hipErrorInvalidValue;
-  const int ncu = (c + 15) / 16;
-  const int ngrp = (q * ncu + STEP_UNITS - 1) / STEP_UNITS;
   if (i0 == 0)
     PICHOL_LAUNCH(k_diag_apply<true>, dim3((unsigned)(4 * q), (unsigned)nmat),
                   dim3(256), 0, s, d, 0, q, c, dinv, ldz, Z, X);
   for (int i = i0; i < i1; ++i) {
-    const int nrows = nt - i - 1;
-    const hipError_t e = step_interp<true>(M, dim3((unsigned)(nmat * nrows * ngrp)),
-                                           s, d, i, nmat, theta, S, q, c, tau_dev,
-                                           ldz, nrows, ngrp, dinv, X, Z, X);
+    const hipError_t e = step_interp<true>(M, nt - i - 1, s, d, i, nmat, theta, S,
+                                           q, c, tau_dev, ldz, dinv, X, Z, X);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();
@@ -935,17 +947,14 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
   }
   // per-lambda form: the first diagonal block of each sweep on its own,
   // every other one inside the step that completes it
-  const int ncu = (c + 15) / 16;
-  const int ngrp = (q * ncu + STEP_UNITS - 1) / STEP_UNITS;
   const hipError_t ef = launch_solve_fwd(d, nmat, c, M, theta, q, tau_dev, ldz,
                                          Z, X, dinv, fwd_from, nt - 1, s);
   if (ef != hipSuccess) return ef;
   PICHOL_LAUNCH(k_diag_apply<false>, agrid, dim3(256), 0, s, d, nt - 1, q, c,
                 dinv, ldz, X, Z);
   for (int i = nt - 1; i > 0; --i) {
-    const hipError_t e = step_interp<false>(M, dim3((unsigned)(nmat * i * ngrp)), s,
-                                            d, i, nmat, theta_t, S, q, c, tau_dev,
-                                            ldz, i, ngrp, dinv, Z, X, Z);
+    const hipError_t e = step_interp<false>(M, i, s, d, i, nmat, theta_t, S, q, c,
+                                            tau_dev, ldz, dinv, Z, X, Z);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();
