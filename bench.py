@@ -749,8 +749,8 @@ def solve_tiles(d: int) -> int:
 
 def stage_rooflines(summ, prob, steps, stage, lookahead, B):
     """Roofline entries of one stage's main kernels, from the event pass:
-    algorithmic work per launch (formulas of DESIGN section 5) over the mean
-    launch duration."""
+    algorithmic work per launch (the per-unit counts written out below, times
+    the units of one launch) over the mean launch duration."""
     d, k, g, q, c, r = prob.d, prob.k, prob.g, prob.q, prob.c, prob.r
     nfac = k * (g if stage == "interp" else q)
     out = {}
