@@ -830,6 +830,9 @@ def main():
                     help="skip the per-kernel event pass (no roofline)")
     ap.add_argument("--lookahead", type=int, default=0, choices=[0, 1],
                     help="side-stream look-ahead in the factorizations")
+    ap.add_argument("--panel-group", type=int, default=0,
+                    help="panel group G of the factorizations, 1..8 (0: the "
+                         "library's default)")
     ap.add_argument("--solve-form", type=int, default=0, choices=[0, 1, 2],
                     help="interpolated solves: automatic (0), stacked over the "
                          "planes (1) or per lambda with fused diagonal blocks (2)")
@@ -869,6 +872,8 @@ def main():
     B.load()
     B.pichol_set_option(B.PICHOL_OPT_LOOKAHEAD, args.lookahead)
     B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, args.solve_form)
+    if args.panel_group:
+        B.pichol_set_option(B.PICHOL_OPT_PANEL_GROUP, args.panel_group)
     dev = torch.device("cuda:0")
 
     log(f"generating workload {args.workload}")
@@ -1079,7 +1084,8 @@ def main():
         "config": {"workload": prob.name, "n": n, "d": d, "c": c, "k": k, "g": g,
                    "r": r, "q": q, "lam_range": list(prob.meta.get("lam_range", [])),
                    "kind": prob.meta.get("kind"), "lookahead": args.lookahead,
-                   "solve_form": args.solve_form},
+                   "solve_form": args.solve_form,
+                   "panel_group": B.pichol_get_option(B.PICHOL_OPT_PANEL_GROUP)},
         **result_extra,
         "precision_forms": variants,
         "batching_form": batching,

@@ -18,16 +18,54 @@ __device__ inline v4d ld4_masked(const double* rowp, int64_t col, int64_t d,
   return v;
 }
 
+// Tile t of the lower triangle of nt x nt tiles in the Gram kernel's order:
+// the triangle is cut into 8 x 8 blocks of tiles (the diagonal blocks keep
+// their lower half), taken block row by block row, and each block's tiles
+// row by row.  The 64 tiles of one block read 8 column strips of X per
+// operand, where 64 tiles taken row by row along the triangle read about 2
+// strips each.
+__device__ inline void gram_tile_of(int t, int nt, int& I, int& J) {
+  constexpr int SB = 8;
+  for (int P = 0; P * SB < nt; ++P) {
+    const int r0 = P * SB, rs = nt - r0 < SB ? nt - r0 : SB;
+    for (int Q = 0; Q <= P; ++Q) {
+      const int c0 = Q * SB;
+      const int n = Q == P ? rs * (rs + 1) / 2 : rs * SB;
+      if (t < n) {
+        if (Q == P) {
+          const int i = tri_row(t);
+          I = r0 + i;
+          J = c0 + (t - (int)tri(i));
+        } else {
+          const int i = t / SB;
+          I = r0 + i;
+          J = c0 + (t - i * SB);
+        }
+        return;
+      }
+      t -= n;
+    }
+  }
+  I = J = 0;  // not reached for t < tri(nt)
+}
+
 // G_b tile (I,J), J <= I, over the rows of block b; FP64 MFMA.  The wave
 // computes D'(n,m) = sum_r X[r][J*128+n] X[r][I*128+m] for its 64 x 64 part,
 // i.e. G(I*128+m, J*128+n), which is element n*128+m of the column-major tile
 // (I,J); the mirror tile (J,I) receives the transpose.
+// Workgroups are spread over the XCDs in contiguous ranges of the logical
+// order (block by block, then gram_tile_of), so the workgroups running
+// together on one XCD stream the same few strips of X through its L2.
 __global__ void __launch_bounds__(256) k_gram_tiles(const double* X,
                                                     int64_t ldx, int64_t d,
                                                     int64_t nt, FoldSplit fs,
                                                     double* G, int vec_ok) {
-  const int b = blockIdx.y;
-  const int I = tri_row(blockIdx.x), J = blockIdx.x - (int)tri(I);
+  const int ntri = (int)gridDim.x;
+  const int id = xcd_remap((int)(blockIdx.x + blockIdx.y * gridDim.x),
+                           ntri * (int)gridDim.y);
+  const int b = id / ntri;
+  int I, J;
+  gram_tile_of(id - b * ntri, (int)nt, I, J);
   const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
   const int64_t r0 = fs.start[b], r1 = fs.start[b + 1];
   const int64_t K = r1 - r0;
