@@ -734,7 +734,8 @@ def layout_leg(args, B, stream):
 
 def merged(summ, base):
     """(launches, total ms) of every instantiation of a kernel."""
-    parts = [v for nm, v in summ.items() if nm == base or nm.startswith(base + "<")]
+    parts = [v for nm, v in summ.items()
+             if nm.strip("()") == base or nm.strip("()").startswith(base + "<")]
     if not parts:
         return None
     return sum(x[0] for x in parts), sum(x[1] for x in parts)
@@ -784,6 +785,29 @@ def stage_rooflines(summ, prob, steps, stage, lookahead, B):
             "method_flops_per_launch": method,
             "method_frac": method / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
             "launches_per_step": nl / steps,
+        }
+    si = merged(summ, "k_step_interp")
+    if si and stage == "interp":
+        nl, tot = si
+        # per-lambda form: every off-diagonal tile of Lhat_t times that
+        # lambda's c columns, once per direction (the method's products);
+        # the MFMA products run on columns padded to a multiple of 16, and
+        # the coefficient planes are read once per fold, the slab rows read
+        # and written once per step
+        tiles = 2 * k * solve_tiles(d) * steps / nl
+        method = q * tiles * 2.0 * NB * NB * c
+        mfma = q * tiles * 2.0 * NB * NB * 16 * ((c + 15) // 16)
+        byts = tiles * ((r + 1) * NB * NB * 8 + 2 * NB * ldz * 8)
+        ms = tot / nl
+        tf = method / (ms * 1e-3) / 1e12
+        out["k_step_interp"] = {
+            "kernel": "k_step_interp", "bound": "mfma", "achieved": tf,
+            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": tf / PEAK_FP64_TFLOPS,
+            "flops_per_launch": method, "mfma_flops_per_launch": mfma,
+            "mfma_frac": mfma / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "bytes_per_launch": byts,
+            "hbm_frac": byts / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "avg_launch_ms": ms, "launches_per_step": nl / steps,
         }
     uf = merged(summ, "k_update_factors")
     if uf and stage == "exact":
