@@ -187,7 +187,41 @@ def cpu_baseline(prob, gpu_err_fold0, gpu_err_exact_fold0=None):
         },
         "exact": exact,
         "lapack": lapack_baseline(prob, H, Bm, Xv, Yv),
+        "conditioning": conditioning(prob, H, float(rel.max())),
     }
+
+
+def conditioning(prob, H, achieved):
+    """The conditioning behind the parity bar at full size (untimed):
+    kappa(H_0 + lambda I) of fold 0 from its eigenvalues at the grid's ends
+    and the samples' ends, and cond(V) of the fit's basis in tau =
+    lambda/lam_ref (the library's and the oracle's) and in raw lambda,
+    beside the relative difference between the GPU's and the oracle's
+    fold-0 hold-out errors.  Two backward-stable FP64 solvers agree to
+    about kappa * eps * (a low power of d)."""
+    ev = np.linalg.eigvalsh(H)
+    eps = float(np.finfo(np.float64).eps)
+
+    def kappa(lam):
+        return float((ev[-1] + lam) / (ev[0] + lam))
+
+    r = prob.r
+    tau = prob.lam_s / prob.lam_ref
+    out = {
+        "eig_min": float(ev[0]), "eig_max": float(ev[-1]),
+        "kappa_at_lambda_min": kappa(float(prob.lam_grid.min())),
+        "kappa_at_lambda_max": kappa(float(prob.lam_grid.max())),
+        "kappa_at_sample_min": kappa(float(prob.lam_s.min())),
+        "cond_V_tau": float(np.linalg.cond(np.vander(tau, r + 1, increasing=True))),
+        "cond_V_raw_lambda": float(np.linalg.cond(
+            np.vander(prob.lam_s, r + 1, increasing=True))),
+        "fold0_err_max_rel_diff_vs_oracle": achieved,
+    }
+    out["kappa_eps_at_lambda_min"] = out["kappa_at_lambda_min"] * eps
+    log(f"conditioning: kappa(H_0 + lambda_min I) = {out['kappa_at_lambda_min']:.3g}, "
+        f"cond(V) = {out['cond_V_tau']:.3g} in tau, "
+        f"{out['cond_V_raw_lambda']:.3g} in raw lambda; achieved {achieved:.2e}")
+    return out
 
 
 def lapack_baseline(prob, H, Bm, Xv, Yv):

@@ -909,14 +909,17 @@ pichol_status pichol_cv_interp(const pichol_problem* p, const double* lam_s,
                              option_lookahead(), 0, stream, os ? &hook : nullptr);
   if (e == hipSuccess)
     e = launch_fit_cols(p->d, k, fc, Lf, th, tht, cols, nt, stream);
+  // the late columns' inverses touch nothing the second stream uses (their
+  // own blocks; flag bits are set atomically), so they run beside its
+  // forward steps
+  if (e == hipSuccess)
+    e = launch_diag_inv(p->d, k, M, th, q, tau, dinv, flags, cols, nt, stream);
   if (os) {
     // join the second stream (its work was forked by the hook, which ran
     // unless an earlier launch failed)
     const hipError_t j = hipStreamWaitEvent(stream, os->done, 0);
     if (e == hipSuccess) e = j;
   }
-  if (e == hipSuccess)
-    e = launch_diag_inv(p->d, k, M, th, q, tau, dinv, flags, cols, nt, stream);
   if (e == hipSuccess)
     e = launch_solve_interp(p->d, k, c, M, th, tht, q, tau, L.ldz, Z,
                             at<double>(ws, L.i_X), flags, dinv, 0, stream, fwd);
