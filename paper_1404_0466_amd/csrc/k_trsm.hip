@@ -432,9 +432,12 @@ k_update_interp(
 // (backward), so that A(row, k) sits at k * 128 + row either way.  MT is
 // the number of planes r+1 (0: any, read inside the k loop).
 // U units per workgroup: 4, or 2 for launches too small to fill the GPU
-// (half the serial work per workgroup, twice the workgroups).
+// and for the steps that run alone (half the serial work per workgroup,
+// twice the workgroups; 164 registers, so three waves share a SIMD where
+// the four-unit form's 242 allow two).
 template <bool FWD, int MT, int U>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(U == 2 ? 3 : 2, U == 2 ? 3 : 2)))
 k_step_interp(int64_t d, int i, int nmat, const double* theta, int64_t S,
               int M, int q, int c, const double* tau, int64_t ldz, int nrows,
               int ngrp, const double* dinv, const double* src, double* dst,
@@ -839,7 +842,10 @@ hipError_t launch_diag_inv(int64_t d, int nmat, int M, const double* theta,
 
 
 // Launches of the per-lambda step with fewer workgroups than this at four
-// units each take two units per workgroup.
+// units each take two units per workgroup, and so do all launches with
+// `narrow` (steps that share the GPU with nothing else: the four-unit form
+// disturbs a concurrent factorization less, the two-unit one finishes a
+// lone step sooner).
 constexpr int STEP_SMALL_LAUNCH = 512;
 
 template <bool FWD>
@@ -847,10 +853,10 @@ static hipError_t step_interp(int M, int nrows, hipStream_t s, int64_t d, int i,
                               int nmat, const double* theta, int64_t S, int q,
                               int c, const double* tau, int64_t ldz,
                               const double* dinv, const double* src,
-                              double* dst, double* out) {
+                              double* dst, double* out, bool narrow) {
   const int nunits = q * ((c + 15) / 16);
   const int g4 = (nunits + 3) / 4;
-  const bool small = (int64_t)nmat * nrows * g4 < STEP_SMALL_LAUNCH;
+  const bool small = narrow || (int64_t)nmat * nrows * g4 < STEP_SMALL_LAUNCH;
   const int ngrp = small ? (nunits + 1) / 2 : g4;
   const dim3 grid((unsigned)(nmat * nrows * ngrp));
 #define PICHOL_STEP(MT, U)                                                      \
@@ -882,7 +888,8 @@ static hipError_t step_interp(int M, int nrows, hipStream_t s, int64_t d, int i,
 hipError_t launch_solve_fwd(int64_t d, int nmat, int c, int M,
                             const double* theta, int q, const double* tau_dev,
                             int64_t ldz, double* Z, double* X,
-                            const double* dinv, int i0, int i1, hipStream_t s) {
+                            const double* dinv, int i0, int i1, hipStream_t s,
+                            bool narrow) {
   const int nt = (int)ntiles_of(d);
   const int64_t S = packed_elems_of(d);
   if (i0 < 0 || i1 > nt - 1 || i0 > i1) return hipErrorInvalidValue;
@@ -891,7 +898,8 @@ hipError_t launch_solve_fwd(int64_t d, int nmat, int c, int M,
                   dim3(256), 0, s, d, 0, q, c, dinv, ldz, Z, X);
   for (int i = i0; i < i1; ++i) {
     const hipError_t e = step_interp<true>(M, nt - i - 1, s, d, i, nmat, theta, S,
-                                           q, c, tau_dev, ldz, dinv, X, Z, X);
+                                           q, c, tau_dev, ldz, dinv, X, Z, X,
+                                           narrow);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();
@@ -948,13 +956,13 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int M,
   // per-lambda form: the first diagonal block of each sweep on its own,
   // every other one inside the step that completes it
   const hipError_t ef = launch_solve_fwd(d, nmat, c, M, theta, q, tau_dev, ldz,
-                                         Z, X, dinv, fwd_from, nt - 1, s);
+                                         Z, X, dinv, fwd_from, nt - 1, s, true);
   if (ef != hipSuccess) return ef;
   PICHOL_LAUNCH(k_diag_apply<false>, agrid, dim3(256), 0, s, d, nt - 1, q, c,
                 dinv, ldz, X, Z);
   for (int i = nt - 1; i > 0; --i) {
     const hipError_t e = step_interp<false>(M, i, s, d, i, nmat, theta_t, S, q, c,
-                                            tau_dev, ldz, dinv, Z, X, Z);
+                                            tau_dev, ldz, dinv, Z, X, Z, true);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();

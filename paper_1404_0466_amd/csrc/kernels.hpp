@@ -142,10 +142,14 @@ hipError_t launch_solve_interp(int64_t d, int nmat, int c, int m,
                                double* Z, double* X, int* flags, double* dinv,
                                int prepare, hipStream_t s, int fwd_from = 0,
                                int form = 0);
+// Forward steps i0 .. i1-1 of the per-lambda form (i0 = 0 also solves the
+// first diagonal block).  narrow: two units per workgroup in every launch,
+// for steps that do not share the GPU with a factorization.
 hipError_t launch_solve_fwd(int64_t d, int nmat, int c, int M,
                             const double* theta, int q, const double* tau_dev,
                             int64_t ldz, double* Z, double* X,
-                            const double* dinv, int i0, int i1, hipStream_t s);
+                            const double* dinv, int i0, int i1, hipStream_t s,
+                            bool narrow = false);
 // With linv (the kept inverses of the factors' diagonal tiles, see
 // launch_potrf_blocked) and a second slab X, each diagonal step is a product
 // with a stored inverse; without them it is a substitution in place.
