@@ -646,6 +646,51 @@ def factorization_leg(args, B, prob, X, Y, stream):
     return out
 
 
+def library_leg(prob, X, stream, ours_ms=None):
+    """GPU library context, not the product path: the ROCm build of torch's
+    batched dense Cholesky (torch.linalg.cholesky_ex) on the same k*g shifted
+    fold matrices H_f + lambda_s I that the piCholesky stage factors, in FP64,
+    event-timed like the factorization leg."""
+    import torch
+    n, d, k, g = prob.n, prob.d, prob.k, prob.g
+    dev = X.device
+    sizes = [len(a) for a in np.array_split(np.arange(n), k)]
+    starts = np.cumsum([0] + sizes)
+    Gb = [X[starts[b]:starts[b + 1]].T @ X[starts[b]:starts[b + 1]] for b in range(k)]
+    Gs = sum(Gb)
+    eye = torch.eye(d, dtype=torch.float64, device=dev)
+    A = torch.empty(k * g, d, d, dtype=torch.float64, device=dev)
+    for f in range(k):
+        Hf = (Gs - Gb[f]) / (n - sizes[f])
+        for s_, lam in enumerate(prob.lam_s):
+            A[f * g + s_] = Hf + float(lam) * eye
+    del Gb, Gs, Hf
+    L, info = torch.linalg.cholesky_ex(A)
+    torch.cuda.synchronize()
+    reps = 3
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        L, info = torch.linalg.cholesky_ex(A)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ok = bool((info == 0).all().item())
+    tf = k * g * potrf_flops(d) / (ms * 1e-3) / 1e12
+    log(f"library context: torch.linalg.cholesky_ex on {k * g} matrices of order {d}: "
+        f"{ms:.2f} ms, {tf:.2f} TFLOP/s")
+    del A, L, info
+    torch.cuda.empty_cache()
+    out = {"what": "torch.linalg.cholesky_ex (ROCm build), dense FP64, the k*g "
+                   "sample matrices H_f + lambda_s I; context only",
+           "torch": torch.__version__, "factors": k * g, "ms": ms, "achieved": tf,
+           "frac": tf / PEAK_FP64_TFLOPS, "info_ok": ok}
+    if ours_ms:
+        out["pichol_potrf_shifted_batched_ms"] = ours_ms
+        out["speedup_of_pichol"] = ms / ours_ms
+    return out
+
+
 def accuracy_leg(args, B, prob, X, Y, stream):
     """Interpolation accuracy on fold 0 of the headline workload (untimed):
     the NRMSE of every interpolated factor at the q grid values against the
@@ -902,6 +947,8 @@ def main():
                     help="skip the vectorisation-layout comparison")
     ap.add_argument("--no-factorization", action="store_true",
                     help="skip the stand-alone factorization timing")
+    ap.add_argument("--no-library", action="store_true",
+                    help="skip the torch.linalg.cholesky_ex context timing")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the fold-0 factor-accuracy diagnostic (NRMSE)")
     ap.add_argument("--no-grad", action="store_true",
@@ -1066,6 +1113,11 @@ def main():
     if not args.no_factorization:
         factorization = factorization_leg(args, B, prob, X, Y, stream)
 
+    library = None
+    if not args.no_library:
+        library = library_leg(prob, X, stream,
+                              factorization["sample_factors"]["ms"] if factorization else None)
+
     accuracy = None
     if not args.no_accuracy:
         accuracy = accuracy_leg(args, B, prob, X, Y, stream)
@@ -1151,6 +1203,7 @@ def main():
         "layout_comparison": layouts,
         "accuracy": accuracy,
         "factorization": factorization,
+        "library_context": library,
         "roofline": roofline,
         "rooflines": rooflines,
         "cpu_baseline": cpu,
