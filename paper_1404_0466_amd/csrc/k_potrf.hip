@@ -340,12 +340,18 @@ __device__ inline void mma_group(Acc64F& acc, const double* Lf, int I, int J,
 
 // Where a fused diagonal factorization writes: the inverse of tile j0 of
 // factor f goes to linv + f * lstride + loff, a failed pivot to info[f].
+// dc0 >= 0: tile (j0, j0) already holds the panels before dc0 (a previous
+// launch took them ahead), so this launch sums only [dc0, c1) for it.
+// pre: the launch also takes the panels [c0, c1) into tile (j0+1, j0+1)
+// ahead of its own column update.
 struct DiagOut {
   int* info;
   double* linv;
   int64_t lstride;
   int64_t loff;
   int fuse;  // 1: the launch also factors diagonal tile (j0, j0)
+  int dc0;
+  int pre;
 };
 
 // Trailing tile (I,J): A_IJ -= sum_{c in [c0,c1)} L_Ic L_Jc^T, for the
@@ -362,32 +368,47 @@ struct DiagOut {
 // it) the first nfac workgroups take those tiles, one per matrix, and after
 // the update go on to factor it (diag_factor_tile), so
 // the diagonal factorization runs while the rest of the launch is still
-// updating; the other workgroups take the remaining tiles.
+// updating; the other workgroups take the remaining tiles.  With dout.pre
+// the last nfac workgroups update tile (j0+1, j0+1) ahead (see DiagOut), so
+// the next column's diagonal workgroup starts its factorization sooner.
 template <typename ACC, bool SRC, bool FUSABLE>
 __device__ inline void potrf_update_body(int64_t S, int nt, int j0, int mode,
                                          int c0, int c1, int ntile, double* L,
                                          int64_t d, const ShiftSrc& src,
                                          const DiagOut& dout) {
   const bool fuse = FUSABLE && dout.fuse;
+  const int nfac = (int)gridDim.x / (ntile + dout.pre);
+  const int nmain = nfac * ntile;  // workgroups of the launch's own tiles
   int f, t;
-  if (fuse) {
-    const int nfac = (int)gridDim.x / ntile;
+  const bool ahead = (int)blockIdx.x >= nmain;
+  if (ahead) {
+    f = (int)blockIdx.x - nmain;
+    t = -1;
+  } else if (fuse) {
     if ((int)blockIdx.x < nfac) {
       f = blockIdx.x;
       t = 0;
     } else {
       const int rest = ntile - 1;  // >= 1 here: the grid holds more tiles
-      const int id = xcd_remap((int)blockIdx.x - nfac, (int)gridDim.x - nfac);
+      const int id = xcd_remap((int)blockIdx.x - nfac, nmain - nfac);
       f = id / rest;
       t = 1 + (id - f * rest);
     }
   } else {
-    const int id = xcd_remap(blockIdx.x, gridDim.x);
+    const int id = xcd_remap(blockIdx.x, nmain);
     f = id / ntile;
     t = id - f * ntile;
   }
+  // tile (j0, j0) taken over from a launch that started its sum
+  const bool resumed = t == 0 && dout.dc0 >= 0;
+  const int ca = resumed ? dout.dc0 : c0;
+  // with SRC the tile is read from the source matrix, unless an earlier
+  // launch has touched it already
+  const bool from_src = SRC && !resumed;
   int I, J;
-  if (mode == 0) {
+  if (ahead) {
+    I = J = j0 + 1;
+  } else if (mode == 0) {
     const int r = tri_row(t);
     I = j0 + r;
     J = j0 + (t - (int)tri(r));
@@ -406,13 +427,13 @@ __device__ inline void potrf_update_body(int64_t S, int nt, int j0, int mode,
   double* ct = Lf + tile_off(I, J);
   if (!(I == J && wi > wj)) {  // that block lies strictly above the diagonal
     // the tile's current value: L itself, or (first touch) the source matrix
-    const double* cs = SRC ? src_tile(src, S, f, tile_off(I, J)) : ct;
+    const double* cs = from_src ? src_tile(src, S, f, tile_off(I, J)) : ct;
     const LaneXY lx;
     const int m0 = wj * 64 + lx.col0();
     ACC acc;
     acc.zero();
-    mma_group(acc, Lf, I, J, c0, c1, wi, wj);
-    const double shift = (SRC && I == J) ? src_shift(src, f) : 0.0;
+    mma_group(acc, Lf, I, J, ca, c1, wi, wj);
+    const double shift = (from_src && I == J) ? src_shift(src, f) : 0.0;
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -428,7 +449,7 @@ __device__ inline void potrf_update_body(int64_t S, int nt, int j0, int mode,
           for (int e = 0; e < 4; ++e)
             if (m0 + e >= n) {
               double cv = q[e];
-              if (SRC && m0 + e == n && (int64_t)I * NB + n < d) cv += shift;
+              if (from_src && m0 + e == n && (int64_t)I * NB + n < d) cv += shift;
               p[e] = cv - val[e];
             }
         }
@@ -462,9 +483,11 @@ k_potrf_update(int64_t S, int nt, int j0, int mode, int c0, int c1, int ntile,
 template <bool SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_potrf_update_f32(int64_t S, int nt, int j0, int mode, int c0, int c1,
-                   int ntile, double* L, int64_t d, ShiftSrc src) {
-  potrf_update_body<Acc64F, SRC, false>(S, nt, j0, mode, c0, c1, ntile, L, d,
-                                        src, DiagOut{nullptr, nullptr, 0, 0, 0});
+                   int ntile, double* L, int64_t d, ShiftSrc src, int dc0,
+                   int pre) {
+  potrf_update_body<Acc64F, SRC, false>(
+      S, nt, j0, mode, c0, c1, ntile, L, d, src,
+      DiagOut{nullptr, nullptr, 0, 0, 0, dc0, pre});
 }
 
 // The mixed-precision column updates inside a group (short launches, with
@@ -557,16 +580,19 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
       PICHOL_LAUNCH(k_potrf_panel<false>, grid, dim3(256), 0, s, S, kk, L,
                     linv_ws, lstride, loff, src);
   };
-  // fd: this launch also factors diagonal tile (j0, j0)
+  // fd: this launch also factors diagonal tile (j0, j0); dc0, pre: see
+  // DiagOut
   auto update = [&](hipStream_t st, int j0, int mode, int c0, int c1,
-                    bool first, bool fd) {
+                    bool first, bool fd, int dc0 = -1, bool pre = false) {
     const int rest = nt - j0;
     if (rest <= 0) return;
     const int m = mode == 0 ? 0 : (mode < rest ? mode : rest);
     const int ntile = m == 0 ? (int)tri(rest) : m * rest - m * (m - 1) / 2;
-    const dim3 grid((unsigned)(ntile * nfac));
+    const int npre = pre ? 1 : 0;
+    const dim3 grid((unsigned)((ntile + npre) * nfac));
     const DiagOut dout{info, linv_ws, lstride,
-                       keep_linv ? (int64_t)j0 * NB2 : 0, fd ? 1 : 0};
+                       keep_linv ? (int64_t)j0 * NB2 : 0, fd ? 1 : 0, dc0,
+                       npre};
     if (mixed && fd && first)
       PICHOL_LAUNCH(k_potrf_update_f32_diag<true>, grid, dim3(256), 0, st, S,
                     nt, j0, m, c0, c1, ntile, L, d, src, dout);
@@ -575,10 +601,10 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
                     nt, j0, m, c0, c1, ntile, L, d, src, dout);
     else if (mixed && first)
       PICHOL_LAUNCH(k_potrf_update_f32<true>, grid, dim3(256), 0, st, S, nt,
-                    j0, m, c0, c1, ntile, L, d, src);
+                    j0, m, c0, c1, ntile, L, d, src, dc0, npre);
     else if (mixed)
       PICHOL_LAUNCH(k_potrf_update_f32<false>, grid, dim3(256), 0, st, S, nt,
-                    j0, m, c0, c1, ntile, L, d, src);
+                    j0, m, c0, c1, ntile, L, d, src, dc0, npre);
     else if (first)
       PICHOL_LAUNCH(k_potrf_update<true>, grid, dim3(256), 0, st, S, nt, j0, m,
                     c0, c1, ntile, L, d, src, dout);
@@ -594,7 +620,13 @@ hipError_t launch_potrf_blocked(int64_t d, int nfac, const ShiftSrc& src,
     // the first group's launches are the first to touch every tile
     const bool first = has_src && kk == 0;
     for (int u = 0; u < G && kk + u < nt; ++u) {
-      if (u > 0) update(s, kk + u, 1, kk, kk + u, first, fuse_cols);
+      // column kk+u's launch also takes the group's panels so far into
+      // diagonal tile kk+u+1, whose own launch then sums only the newest
+      // panel before that tile's factorization starts (the same sums on
+      // every path, so results do not depend on the batch size)
+      if (u > 0)
+        update(s, kk + u, 1, kk, kk + u, first, fuse_cols,
+               u >= 2 ? kk + u - 1 : -1, u + 1 < G && kk + u + 1 < nt);
       // tile kk (u = 0) was factored by the previous group's trailing update
       // on the FP64 path
       diag_panel(kk + u, first && u == 0,
