@@ -146,8 +146,12 @@ def lebesgue(lam_s, lam_grid, r):
 
 
 @pytest.mark.parametrize("method", ["interp", "exact"])
-def test_mixed_cv_close_to_fp64_oracle(gu, method):
-    prob = workloads.gaussian_problem(1500, 520, 5, seed=3, g=5, r=2, q=12)
+@pytest.mark.parametrize("n,d,c,g,q", [(1500, 520, 5, 5, 12),
+                                       # q c = 640: solve launches of
+                                       # 512 and more workgroups
+                                       (6000, 1024, 10, 6, 64)])
+def test_mixed_cv_close_to_fp64_oracle(gu, method, n, d, c, g, q):
+    prob = workloads.gaussian_problem(n, d, c, seed=3, g=g, r=2, q=q)
     got = gu.cv(prob, method, precision=gu.B.PICHOL_PREC_MIXED)
     assert np.all(got["info"] == 0) and np.all(got["flags"] == 0)
     if method == "interp":
