@@ -472,16 +472,23 @@ def test_cv_rff_midsize(gu):
     _check_cv(gote, wante)
 
 
-@pytest.mark.parametrize("d", [1536, 1537, 1700, 1800])
-def test_cv_interp_around_overlap_threshold(gu, d):
+@pytest.mark.parametrize("d,form", [(1536, 0), (1537, 0), (1700, 0), (1800, 0),
+                                    (1800, 1)])
+def test_cv_interp_around_overlap_threshold(gu, d, form):
     """Above twelve tile columns the fit and the diagonal-block inverses of
     the finished columns, and the forward solve steps that need only them,
     run on a second stream while the last twelve columns are factored: at
     d=1536 (twelve columns) nothing is forked, at 1537 one column is (the
     thirteenth is a one-row ragged tile; no forward step can start early),
-    at 1700 two (one early forward step), at 1800 three (two)."""
+    at 1700 two (one early forward step), at 1800 three (two).  With the
+    stacked solve form (form 1) only the fit and the inverses are forked."""
+    B = gu.B
     p = workloads.gaussian_problem(2 * d + 7, d, 3, seed=21, g=4, q=8)
-    got = gu.cv(p, "interp")
+    B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, form)
+    try:
+        got = gu.cv(p, "interp")
+    finally:
+        B.pichol_set_option(B.PICHOL_OPT_SOLVE_FORM, 0)
     want = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r, want_W=True)
     _check_cv(got, want)
 
