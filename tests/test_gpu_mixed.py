@@ -149,7 +149,9 @@ def lebesgue(lam_s, lam_grid, r):
 @pytest.mark.parametrize("n,d,c,g,q", [(1500, 520, 5, 5, 12),
                                        # q c = 640: solve launches of
                                        # 512 and more workgroups
-                                       (6000, 1024, 10, 6, 64)])
+                                       (6000, 1024, 10, 6, 64),
+                                       # past the second-stream threshold
+                                       (3407, 1700, 3, 4, 8)])
 def test_mixed_cv_close_to_fp64_oracle(gu, method, n, d, c, g, q):
     prob = workloads.gaussian_problem(n, d, c, seed=3, g=g, r=2, q=q)
     got = gu.cv(prob, method, precision=gu.B.PICHOL_PREC_MIXED)
