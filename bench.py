@@ -641,6 +641,25 @@ def factorization_leg(args, B, prob, X, Y, stream):
                      "frac": tf / PEAK_FP64_TFLOPS, "info_ok": ok}
         log(f"factorization: {k * ns} factors of order {d} in {ms:.2f} ms, "
             f"{tf:.2f} TFLOP/s ({100 * tf / PEAK_FP64_TFLOPS:.1f}% of FP64 peak)")
+        if not args.no_profile:
+            # the trailing-update kernel alone, on a GPU it does not share
+            # (in the piCholesky stage the second stream runs beside the
+            # last columns' launches)
+            B.pichol_profile_start(4000 * reps)
+            for _ in range(reps):
+                run()
+            torch.cuda.synchronize()
+            B.pichol_profile_stop()
+            upd = merged(B.pichol_profile_summary(), "k_potrf_update")
+            B.pichol_profile_reset()
+            if upd:
+                nl, tot = upd
+                ut = update_flops(d, k * ns) * reps / nl / (tot / nl * 1e-3) / 1e12
+                out[name]["k_potrf_update"] = {
+                    "achieved": ut, "frac": ut / PEAK_FP64_TFLOPS,
+                    "avg_launch_ms": tot / nl, "launches": nl / reps}
+                log(f"factorization: k_potrf_update alone {ut:.2f} TFLOP/s "
+                    f"({100 * ut / PEAK_FP64_TFLOPS:.1f}% of FP64 peak)")
     del L, H, wsp
     torch.cuda.empty_cache()
     return out
