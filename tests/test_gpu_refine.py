@@ -77,3 +77,17 @@ def test_refined_interp_converges_toward_exact(gu, prob):
         gaps.append(np.max(np.abs(got["mse"] - ex["mse"]) / ex["mse"]))
     print("interp vs exact after 0/2/6 steps:", ["%.2e" % g for g in gaps])
     assert gaps[1] < gaps[0] and gaps[2] < gaps[1]
+
+
+def test_refined_interp_past_overlap_threshold(gu):
+    """Refinement after a call that forked its second stream (d = 1700:
+    the fit, inverses and early forward steps of the first columns ran
+    beside the last columns' factorization, and the correction solves
+    follow the join)."""
+    p = workloads.gaussian_problem(3407, 1700, 3, seed=21, g=4, r=2, q=8)
+    got = gu.cv(p, "interp", refine=1)
+    want = oracle.cv_interp(p.X, p.Y, p.k, p.lam_s, p.lam_grid, p.r, want_W=True,
+                            refine=1)
+    assert np.all(got["info"] == 0) and np.all(got["flags"] == 0)
+    np.testing.assert_allclose(got["mse"], want["mse"], rtol=1e-10, atol=0)
+    _wclose(got["W"], want["W"], 1e-9)
