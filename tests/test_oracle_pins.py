@@ -826,3 +826,63 @@ def test_parity_bar_is_attainable_on_the_parity_workloads():
         assert np.linalg.cond(V) < 1e3
     V_raw = np.vander(p.lam_s, p.r + 1, increasing=True)
     assert np.linalg.cond(V_raw) > 1e6
+
+
+def test_interpolated_cv_matches_50_digit_arithmetic():
+    """The oracle's whole piCholesky CV (fold Gram matrices, sample
+    factorizations, the least-squares fit in tau, evaluation at grid values
+    between and beyond the samples, the two substitutions and the hold-out
+    MSE) against the same mathematics carried out in 50-digit arithmetic
+    (mpmath) at d = 6.  The interpolated factor is linear in the sample
+    factors, Lhat(tau) = sum_s w_s(tau) L_s with w(tau) = phi(tau)^T V^+, and
+    the solution is (Lhat Lhat^T)^{-1} B_f; kappa(H_f + lambda I) is about
+    10 here, so FP64 agrees to well inside 1e-10."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 50
+    rng = np.random.default_rng(11)
+    n, d, c, k, g, r = 40, 6, 2, 4, 4, 2
+    X = rng.standard_normal((n, d))
+    Y = rng.standard_normal((n, c))
+    lam_s = np.array([0.05, 0.1, 0.2, 0.4])
+    lam_grid = np.array([0.03, 0.07, 0.15, 0.3, 0.6])
+    got = oracle.cv_interp(X, Y, k, lam_s, lam_grid, r, want_W=True)
+    starts = np.cumsum([0] + [len(a) for a in np.array_split(np.arange(n), k)])
+    lam_ref = mp.mpf(float(lam_s.max()))
+    tau_s = [mp.mpf(float(x)) / lam_ref for x in lam_s]
+    V = mp.matrix([[t ** j for j in range(r + 1)] for t in tau_s])
+    Vp = (V.T * V) ** -1 * V.T  # the pseudo-inverse, (r+1) x g
+    Xm = [[mp.mpf(float(x)) for x in row] for row in X]
+    Ym = [[mp.mpf(float(y)) for y in row] for row in Y]
+    for f in range(k):
+        val = range(starts[f], starts[f + 1])
+        keep = [i for i in range(n) if i not in val]
+        H = mp.matrix(d, d)
+        B = mp.matrix(d, c)
+        for i in keep:
+            for a in range(d):
+                for b in range(d):
+                    H[a, b] += Xm[i][a] * Xm[i][b]
+                for j in range(c):
+                    B[a, j] += Xm[i][a] * Ym[i][j]
+        H /= len(keep)
+        B /= len(keep)
+        Ls = [mp.cholesky(H + mp.mpf(float(lam)) * mp.eye(d)) for lam in lam_s]
+        for t, lam in enumerate(lam_grid):
+            tau = mp.mpf(float(lam)) / lam_ref
+            w = [sum(Vp[j, s] * tau ** j for j in range(r + 1)) for s in range(g)]
+            Lh = mp.matrix(d, d)
+            for a in range(d):
+                for b in range(a + 1):
+                    Lh[a, b] = sum(w[s] * Ls[s][a, b] for s in range(g))
+            A = Lh * Lh.T
+            sse = mp.mpf(0)
+            for j in range(c):
+                wj = mp.lu_solve(A, B[:, j])
+                np.testing.assert_allclose(
+                    got["W"][f, t, :, j], [float(x) for x in wj], rtol=1e-10,
+                    atol=1e-10 * float(mp.norm(wj, mp.inf)))
+                for i in val:
+                    res = Ym[i][j] - sum(Xm[i][a] * wj[a] for a in range(d))
+                    sse += res * res
+            want = float(sse / (len(val) * c))
+            assert abs(got["mse"][f, t] - want) <= 1e-10 * want, (f, t)
