@@ -17,16 +17,18 @@ C-contiguous float64 copies, outputs are freshly allocated.
 
 Parity status: every entry point is pinned by the CPU tests in
 ``tests/test_oracle_pins.py`` (closed forms, LAPACK, SVD ridge form,
-polynomial reproduction, interpolation of the samples, and the order of the
-Sec. 4 main result at tiny sizes: the degree-2 factor's error falls as the
-cube of the sample width.  The bound's constants, M_s, E_s and R, are not
-evaluated: the derivation takes vec(Gamma^T) = vec(Gamma) for a lower
-triangular Gamma, so its M_s^-1 v_I is not the factor's derivative, and only
-the cubic order is used as a pin).  The whole interpolated pipeline off the samples is pinned at
-small d against the same steps composed from library routines (LAPACK
-Cholesky, numpy polyfit/polyval, LAPACK triangular solves, the validation
-residual).  At large d the curve has no pin beyond these: its parity there is
-"parity unpinned" beyond the oracle itself.
+polynomial reproduction, interpolation of the samples, and the Sec. 4 main
+result at tiny sizes: the degree-2 factor's error falls as the cube of the
+sample width, and it stays within the theorem's bound with the constants
+M_s, E_s and R evaluated as the paper writes them.  That derivation takes
+vec(Gamma^T) = vec(Gamma) for a lower triangular Gamma, so its M_s^-1 v_I is
+not the factor's derivative; the bound is used as printed and is loose).
+The whole interpolated pipeline off the samples is pinned at small d against
+the same steps composed from library routines (LAPACK Cholesky, numpy
+polyfit/polyval, LAPACK triangular solves, the validation residual) and
+against the same mathematics in 50-digit arithmetic.  At large d the curve
+has no pin beyond these: its parity there is "parity unpinned" beyond the
+oracle itself.
 """
 from __future__ import annotations
 

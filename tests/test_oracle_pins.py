@@ -886,3 +886,49 @@ def test_interpolated_cv_matches_50_digit_arithmetic():
                     sse += res * res
             want = float(sse / (len(val) * c))
             assert abs(got["mse"][f, t] - want) <= 1e-10 * want, (f, t)
+
+
+@pytest.mark.parametrize("w", [0.2, 0.05])
+def test_interpolation_error_within_main_result_bound(w):
+    """The Sec. 4 main result at a tiny size (A of order 4): with g samples
+    in [lam_c - w, lam_c + w] and lam_c > gamma >= w, the degree-2 factor
+    from the oracle's fit and evaluation satisfies, for lambda in
+    [lam_c - gamma, lam_c + gamma],
+        ||C(A + lambda I) - p(lambda)||_F
+            <= [gamma^3 + sqrt(g) w^3 (1 + gamma^2)(lam_c + 1) ||V^+||_2] R,
+    with V the raw-lambda Vandermonde matrix of the samples and
+    R = max_s (||M^-1 E||^2 ||M^-1 v_I|| + ||M^-1|| ||M^-1 E|| ||M^-1 v_I||^2)
+    over [lam_c - gamma, lam_c + gamma], M = L_s (x) I + I (x) L_s,
+    E = K (x) I + I (x) K, K = vec^-1(M^-1 v_I), all taken literally from the
+    paper (the maximum over s by a grid of 81 points).  The bound is loose
+    (the error reaches about 1% of it, where the fit extrapolates furthest
+    from samples within w = 0.05)."""
+    rng = np.random.default_rng(5)
+    n = 4
+    Bm = rng.standard_normal((n, n + 2))
+    A = Bm @ Bm.T / (n + 2) + 0.1 * np.eye(n)
+    lam_c, gam, g, r = 1.0, 0.4, 5, 2
+    lam_s = np.linspace(lam_c - w, lam_c + w, g)
+    lam_ref = float(lam_s.max())
+    T = np.stack([oracle.pack_lower(oracle.cholesky(A, float(x))[0]) for x in lam_s])
+    Th = oracle.fit(T, lam_s, r, lam_ref)
+    I = np.eye(n)
+    vI = I.reshape(-1, order="F")
+
+    def r_term(s):
+        L = np.linalg.cholesky(A + s * I)
+        Mi = np.linalg.inv(np.kron(L, I) + np.kron(I, L))
+        x = Mi @ vI
+        K = x.reshape(n, n, order="F")
+        ME = Mi @ (np.kron(K, I) + np.kron(I, K))
+        nx = np.linalg.norm(x)
+        return (np.linalg.norm(ME, 2) ** 2 * nx
+                + np.linalg.norm(Mi, 2) * np.linalg.norm(ME, 2) * nx ** 2)
+
+    R = max(r_term(s) for s in np.linspace(lam_c - gam, lam_c + gam, 81))
+    Vp = np.linalg.norm(np.linalg.pinv(np.vander(lam_s, r + 1, increasing=True)), 2)
+    bound = (gam ** 3 + np.sqrt(g) * w ** 3 * (1 + gam ** 2) * (lam_c + 1) * Vp) * R
+    for lam in np.linspace(lam_c - gam, lam_c + gam, 9):
+        p = oracle.unpack_lower(oracle.evaluate(Th, float(lam), lam_ref), n)
+        err = np.linalg.norm(np.linalg.cholesky(A + lam * I) - p)
+        assert err <= bound, (lam, err, bound)
