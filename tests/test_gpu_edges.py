@@ -158,3 +158,42 @@ def test_log_basis_rejects_nonpositive_lambda(gu):
                            gu.empty(p.k * p.q, torch.int32))
     assert e.value.status == B.PICHOL_ERR_ARG
 
+
+
+@pytest.mark.parametrize("k,g", [(64, 4), (5, 32)])
+def test_largest_fold_and_sample_counts(gu, k, g):
+    """The boundary's limits on the problem: 64 folds (the hold-out
+    normalisation and the fold split hold 64 entries), 32 samples (the
+    fit's pseudo-inverse holds 32 columns)."""
+    p = workloads.gaussian_problem(640, 96, 2, seed=60 + k + g, g=g, r=2, q=6, k=k)
+    got = gu.cv(p, "interp")
+    want = oracle.cv_interp(p.X, p.Y, k, p.lam_s, p.lam_grid, p.r, want_W=True)
+    _check(got, want)
+    ge = gu.cv(p, "exact")
+    we = oracle.cv_exact(p.X, p.Y, k, p.lam_grid, want_W=True)
+    _check(ge, we)
+
+
+def test_largest_degree(gu):
+    """Degree 7 (eight planes, the largest the fit takes) from eight samples
+    over one decade, against the same steps composed from LAPACK routines
+    (cond(V) = 7e5 in tau: the oracle's normal equations would lose
+    cond(V)^2 eps; two backward-stable fits evaluated inside the sampled
+    range meet far closer)."""
+    import gpu_util
+    p = workloads.gaussian_problem(900, 120, 3, seed=71, k=3, g=8, q=9,
+                                   lam_range=(1e-1, 1.0))
+    lam_s = np.logspace(np.log10(p.lam_grid[0]), np.log10(p.lam_grid[-1]), 8)
+    got = gu.cv(p, "interp", lam_s=lam_s, r=7)
+    assert np.all(got["info"] == 0) and np.all(got["flags"] == 0)
+    b = oracle.fold_bounds(p.n, p.k)
+    for f in range(p.k):
+        mask = np.ones(p.n, bool)
+        mask[b[f]:b[f + 1]] = False
+        Xt, Yt, Xv, Yv = p.X[mask], p.Y[mask], p.X[~mask], p.Y[~mask]
+        ntr = mask.sum()
+        W = gpu_util.library_fit_solve(Xt.T @ Xt / ntr, lam_s, lam_s.max(), 7,
+                                       p.lam_grid, Xt.T @ Yt / ntr)
+        for t in range(len(p.lam_grid)):
+            mse = np.sum((Yv - Xv @ W[t]) ** 2) / Yv.size
+            assert abs(got["mse"][f, t] - mse) <= 1e-9 * mse, (f, t)

@@ -285,24 +285,8 @@ def test_solve_interp_matches_oracle(gu, d, c, g, r, q):
 
 
 def _library_fit_solve(H, lam_s, lam_ref, r, lam, Bd):
-    """The interpolated solve composed from library routines: LAPACK
-    Cholesky at the samples, a least-squares fit of every entry in
-    tau = lambda/lam_ref by LAPACK (SVD based, accurate to cond(V) eps, not
-    cond(V)^2 eps as the normal equations), evaluation, and LAPACK
-    triangular solves."""
-    import scipy.linalg
-    d = H.shape[0]
-    g = len(lam_s)
-    Ls = np.stack([np.linalg.cholesky(H + l * np.eye(d)) for l in lam_s])
-    V = np.vander(np.asarray(lam_s) / lam_ref, r + 1, increasing=True)
-    coef, *_ = np.linalg.lstsq(V, Ls.reshape(g, -1), rcond=None)
-    out = []
-    for l in lam:
-        L = np.tril((np.vander([l / lam_ref], r + 1, increasing=True)[0] @ coef)
-                    .reshape(d, d))
-        z = scipy.linalg.solve_triangular(L, Bd, lower=True)
-        out.append(scipy.linalg.solve_triangular(L.T, z, lower=False))
-    return np.stack(out)
+    import gpu_util
+    return gpu_util.library_fit_solve(H, lam_s, lam_ref, r, lam, Bd)
 
 
 @pytest.mark.parametrize("d,c,g,r,q", [(140, 5, 5, 4, 9), (140, 5, 6, 4, 9),
