@@ -758,13 +758,23 @@ __global__ void __launch_bounds__(128) k_update_factors(int64_t d, int i,
       // A(n, k) = L(I,i)(w*64 + n, k) at k*128 + w*64 + n
       const double* pa = tile + (int64_t)lq * NB + w * 64 + 4 * lr;
       const double* pb = zsrc + (int64_t)lq * ldz + cg + lr;
-#pragma unroll 4
-      for (int k0 = 0; k0 < NB; k0 += 4) {
-        const v4d av = ld4(pa + (int64_t)k0 * NB);
-        const double bv = cok ? pb[(int64_t)k0 * ldz] : 0.0;
+      // four groups of eight k steps, all of a group's loads issued before
+      // its products: sixteen loads per lane in flight at occupancy two
+#pragma unroll 1
+      for (int h = 0; h < 4; ++h) {
+        v4d av[8];
+        double bv[8];
 #pragma unroll
-        for (int bi = 0; bi < 4; ++bi)
-          acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv, acc[bi], 0, 0, 0);
+        for (int st = 0; st < 8; ++st) {
+          const int k0 = 32 * h + 4 * st;
+          av[st] = ld4(pa + (int64_t)k0 * NB);
+          bv[st] = cok ? pb[(int64_t)k0 * ldz] : 0.0;
+        }
+#pragma unroll
+        for (int st = 0; st < 8; ++st)
+#pragma unroll
+          for (int bi = 0; bi < 4; ++bi)
+            acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st][bi], bv[st], acc[bi], 0, 0, 0);
       }
     } else {
       // A(n, k) = L(i,I)(k, w*64 + n) at (w*64 + n)*128 + k
