@@ -2,6 +2,9 @@
 // cross-validation.  Each fold's validation block b contributes
 // G_b = X_b^T X_b and C_b = X_b^T Y_b; the training Gram of fold f is the sum
 // of the other blocks, so no cancellation occurs.
+#include <algorithm>
+#include <atomic>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -49,32 +52,13 @@ __device__ inline void gram_tile_of(int t, int nt, int& I, int& J) {
   I = J = 0;  // not reached for t < tri(nt)
 }
 
-// G_b tile (I,J), J <= I, over the rows of block b; FP64 MFMA.  The wave
-// computes D'(n,m) = sum_r X[r][J*128+n] X[r][I*128+m] for its 64 x 64 part,
-// i.e. G(I*128+m, J*128+n), which is element n*128+m of the column-major tile
-// (I,J); the mirror tile (J,I) receives the transpose.
-// Workgroups are spread over the XCDs in contiguous ranges of the logical
-// order (block by block, then gram_tile_of), so the workgroups running
-// together on one XCD stream the same few strips of X through its L2.
-__global__ void __launch_bounds__(256) k_gram_tiles(const double* X,
-                                                    int64_t ldx, int64_t d,
-                                                    int64_t nt, FoldSplit fs,
-                                                    double* G, int vec_ok) {
-  const int ntri = (int)gridDim.x;
-  const int id = xcd_remap((int)(blockIdx.x + blockIdx.y * gridDim.x),
-                           ntri * (int)gridDim.y);
-  const int b = id / ntri;
-  int I, J;
-  gram_tile_of(id - b * ntri, (int)nt, I, J);
-  const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
-  const int64_t r0 = fs.start[b], r1 = fs.start[b + 1];
-  const int64_t K = r1 - r0;
-  const int64_t ncol = (int64_t)J * NB + wi * 64;  // A' columns of X
-  const int64_t mcol = (int64_t)I * NB + wj * 64;  // B' columns of X
+// The wave's 64 x 64 part of a Gram tile summed over rows ra .. rb-1 of X:
+// D'(n,m) += sum_r X[r][ncol+n] X[r][mcol+m] on FP64 MFMA.
+__device__ inline void gram_rows(Acc64& acc, const double* X, int64_t ldx,
+                                 int64_t d, int64_t ncol, int64_t mcol,
+                                 int64_t ra, int64_t rb, int vec_ok) {
   const LaneXY lx;
-
-  Acc64 acc;
-  acc.zero();
+  const int64_t K = rb - ra;
   const bool fast = vec_ok && ncol + 64 <= d && mcol + 64 <= d;
   int64_t kdone = 0;
   if (fast && K >= 4) {
@@ -82,23 +66,75 @@ __global__ void __launch_bounds__(256) k_gram_tiles(const double* X,
     // mma_panel takes an int K; split very long blocks into chunks
     for (int64_t k0 = 0; k0 < K4; k0 += (1 << 28)) {
       int kk = (int)((K4 - k0) < (1 << 28) ? (K4 - k0) : (1 << 28));
-      mma_panel(acc, X + (r0 + k0) * ldx + ncol, ldx,
-                X + (r0 + k0) * ldx + mcol, ldx, kk);
+      mma_panel(acc, X + (ra + k0) * ldx + ncol, ldx,
+                X + (ra + k0) * ldx + mcol, ldx, kk);
     }
     kdone = K4;
   }
   // remaining rows (all rows on the masked path), four at a time
   for (int64_t k0 = kdone; k0 < K; k0 += 4) {
-    const int64_t r = r0 + k0 + lx.lq;
-    const bool ok = r < r1;
-    const double* rowp = X + (ok ? r : r0) * ldx;
+    const int64_t r = ra + k0 + lx.lq;
+    const bool ok = r < rb;
+    const double* rowp = X + (ok ? r : ra) * ldx;
     v4d av = ld4_masked(rowp, ncol + lx.col0(), d, ok);
     v4d bv = ld4_masked(rowp, mcol + lx.col0(), d, ok);
     acc.mma(av, bv);
   }
+}
+
+// G_b tile (I,J), J <= I, over the rows of block b; FP64 MFMA.  The wave
+// computes D'(n,m) = sum_r X[r][J*128+n] X[r][I*128+m] for its 64 x 64 part,
+// i.e. G(I*128+m, J*128+n), which is element n*128+m of the column-major tile
+// (I,J); the mirror tile (J,I) receives the transpose.
+// Tiles are numbered block by block, then in gram_tile_of's order.  The
+// first nmain workgroups take tiles 0 .. nmain-1 whole, spread over the XCDs
+// in contiguous ranges so that the workgroups running together on one XCD
+// stream the same few strips of X through its L2.  When the tile count is
+// not a multiple of the workgroups the GPU holds at once, the last ntail
+// tiles would run as a thin final round; they are cut instead into nsplit
+// chunks of their block's rows, one workgroup per (chunk, tile) after the
+// whole tiles, each writing its partial tile (column-major, the chunk-major
+// order of the workgroups) to part for k_gram_tail to add up.
+__global__ void __launch_bounds__(256) k_gram_tiles(const double* X,
+                                                    int64_t ldx, int64_t d,
+                                                    int64_t nt, FoldSplit fs,
+                                                    double* G, int vec_ok,
+                                                    int nmain, int ntail,
+                                                    int nsplit, double* part) {
+  const int ntri = (int)tri(nt);
+  const int u = (int)blockIdx.x;
+  const bool whole = u < nmain;
+  int tl, p = 0;
+  if (whole) {
+    tl = xcd_remap(u, nmain);
+  } else {
+    p = (u - nmain) / ntail;
+    tl = nmain + (u - nmain - p * ntail);
+  }
+  const int b = tl / ntri;
+  int I, J;
+  gram_tile_of(tl - b * ntri, (int)nt, I, J);
+  const int w = threadIdx.x >> 6, wi = w >> 1, wj = w & 1;
+  int64_t ra = fs.start[b], rb = fs.start[b + 1];
+  if (!whole) {
+    // chunk p of the block's rows, a multiple of four rows long
+    const int64_t kc = ((rb - ra + nsplit - 1) / nsplit + 3) & ~(int64_t)3;
+    const int64_t a0 = ra + p * kc;
+    const int64_t a1 = a0 + kc;
+    ra = a0 < rb ? a0 : rb;
+    rb = a1 < rb ? a1 : rb;
+  }
+  const int64_t ncol = (int64_t)J * NB + wi * 64;  // A' columns of X
+  const int64_t mcol = (int64_t)I * NB + wj * 64;  // B' columns of X
+  const LaneXY lx;
+
+  Acc64 acc;
+  acc.zero();
+  gram_rows(acc, X, ldx, d, ncol, mcol, ra, rb, vec_ok);
 
   double* gb = G + (int64_t)b * nt * nt * NB2;
-  double* gt = gb + ((int64_t)I * nt + J) * NB2;
+  double* gt = whole ? gb + ((int64_t)I * nt + J) * NB2
+                     : part + (int64_t)(u - nmain) * NB2;
   double* gm = gb + ((int64_t)J * nt + I) * NB2;
   const int m0 = wj * 64 + lx.col0();
 #pragma unroll
@@ -108,11 +144,36 @@ __global__ void __launch_bounds__(256) k_gram_tiles(const double* X,
       const int n = wi * 64 + lx.row(v, bi);
       const v4d val = acc.row(v, bi);
       st4(gt + n * NB + m0, val);
-      if (I != J) {
+      if (whole && I != J) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) gm[(m0 + e) * NB + n] = val[e];
       }
     }
+}
+
+// The split tiles of k_gram_tiles: tile nmain + j is the sum of its nsplit
+// partial tiles, added in chunk order, written with its mirror.
+__global__ void __launch_bounds__(256) k_gram_tail(int64_t nt, int nmain,
+                                                   int ntail, int nsplit,
+                                                   const double* part,
+                                                   double* G) {
+  const int ntri = (int)tri(nt);
+  const int j = (int)blockIdx.x;
+  const int tl = nmain + j;
+  const int b = tl / ntri;
+  int I, J;
+  gram_tile_of(tl - b * ntri, (int)nt, I, J);
+  double* gb = G + (int64_t)b * nt * nt * NB2;
+  double* gt = gb + ((int64_t)I * nt + J) * NB2;
+  double* gm = gb + ((int64_t)J * nt + I) * NB2;
+  for (int e = threadIdx.x; e < NB2; e += blockDim.x) {
+    double acc = part[(int64_t)j * NB2 + e];
+    for (int p = 1; p < nsplit; ++p)
+      acc += part[((int64_t)p * ntail + j) * NB2 + e];
+    gt[e] = acc;
+    // element e = n*128 + m of the tile is element m*128 + n of its mirror
+    if (I != J) gm[(e & (NB - 1)) * NB + (e >> 7)] = acc;
+  }
 }
 
 // C_b = X_b^T Y_b (dp x c, row-major, padding rows 0) on FP64 MFMA.  A
@@ -259,14 +320,68 @@ __global__ void __launch_bounds__(256) k_gram_combine_b(int64_t n_el,
   }
 }
 
+// Workgroups of k_gram_tiles the current device runs at once (0 if
+// unknown), looked up once per device.
+static int gram_slots() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  int v = cache[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
+    int cu = 0, per = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount,
+                              dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gram_tiles, 256,
+                                                     0) != hipSuccess)
+      cu = per = 0;
+    v = cu * per > 0 ? cu * per : -1;
+    cache[dev].store(v, std::memory_order_relaxed);
+  }
+  return v > 0 ? v : 0;
+}
+
+// Row chunks for the tiles of the last, partly filled round of
+// k_gram_tiles: the count s (1 = no split) that minimises that round's
+// length ceil(tail*s / slots) / s in whole-tile times.  The tail*s partial
+// tiles must fit in H (one tile of H per Gram tile) and each chunk keeps at
+// least 256 rows.
+static int gram_split(int ntiles, int slots, int64_t kmin) {
+  if (slots <= 0) return 1;
+  const int tail = ntiles % slots;
+  if (tail == 0) return 1;
+  int best = 1;
+  double best_len = 1.0;
+  for (int sp = 2; sp <= 8; ++sp) {
+    if ((int64_t)tail * sp > ntiles || kmin / sp < 256) break;
+    const double len = (double)((tail * sp + slots - 1) / slots) / sp;
+    if (len < best_len) {
+      best_len = len;
+      best = sp;
+    }
+  }
+  return best;
+}
+
 hipError_t launch_gram(const double* X, int64_t ldx, const double* Y,
                        int64_t ldy, int64_t d, int64_t c,
                        const FoldSplit& fs, double* G, double* C, double* yy,
                        double* H, double* B, hipStream_t s) {
   const int64_t nt = ntiles_of(d), dp = nt * NB, S = packed_elems_of(d);
   const int vec_ok = ((ldx & 3) == 0) && ((((uintptr_t)X) & 31) == 0);
-  PICHOL_LAUNCH(k_gram_tiles, dim3((unsigned)tri(nt), (unsigned)fs.k),
-                     dim3(256), 0, s, X, ldx, d, nt, fs, G, vec_ok);
+  const int ntiles = (int)tri(nt) * fs.k;
+  int64_t kmin = fs.start[1] - fs.start[0];
+  for (int b = 1; b < fs.k; ++b)
+    kmin = std::min<int64_t>(kmin, fs.start[b + 1] - fs.start[b]);
+  const int nsplit = gram_split(ntiles, gram_slots(), kmin);
+  const int ntail = nsplit > 1 ? ntiles % gram_slots() : 0;
+  const int nmain = ntiles - ntail;
+  // the partial tiles live in H until k_gram_combine_h writes it
+  PICHOL_LAUNCH(k_gram_tiles, dim3((unsigned)(nmain + ntail * nsplit)),
+                dim3(256), 0, s, X, ldx, d, nt, fs, G, vec_ok, nmain, ntail,
+                nsplit, H);
+  if (ntail > 0)
+    PICHOL_LAUNCH(k_gram_tail, dim3((unsigned)ntail), dim3(256), 0, s, nt,
+                  nmain, ntail, nsplit, H, G);
   PICHOL_LAUNCH(k_gram_rhs, dim3((unsigned)(dp / 64), (unsigned)fs.k),
                      dim3(256), 0, s, X, ldx, Y, ldy, d, c, dp, fs, vec_ok, C,
                      yy);
