@@ -278,29 +278,50 @@ __global__ void __launch_bounds__(256) k_gram_rhs(const double* X, int64_t ldx,
   }
 }
 
+// H_f = scale_f * sum_{b != f} G_b on the lower tiles, the blocks added in
+// increasing order; padding gets the identity.  With at most KM folds a
+// workgroup takes a quarter of one tile for every fold at once: each
+// element of the k blocks is read once into registers and every fold's sum
+// is formed from them.  With more folds, blockIdx.y is the fold and each
+// fold's workgroups read the blocks again.
+template <int KM>
 __global__ void __launch_bounds__(256) k_gram_combine_h(int64_t d, int64_t nt,
                                                         FoldSplit fs,
                                                         const double* G,
                                                         double* H, int64_t S) {
-  const int f = blockIdx.y;
   const int I = tri_row(blockIdx.x), J = blockIdx.x - (int)tri(I);
-  const double sc = fs.scale[f];
-  double* h = H + (int64_t)f * S + tile_off(I, J);
   const int64_t gstride = nt * nt * NB2;
   const double* g0 = G + ((int64_t)I * nt + J) * NB2;
-  for (int e = threadIdx.x; e < NB2; e += blockDim.x) {
+  const int64_t hoff = tile_off(I, J);
+  const int k = fs.k;
+  const int e0 = KM > 0 ? (int)blockIdx.y * (NB2 / 4) : 0;
+  const int e1 = KM > 0 ? e0 + NB2 / 4 : NB2;
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
     const int64_t i = (int64_t)I * NB + (e & (NB - 1));
     const int64_t j = (int64_t)J * NB + (e >> 7);
-    double v;
-    if (i >= d || j >= d) {
-      v = (i == j) ? 1.0 : 0.0;
+    const bool pad = i >= d || j >= d;
+    if (KM > 0) {
+      double v[KM > 0 ? KM : 1];
+#pragma unroll
+      for (int b = 0; b < KM; ++b)
+        v[b] = (b < k && !pad) ? g0[b * gstride + e] : 0.0;
+#pragma unroll
+      for (int f = 0; f < KM; ++f) {
+        if (f >= k) break;
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < KM; ++b)
+          if (b < k && b != f) acc += v[b];
+        H[f * S + hoff + e] = pad ? (i == j ? 1.0 : 0.0) : acc * fs.scale[f];
+      }
     } else {
+      const int f = blockIdx.y;
       double acc = 0.0;
-      for (int b = 0; b < fs.k; ++b)
-        if (b != f) acc += g0[b * gstride + e];
-      v = acc * sc;
+      if (!pad)
+        for (int b = 0; b < k; ++b)
+          if (b != f) acc += g0[b * gstride + e];
+      H[f * S + hoff + e] = pad ? (i == j ? 1.0 : 0.0) : acc * fs.scale[f];
     }
-    h[e] = v;
   }
 }
 
@@ -385,8 +406,12 @@ hipError_t launch_gram(const double* X, int64_t ldx, const double* Y,
   PICHOL_LAUNCH(k_gram_rhs, dim3((unsigned)(dp / 64), (unsigned)fs.k),
                      dim3(256), 0, s, X, ldx, Y, ldy, d, c, dp, fs, vec_ok, C,
                      yy);
-  PICHOL_LAUNCH(k_gram_combine_h, dim3((unsigned)tri(nt), (unsigned)fs.k),
-                     dim3(256), 0, s, d, nt, fs, G, H, S);
+  if (fs.k <= 8)
+    PICHOL_LAUNCH(k_gram_combine_h<8>, dim3((unsigned)tri(nt), 4u), dim3(256),
+                  0, s, d, nt, fs, G, H, S);
+  else
+    PICHOL_LAUNCH(k_gram_combine_h<0>, dim3((unsigned)tri(nt), (unsigned)fs.k),
+                  dim3(256), 0, s, d, nt, fs, G, H, S);
   const int64_t nb = dp * c;
   unsigned bx = (unsigned)((nb + 255) / 256);
   if (bx > 2048) bx = 2048;
