@@ -189,7 +189,8 @@ pichol_status pichol_unpack(int64_t d, int32_t nmat, const double *P,
  *   yy  k: yy[b] = sum of Y_b^2;
  *   H   k packed: H_f = sum_{b != f} G[b] (/ n_tr when normalize);
  *   B   k x dp x c row-major: B_f = sum_{b != f} C[b] (/ n_tr).
- * Sums over blocks run in increasing block order. */
+ * Sums over blocks run in increasing block order.  H must not overlap X, Y
+ * or G: the call also keeps partial Gram tiles in it before writing H. */
 pichol_status pichol_gram(const pichol_problem *p, const double *X,
                           const double *Y, double *G, double *C, double *yy,
                           double *H, double *B, hipStream_t stream);

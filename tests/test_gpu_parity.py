@@ -85,6 +85,39 @@ def test_gram_matches_oracle(gu, n, d, c, k):
         np.testing.assert_allclose(yy[f], np.sum(Yb * Yb), rtol=1e-13)
 
 
+def test_gram_split_last_round_matches_oracle(gu):
+    """8 folds of 2048 rows, d = 1371 (11 tile columns, the last one ragged):
+    8 x 66 = 528 Gram tiles, 16 more than one round of 512 workgroups on a
+    256-CU MI355X, so the last 16 tiles (among them the ragged diagonal
+    tile) are summed over eight row chunks and added up by the tail kernel.
+    Every block's G and C, and H of the first and last fold, against the
+    oracle's definitions."""
+    n, d, c, k = 16384, 1371, 3, 8
+    rng = np.random.default_rng(1371)
+    X = rng.standard_normal((n, d))
+    Y = rng.standard_normal((n, c))
+    out = gu.gram(X, Y, k)
+    torch.cuda.synchronize()
+    H = gu.unpack(out["H"], d, k)
+    dp = gu.B.pichol_padded_order(d)
+    G = out["G"].cpu().numpy().reshape(k, dp // 128, dp // 128, 128, 128)
+    C = out["C"].cpu().numpy().reshape(k, dp, c)
+    starts = np.concatenate([[0], np.cumsum(gu.fold_sizes(n, k))])
+    for b in range(k):
+        Xb, Yb = X[starts[b]:starts[b + 1]], Y[starts[b]:starts[b + 1]]
+        Gd = G[b].transpose(0, 3, 1, 2).reshape(dp, dp)
+        close(Gd[:d, :d], Xb.T @ Xb, 1e-13, "G")
+        assert np.all(Gd[d:, :] == 0.0) and np.all(Gd[:, d:] == 0.0)
+        # the mirror of every tile below the diagonal is its exact transpose
+        for I in range(dp // 128):
+            for J in range(I):
+                np.testing.assert_array_equal(G[b, J, I], G[b, I, J].T)
+        close(C[b, :d], Xb.T @ Yb, 1e-13, "C")
+    for f in (0, k - 1):
+        Ho, _, _ = oracle.fold_gram(X, Y, k, f)
+        close(H[f], np.tril(Ho), 1e-13, "H")
+
+
 # ------------------------------------------------------------------ factorization
 
 @pytest.mark.parametrize("d", [1, 5, 127, 128, 129, 257, 384])
