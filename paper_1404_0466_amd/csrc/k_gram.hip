@@ -152,7 +152,11 @@ __global__ void __launch_bounds__(256) k_gram_tiles(const double* X,
 }
 
 // The split tiles of k_gram_tiles: tile nmain + j is the sum of its nsplit
-// partial tiles, added in chunk order, written with its mirror.
+// (at most 8) partial tiles, added in chunk order, written with its mirror.
+// Workgroup (j, y) takes elements y*1024 .. y*1024+1023 of the tile, four
+// consecutive ones per thread, with the loads of every chunk in flight
+// together.
+constexpr int GRAM_SPLIT_MAX = 8;
 __global__ void __launch_bounds__(256) k_gram_tail(int64_t nt, int nmain,
                                                    int ntail, int nsplit,
                                                    const double* part,
@@ -166,13 +170,21 @@ __global__ void __launch_bounds__(256) k_gram_tail(int64_t nt, int nmain,
   double* gb = G + (int64_t)b * nt * nt * NB2;
   double* gt = gb + ((int64_t)I * nt + J) * NB2;
   double* gm = gb + ((int64_t)J * nt + I) * NB2;
-  for (int e = threadIdx.x; e < NB2; e += blockDim.x) {
-    double acc = part[(int64_t)j * NB2 + e];
-    for (int p = 1; p < nsplit; ++p)
-      acc += part[((int64_t)p * ntail + j) * NB2 + e];
-    gt[e] = acc;
-    // element e = n*128 + m of the tile is element m*128 + n of its mirror
-    if (I != J) gm[(e & (NB - 1)) * NB + (e >> 7)] = acc;
+  const int e = (int)blockIdx.y * 1024 + 4 * (int)threadIdx.x;
+  v4d v[GRAM_SPLIT_MAX];
+#pragma unroll
+  for (int p = 0; p < GRAM_SPLIT_MAX; ++p)
+    if (p < nsplit) v[p] = ld4(part + ((int64_t)p * ntail + j) * NB2 + e);
+  v4d acc = v[0];
+#pragma unroll
+  for (int p = 1; p < GRAM_SPLIT_MAX; ++p)
+    if (p < nsplit) acc += v[p];
+  st4(gt + e, acc);
+  // element e = n*128 + m of the tile is element m*128 + n of its mirror
+  if (I != J) {
+    const int n = e >> 7, m = e & (NB - 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) gm[(m + q) * NB + n] = acc[q];
   }
 }
 
@@ -372,7 +384,7 @@ static int gram_split(int ntiles, int slots, int64_t kmin) {
   if (tail == 0) return 1;
   int best = 1;
   double best_len = 1.0;
-  for (int sp = 2; sp <= 8; ++sp) {
+  for (int sp = 2; sp <= GRAM_SPLIT_MAX; ++sp) {
     if ((int64_t)tail * sp > ntiles || kmin / sp < 256) break;
     const double len = (double)((tail * sp + slots - 1) / slots) / sp;
     if (len < best_len) {
@@ -401,8 +413,8 @@ hipError_t launch_gram(const double* X, int64_t ldx, const double* Y,
                 dim3(256), 0, s, X, ldx, d, nt, fs, G, vec_ok, nmain, ntail,
                 nsplit, H);
   if (ntail > 0)
-    PICHOL_LAUNCH(k_gram_tail, dim3((unsigned)ntail), dim3(256), 0, s, nt,
-                  nmain, ntail, nsplit, H, G);
+    PICHOL_LAUNCH(k_gram_tail, dim3((unsigned)ntail, NB2 / 1024), dim3(256), 0,
+                  s, nt, nmain, ntail, nsplit, H, G);
   PICHOL_LAUNCH(k_gram_rhs, dim3((unsigned)(dp / 64), (unsigned)fs.k),
                      dim3(256), 0, s, X, ldx, Y, ldy, d, c, dp, fs, vec_ok, C,
                      yy);
