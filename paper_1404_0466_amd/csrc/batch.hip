@@ -426,6 +426,7 @@ pichol_status pichol_cv_batch_graph(int32_t nprob,
     hipError_t e = batch_streams(&S);
     if (e != hipSuccess) return hip_status(e);
   }
+  prepare_gram();
   hipStream_t cs = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_status(e);
@@ -462,6 +463,7 @@ pichol_status pichol_graph_begin(hipStream_t stream) {
     hipError_t e = batch_streams(&S);
     if (e != hipSuccess) return hip_status(e);
   }
+  prepare_gram();
   return hip_status(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
 }
 

@@ -373,6 +373,8 @@ static int gram_slots() {
   return v > 0 ? v : 0;
 }
 
+void prepare_gram() { (void)gram_slots(); }
+
 // Row chunks for the tiles of the last, partly filled round of
 // k_gram_tiles: the count s (1 = no split) that minimises that round's
 // length ceil(tail*s / slots) / s in whole-tile times.  The tail*s partial

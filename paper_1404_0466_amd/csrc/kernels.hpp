@@ -58,6 +58,9 @@ struct FoldSplit {
   int64_t start[65];  // start[f] .. start[f+1] rows of fold f (k <= 64)
   double scale[64];   // 1/n_tr or 1
 };
+// Looks up, once per device, the device facts the Gram launch depends on
+// (for callers about to start a stream capture).
+void prepare_gram();
 hipError_t launch_gram(const double* X, int64_t ldx, const double* Y,
                        int64_t ldy, int64_t d, int64_t c,
                        const FoldSplit& fs, double* G, double* C, double* yy,
