@@ -116,6 +116,11 @@ def test_gram_split_last_round_matches_oracle(gu):
     for f in (0, k - 1):
         Ho, _, _ = oracle.fold_gram(X, Y, k, f)
         close(H[f], np.tril(Ho), 1e-13, "H")
+    # no atomics anywhere: a second call gives the same bits
+    again = gu.gram(X, Y, k)
+    torch.cuda.synchronize()
+    for name in ("G", "C", "H", "B", "yy"):
+        assert torch.equal(again[name], out[name]), name
 
 
 # ------------------------------------------------------------------ factorization
