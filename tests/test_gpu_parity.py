@@ -85,15 +85,23 @@ def test_gram_matches_oracle(gu, n, d, c, k):
         np.testing.assert_allclose(yy[f], np.sum(Yb * Yb), rtol=1e-13)
 
 
-def test_gram_split_last_round_matches_oracle(gu):
-    """8 folds of 2048 rows, d = 1371 (11 tile columns, the last one ragged):
-    8 x 66 = 528 Gram tiles, 16 more than one round of 512 workgroups on a
-    256-CU MI355X, so the last 16 tiles (among them the ragged diagonal
-    tile) are summed over eight row chunks and added up by the tail kernel.
+@pytest.mark.parametrize("n,d,k", [(16384, 1371, 8), (16392, 1371, 8),
+                                   (24576, 1152, 12)])
+def test_gram_split_last_round_matches_oracle(gu, n, d, k):
+    """Gram tile counts just above one round of 512 workgroups (two per CU
+    on a 256-CU MI355X), so the last tiles are summed over row chunks and
+    added up by the tail kernel:
+      - 8 folds of 2048 rows, d = 1371 (11 tile columns, the last one
+        ragged): 8 x 66 = 528 tiles, the last 16 (among them the ragged
+        diagonal tile) in eight chunks;
+      - the same with folds of 2049 rows (chunks of 260 rows, the last one
+        229 rows long, not a multiple of four);
+      - 12 folds of 2048 rows, d = 1152: 12 x 45 = 540 tiles, the last 28
+        in eight chunks, and the combine for more than eight folds.
     Every block's G and C, and H of the first and last fold, against the
     oracle's definitions."""
-    n, d, c, k = 16384, 1371, 3, 8
-    rng = np.random.default_rng(1371)
+    c = 3
+    rng = np.random.default_rng(n + d)
     X = rng.standard_normal((n, d))
     Y = rng.standard_normal((n, c))
     out = gu.gram(X, Y, k)
